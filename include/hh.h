@@ -1,0 +1,183 @@
+/*
+ * hh.h -- C ABI of the MI355X (gfx950) hierarchical-homogenization library.
+ *
+ * Computes effective elastic stiffnesses of segmented 3-D images by the
+ * periodic FFT (Fourier-Galerkin) elasticity solve of the paper's Appendix A,
+ * averaged over a region as in Sec. 4, and the two-level hierarchical scheme
+ * of Sec. 3 with the n^-1 extrapolation of Sec. 5 (eq_fit_power_law).
+ *
+ * Conventions (all entry points):
+ *  - Images are C-contiguous arrays indexed [z][y][x] (x fastest); tensor
+ *    index 1/2/3 is x/y/z.  Sizes are in voxels; moduli in GPa.
+ *  - Stiffness matrices are 6x6 Voigt matrices, row-major, in the order
+ *    (11, 22, 33, 23, 13, 12), acting on strain vectors with engineering
+ *    shear components (2 eps_ij); an isotropic phase has C44 = G.
+ *  - "21 components" is the upper triangle of a symmetric 6x6, row-major.
+ *  - Pointers flagged *_on_device are device pointers of the context's
+ *    device; all others are host pointers.  The caller owns every buffer it
+ *    passes; the library owns its workspace and returns no allocations.
+ *  - Return value: HH_OK (0) or a negative HH_E* code; hh_last_error()
+ *    describes the last failure on that context.  No exception crosses the
+ *    ABI.  A context is not thread-safe: use one per host thread / stream.
+ *  - Calls are synchronous with respect to the host: outputs are written
+ *    when the call returns.  Device work runs on the context's stream.
+ */
+#ifndef HH_H
+#define HH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HH_OK 0
+#define HH_EINVAL (-1)        /* bad sizes / arguments, label >= nphase, N % n != 0, ... */
+#define HH_EUNSUPPORTED (-2)  /* axis length without compiled FFT passes (not 5-smooth, too large) */
+#define HH_ENOMEM (-3)        /* device allocation failed */
+#define HH_EDEVICE (-4)       /* HIP runtime error or not a gfx950 device */
+#define HH_ESINGULAR (-5)     /* averaged strain matrix E_R not invertible */
+#define HH_ENOCONV (-6)       /* max_iter reached: best C still written, report.status set */
+#define HH_ESTAGNATED (-7)    /* residual stopped decreasing (e.g. tol below FP32 floor) */
+#define HH_EBREAKDOWN (-8)    /* (p, A p) <= 0 or non-finite values in the iteration */
+
+#define HH_NKERNEL 8          /* kernel classes timed in hh_report.kernel_ms */
+/* kernel class indices */
+#define HH_K_ZINV 0
+#define HH_K_YINV 1
+#define HH_K_X 2
+#define HH_K_YFWD 3
+#define HH_K_ZFWD 4
+#define HH_K_FIN 5
+#define HH_K_SETUP 6
+#define HH_K_OTHER 7
+
+typedef struct hh_ctx hh_ctx;
+
+/* Isotropic phase: bulk modulus K and shear modulus G (both > 0), Sec. 4. */
+typedef struct {
+  double K, G;
+} hh_phase;
+
+/* Solver options.  hh_default_opts() fills the defaults given here. */
+typedef struct {
+  double tol;        /* stop when ||r|| <= tol ||b||, r = -G*(C:(E+eps*)); default 1e-6 */
+  int max_iter;      /* per load case; default 1000 */
+  int scheme;        /* 0: conjugate gradients (Appendix A); 1: basic fixed point with
+                        reference medium (ref_lambda, ref_mu); default 0 */
+  int precision;     /* 0: FP32 fields and FFTs, FP64 reductions/scalars/averages;
+                        1: FP64 throughout; default 0 */
+  int nyquist;       /* even axes: 0 = Nyquist wavenumber component set to 0;
+                        1 = operator zero at every frequency with a Nyquist component */
+  int profile;       /* 1: time every kernel class with HIP events (hh_report.kernel_ms) */
+  int stall_limit;   /* iterations without a new smallest residual before
+                        HH_ESTAGNATED; default 100 */
+  int chunk;         /* iterations launched between convergence polls; default 8 */
+  double ref_lambda, ref_mu; /* basic scheme reference medium; <= 0: mid-range of the phases */
+} hh_opts;
+
+/* Per-call report. */
+typedef struct {
+  int status;                   /* HH_OK or the worst per-load status */
+  int iters[6];                 /* iterations per load (first item for batched calls) */
+  double rel_resid[6];          /* final ||r|| / ||b|| per load (first item) */
+  double asym;                  /* max |C - C^T| / max |C| of the raw Sigma E^-1 */
+  double seconds;               /* device wall time of the call (HIP events) */
+  double voxel_iters;           /* sum over items and loads of voxels x iterations */
+  long long items;              /* images homogenized by the call */
+  double kernel_ms[HH_NKERNEL]; /* with opts.profile: summed device time per class */
+  int kernel_launches[HH_NKERNEL];
+} hh_report;
+
+/* Fills *opts with the defaults listed in hh_opts. */
+void hh_default_opts(hh_opts *opts);
+
+/* Creates a context on HIP device `device`, launching on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Fails with HH_EDEVICE if the
+ * device is not gfx950. */
+int hh_create(hh_ctx **ctx, int device, void *hip_stream);
+/* Changes the stream of an existing context. */
+int hh_set_stream(hh_ctx *ctx, void *hip_stream);
+/* Frees the context and its device workspace.  NULL is ignored. */
+void hh_destroy(hh_ctx *ctx);
+/* Message describing the last failing call on ctx (empty if none). */
+const char *hh_last_error(const hh_ctx *ctx);
+/* Device workspace currently held by the context, in bytes. */
+long long hh_workspace_bytes(const hh_ctx *ctx);
+/* Releases the context's workspace (it is re-allocated on demand). */
+void hh_release_workspace(hh_ctx *ctx);
+/* 1 if axis length n has compiled FFT passes at `precision`, else 0. */
+int hh_size_supported(int n, int precision);
+
+/*
+ * Effective stiffness of one label image (Sec. 4; Appendix A solve).
+ * labels: uint8[nz][ny][nx] phase indices < nphase.  phases[nphase].
+ * loads: 6x6, column a = the engineering-Voigt macroscopic strain of load a
+ *   (column-major, loads[6*a + i]); NULL = the six unit strains.  The six
+ *   loads must be independent.
+ * region: {x0, y0, z0, x1, y1, z1}, half open, the averaging region
+ *   Omega_R inside the periodic box; NULL = the whole box.
+ * C_out: symmetrized (C + C^T)/2 of C_R = Sigma_R E_R^-1, 36 doubles.
+ * C_raw: the raw C_R (may be NULL).  report: may be NULL.
+ */
+int hh_homogenize(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, int labels_on_device,
+                  const hh_phase *phases, int nphase, const double *loads, const int *region,
+                  const hh_opts *opts, double C_out[36], double C_raw[36], hh_report *report);
+
+/*
+ * Effective stiffness of an image of anisotropic voxels (the intermediate
+ * image of Sec. 3, solved as stated at the end of Sec. 4).
+ * C21: per voxel 21 upper-triangle components, [nz][ny][nx][21] doubles
+ *   (host or device); each voxel stiffness must be positive definite.
+ */
+int hh_homogenize_aniso(hh_ctx *ctx, const double *C21, int nx, int ny, int nz, int c21_on_device,
+                        const hh_opts *opts, double C_out[36], double C_raw[36], hh_report *report);
+
+/*
+ * Batch of independent images of possibly different sizes and phase sets
+ * (the subimage solves of Sec. 3 are independent).  Item i has shape
+ * dims[3*i .. 3*i+2] = (nx, ny, nz), labels at byte
+ * offset label_off[i] of `labels` (uint8, [z][y][x]), phases
+ * phases[phase_off[i] .. phase_off[i] + nphase[i]), and averaging region
+ * regions[6*i ..] (NULL = whole boxes).  Items of equal shape are solved in
+ * one launch per pass.  C_out: nitems x 36 symmetrized stiffnesses;
+ * C_raw: nitems x 36 raw (may be NULL); item_status: nitems HH codes (may be
+ * NULL); item_iters: nitems x 6 iteration counts (may be NULL).
+ */
+int hh_homogenize_batch(hh_ctx *ctx, int nitems, const int *dims, const uint8_t *labels,
+                        long long labels_bytes, int labels_on_device, const long long *label_off,
+                        const hh_phase *phases, const int *phase_off, const int *nphase,
+                        const int *regions, const hh_opts *opts, double *C_out, double *C_raw,
+                        int *item_status, int *item_iters, hh_report *report);
+
+/*
+ * Two-level hierarchical homogenization (Sec. 3, Fig. 2; padding Sec. 4,
+ * Fig. 4).  labels: uint8[nz][ny][nx]; n_sub must divide each dimension and
+ * 2 pad < each dimension.  Each n_sub^3 block is solved in the box
+ * extended by `pad` voxels of surrounding material (periodic wrap at the
+ * image edge) and averaged over the block; the symmetrized block stiffnesses
+ * form the intermediate image, which is solved with anisotropic voxels.
+ * C_out: final C* (36).  C_sub: (nz/n)(ny/n)(nx/n) x 21 symmetrized block
+ * stiffnesses, C order (may be NULL).  use_surrogate must be 0.
+ */
+int hh_hierarchical(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, int labels_on_device,
+                    const hh_phase *phases, int nphase, int n_sub, int pad, int use_surrogate,
+                    const hh_opts *opts, double C_out[36], double *C_sub, hh_report *report);
+
+/*
+ * Least-squares fit M(n) = M_inf + slope / n of each of the 36 entries over
+ * m >= 2 distinct subimage sizes (Sec. 5, eq_fit_power_law).  C: m x 36
+ * (row i belongs to n[i]).  Host only.
+ */
+int hh_richardson(const int *n, const double *C, int m, double C_inf[36], double slope[36]);
+
+/* Bulk and shear moduli of the Voigt isotropic projection of a 6x6
+ * stiffness: K = (C11+C22+C33 + 2(C12+C13+C23))/9,
+ * G = (C11+C22+C33 - (C12+C13+C23) + 3(C44+C55+C66))/15.  Host only. */
+int hh_moduli(const double C[36], double *K, double *G);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HH_H */

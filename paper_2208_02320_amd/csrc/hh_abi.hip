@@ -1,0 +1,851 @@
+// Host side of the C ABI declared in include/hh.h: validation, workspace,
+// the per-group solve loop, and the hierarchical driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/hh.h"
+#include "hh_internal.hpp"
+#include "kernels.hpp"
+
+using namespace hh;
+
+struct hh_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<std::string, std::pair<void*, size_t>> bufs;
+  std::vector<hipEvent_t> evpool;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+namespace {
+
+struct Fail {
+  int code;
+};
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                       \
+      throw Fail{e_ == hipErrorOutOfMemory ? HH_ENOMEM : HH_EDEVICE};                      \
+    }                                                                                      \
+  } while (0)
+
+[[noreturn]] void fail(hh_ctx* ctx, int code, const std::string& msg) {
+  ctx->err = msg;
+  throw Fail{code};
+}
+
+void* ws(hh_ctx* ctx, const std::string& name, size_t bytes) {
+  auto it = ctx->bufs.find(name);
+  if (it != ctx->bufs.end() && it->second.second >= bytes) return it->second.first;
+  if (it != ctx->bufs.end()) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipFree(it->second.first));
+    ctx->bufs.erase(it);
+  }
+  void* p = nullptr;
+  const size_t sz = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(ctx, HH_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes for " + name + " failed");
+  }
+  ctx->bufs[name] = {p, sz};
+  return p;
+}
+
+int status_code(int s) {
+  switch (s) {
+    case kConverged: return HH_OK;
+    case kNoConv: return HH_ENOCONV;
+    case kStagnated: return HH_ESTAGNATED;
+    case kBreakdown: return HH_EBREAKDOWN;
+    case kNonFinite: return HH_EBREAKDOWN;
+    case kSingularStatus: return HH_ESINGULAR;
+    case kRunning: return HH_ENOCONV;
+    default: return HH_EDEVICE;
+  }
+}
+
+// Severity order used to report the worst status of several results.
+int worse(int a, int b) {
+  auto rank = [](int c) {
+    switch (c) {
+      case HH_OK: return 0;
+      case HH_ENOCONV: return 1;
+      case HH_ESTAGNATED: return 2;
+      case HH_ESINGULAR: return 3;
+      case HH_EBREAKDOWN: return 4;
+      default: return 5;
+    }
+  };
+  return rank(b) > rank(a) ? b : a;
+}
+
+struct Profile {
+  hh_ctx* ctx;
+  bool on;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> marks;
+  size_t used = 0;
+  hh_report* rep;
+  hipEvent_t ev() {
+    if (used >= ctx->evpool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      ctx->evpool.push_back(e);
+    }
+    return ctx->evpool[used++];
+  }
+  template <class F>
+  void run(int cls, F&& f) {
+    if (!on) {
+      f();
+      return;
+    }
+    hipEvent_t a = ev(), b = ev();
+    HIPCHK(hipEventRecord(a, ctx->stream));
+    f();
+    HIPCHK(hipEventRecord(b, ctx->stream));
+    marks.emplace_back(cls, a, b);
+  }
+  // Called after a stream synchronisation: accumulate and recycle events.
+  void flush() {
+    if (!on) return;
+    for (auto& m : marks) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, std::get<1>(m), std::get<2>(m)));
+      if (rep) {
+        rep->kernel_ms[std::get<0>(m)] += ms;
+        rep->kernel_launches[std::get<0>(m)] += 1;
+      }
+    }
+    marks.clear();
+    used = 0;
+  }
+};
+
+struct Item {
+  int nx, ny, nz;
+  long long lab_off;  // iso: byte offset into the label pack
+  long long cf_off;   // aniso: element offset into the stiffness pack
+  int region[6];
+  std::vector<hh_phase> phases;
+};
+
+struct GroupResult {
+  std::vector<double> C72;  // per item: raw (36) then symmetrized (36)
+  std::vector<int> status;  // per item HH code
+  std::vector<int> iters;   // per item x 6
+  std::vector<double> rel;  // per item x 6
+  double voxel_iters = 0.0;
+};
+
+void unit_loads(double L[6][6]) {
+  for (int a = 0; a < 6; ++a)
+    for (int c = 0; c < 6; ++c) L[a][c] = (a == c) ? (c < 3 ? 1.0 : 0.5) : 0.0;
+}
+
+void loads_from_voigt(const double* v, double L[6][6]) {
+  for (int a = 0; a < 6; ++a)
+    for (int c = 0; c < 6; ++c) L[a][c] = v[6 * a + c] * (c < 3 ? 1.0 : 0.5);
+}
+
+bool loads_independent(const double L[6][6]) {
+  double A[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) A[i][j] = L[i][j];
+  double scale = 0.0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) scale = std::max(scale, std::fabs(A[i][j]));
+  if (scale == 0.0) return false;
+  for (int c = 0; c < 6; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 6; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    if (std::fabs(A[piv][c]) <= 1e-12 * scale) return false;
+    for (int j = 0; j < 6; ++j) std::swap(A[c][j], A[piv][j]);
+    for (int r = c + 1; r < 6; ++r) {
+      const double f = A[r][c] / A[c][c];
+      for (int j = 0; j < 6; ++j) A[r][j] -= f * A[c][j];
+    }
+  }
+  return true;
+}
+
+void check_opts(hh_ctx* ctx, const hh_opts& o) {
+  if (!(o.tol > 0.0) || !(o.tol < 1.0)) fail(ctx, HH_EINVAL, "tol must be in (0, 1)");
+  if (o.max_iter < 1) fail(ctx, HH_EINVAL, "max_iter must be >= 1");
+  if (o.scheme != 0 && o.scheme != 1) fail(ctx, HH_EINVAL, "scheme must be 0 (CG) or 1 (basic)");
+  if (o.precision != 0 && o.precision != 1) fail(ctx, HH_EINVAL, "precision must be 0 or 1");
+  if (o.nyquist != 0 && o.nyquist != 1) fail(ctx, HH_EINVAL, "nyquist must be 0 or 1");
+  if (o.stall_limit < 1) fail(ctx, HH_EINVAL, "stall_limit must be >= 1");
+  if (o.chunk < 1) fail(ctx, HH_EINVAL, "chunk must be >= 1");
+}
+
+void check_shape(hh_ctx* ctx, int nx, int ny, int nz, int precision) {
+  if (nx < 1 || ny < 1 || nz < 1) fail(ctx, HH_EINVAL, "image dimensions must be positive");
+  for (int n : {nx, ny, nz})
+    if (!size_ops(n, precision))
+      fail(ctx, HH_EUNSUPPORTED, "axis length " + std::to_string(n) + " has no compiled FFT passes at this precision");
+}
+
+void check_phases(hh_ctx* ctx, const hh_phase* ph, int nphase) {
+  if (!ph || nphase < 1 || nphase > kMaxPhase)
+    fail(ctx, HH_EINVAL, "need 1.." + std::to_string(kMaxPhase) + " phases");
+  for (int i = 0; i < nphase; ++i)
+    if (!(ph[i].K > 0.0) || !(ph[i].G > 0.0) || !std::isfinite(ph[i].K) || !std::isfinite(ph[i].G))
+      fail(ctx, HH_EINVAL, "phase moduli must be positive and finite");
+}
+
+void check_region(hh_ctx* ctx, const int* r, int nx, int ny, int nz) {
+  if (!(0 <= r[0] && r[0] < r[3] && r[3] <= nx && 0 <= r[1] && r[1] < r[4] && r[4] <= ny && 0 <= r[2] &&
+        r[2] < r[5] && r[5] <= nz))
+    fail(ctx, HH_EINVAL, "region must satisfy 0 <= lo < hi <= size on every axis");
+}
+
+// Solves all items (same shape) for six loads; results per item.
+GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsigned char* labels,
+                        const void* cfield, bool aniso, const hh_opts& o, const double loads[6][6],
+                        Profile& prof, void* cfield_out) {
+  const int nx = items[0].nx, ny = items[0].ny, nz = items[0].nz;
+  const int P = o.precision;
+  SizeOpsFn ox = size_ops(nx, P), oy = size_ops(ny, P), oz = size_ops(nz, P);
+  if (!ox || !oy || !oz) fail(ctx, HH_EUNSUPPORTED, "unsupported axis length");
+  int Mz = 0, Rx = 0;
+  oz(kOpInfoZ, 0, nullptr, nullptr, &Mz);
+  ox(kOpInfoX, 0, nullptr, nullptr, &Rx);
+  const int hx = nx / 2 + 1;
+  const long long nfreq = (long long)hx * ny * nz;
+  const size_t cb = P == 0 ? 8 : 16;
+  const size_t per_sys = size_t(nfreq) * 12 * cb;  // tmp (6) + ar (3) + ap (3)
+  const int nwg_z = ny * ((hx + Mz - 1) / Mz);
+  const int nwg_x = (ny * nz + Rx - 1) / Rx;
+
+  size_t freeb = 0, totalb = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &totalb));
+  const size_t budget = std::min<size_t>(size_t(24) << 30, freeb / 2);
+  int wave = int(std::max<size_t>(1, budget / (6 * per_sys)));
+  wave = std::min<int>(wave, int(items.size()));
+  wave = std::min(wave, 65535 / 6);
+
+  GroupResult res;
+  const int nitems = int(items.size());
+  res.C72.assign(size_t(nitems) * 72, 0.0);
+  res.status.assign(nitems, HH_OK);
+  res.iters.assign(size_t(nitems) * 6, 0);
+  res.rel.assign(size_t(nitems) * 6, 0.0);
+
+  // reference medium of the basic scheme
+  double ref_lam = o.ref_lambda, ref_mu = o.ref_mu;
+  if (o.scheme == 1 && (ref_lam <= 0.0 || ref_mu <= 0.0)) {
+    if (aniso) fail(ctx, HH_EINVAL, "the basic scheme on anisotropic voxels needs ref_lambda and ref_mu");
+    double lmin = 1e300, lmax = -1e300, mmin = 1e300, mmax = -1e300;
+    for (const Item& it : items)
+      for (const hh_phase& p : it.phases) {
+        const double l = p.K - 2.0 * p.G / 3.0;
+        lmin = std::min(lmin, l);
+        lmax = std::max(lmax, l);
+        mmin = std::min(mmin, p.G);
+        mmax = std::max(mmax, p.G);
+      }
+    ref_lam = 0.5 * (lmin + lmax);
+    ref_mu = 0.5 * (mmin + mmax);
+    if (ref_lam + 2.0 * ref_mu / 3.0 <= 0.0) ref_lam = 0.0;
+  }
+
+  for (int w0 = 0; w0 < nitems; w0 += wave) {
+    const int nw = std::min(wave, nitems - w0);
+    const int nsys = nw * 6;
+    std::vector<ItemDesc> idesc(nw);
+    std::vector<SysDesc> sdesc(nsys);
+    for (int i = 0; i < nw; ++i) {
+      const Item& it = items[w0 + i];
+      ItemDesc& d = idesc[i];
+      std::memset(&d, 0, sizeof(d));
+      d.lab_off = it.lab_off;
+      d.cf_off = it.cf_off;
+      for (int k = 0; k < 6; ++k) d.region[k] = it.region[k];
+      d.nphase = int(it.phases.size());
+      const double vol = double(it.region[3] - it.region[0]) * (it.region[4] - it.region[1]) *
+                         (it.region[5] - it.region[2]);
+      d.inv_region = 1.0 / vol;
+      for (int k = 0; k < d.nphase; ++k) {
+        d.lam[k] = it.phases[k].K - 2.0 * it.phases[k].G / 3.0;
+        d.mu[k] = it.phases[k].G;
+      }
+      for (int a = 0; a < 6; ++a) sdesc[i * 6 + a] = SysDesc{i, a};
+    }
+    auto* d_items = static_cast<ItemDesc*>(ws(ctx, "items", sizeof(ItemDesc) * nw));
+    auto* d_sys = static_cast<SysDesc*>(ws(ctx, "sys", sizeof(SysDesc) * nsys));
+    auto* d_state = static_cast<SysState*>(ws(ctx, "state", sizeof(SysState) * nsys));
+    auto* d_px = static_cast<double*>(ws(ctx, "part_x", sizeof(double) * kPartX * size_t(nwg_x) * nsys));
+    auto* d_pz = static_cast<double*>(ws(ctx, "part_z", sizeof(double) * size_t(nwg_z) * nsys));
+    void* d_tmp = ws(ctx, "tmp", size_t(nfreq) * 6 * cb * nsys);
+    void* d_ar = ws(ctx, "ar", size_t(nfreq) * 3 * cb * nsys);
+    void* d_ap = ws(ctx, "ap", size_t(nfreq) * 3 * cb * nsys);
+    auto* d_out = static_cast<double*>(ws(ctx, "cout", sizeof(double) * 72 * nw));
+    auto* d_ist = static_cast<int*>(ws(ctx, "istatus", sizeof(int) * nw));
+    auto* d_cnt = static_cast<int*>(ws(ctx, "count", sizeof(int)));
+    HIPCHK(hipMemcpyAsync(d_items, idesc.data(), sizeof(ItemDesc) * nw, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_sys, sdesc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemsetAsync(d_state, 0, sizeof(SysState) * nsys, ctx->stream));
+    HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nfreq) * 3 * cb * nsys, ctx->stream));
+    if (o.scheme == 1) HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nfreq) * 3 * cb * nsys, ctx->stream));
+
+    GroupArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.hx = hx;
+    g.nsys = nsys;
+    g.nyq_zero = o.nyquist;
+    g.max_iter = o.max_iter;
+    g.scheme = o.scheme;
+    g.aniso = aniso ? 1 : 0;
+    g.stall_limit = o.stall_limit;
+    g.tol2 = o.tol * o.tol;
+    const double u = P == 0 ? 5.96e-8 : 1.11e-16;
+    g.zero_rhs2 = (64.0 * u) * (64.0 * u);
+    g.ref_lam = o.scheme == 1 ? ref_lam : 0.0;
+    g.ref_mu = o.scheme == 1 ? ref_mu : 0.5;
+    for (int a = 0; a < 6; ++a)
+      for (int c = 0; c < 6; ++c) g.loads[a][c] = loads[a][c];
+    g.sys = d_sys;
+    g.items = d_items;
+    g.labels = labels;
+    g.cfield = cfield;
+    g.tmp = d_tmp;
+    g.ar = d_ar;
+    g.ap = d_ap;
+    g.tmp_stride = nfreq * 6;
+    g.a_stride = nfreq * 3;
+    g.state = d_state;
+    g.part_x = d_px;
+    g.part_z = d_pz;
+    g.nwg_x = nwg_x;
+    g.nwg_z = nwg_z;
+
+    const hipStream_t st = ctx->stream;
+    // right-hand side b = -G * (C : E)
+    prof.run(HH_K_SETUP, [&] { ox(kOpX, kXRhs, &g, st, nullptr); });
+    prof.run(HH_K_FIN, [&] { launch_fin_x(kXRhs, g, st); });
+    if (o.scheme == 0) {
+      prof.run(HH_K_SETUP, [&] { oy(kOpY, -1, &g, st, nullptr); });
+      prof.run(HH_K_SETUP, [&] { oz(kOpZ, kZFwdRhs, &g, st, nullptr); });
+      prof.run(HH_K_FIN, [&] { launch_fin_z(kZFwdRhs, g, st); });
+    }
+    const bool cg = o.scheme == 0;
+    int launched = 0;
+    const int limit = o.max_iter + 1;
+    while (launched < limit) {
+      const int chunk = std::min(o.chunk, limit - launched);
+      for (int k = 0; k < chunk; ++k) {
+        prof.run(HH_K_ZINV, [&] { oz(kOpZ, cg ? kZInvCg : kZInvFp, &g, st, nullptr); });
+        prof.run(HH_K_YINV, [&] { oy(kOpY, +1, &g, st, nullptr); });
+        prof.run(HH_K_X, [&] { ox(kOpX, cg ? kXCg : kXFp, &g, st, nullptr); });
+        prof.run(HH_K_FIN, [&] { launch_fin_x(cg ? kXCg : kXFp, g, st); });
+        prof.run(HH_K_YFWD, [&] { oy(kOpY, -1, &g, st, nullptr); });
+        prof.run(HH_K_ZFWD, [&] { oz(kOpZ, cg ? kZFwdCg : kZFwdFp, &g, st, nullptr); });
+        prof.run(HH_K_FIN, [&] { launch_fin_z(cg ? kZFwdCg : kZFwdFp, g, st); });
+      }
+      launched += chunk;
+      HIPCHK(hipGetLastError());
+      launch_count_running(d_state, nsys, d_cnt, st);
+      int running = 0;
+      HIPCHK(hipMemcpyAsync(&running, d_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      prof.flush();
+      if (running == 0) break;
+    }
+    void* cf_out = nullptr;
+    if (cfield_out) cf_out = static_cast<char*>(cfield_out) + size_t(w0) * 21 * (P == 0 ? 4 : 8);
+    prof.run(HH_K_OTHER, [&] { launch_stiffness(P, d_state, nw, d_out, cf_out, d_ist, st); });
+    HIPCHK(hipGetLastError());
+    std::vector<SysState> hst(nsys);
+    std::vector<int> ist(nw);
+    HIPCHK(hipMemcpyAsync(res.C72.data() + size_t(w0) * 72, d_out, sizeof(double) * 72 * nw, hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(hipMemcpyAsync(hst.data(), d_state, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ist.data(), d_ist, sizeof(int) * nw, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    prof.flush();
+    const double vox = double(nx) * ny * nz;
+    for (int i = 0; i < nw; ++i) {
+      int code = status_code(ist[i]);
+      for (int a = 0; a < 6; ++a) {
+        const SysState& s = hst[i * 6 + a];
+        res.iters[size_t(w0 + i) * 6 + a] = s.iter;
+        res.rel[size_t(w0 + i) * 6 + a] = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
+        res.voxel_iters += vox * s.iter;
+        code = worse(code, status_code(s.status == kRunning ? kNoConv : s.status));
+      }
+      res.status[w0 + i] = code;
+    }
+  }
+  return res;
+}
+
+int finish(hh_ctx* ctx, int rc) { return rc; }
+
+template <class F>
+int guarded(hh_ctx* ctx, F&& f) {
+  if (!ctx) return HH_EINVAL;
+  ctx->err.clear();
+  try {
+    HIPCHK(hipSetDevice(ctx->device));
+    return f();
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return HH_EDEVICE;
+  } catch (...) {
+    ctx->err = "unknown error";
+    return HH_EDEVICE;
+  }
+}
+
+void begin_report(hh_ctx* ctx, hh_report* rep) {
+  if (rep) std::memset(rep, 0, sizeof(*rep));
+  HIPCHK(hipEventRecord(ctx->t0, ctx->stream));
+}
+
+void end_report(hh_ctx* ctx, hh_report* rep) {
+  HIPCHK(hipEventRecord(ctx->t1, ctx->stream));
+  HIPCHK(hipEventSynchronize(ctx->t1));
+  if (rep) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
+    rep->seconds = ms * 1e-3;
+  }
+}
+
+void fill_item_report(hh_report* rep, const GroupResult& r, int item) {
+  if (!rep) return;
+  for (int a = 0; a < 6; ++a) {
+    rep->iters[a] = r.iters[size_t(item) * 6 + a];
+    rep->rel_resid[a] = r.rel[size_t(item) * 6 + a];
+  }
+  const double* C = r.C72.data() + size_t(item) * 72;
+  double mx = 0.0, md = 0.0;
+  for (int i = 0; i < 36; ++i) mx = std::max(mx, std::fabs(C[i]));
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) md = std::max(md, std::fabs(C[i * 6 + j] - C[j * 6 + i]));
+  rep->asym = mx > 0.0 ? md / mx : 0.0;
+}
+
+// Labels to the device (copy when on host) and check them against nphase.
+const unsigned char* device_labels(hh_ctx* ctx, const uint8_t* labels, long long bytes, bool on_device,
+                                   const std::vector<long long>& off, const std::vector<long long>& cnt,
+                                   const std::vector<int>& nphase, const char* bufname) {
+  const unsigned char* d = nullptr;
+  const int n = int(off.size());
+  if (!on_device) {
+    for (int i = 0; i < n; ++i) {
+      const uint8_t* p = labels + off[i];
+      uint8_t m = 0;
+      for (long long k = 0; k < cnt[i]; ++k) m = std::max(m, p[k]);
+      if (m >= nphase[i]) fail(ctx, HH_EINVAL, "label " + std::to_string(m) + " >= nphase in item " + std::to_string(i));
+    }
+    auto* buf = static_cast<unsigned char*>(ws(ctx, bufname, size_t(bytes)));
+    HIPCHK(hipMemcpyAsync(buf, labels, size_t(bytes), hipMemcpyHostToDevice, ctx->stream));
+    d = buf;
+  } else {
+    d = labels;
+    auto* d_off = static_cast<long long*>(ws(ctx, "lm_off", sizeof(long long) * n));
+    auto* d_cnt = static_cast<long long*>(ws(ctx, "lm_cnt", sizeof(long long) * n));
+    auto* d_max = static_cast<int*>(ws(ctx, "lm_max", sizeof(int) * n));
+    HIPCHK(hipMemcpyAsync(d_off, off.data(), sizeof(long long) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_cnt, cnt.data(), sizeof(long long) * n, hipMemcpyHostToDevice, ctx->stream));
+    launch_label_max(d, d_off, d_cnt, n, d_max, ctx->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<int> mx(n);
+    HIPCHK(hipMemcpyAsync(mx.data(), d_max, sizeof(int) * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < n; ++i)
+      if (mx[i] >= nphase[i])
+        fail(ctx, HH_EINVAL, "label " + std::to_string(mx[i]) + " >= nphase in item " + std::to_string(i));
+  }
+  return d;
+}
+
+void write_C(const GroupResult& r, int item, double* C_out, double* C_raw) {
+  const double* C = r.C72.data() + size_t(item) * 72;
+  if (C_out) std::memcpy(C_out, C + 36, sizeof(double) * 36);
+  if (C_raw) std::memcpy(C_raw, C, sizeof(double) * 36);
+}
+
+}  // namespace
+
+extern "C" {
+
+void hh_default_opts(hh_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-6;
+  o->max_iter = 1000;
+  o->scheme = 0;
+  o->precision = 0;
+  o->nyquist = 0;
+  o->profile = 0;
+  o->stall_limit = 100;
+  o->chunk = 8;
+  o->ref_lambda = 0.0;
+  o->ref_mu = 0.0;
+}
+
+int hh_create(hh_ctx** out, int device, void* hip_stream) {
+  if (!out) return HH_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HH_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HH_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HH_EDEVICE;
+  auto* ctx = new hh_ctx();
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess || hipEventCreate(&ctx->t0) != hipSuccess ||
+      hipEventCreate(&ctx->t1) != hipSuccess) {
+    delete ctx;
+    return HH_EDEVICE;
+  }
+  *out = ctx;
+  return HH_OK;
+}
+
+int hh_set_stream(hh_ctx* ctx, void* hip_stream) {
+  if (!ctx) return HH_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return HH_OK;
+}
+
+void hh_release_workspace(hh_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& b : ctx->bufs) (void)hipFree(b.second.first);
+  ctx->bufs.clear();
+}
+
+void hh_destroy(hh_ctx* ctx) {
+  if (!ctx) return;
+  hh_release_workspace(ctx);
+  for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+  if (ctx->t0) (void)hipEventDestroy(ctx->t0);
+  if (ctx->t1) (void)hipEventDestroy(ctx->t1);
+  delete ctx;
+}
+
+const char* hh_last_error(const hh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+long long hh_workspace_bytes(const hh_ctx* ctx) {
+  if (!ctx) return 0;
+  long long s = 0;
+  for (auto& b : ctx->bufs) s += (long long)b.second.second;
+  return s;
+}
+
+int hh_size_supported(int n, int precision) {
+  if (precision != 0 && precision != 1) return 0;
+  return size_ops(n, precision) ? 1 : 0;
+}
+
+int hh_homogenize(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, int labels_on_device,
+                  const hh_phase* phases, int nphase, const double* loads, const int* region, const hh_opts* opts,
+                  double C_out[36], double C_raw[36], hh_report* report) {
+  return guarded(ctx, [&]() -> int {
+    hh_opts o;
+    hh_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(ctx, o);
+    if (!labels || !C_out) fail(ctx, HH_EINVAL, "labels and C_out are required");
+    check_shape(ctx, nx, ny, nz, o.precision);
+    check_phases(ctx, phases, nphase);
+    Item it;
+    it.nx = nx;
+    it.ny = ny;
+    it.nz = nz;
+    it.lab_off = 0;
+    it.cf_off = -1;
+    const int whole[6] = {0, 0, 0, nx, ny, nz};
+    const int* r = region ? region : whole;
+    check_region(ctx, r, nx, ny, nz);
+    std::memcpy(it.region, r, sizeof(it.region));
+    it.phases.assign(phases, phases + nphase);
+    double L[6][6];
+    if (loads) {
+      loads_from_voigt(loads, L);
+      if (!loads_independent(L)) fail(ctx, HH_EINVAL, "the six loads are not independent");
+    } else {
+      unit_loads(L);
+    }
+    const long long nvox = (long long)nx * ny * nz;
+    begin_report(ctx, report);
+    const unsigned char* d_lab =
+        device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "labels");
+    Profile prof{ctx, o.profile != 0, {}, 0, report};
+    GroupResult res = solve_group(ctx, {it}, d_lab, nullptr, false, o, L, prof, nullptr);
+    end_report(ctx, report);
+    write_C(res, 0, C_out, C_raw);
+    if (report) {
+      fill_item_report(report, res, 0);
+      report->voxel_iters = res.voxel_iters;
+      report->items = 1;
+      report->status = res.status[0];
+    }
+    if (res.status[0] != HH_OK) ctx->err = "solve did not converge cleanly (see report.status)";
+    return res.status[0];
+  });
+}
+
+int hh_homogenize_aniso(hh_ctx* ctx, const double* C21, int nx, int ny, int nz, int c21_on_device,
+                        const hh_opts* opts, double C_out[36], double C_raw[36], hh_report* report) {
+  return guarded(ctx, [&]() -> int {
+    hh_opts o;
+    hh_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(ctx, o);
+    if (!C21 || !C_out) fail(ctx, HH_EINVAL, "C21 and C_out are required");
+    check_shape(ctx, nx, ny, nz, o.precision);
+    const long long nvox = (long long)nx * ny * nz;
+    const long long nval = nvox * 21;
+    if (!c21_on_device) {
+      for (long long i = 0; i < nval; ++i)
+        if (!std::isfinite(C21[i])) fail(ctx, HH_EINVAL, "non-finite stiffness component");
+    }
+    begin_report(ctx, report);
+    const double* src = C21;
+    if (!c21_on_device) {
+      auto* d = static_cast<double*>(ws(ctx, "c21_in", sizeof(double) * nval));
+      HIPCHK(hipMemcpyAsync(d, C21, sizeof(double) * nval, hipMemcpyHostToDevice, ctx->stream));
+      src = d;
+    }
+    void* cf = ws(ctx, "cfield", size_t(nval) * (o.precision == 0 ? 4 : 8));
+    launch_convert_field(o.precision, src, cf, nval, ctx->stream);
+    HIPCHK(hipGetLastError());
+    Item it;
+    it.nx = nx;
+    it.ny = ny;
+    it.nz = nz;
+    it.lab_off = 0;
+    it.cf_off = 0;
+    const int whole[6] = {0, 0, 0, nx, ny, nz};
+    std::memcpy(it.region, whole, sizeof(it.region));
+    it.phases.assign(1, hh_phase{1.0, 1.0});
+    double L[6][6];
+    unit_loads(L);
+    Profile prof{ctx, o.profile != 0, {}, 0, report};
+    GroupResult res = solve_group(ctx, {it}, nullptr, cf, true, o, L, prof, nullptr);
+    end_report(ctx, report);
+    write_C(res, 0, C_out, C_raw);
+    if (report) {
+      fill_item_report(report, res, 0);
+      report->voxel_iters = res.voxel_iters;
+      report->items = 1;
+      report->status = res.status[0];
+    }
+    return res.status[0];
+  });
+}
+
+int hh_homogenize_batch(hh_ctx* ctx, int nitems, const int* dims, const uint8_t* labels, long long labels_bytes,
+                        int labels_on_device, const long long* label_off, const hh_phase* phases,
+                        const int* phase_off, const int* nphase, const int* regions, const hh_opts* opts,
+                        double* C_out, double* C_raw, int* item_status, int* item_iters, hh_report* report) {
+  return guarded(ctx, [&]() -> int {
+    hh_opts o;
+    hh_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(ctx, o);
+    if (nitems < 1 || !dims || !labels || !label_off || !phases || !phase_off || !nphase || !C_out)
+      fail(ctx, HH_EINVAL, "missing batch arguments");
+    std::vector<Item> items(nitems);
+    std::vector<long long> off(nitems), cnt(nitems);
+    std::vector<int> nph(nitems);
+    for (int i = 0; i < nitems; ++i) {
+      Item& it = items[i];
+      it.nx = dims[3 * i];
+      it.ny = dims[3 * i + 1];
+      it.nz = dims[3 * i + 2];
+      check_shape(ctx, it.nx, it.ny, it.nz, o.precision);
+      check_phases(ctx, phases + phase_off[i], nphase[i]);
+      it.phases.assign(phases + phase_off[i], phases + phase_off[i] + nphase[i]);
+      it.lab_off = label_off[i];
+      it.cf_off = -1;
+      const long long nv = (long long)it.nx * it.ny * it.nz;
+      if (it.lab_off < 0 || it.lab_off + nv > labels_bytes) fail(ctx, HH_EINVAL, "item labels outside the pack");
+      off[i] = it.lab_off;
+      cnt[i] = nv;
+      nph[i] = nphase[i];
+      const int whole[6] = {0, 0, 0, it.nx, it.ny, it.nz};
+      const int* r = regions ? regions + 6 * i : whole;
+      check_region(ctx, r, it.nx, it.ny, it.nz);
+      std::memcpy(it.region, r, sizeof(it.region));
+    }
+    double L[6][6];
+    unit_loads(L);
+    begin_report(ctx, report);
+    const unsigned char* d_lab =
+        device_labels(ctx, labels, labels_bytes, labels_on_device != 0, off, cnt, nph, "labels");
+    // group by shape
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    for (int i = 0; i < nitems; ++i) groups[{items[i].nx, items[i].ny, items[i].nz}].push_back(i);
+    Profile prof{ctx, o.profile != 0, {}, 0, report};
+    int rc = HH_OK;
+    double vi = 0.0;
+    bool first = true;
+    for (auto& kv : groups) {
+      std::vector<Item> gi;
+      for (int i : kv.second) gi.push_back(items[i]);
+      GroupResult res = solve_group(ctx, gi, d_lab, nullptr, false, o, L, prof, nullptr);
+      vi += res.voxel_iters;
+      for (size_t k = 0; k < kv.second.size(); ++k) {
+        const int i = kv.second[k];
+        write_C(res, int(k), C_out + size_t(i) * 36, C_raw ? C_raw + size_t(i) * 36 : nullptr);
+        if (item_status) item_status[i] = res.status[k];
+        if (item_iters)
+          for (int a = 0; a < 6; ++a) item_iters[size_t(i) * 6 + a] = res.iters[k * 6 + a];
+        rc = worse(rc, res.status[k]);
+        if (report && i == 0) fill_item_report(report, res, int(k));
+      }
+      first = false;
+    }
+    (void)first;
+    end_report(ctx, report);
+    if (report) {
+      report->voxel_iters = vi;
+      report->items = nitems;
+      report->status = rc;
+    }
+    return rc;
+  });
+}
+
+int hh_hierarchical(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, int labels_on_device,
+                    const hh_phase* phases, int nphase, int n_sub, int pad, int use_surrogate, const hh_opts* opts,
+                    double C_out[36], double* C_sub, hh_report* report) {
+  return guarded(ctx, [&]() -> int {
+    hh_opts o;
+    hh_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(ctx, o);
+    if (use_surrogate != 0) fail(ctx, HH_EINVAL, "use_surrogate must be 0");
+    if (!labels || !C_out) fail(ctx, HH_EINVAL, "labels and C_out are required");
+    if (nx < 1 || ny < 1 || nz < 1 || n_sub < 1) fail(ctx, HH_EINVAL, "sizes must be positive");
+    if (nx % n_sub || ny % n_sub || nz % n_sub) fail(ctx, HH_EINVAL, "the subimage size must divide the image size");
+    if (pad < 0 || 2 * pad >= std::min(nx, std::min(ny, nz)))
+      fail(ctx, HH_EINVAL, "padding must satisfy 0 <= 2 pad < image size");
+    const int b = n_sub + 2 * pad;
+    const int mx = nx / n_sub, my = ny / n_sub, mz = nz / n_sub;
+    check_shape(ctx, b, b, b, o.precision);
+    check_shape(ctx, mx, my, mz, o.precision);
+    check_phases(ctx, phases, nphase);
+    const long long nvox = (long long)nx * ny * nz;
+    const int nitems = mx * my * mz;
+    begin_report(ctx, report);
+    const unsigned char* d_img =
+        device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "image");
+    const long long box = (long long)b * b * b;
+    auto* d_pack = static_cast<unsigned char*>(ws(ctx, "pack", size_t(box * nitems)));
+    Profile prof{ctx, o.profile != 0, {}, 0, report};
+    prof.run(HH_K_SETUP, [&] { launch_gather_pad(d_img, nx, ny, nz, n_sub, pad, d_pack, ctx->stream); });
+    HIPCHK(hipGetLastError());
+    std::vector<Item> items(nitems);
+    for (int i = 0; i < nitems; ++i) {
+      Item& it = items[i];
+      it.nx = it.ny = it.nz = b;
+      it.lab_off = box * i;
+      it.cf_off = -1;
+      const int r[6] = {pad, pad, pad, pad + n_sub, pad + n_sub, pad + n_sub};
+      std::memcpy(it.region, r, sizeof(r));
+      it.phases.assign(phases, phases + nphase);
+    }
+    double L[6][6];
+    unit_loads(L);
+    void* cf = ws(ctx, "cfield", size_t(nitems) * 21 * (o.precision == 0 ? 4 : 8));
+    GroupResult r1 = solve_group(ctx, items, d_pack, nullptr, false, o, L, prof, cf);
+    int rc = HH_OK;
+    for (int i = 0; i < nitems; ++i) rc = worse(rc, r1.status[i]);
+    if (C_sub) {
+      for (int i = 0; i < nitems; ++i) {
+        const double* S = r1.C72.data() + size_t(i) * 72 + 36;
+        int k = 0;
+        for (int p = 0; p < 6; ++p)
+          for (int q = p; q < 6; ++q) C_sub[size_t(i) * 21 + k++] = S[p * 6 + q];
+      }
+    }
+    Item l2;
+    l2.nx = mx;
+    l2.ny = my;
+    l2.nz = mz;
+    l2.lab_off = 0;
+    l2.cf_off = 0;
+    const int whole[6] = {0, 0, 0, mx, my, mz};
+    std::memcpy(l2.region, whole, sizeof(l2.region));
+    l2.phases.assign(1, hh_phase{1.0, 1.0});
+    GroupResult r2 = solve_group(ctx, {l2}, nullptr, cf, true, o, L, prof, nullptr);
+    end_report(ctx, report);
+    write_C(r2, 0, C_out, nullptr);
+    rc = worse(rc, r2.status[0]);
+    if (report) {
+      fill_item_report(report, r2, 0);
+      report->voxel_iters = r1.voxel_iters + r2.voxel_iters;
+      report->items = nitems;
+      report->status = rc;
+    }
+    return rc;
+  });
+}
+
+int hh_richardson(const int* n, const double* C, int m, double C_inf[36], double slope[36]) {
+  if (!n || !C || !C_inf || m < 2) return HH_EINVAL;
+  // least squares of v = a + b / n over the m sizes, per entry
+  double s1 = 0, sx = 0, sxx = 0;
+  for (int i = 0; i < m; ++i) {
+    if (n[i] <= 0) return HH_EINVAL;
+    const double x = 1.0 / n[i];
+    s1 += 1;
+    sx += x;
+    sxx += x * x;
+  }
+  const double det = s1 * sxx - sx * sx;
+  if (!(std::fabs(det) > 1e-300 * std::max(1.0, sxx))) return HH_EINVAL;
+  for (int k = 0; k < 36; ++k) {
+    double sy = 0, sxy = 0;
+    for (int i = 0; i < m; ++i) {
+      const double x = 1.0 / n[i], y = C[size_t(i) * 36 + k];
+      sy += y;
+      sxy += x * y;
+    }
+    const double a = (sxx * sy - sx * sxy) / det;
+    const double b = (s1 * sxy - sx * sy) / det;
+    C_inf[k] = a;
+    if (slope) slope[k] = b;
+  }
+  return HH_OK;
+}
+
+int hh_moduli(const double C[36], double* K, double* G) {
+  if (!C || !K || !G) return HH_EINVAL;
+  const double d = C[0] + C[7] + C[14];
+  const double o = C[1] + C[2] + C[8];
+  const double s = C[21] + C[28] + C[35];
+  *K = (d + 2.0 * o) / 9.0;
+  *G = (d - o + 3.0 * s) / 15.0;
+  return HH_OK;
+}
+
+}  // extern "C"

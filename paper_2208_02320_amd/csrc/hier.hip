@@ -1,0 +1,100 @@
+// Hierarchical-scheme data movement and small utility kernels.
+//
+// Partition + padding (paper, Sec. 3 and Sec. 4 / Fig. 4): every n^3 block
+// of the image is copied with p voxels of surrounding material on each side
+// into a contiguous pack of (n + 2p)^3 boxes; indices wrap periodically at
+// the image edge.
+#include <hip/hip_runtime.h>
+
+#include "hh_internal.hpp"
+#include "kernels.hpp"
+
+namespace hh {
+
+__global__ void k_gather_pad(const unsigned char* __restrict__ img, int nx, int ny, int nz, int n, int p,
+                             int mx, int my, long long nitems, unsigned char* __restrict__ out) {
+  const int b = n + 2 * p;
+  const long long box = (long long)b * b * b;
+  const long long total = nitems * box;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long item = i / box;
+    const long long r = i - item * box;
+    const int zz = int(r / ((long long)b * b));
+    const int yy = int((r / b) % b);
+    const int xx = int(r % b);
+    const int bx = int(item % mx), by = int((item / mx) % my), bz = int(item / ((long long)mx * my));
+    int z = bz * n - p + zz, y = by * n - p + yy, x = bx * n - p + xx;
+    z = ((z % nz) + nz) % nz;
+    y = ((y % ny) + ny) % ny;
+    x = ((x % nx) + nx) % nx;
+    out[i] = img[((long long)z * ny + y) * nx + x];
+  }
+}
+
+// Largest label of each item (one block per item).
+__global__ void k_label_max(const unsigned char* __restrict__ labels, const long long* __restrict__ off,
+                            const long long* __restrict__ count, int* __restrict__ out) {
+  __shared__ int smax[256];
+  const int item = blockIdx.x;
+  const unsigned char* p = labels + off[item];
+  const long long n = count[item];
+  int m = 0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = max(m, int(p[i]));
+  smax[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[item] = smax[0];
+}
+
+// Number of systems still iterating.
+__global__ void k_count_running(const SysState* __restrict__ st, int n, int* __restrict__ count) {
+  __shared__ int sc[256];
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c += (st[i].status == kRunning) ? 1 : 0;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sc[threadIdx.x] += sc[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = sc[0];
+}
+
+template <class T>
+__global__ void k_convert_field(const double* __restrict__ src, T* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = T(src[i]);
+}
+
+void launch_gather_pad(const unsigned char* img, int nx, int ny, int nz, int n, int p, unsigned char* out,
+                       hipStream_t st) {
+  const int mx = nx / n, my = ny / n, mz = nz / n;
+  const long long nitems = (long long)mx * my * mz;
+  const long long total = nitems * (long long)(n + 2 * p) * (n + 2 * p) * (n + 2 * p);
+  const long long blocks = (total + 255) / 256;
+  k_gather_pad<<<int(blocks < 65536 ? blocks : 65536), 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, nitems,
+                                                                      out);
+}
+
+void launch_label_max(const unsigned char* labels, const long long* off, const long long* count, int nitems,
+                      int* out, hipStream_t st) {
+  k_label_max<<<nitems, 256, 0, st>>>(labels, off, count, out);
+}
+
+void launch_count_running(const SysState* st, int n, int* count, hipStream_t s) {
+  k_count_running<<<1, 256, 0, s>>>(st, n, count);
+}
+
+void launch_convert_field(int precision, const double* src, void* dst, long long n, hipStream_t st) {
+  const long long blocks = (n + 255) / 256;
+  const int nb = int(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096);
+  if (precision == 0) k_convert_field<float><<<nb, 256, 0, st>>>(src, reinterpret_cast<float*>(dst), n);
+  else k_convert_field<double><<<nb, 256, 0, st>>>(src, reinterpret_cast<double*>(dst), n);
+}
+
+}  // namespace hh

@@ -1,0 +1,39 @@
+// Launch interface between the host orchestration and the pass kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hh_internal.hpp"
+
+namespace hh {
+
+enum : int { kZInvCg = 0, kZFwdCg = 1, kZFwdRhs = 2, kZInvFp = 3, kZFwdFp = 4 };
+enum : int { kXCg = 0, kXRhs = 1, kXFp = 2 };
+enum : int { kOpZ = 0, kOpY = 1, kOpX = 2, kOpInfoZ = 3, kOpInfoX = 4 };
+
+using SizeOpsFn = void (*)(int what, int mode, const GroupArgs* g, hipStream_t st, int* info);
+
+SizeOpsFn size_ops(int n, int precision);
+// per-file size tables (sizes_f32_*.hip, sizes_f64_*.hip)
+SizeOpsFn size_ops_f32_0(int n);
+SizeOpsFn size_ops_f32_1(int n);
+SizeOpsFn size_ops_f32_2(int n);
+SizeOpsFn size_ops_f32_3(int n);
+SizeOpsFn size_ops_f32_4(int n);
+SizeOpsFn size_ops_f32_5(int n);
+SizeOpsFn size_ops_f64_0(int n);
+SizeOpsFn size_ops_f64_1(int n);
+SizeOpsFn size_ops_f64_2(int n);
+void launch_fin_x(int mode, const GroupArgs& g, hipStream_t st);
+void launch_fin_z(int mode, const GroupArgs& g, hipStream_t st);
+void launch_stiffness(int precision, const SysState* state, int nitems, double* out, void* cfield_out,
+                      int* status_out, hipStream_t st);
+
+void launch_gather_pad(const unsigned char* img, int nx, int ny, int nz, int n, int p, unsigned char* out,
+                       hipStream_t st);
+void launch_label_max(const unsigned char* labels, const long long* off, const long long* count, int nitems,
+                      int* out, hipStream_t st);
+void launch_count_running(const SysState* st, int n, int* count, hipStream_t s);
+void launch_convert_field(int precision, const double* src, void* dst, long long n, hipStream_t st);
+
+}  // namespace hh

@@ -1,0 +1,13 @@
+// Instantiation of the pass kernels for one set of axis lengths (F64).
+#include "solver_kernels.hpp"
+
+namespace hh {
+
+SizeOpsFn size_ops_f64_2(int n) {
+  switch (n) {
+    HH_CASE_D(64) HH_CASE_D(80) HH_CASE_D(96) HH_CASE_D(128)
+  }
+  return nullptr;
+}
+
+}  // namespace hh

@@ -1,0 +1,508 @@
+// Pass kernels of the periodic Fourier-Galerkin elasticity solve on gfx950.
+//
+// The discrete problem (paper, Appendix A): find the compatible zero-mean
+// strain eps* with  G * (C : eps*) = - G * (C : E),  G the projection onto
+// compatible fields, solved by conjugate gradients; then average stress and
+// strain over Omega_R (Sec. 4).
+//
+// Data layout (per system = one image and one load case):
+//   tmp : 6 strain/stress components of the half spectrum, complex,
+//         [z][y][kx][c] with kx in [0, nx/2] and c = 11 22 33 23 13 12
+//   ar, ap : residual and search direction, kept in frequency space in their
+//         3-vector form: a compatible symmetric field is n (x) a + a (x) n at
+//         each frequency (n the unit wave vector), so 3 complex values per
+//         frequency describe it exactly and keep it compatible by construction.
+//
+// One CG iteration is five passes over the spectrum, each a kernel:
+//   zinv : p = r + beta p (3-vector), expand to 6 components, inverse z-FFT
+//   yinv : inverse y-FFT
+//   x    : inverse x-FFT (two real lines per complex line), sigma = C : p,
+//          (p, sigma) and region sums in FP64, forward x-FFT
+//   yfwd : forward y-FFT
+//   zfwd : forward z-FFT, projection to 3-vector form q, r -= alpha q, (r, r)
+// with small FP64 finalize kernels for alpha and beta in between.
+//
+// Numerics: fields and FFTs in T (float or double); every reduction, the CG
+// scalars and the averages in double.  (p, A p) equals (p, C:p) because p is
+// compatible, so it is formed in real space where C:p is at hand.  x is never
+// stored: the averages of eps and sigma are linear in it and are accumulated
+// as sum_k alpha_k <p_k>_R and sum_k alpha_k <C:p_k>_R.
+#pragma once
+
+#include "fft.hpp"
+#include "hh_internal.hpp"
+#include "kernels.hpp"
+
+namespace hh {
+
+inline constexpr int kLdsTile = 48 * 1024;
+
+constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+constexpr int round64(int v) { return (v + 63) / 64 * 64; }
+constexpr int maxi(int a, int b) { return a > b ? a : b; }
+
+template <int N, class T>
+struct AxisCfg {
+  static constexpr int N1 = split_n1(N), N2 = N / N1;
+  static constexpr int CB = int(sizeof(cx<T>));
+  static constexpr int M = clampi(kLdsTile / (N * 6 * CB), 1, 16);
+  static constexpr int L = 6 * M;
+  static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);
+  static constexpr int LDS = (N * L + N) * CB;
+};
+
+template <int N, class T>
+struct XCfg {
+  static constexpr int N1 = split_n1(N), N2 = N / N1;
+  static constexpr int CB = int(sizeof(cx<T>));
+  static constexpr int R = clampi(kLdsTile / (N * 3 * CB), 1, 32);
+  static constexpr int L = 3 * R;
+  static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);
+  static constexpr int LDS = (N * L + N) * CB;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Wave number component of FFT index i on an n-point axis (unit voxel);
+// the Nyquist component is zero.  Sets nyq when i is the Nyquist index.
+__device__ __forceinline__ double kcomp(int i, int n, bool& nyq) {
+  nyq = (2 * i == n);
+  const int m = (2 * i <= n) ? i : i - n;
+  return nyq ? 0.0 : double(m) / double(n);
+}
+
+// Unit wave vector of frequency (kx, ky, kz); false where the operator is zero.
+template <class T>
+__device__ __forceinline__ bool unit_k(const GroupArgs& g, int kx, int ky, int kz, T n[3]) {
+  bool qx, qy, qz;
+  const double a = kcomp(kx, g.nx, qx), b = kcomp(ky, g.ny, qy), c = kcomp(kz, g.nz, qz);
+  const double k2 = a * a + b * b + c * c;
+  if (k2 == 0.0 || (g.nyq_zero && (qx || qy || qz))) {
+    n[0] = n[1] = n[2] = T(0);
+    return false;
+  }
+  const double inv = 1.0 / sqrt(k2);
+  n[0] = T(a * inv);
+  n[1] = T(b * inv);
+  n[2] = T(c * inv);
+  return true;
+}
+
+// Symmetric field n (x) a + a (x) n in components 11 22 33 23 13 12.
+template <class T>
+__device__ __forceinline__ void expand_sym(const T n[3], const cx<T> a[3], cx<T> e[6]) {
+  e[0] = T(2) * n[0] * a[0];
+  e[1] = T(2) * n[1] * a[1];
+  e[2] = T(2) * n[2] * a[2];
+  e[3] = n[1] * a[2] + n[2] * a[1];
+  e[4] = n[0] * a[2] + n[2] * a[0];
+  e[5] = n[0] * a[1] + n[1] * a[0];
+}
+
+// t = S n for the symmetric S given by its 6 components; returns n.S.n.
+template <class T>
+__device__ __forceinline__ cx<T> sym_dot_n(const cx<T> s[6], const T n[3], cx<T> t[3]) {
+  t[0] = n[0] * s[0] + n[1] * s[5] + n[2] * s[4];
+  t[1] = n[0] * s[5] + n[1] * s[1] + n[2] * s[3];
+  t[2] = n[0] * s[4] + n[1] * s[3] + n[2] * s[2];
+  return n[0] * t[0] + n[1] * t[1] + n[2] * t[2];
+}
+
+// ||n (x) a + a (x) n||_F^2 = 2 |a|^2 + 2 |n.a|^2
+template <class T>
+__device__ __forceinline__ double sym_norm2(const T n[3], const cx<T> a[3]) {
+  double aa = 0.0;
+  for (int i = 0; i < 3; ++i) aa += double(a[i].re) * a[i].re + double(a[i].im) * a[i].im;
+  const double nr = double(n[0]) * a[0].re + double(n[1]) * a[1].re + double(n[2]) * a[2].re;
+  const double ni = double(n[0]) * a[0].im + double(n[1]) * a[1].im + double(n[2]) * a[2].im;
+  return 2.0 * aa + 2.0 * (nr * nr + ni * ni);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum NV doubles over the block; result valid in thread 0.  scratch holds
+// at least (blockDim.x / 64) * NV doubles and is not otherwise in use.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) scratch[wid * NV + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += scratch[w * NV + i];
+      v[i] = s;
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ cx<T>* cptr(void* p, long long off) {
+  return reinterpret_cast<cx<T>*>(p) + off;
+}
+
+// ---------------------------------------------------------------------------
+// z pass
+// ---------------------------------------------------------------------------
+template <int N, class T, int MODE>
+__global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g) {
+  using Cf = AxisCfg<N, T>;
+  constexpr int N1 = Cf::N1, N2 = Cf::N2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + N;
+
+  const int s = blockIdx.y;
+  SysState* st = g.state + s;
+  if (MODE != kZFwdRhs && st->status != kRunning) return;
+  const int ntx = (g.hx + Cf::M - 1) / Cf::M;
+  const int y = blockIdx.x / ntx;
+  const int kx0 = (blockIdx.x % ntx) * Cf::M;
+  const int mk = min(Cf::M, g.hx - kx0);
+  const int L = 6 * mk;
+  cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride);
+  cx<T>* ar = cptr<T>(g.ar, s * g.a_stride);
+  cx<T>* ap = cptr<T>(g.ap, s * g.a_stride);
+  const long long plane = (long long)g.ny * g.hx;  // frequencies per z plane
+
+  fill_twiddles<N, T>(tw);
+
+  if constexpr (MODE == kZInvCg || MODE == kZInvFp) {
+    const T beta = T(st->beta);
+    for (int task = threadIdx.x; task < N * mk; task += blockDim.x) {
+      const int kxl = task % mk, z = task / mk, kx = kx0 + kxl;
+      const long long off = ((long long)z * plane + (long long)y * g.hx + kx) * 3;
+      cx<T> a[3];
+      if constexpr (MODE == kZInvCg) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          a[i] = ar[off + i] + beta * ap[off + i];
+          ap[off + i] = a[i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) a[i] = ar[off + i];
+      }
+      T n[3];
+      unit_k<T>(g, kx, y, z, n);
+      cx<T> e[6];
+      expand_sym(n, a, e);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) buf[z * L + kxl * 6 + c] = e[c];
+    }
+    __syncthreads();
+    fft_nat2perm<N1, N2, +1, T>(buf, L, tw);
+    for (int f = threadIdx.x; f < N * L; f += blockDim.x) {
+      const int l = f % L, pos = f / L;
+      const int z = perm_idx<N1, N2>(pos);
+      tmp[((long long)z * plane + (long long)y * g.hx + kx0) * 6 + l] = buf[pos * L + l];
+    }
+  } else {
+    for (int f = threadIdx.x; f < N * L; f += blockDim.x) {
+      const int l = f % L, z = f / L;
+      buf[z * L + l] = tmp[((long long)z * plane + (long long)y * g.hx + kx0) * 6 + l];
+    }
+    __syncthreads();
+    fft_nat2perm<N1, N2, -1, T>(buf, L, tw);
+    const T alpha = T(st->alpha);
+    const T g1 = T(0.5 / g.ref_mu);
+    const T g2 = T((g.ref_lam + g.ref_mu) / (g.ref_lam + 2.0 * g.ref_mu));
+    double acc[1] = {0.0};
+    for (int task = threadIdx.x; task < N * mk; task += blockDim.x) {
+      const int kxl = task % mk, pos = task / mk, kx = kx0 + kxl;
+      const int kz = perm_idx<N1, N2>(pos);
+      cx<T> sg[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sg[c] = buf[pos * L + kxl * 6 + c];
+      T n[3];
+      const bool live = unit_k<T>(g, kx, y, kz, n);
+      cx<T> t[3];
+      const cx<T> ntn = sym_dot_n(sg, n, t);
+      cx<T> q[3];  // 3-vector form of the projection of sigma
+#pragma unroll
+      for (int i = 0; i < 3; ++i) q[i] = live ? t[i] - (T(0.5) * n[i]) * ntn : cx<T>{T(0), T(0)};
+      const long long off = ((long long)kz * plane + (long long)y * g.hx + kx) * 3;
+      const double w = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+      if constexpr (MODE == kZFwdCg) {
+        cx<T> r[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          r[i] = ar[off + i] - alpha * q[i];
+          ar[off + i] = r[i];
+        }
+        acc[0] += w * sym_norm2(n, r);
+      } else if constexpr (MODE == kZFwdRhs) {
+        cx<T> r[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          r[i] = cx<T>{-q[i].re, -q[i].im};
+          ar[off + i] = r[i];
+        }
+        acc[0] += w * sym_norm2(n, r);
+      } else {  // basic fixed point: eps* <- eps* - Gamma0 sigma
+        cx<T> x[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const cx<T> gi = live ? g1 * (t[i] - (g2 * n[i]) * ntn) : cx<T>{T(0), T(0)};
+          x[i] = ar[off + i] - gi;
+          ar[off + i] = x[i];
+        }
+        acc[0] += w * sym_norm2(n, q);
+      }
+    }
+    __syncthreads();
+    block_sum<1>(acc, reinterpret_cast<double*>(buf));
+    if (threadIdx.x == 0) g.part_z[(long long)s * g.nwg_z + blockIdx.x] = acc[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y pass (plain FFT along y of the 6-component spectrum, in place)
+// ---------------------------------------------------------------------------
+template <int N, class T, int S>
+__global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_ypass(GroupArgs g) {
+  using Cf = AxisCfg<N, T>;
+  constexpr int N1 = Cf::N1, N2 = Cf::N2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + N;
+  const int s = blockIdx.y;
+  if (g.state[s].status != kRunning) return;
+  const int ntx = (g.hx + Cf::M - 1) / Cf::M;
+  const int z = blockIdx.x / ntx;
+  const int kx0 = (blockIdx.x % ntx) * Cf::M;
+  const int mk = min(Cf::M, g.hx - kx0);
+  const int L = 6 * mk;
+  cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride) + ((long long)z * g.ny * g.hx + kx0) * 6;
+  const long long stride = (long long)g.hx * 6;
+  fill_twiddles<N, T>(tw);
+  for (int f = threadIdx.x; f < N * L; f += blockDim.x) {
+    const int l = f % L, y = f / L;
+    buf[y * L + l] = tmp[y * stride + l];
+  }
+  __syncthreads();
+  fft_nat2perm<N1, N2, S, T>(buf, L, tw);
+  for (int f = threadIdx.x; f < N * L; f += blockDim.x) {
+    const int l = f % L, pos = f / L;
+    tmp[perm_idx<N1, N2>(pos) * stride + l] = buf[pos * L + l];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x pass: C2R, constitutive law, reductions, R2C
+// ---------------------------------------------------------------------------
+template <int N, class T, int MODE>
+__global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
+  using Cf = XCfg<N, T>;
+  constexpr int N1 = Cf::N1, N2 = Cf::N2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + N;
+  __shared__ T s_lam[kMaxPhase], s_mu[kMaxPhase];
+
+  const int s = blockIdx.y;
+  SysState* st = g.state + s;
+  if (MODE != kXRhs && st->status != kRunning) return;
+  const SysDesc sd = g.sys[s];
+  const ItemDesc& it = g.items[sd.item];
+  const int rows = g.ny * g.nz;
+  const int r0 = blockIdx.x * Cf::R;
+  const int nr = min(Cf::R, rows - r0);
+  const int L = 3 * nr;
+  const int hx = g.hx;
+  cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride) + (long long)r0 * hx * 6;
+
+  fill_twiddles<N, T>(tw);
+  if (threadIdx.x < kMaxPhase) {
+    const int i = threadIdx.x < it.nphase ? threadIdx.x : 0;
+    s_lam[threadIdx.x] = T(it.lam[i]);
+    s_mu[threadIdx.x] = T(it.mu[i]);
+  }
+
+  if constexpr (MODE != kXRhs) {
+    // unpack: complex line (pair) = A + i B with A, B the spectra of two real lines
+    for (int f = threadIdx.x; f < nr * hx * 3; f += blockDim.x) {
+      const int pr = f % 3, kx = (f / 3) % hx, rl = f / (3 * hx);
+      const cx<T> A = tmp[((long long)rl * hx + kx) * 6 + 2 * pr];
+      const cx<T> B = tmp[((long long)rl * hx + kx) * 6 + 2 * pr + 1];
+      const int l = rl * 3 + pr;
+      if (kx == 0 || 2 * kx == N) {
+        buf[kx * L + l] = cx<T>{A.re, B.re};
+      } else {
+        buf[kx * L + l] = cx<T>{A.re - B.im, A.im + B.re};
+        buf[(N - kx) * L + l] = cx<T>{A.re + B.im, B.re - A.im};
+      }
+    }
+    __syncthreads();
+    fft_nat2perm<N1, N2, +1, T>(buf, L, tw);
+  } else {
+    __syncthreads();
+  }
+
+  // constitutive law on the voxels of this tile (positions are permuted)
+  const T invV = T(1.0 / (double(N) * g.ny * g.nz));
+  T E[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) E[c] = T(g.loads[sd.load][c]);
+  const int x0 = it.region[0], y0 = it.region[1], z0 = it.region[2];
+  const int x1 = it.region[3], y1 = it.region[4], z1 = it.region[5];
+  double acc[kPartX];
+#pragma unroll
+  for (int i = 0; i < kPartX; ++i) acc[i] = 0.0;
+  for (int task = threadIdx.x; task < nr * N; task += blockDim.x) {
+    const int rl = task % nr, pos = task / nr;
+    const int x = perm_idx<N1, N2>(pos);
+    const int row = r0 + rl, z = row / g.ny, y = row - z * g.ny;
+    T p[6];
+    if constexpr (MODE == kXRhs) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) p[c] = E[c];
+    } else {
+#pragma unroll
+      for (int pr = 0; pr < 3; ++pr) {
+        const cx<T> v = buf[pos * L + rl * 3 + pr];
+        p[2 * pr] = v.re * invV;
+        p[2 * pr + 1] = v.im * invV;
+      }
+      if constexpr (MODE == kXFp) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) p[c] += E[c];
+      }
+    }
+    const long long vox = (long long)row * N + x;
+    T sg[6];
+    if (g.aniso) {
+      const T* Cv = reinterpret_cast<const T*>(g.cfield) + it.cf_off + vox * 21;
+      // sigma_V = C_V eps_eng with eps_eng = (e11 e22 e33 2e23 2e13 2e12)
+      const T ee[6] = {p[0], p[1], p[2], T(2) * p[3], T(2) * p[4], T(2) * p[5]};
+      int k = 0;
+      T Cm[6][6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+          Cm[i][j] = Cv[k];
+          Cm[j][i] = Cv[k];
+          ++k;
+        }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        T a = T(0);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a += Cm[i][j] * ee[j];
+        sg[i] = a;
+      }
+    } else {
+      const int lab = g.labels[it.lab_off + vox];
+      const T lam = s_lam[lab], mu2 = T(2) * s_mu[lab];
+      const T tr = lam * (p[0] + p[1] + p[2]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sg[c] = mu2 * p[c] + (c < 3 ? tr : T(0));
+    }
+    if constexpr (MODE == kXRhs) {
+      double ss = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ss += (c < 3 ? 1.0 : 2.0) * double(sg[c]) * sg[c];
+      acc[0] += ss;
+    } else if constexpr (MODE == kXCg) {
+      double ps = 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ps += (c < 3 ? 1.0 : 2.0) * double(p[c]) * sg[c];
+      acc[0] += ps;
+    }
+    if (x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        acc[1 + c] += double(p[c]);
+        acc[7 + c] += double(sg[c]);
+      }
+    }
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr) buf[pos * L + rl * 3 + pr] = cx<T>{sg[2 * pr], sg[2 * pr + 1]};
+  }
+  __syncthreads();
+  fft_perm2nat<N1, N2, -1, T>(buf, L, tw);
+  for (int f = threadIdx.x; f < nr * hx * 3; f += blockDim.x) {
+    const int pr = f % 3, kx = (f / 3) % hx, rl = f / (3 * hx);
+    const int l = rl * 3 + pr;
+    const cx<T> zk = buf[kx * L + l];
+    const cx<T> zm = buf[((N - kx) % N) * L + l];
+    const cx<T> A{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+    const cx<T> B{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
+    tmp[((long long)rl * hx + kx) * 6 + 2 * pr] = A;
+    tmp[((long long)rl * hx + kx) * 6 + 2 * pr + 1] = B;
+  }
+  __syncthreads();
+  block_sum<kPartX>(acc, reinterpret_cast<double*>(buf));
+  if (threadIdx.x == 0) {
+    double* out = g.part_x + ((long long)s * g.nwg_x + blockIdx.x) * kPartX;
+#pragma unroll
+    for (int i = 0; i < kPartX; ++i) out[i] = acc[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+template <int N, class T>
+struct Ops {
+  static int zm() { return AxisCfg<N, T>::M; }
+  static int xr() { return XCfg<N, T>::R; }
+  static void z(int mode, const GroupArgs& g, hipStream_t st) {
+    using Cf = AxisCfg<N, T>;
+    const dim3 grid(g.ny * ((g.hx + Cf::M - 1) / Cf::M), g.nsys);
+    switch (mode) {
+      case kZInvCg: k_zpass<N, T, kZInvCg><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZFwdCg: k_zpass<N, T, kZFwdCg><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZFwdRhs: k_zpass<N, T, kZFwdRhs><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZInvFp: k_zpass<N, T, kZInvFp><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZFwdFp: k_zpass<N, T, kZFwdFp><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+    }
+  }
+  static void y(int dir, const GroupArgs& g, hipStream_t st) {
+    using Cf = AxisCfg<N, T>;
+    const dim3 grid(g.nz * ((g.hx + Cf::M - 1) / Cf::M), g.nsys);
+    if (dir < 0) k_ypass<N, T, -1><<<grid, Cf::THREADS, Cf::LDS, st>>>(g);
+    else k_ypass<N, T, +1><<<grid, Cf::THREADS, Cf::LDS, st>>>(g);
+  }
+  static void x(int mode, const GroupArgs& g, hipStream_t st) {
+    using Cf = XCfg<N, T>;
+    const dim3 grid((g.ny * g.nz + Cf::R - 1) / Cf::R, g.nsys);
+    switch (mode) {
+      case kXCg: k_xpass<N, T, kXCg><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kXRhs: k_xpass<N, T, kXRhs><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kXFp: k_xpass<N, T, kXFp><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+    }
+  }
+};
+
+#define HH_CASE_F(N) \
+  case N:            \
+    return &size_ops_impl<N, float>;
+#define HH_CASE_D(N) \
+  case N:            \
+    return &size_ops_impl<N, double>;
+
+template <int N, class T>
+void size_ops_impl(int what, int mode, const GroupArgs* g, hipStream_t st, int* info) {
+  switch (what) {
+    case kOpZ: Ops<N, T>::z(mode, *g, st); break;
+    case kOpY: Ops<N, T>::y(mode, *g, st); break;
+    case kOpX: Ops<N, T>::x(mode, *g, st); break;
+    case kOpInfoZ: *info = Ops<N, T>::zm(); break;
+    case kOpInfoX: *info = Ops<N, T>::xr(); break;
+  }
+}
+
+}  // namespace hh

@@ -1,0 +1,343 @@
+"""Python binding of the C ABI in include/hh.h (ctypes; argument marshalling only).
+
+Every step of the computation runs in the HIP library ``libhh.so``; this
+module only converts arguments.  PyTorch supplies device memory (CUDA/HIP
+tensors are passed by ``data_ptr()``) and the stream (the current torch
+stream unless another is given).  Importing it without the built library,
+or calling it without a gfx950 GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhh.so")
+
+HH_OK = 0
+ERRORS = {
+    -1: "HH_EINVAL", -2: "HH_EUNSUPPORTED", -3: "HH_ENOMEM", -4: "HH_EDEVICE",
+    -5: "HH_ESINGULAR", -6: "HH_ENOCONV", -7: "HH_ESTAGNATED", -8: "HH_EBREAKDOWN",
+}
+KERNEL_CLASSES = ("zinv", "yinv", "x", "yfwd", "zfwd", "fin", "setup", "other")
+NKERNEL = len(KERNEL_CLASSES)
+
+# Exported symbols (checked by the CPU test suite against include/hh.h).
+SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_last_error",
+           "hh_workspace_bytes", "hh_release_workspace", "hh_size_supported", "hh_homogenize",
+           "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_richardson",
+           "hh_moduli")
+
+
+class HHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "HH_E?"), code, msg))
+        self.code = code
+
+
+class Phase(ct.Structure):
+    _fields_ = [("K", ct.c_double), ("G", ct.c_double)]
+
+
+class Opts(ct.Structure):
+    _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int), ("scheme", ct.c_int),
+                ("precision", ct.c_int), ("nyquist", ct.c_int), ("profile", ct.c_int),
+                ("stall_limit", ct.c_int), ("chunk", ct.c_int),
+                ("ref_lambda", ct.c_double), ("ref_mu", ct.c_double)]
+
+
+class Report(ct.Structure):
+    _fields_ = [("status", ct.c_int), ("iters", ct.c_int * 6), ("rel_resid", ct.c_double * 6),
+                ("asym", ct.c_double), ("seconds", ct.c_double), ("voxel_iters", ct.c_double),
+                ("items", ct.c_longlong), ("kernel_ms", ct.c_double * NKERNEL),
+                ("kernel_launches", ct.c_int * NKERNEL)]
+
+    def as_dict(self):
+        return dict(status=self.status, iters=list(self.iters), rel_resid=list(self.rel_resid),
+                    asym=self.asym, seconds=self.seconds, voxel_iters=self.voxel_iters,
+                    items=self.items,
+                    kernel_ms={k: self.kernel_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
+                    kernel_launches={k: self.kernel_launches[i] for i, k in enumerate(KERNEL_CLASSES)})
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libhh.so (built by ``python -m paper_2208_02320_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("HIP library %s is not built; run python -m paper_2208_02320_amd.build" % path)
+    lib = ct.CDLL(path)
+    P, I, D, LL = ct.c_void_p, ct.c_int, ct.c_double, ct.c_longlong
+    DP = ct.POINTER(ct.c_double)
+    lib.hh_default_opts.argtypes = [ct.POINTER(Opts)]
+    lib.hh_default_opts.restype = None
+    lib.hh_create.argtypes = [ct.POINTER(P), I, P]
+    lib.hh_set_stream.argtypes = [P, P]
+    lib.hh_destroy.argtypes = [P]
+    lib.hh_destroy.restype = None
+    lib.hh_last_error.argtypes = [P]
+    lib.hh_last_error.restype = ct.c_char_p
+    lib.hh_workspace_bytes.argtypes = [P]
+    lib.hh_workspace_bytes.restype = LL
+    lib.hh_release_workspace.argtypes = [P]
+    lib.hh_release_workspace.restype = None
+    lib.hh_size_supported.argtypes = [I, I]
+    lib.hh_homogenize.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, DP, ct.POINTER(I),
+                                  ct.POINTER(Opts), DP, DP, ct.POINTER(Report)]
+    lib.hh_homogenize_aniso.argtypes = [P, P, I, I, I, I, ct.POINTER(Opts), DP, DP, ct.POINTER(Report)]
+    lib.hh_homogenize_batch.argtypes = [P, I, ct.POINTER(I), P, LL, I, ct.POINTER(LL), ct.POINTER(Phase),
+                                        ct.POINTER(I), ct.POINTER(I), ct.POINTER(I), ct.POINTER(Opts),
+                                        DP, DP, ct.POINTER(I), ct.POINTER(I), ct.POINTER(Report)]
+    lib.hh_hierarchical.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, I, I, I, ct.POINTER(Opts),
+                                    DP, DP, ct.POINTER(Report)]
+    lib.hh_richardson.argtypes = [ct.POINTER(I), DP, I, DP, DP]
+    lib.hh_moduli.argtypes = [DP, DP, DP]
+    for name in SYMBOLS:
+        getattr(lib, name)
+    _lib = lib
+    return lib
+
+
+def default_opts(**kw):
+    lib = load_library()
+    o = Opts()
+    lib.hh_default_opts(ct.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, v)
+    return o
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _phases(phases):
+    arr = (Phase * len(phases))()
+    for i, (K, G) in enumerate(phases):
+        arr[i].K, arr[i].G = float(K), float(G)
+    return arr
+
+
+def size_supported(n, precision=0):
+    return bool(load_library().hh_size_supported(int(n), int(precision)))
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _buffer(x, dtype):
+    """(pointer, on_device, keepalive) for a torch tensor or array-like."""
+    if _is_torch(x):
+        import torch
+        want = {np.uint8: torch.uint8, np.float64: torch.float64}[dtype]
+        if x.dtype != want:
+            raise TypeError("expected a %s tensor" % want)
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ct.c_void_p(x.data_ptr()), int(x.is_cuda), x
+    a = np.ascontiguousarray(np.asarray(x), dtype=dtype)
+    return a.ctypes.data_as(ct.c_void_p), 0, a
+
+
+@dataclass
+class Result:
+    C: np.ndarray
+    C_raw: np.ndarray | None
+    report: dict
+
+
+class Context:
+    """A library context bound to one device and stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library needs a gfx950 device")
+        self._lib = load_library()
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._stream = stream
+        h = ct.c_void_p()
+        rc = self._lib.hh_create(ct.byref(h), self.device, ct.c_void_p(stream.cuda_stream))
+        if rc != HH_OK:
+            raise HHError(rc, "hh_create failed (is this a gfx950 device?)")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_stream(self, stream):
+        self._stream = stream
+        self._lib.hh_set_stream(self._h, ct.c_void_p(stream.cuda_stream))
+
+    def _check(self, rc, allow=()):
+        if rc != HH_OK and rc not in allow:
+            raise HHError(rc, self._lib.hh_last_error(self._h).decode())
+        return rc
+
+    def workspace_bytes(self):
+        return self._lib.hh_workspace_bytes(self._h)
+
+    def release_workspace(self):
+        self._lib.hh_release_workspace(self._h)
+
+    def homogenize(self, labels, phases, loads=None, region=None, check=True, **opts):
+        """C (6x6 Voigt, symmetrized), raw C, report for one label image [z][y][x]."""
+        nz, ny, nx = tuple(labels.shape)
+        ptr, dev, keep = _buffer(labels, np.uint8)
+        o = default_opts(**opts)
+        ph = _phases(phases)
+        C = np.zeros(36)
+        Craw = np.zeros(36)
+        rep = Report()
+        ld = None if loads is None else np.ascontiguousarray(np.asarray(loads, dtype=np.float64).T)
+        rg = None if region is None else (ct.c_int * 6)(*[int(v) for v in region])
+        rc = self._lib.hh_homogenize(self._h, ptr, nx, ny, nz, dev, ph, len(phases),
+                                     None if ld is None else _dptr(ld), rg, ct.byref(o),
+                                     _dptr(C), _dptr(Craw), ct.byref(rep))
+        if check:
+            self._check(rc)
+        del keep
+        return Result(C.reshape(6, 6), Craw.reshape(6, 6), rep.as_dict())
+
+    def homogenize_aniso(self, C21, check=True, **opts):
+        """Stiffness of an image of anisotropic voxels; C21 has shape (nz, ny, nx, 21)."""
+        nz, ny, nx, k = tuple(C21.shape)
+        if k != 21:
+            raise ValueError("expected 21 components per voxel")
+        ptr, dev, keep = _buffer(C21, np.float64)
+        o = default_opts(**opts)
+        C = np.zeros(36)
+        Craw = np.zeros(36)
+        rep = Report()
+        rc = self._lib.hh_homogenize_aniso(self._h, ptr, nx, ny, nz, dev, ct.byref(o), _dptr(C),
+                                           _dptr(Craw), ct.byref(rep))
+        if check:
+            self._check(rc)
+        del keep
+        return Result(C.reshape(6, 6), Craw.reshape(6, 6), rep.as_dict())
+
+    def homogenize_batch(self, images, phase_sets, regions=None, labels_pack=None, check=True,
+                         **opts):
+        """Independent images (arrays [z][y][x], or shapes with ``labels_pack`` a
+        device uint8 tensor holding them back to back).  Returns
+        (C[n,6,6], C_raw[n,6,6], status[n], iters[n,6], report)."""
+        n = len(images)
+        dims = np.zeros(3 * n, dtype=np.int32)
+        off = np.zeros(n, dtype=np.int64)
+        pos = 0
+        shapes = []
+        for i, im in enumerate(images):
+            shp = tuple(im) if labels_pack is not None else tuple(np.asarray(im).shape)
+            nz, ny, nx = shp
+            dims[3 * i:3 * i + 3] = (nx, ny, nz)
+            off[i] = pos
+            pos += nx * ny * nz
+            shapes.append(shp)
+        if labels_pack is None:
+            pack = np.concatenate([np.ascontiguousarray(np.asarray(im, dtype=np.uint8)).ravel()
+                                   for im in images])
+            ptr, dev, keep = _buffer(pack, np.uint8)
+        else:
+            ptr, dev, keep = _buffer(labels_pack, np.uint8)
+            if labels_pack.numel() < pos:
+                raise ValueError("label pack too small")
+        flat = []
+        poff = np.zeros(n, dtype=np.int32)
+        nph = np.zeros(n, dtype=np.int32)
+        for i, ps in enumerate(phase_sets):
+            poff[i] = len(flat)
+            nph[i] = len(ps)
+            flat.extend(ps)
+        ph = _phases(flat)
+        rg = None
+        if regions is not None:
+            rg = np.ascontiguousarray(np.asarray(regions, dtype=np.int32).reshape(n * 6))
+        o = default_opts(**opts)
+        C = np.zeros(36 * n)
+        Craw = np.zeros(36 * n)
+        st = np.zeros(n, dtype=np.int32)
+        it = np.zeros(6 * n, dtype=np.int32)
+        rep = Report()
+        IP = ct.POINTER(ct.c_int)
+        rc = self._lib.hh_homogenize_batch(
+            self._h, n, dims.ctypes.data_as(IP), ptr, ct.c_longlong(pos), dev,
+            off.ctypes.data_as(ct.POINTER(ct.c_longlong)), ph, poff.ctypes.data_as(IP),
+            nph.ctypes.data_as(IP), None if rg is None else rg.ctypes.data_as(IP), ct.byref(o),
+            _dptr(C), _dptr(Craw), st.ctypes.data_as(IP), it.ctypes.data_as(IP), ct.byref(rep))
+        if check:
+            self._check(rc)
+        del keep
+        return C.reshape(n, 6, 6), Craw.reshape(n, 6, 6), st, it.reshape(n, 6), rep.as_dict()
+
+    def hierarchical(self, labels, phases, n_sub, pad=0, check=True, **opts):
+        """Two-level hierarchical C*; returns (C*, C_sub[(N/n)^3, 21], report)."""
+        nz, ny, nx = tuple(labels.shape)
+        ptr, dev, keep = _buffer(labels, np.uint8)
+        o = default_opts(**opts)
+        ph = _phases(phases)
+        m = (nx // n_sub) * (ny // n_sub) * (nz // n_sub) if n_sub > 0 else 0
+        C = np.zeros(36)
+        Cs = np.zeros(max(1, m) * 21)
+        rep = Report()
+        rc = self._lib.hh_hierarchical(self._h, ptr, nx, ny, nz, dev, ph, len(phases), int(n_sub),
+                                       int(pad), 0, ct.byref(o), _dptr(C), _dptr(Cs), ct.byref(rep))
+        if check:
+            self._check(rc)
+        del keep
+        return C.reshape(6, 6), Cs[:21 * m].reshape(m, 21), rep.as_dict()
+
+
+def richardson(ns, Cs):
+    """Fit M(n) = M_inf + slope / n entrywise; Cs has shape (m, 6, 6)."""
+    lib = load_library()
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    Cs = np.ascontiguousarray(np.asarray(Cs, dtype=np.float64).reshape(len(ns), 36))
+    Ci = np.zeros(36)
+    sl = np.zeros(36)
+    rc = lib.hh_richardson(ns.ctypes.data_as(ct.POINTER(ct.c_int)), _dptr(Cs), len(ns), _dptr(Ci),
+                           _dptr(sl))
+    if rc != HH_OK:
+        raise HHError(rc, "hh_richardson: need >= 2 distinct positive sizes")
+    return Ci.reshape(6, 6), sl.reshape(6, 6)
+
+
+def moduli(C):
+    """(K, G) of the Voigt isotropic projection of a 6x6 stiffness."""
+    lib = load_library()
+    C = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(36))
+    K, G = ct.c_double(), ct.c_double()
+    rc = lib.hh_moduli(_dptr(C), ct.byref(K), ct.byref(G))
+    if rc != HH_OK:
+        raise HHError(rc, "hh_moduli")
+    return K.value, G.value
+
+
+def upper21(C):
+    C = np.asarray(C)
+    return np.array([C[i, j] for i in range(6) for j in range(i, 6)])

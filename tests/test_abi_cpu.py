@@ -1,0 +1,73 @@
+"""CPU checks of the C ABI library: it loads, exports every declared symbol,
+and its host-only entry points (moduli, Richardson fit) agree with the
+oracle.  No GPU compute is called."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bounds, hier
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2208_02320_amd", "libhh.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhh.so not built")
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "hh.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*|long long)\s*\*?\s*(hh_\w+)\(", txt, re.M)))
+
+
+def test_header_declares_the_binding_symbols():
+    from paper_2208_02320_amd import hh
+    assert declared_symbols() == sorted(hh.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ct.CDLL(LIB)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_binding_loads():
+    from paper_2208_02320_amd import hh
+    lib = hh.load_library()
+    o = hh.default_opts()
+    assert o.tol == 1e-6 and o.max_iter == 1000 and o.scheme == 0 and o.precision == 0
+    assert lib.hh_size_supported(256, 0) == 1 and lib.hh_size_supported(7, 0) == 0
+    assert lib.hh_size_supported(80, 1) == 1 and lib.hh_size_supported(80, 2) == 0
+
+
+def test_moduli_host_entry_point():
+    from paper_2208_02320_amd import hh
+    C = bounds.iso_voigt_matrix(37.0, 44.0)
+    K, G = hh.moduli(C)
+    assert np.isclose(K, 37.0) and np.isclose(G, 44.0)
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((6, 6))
+    C = A @ A.T + 6 * np.eye(6)
+    assert np.allclose(hh.moduli(C), hier.voigt_moduli(C), rtol=1e-14)
+
+
+def test_richardson_host_entry_point():
+    from paper_2208_02320_amd import hh
+    rng = np.random.default_rng(1)
+    ns = [32, 64, 128]
+    Cs = rng.standard_normal((3, 6, 6)) + 10
+    Ci, sl = hh.richardson(ns, Cs)
+    m, c = hier.richardson(ns, Cs.reshape(3, 36))
+    assert np.allclose(Ci.ravel(), m, rtol=1e-12) and np.allclose(sl.ravel(), c, rtol=1e-10)
+    with pytest.raises(hh.HHError):
+        hh.richardson([32, 32], Cs[:2])
+
+
+def test_context_needs_gpu():
+    import torch
+    from paper_2208_02320_amd import hh
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        hh.Context(0)

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances: FP32 fields with FP64 reductions at residual tol 1e-6 must
+match the oracle (tol 1e-10) to a relative Frobenius error of 1e-5 on the
+Mandel-scaled stiffness; the FP64 path at tol 1e-10 to 1e-8.
+"""
+import numpy as np
+import pytest
+
+from oracle import bounds, galerkin as g, hier
+from paper_2208_02320_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+QP = [synth.QUARTZ, synth.PORE]
+FOUR = synth.FOUR_PHASE["phases"]
+TOL32 = 1e-5
+TOL64 = 1e-8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2208_02320_amd import hh
+    c = hh.Context(0)
+    yield c
+    c.close()
+
+
+def oracle(lab, phases, **kw):
+    kw.setdefault("tol", 1e-10)
+    kw.setdefault("form", "sym6")
+    return g.homogenize(g.IsotropicMedium(lab, phases), **kw)
+
+
+def rand_labels(shape, nphase=2, seed=0, frac=0.3):
+    rng = np.random.default_rng(seed)
+    if nphase == 2:
+        return (rng.random(shape) < frac).astype(np.uint8)
+    return rng.integers(0, nphase, size=shape).astype(np.uint8)
+
+
+def test_homogeneous_medium_exact(ctx):
+    lab = np.zeros((16, 16, 16), np.uint8)
+    r = ctx.homogenize(lab, [(37.0, 44.0)])
+    assert g.rel_error(r.C, bounds.iso_voigt_matrix(37.0, 44.0)) < 1e-6
+    assert max(r.report["iters"]) <= 1
+
+
+def test_two_phase_32_fp32(ctx):
+    """The 32^3 two-phase benchmark image (pore 20 %, sigma 2, seed 0)."""
+    lab = synth.two_phase(32, 0.2, 2.0, 0)
+    r = ctx.homogenize(lab, QP, tol=1e-6)
+    ref = oracle(lab, QP)
+    err = g.rel_error(r.C, ref.C_sym)
+    print("32^3 fp32 err %.3e iters %s oracle iters %s" % (err, r.report["iters"], ref.iters))
+    assert err < TOL32
+    ref6 = oracle(lab, QP, tol=1e-6)
+    for a, b in zip(r.report["iters"], ref6.iters):
+        assert abs(a - b) <= 3
+
+
+def test_two_phase_32_fp64(ctx):
+    lab = synth.two_phase(32, 0.2, 2.0, 0)
+    r = ctx.homogenize(lab, QP, tol=1e-10, precision=1)
+    ref = oracle(lab, QP)
+    assert g.rel_error(r.C, ref.C_sym) < TOL64
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 8), (9, 4, 10), (15, 12, 16)])
+def test_non_cubic_odd_even_fp64(ctx, shape):
+    lab = rand_labels(shape, nphase=3, seed=sum(shape))
+    ph = [synth.QUARTZ, synth.CLAY, synth.PORE]
+    r = ctx.homogenize(lab, ph, tol=1e-11, precision=1)
+    ref = oracle(lab, ph, tol=1e-12)
+    assert g.rel_error(r.C, ref.C_sym) < TOL64
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 20, 24, 27, 48])
+def test_sizes_fp32(ctx, n):
+    lab = synth.rocklike(n, [0.6, 0.25, 0.15], sigma=1.0, seed=n, low_to_high=[2, 1, 0])
+    ph = [synth.QUARTZ, synth.FELDSPAR, synth.PORE]
+    r = ctx.homogenize(lab, ph, tol=1e-6)
+    ref = oracle(lab, ph)
+    assert g.rel_error(r.C, ref.C_sym) < TOL32
+
+
+def test_laminate_backus_fp32(ctx):
+    lab = synth.laminate(16, 4, axis=0)
+    r = ctx.homogenize(lab, QP, tol=1e-7)
+    f = bounds.fractions(lab, 2)
+    assert g.rel_error(r.C, bounds.backus(f, QP)) < TOL32
+
+
+def test_region_average_fp64(ctx):
+    lab = rand_labels((12, 12, 12), seed=3)
+    region = (2, 3, 1, 10, 9, 11)
+    r = ctx.homogenize(lab, QP, region=region, tol=1e-11, precision=1)
+    ref = oracle(lab, QP, region=region, tol=1e-12)
+    assert g.rel_error(r.C_raw, ref.C) < TOL64
+    assert g.rel_error(r.C, ref.C_sym) < TOL64
+
+
+def test_nyquist_zero_convention(ctx):
+    lab = rand_labels((8, 8, 8), seed=4)
+    r = ctx.homogenize(lab, QP, tol=1e-11, precision=1, nyquist=1)
+    ref = oracle(lab, QP, tol=1e-12, nyquist="zero")
+    assert g.rel_error(r.C, ref.C_sym) < TOL64
+
+
+def test_custom_loads(ctx):
+    lab = rand_labels((8, 10, 6), seed=5)
+    rng = np.random.default_rng(0)
+    loads = rng.standard_normal((6, 6)) + 3 * np.eye(6)
+    r = ctx.homogenize(lab, QP, loads=loads, tol=1e-11, precision=1)
+    ref = oracle(lab, QP, tol=1e-12)
+    assert g.rel_error(r.C, ref.C_sym) < 1e-7
+
+
+def test_basic_scheme(ctx):
+    lab = rand_labels((8, 8, 8), seed=6)
+    r = ctx.homogenize(lab, QP, tol=1e-9, precision=1, scheme=1, max_iter=5000)
+    ref = oracle(lab, QP)
+    assert g.rel_error(r.C, ref.C_sym) < 1e-7
+    rb = oracle(lab, QP, tol=1e-9, scheme="basic")
+    assert abs(max(r.report["iters"]) - max(rb.iters)) <= 2
+
+
+def test_anisotropic_voxels(ctx):
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((6, 5, 4, 6, 6))
+    Cv = np.einsum("...ij,...kj->...ik", A, A) + 5 * np.eye(6)
+    C21 = np.stack([Cv[..., i, j] for i in range(6) for j in range(i, 6)], axis=-1)
+    r = ctx.homogenize_aniso(C21, tol=1e-11, precision=1)
+    ref = g.homogenize(g.AnisotropicMedium(Cv), tol=1e-12, form="sym6")
+    assert g.rel_error(r.C, ref.C_sym) < TOL64
+    r32 = ctx.homogenize_aniso(C21, tol=1e-6)
+    assert g.rel_error(r32.C, ref.C_sym) < TOL32
+
+
+def test_hierarchical_small_fp64(ctx):
+    lab = synth.rocklike(24, [0.75, 0.25], sigma=1.5, seed=3, low_to_high=[1, 0])
+    C, Cs, rep = ctx.hierarchical(lab, QP, 8, 2, tol=1e-11, precision=1)
+    ref = hier.hierarchical(lab, QP, 8, 2, tol=1e-12, form="sym6")
+    assert g.rel_error(C, ref.C) < TOL64
+    sub = np.stack([hier.to21(c) for c in ref.C_sub.reshape(-1, 6, 6)])
+    assert np.abs(Cs - sub).max() < 1e-7 * np.abs(sub).max()
+
+
+def test_hierarchical_fp32(ctx):
+    lab = synth.four_phase(32, seed=2)
+    C, Cs, rep = ctx.hierarchical(lab, FOUR, 16, 4, tol=1e-6)
+    ref = hier.hierarchical(lab, FOUR, 16, 4, tol=1e-10, form="sym6")
+    assert g.rel_error(C, ref.C) < TOL32
+
+
+def test_batch_mixed_sizes(ctx):
+    recipe = synth.uneven_batch(6, sizes=(8, 12, 16), seed=77)
+    imgs = [synth.item_image(it) for it in recipe]
+    phs = [it["phases"] for it in recipe]
+    C, Craw, st, iters, rep = ctx.homogenize_batch(imgs, phs, tol=1e-6)
+    assert (st == 0).all()
+    for i in range(len(imgs)):
+        ref = oracle(imgs[i], phs[i])
+        assert g.rel_error(C[i], ref.C_sym) < TOL32, i
+
+
+def test_device_tensor_inputs(ctx):
+    import torch
+    lab = synth.two_phase(16, 0.3, 1.5, 1)
+    d = torch.from_numpy(lab).cuda()
+    r1 = ctx.homogenize(d, QP, tol=1e-6)
+    r2 = ctx.homogenize(lab, QP, tol=1e-6)
+    assert np.array_equal(r1.C, r2.C)
+
+
+def test_errors(ctx):
+    from paper_2208_02320_amd import hh
+    lab = np.full((8, 8, 8), 2, np.uint8)
+    with pytest.raises(hh.HHError) as e:
+        ctx.homogenize(lab, QP)
+    assert e.value.code == -1
+    with pytest.raises(hh.HHError) as e:
+        ctx.homogenize(np.zeros((7, 8, 8), np.uint8), QP)
+    assert e.value.code == -2
+    with pytest.raises(hh.HHError) as e:
+        ctx.hierarchical(np.zeros((24, 24, 24), np.uint8), QP, 10, 0)
+    assert e.value.code == -1
+    with pytest.raises(hh.HHError) as e:
+        ctx.homogenize(np.zeros((8, 8, 8), np.uint8), [(1.0, -1.0)])
+    assert e.value.code == -1
+
+
+def test_fp32_tolerance_floor_reports_status(ctx):
+    lab = synth.two_phase(32, 0.2, 2.0, 0)
+    r = ctx.homogenize(lab, QP, tol=1e-9, max_iter=400, stall_limit=40, check=False)
+    assert r.report["status"] in (0, -6, -7)
+    ref = oracle(lab, QP)
+    assert g.rel_error(r.C, ref.C_sym) < TOL32
+
+
+def test_max_iter_one(ctx):
+    lab = synth.two_phase(16, 0.2, 2.0, 0)
+    r = ctx.homogenize(lab, QP, tol=1e-6, max_iter=1, check=False)
+    assert r.report["status"] == -6 and max(r.report["iters"]) == 1
