@@ -1,0 +1,142 @@
+"""Benchmark: voxel-iterations per second of the FFT elasticity solve.
+
+Workload (one step): effective stiffness of one 256^3 four-phase rock-like
+image (quartz/feldspar/clay/pore, fractions 0.55/0.15/0.10/0.20, smoothing
+sigma 2 voxels, seed 1) under the six unit macroscopic strains, FP32 fields
+and FFTs with FP64 reductions, CG to a relative residual of 1e-6.  Labels
+are resident in device memory before the timed region.
+
+voxel-iters = sum over the six loads of (voxels x CG iterations).
+
+Prints one JSON line with the metric, a roofline entry for the dominant
+kernel (algorithmic bytes per launch / mean launch time from HIP events on
+the library stream) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KCLS = ("zinv", "yinv", "x", "yfwd", "zfwd")
+
+
+def algorithmic_bytes(nx, ny, nz, cbytes=8):
+    """Bytes each pass class must move per system-iteration."""
+    nf = (nx // 2 + 1) * ny * nz  # half-spectrum frequencies
+    V = nx * ny * nz
+    return {
+        "zinv": nf * cbytes * (3 + 3 + 3 + 6),   # read r, p; write p, spectrum
+        "yinv": nf * cbytes * 12,                # read + write 6 components
+        "x": nf * cbytes * 12 + V,               # read + write 6 components, labels
+        "yfwd": nf * cbytes * 12,
+        "zfwd": nf * cbytes * (6 + 3 + 3),       # read spectrum, r; write r
+    }
+
+
+def cpu_baseline(lab, phases, iters=2):
+    """FP64 oracle on a bounded sample: load 1 of the same image, the right-hand
+    side plus the first ``iters`` CG iterations."""
+    from oracle import galerkin as g
+    med = g.IsotropicMedium(lab, phases)
+    t = time.perf_counter()
+    _, info = g.solve_load(med, g.unit_strain(0), tol=1e-6, maxit=iters, form="paper9")
+    dt = time.perf_counter() - t
+    V = float(lab.size)
+    return {"value": V * info.iters / dt, "unit": "voxel-iters/s", "cores": g.workers(),
+            "kind": "oracle",
+            "sample": "FP64 oracle (paper's 9-component projection, scipy.fft with %d workers), "
+                      "load 1 of the same %s image: right-hand side and the first %d CG "
+                      "iterations, %.1f s" % (g.workers(), "x".join(map(str, lab.shape)),
+                                               info.iters, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2208_02320_amd import hh, synth
+
+    n = args.size
+    lab = synth.four_phase(n, sigma=2.0, seed=1)
+    phases = synth.FOUR_PHASE["phases"]
+    dev = torch.from_numpy(lab).to("cuda:0")
+    ctx = hh.Context(0)
+    opts = dict(tol=1e-6, precision=0)
+    print("bench: %d^3 four-phase, warmup %d" % (n, args.warmup), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.homogenize(dev, phases, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        reps.append(ctx.homogenize(dev, phases, profile=1, **opts).report)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    vi = sum(r["voxel_iters"] for r in reps)
+    iters = reps[-1]["iters"]
+    print("bench: %d steps %.3f s, iters %s" % (args.steps, dt, iters), file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel class
+    ab = algorithmic_bytes(n, n, n)
+    sys_iters = sum(sum(r["iters"]) for r in reps)
+    ms = {k: sum(r["kernel_ms"][k] for r in reps) for k in KCLS}
+    launches = {k: sum(r["kernel_launches"][k] for r in reps) for k in KCLS}
+    dom = max(KCLS, key=lambda k: ms[k])
+    bytes_dom = ab[dom] * sys_iters
+    achieved = bytes_dom / (ms[dom] * 1e-3) / 1e9
+    per_class = {k: {"ms": round(ms[k], 3), "launches": launches[k],
+                     "GBs": round(ab[k] * sys_iters / max(ms[k] * 1e-3, 1e-12) / 1e9, 1)}
+                 for k in KCLS}
+    print("bench: per-class %s" % json.dumps(per_class), file=sys.stderr, flush=True)
+
+    cpu = None if args.no_cpu else cpu_baseline(lab, phases, args.cpu_iters)
+    out = {
+        "metric": "voxel-iters/s of FFT elasticity solve",
+        "value": vi / dt,
+        "unit": "voxel-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain FFT solve, %d^3 four-phase rock-like image, 6 unit loads, "
+                               "FP32 fields / FP64 reductions, tol 1e-6" % n,
+                   "voxels": n ** 3, "iters_per_load": iters,
+                   "voxel_iters_per_step": vi / args.steps},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes_per_system_iter": ab[dom],
+                     "mean_launch_ms": round(ms[dom] / max(launches[dom], 1), 4)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -226,10 +226,13 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
   oz(kOpInfoZ, 0, nullptr, nullptr, &Mz);
   ox(kOpInfoX, 0, nullptr, nullptr, &Rx);
   const int hx = nx / 2 + 1;
-  const long long nfreq = (long long)hx * ny * nz;
+  const int hxp = (hx + 3) / 4 * 4;  // 64-byte aligned spectrum rows
+  const long long nfreq = (long long)hxp * ny * nz;
   const size_t cb = P == 0 ? 8 : 16;
-  const size_t per_sys = size_t(nfreq) * 12 * cb;  // tmp (6) + ar (3) + ap (3)
   const int nwg_z = ny * ((hx + Mz - 1) / Mz);
+  // 3-vector fields are stored per z-pass tile: [tile][z][Mz][3]
+  const long long nafreq = (long long)nwg_z * nz * Mz;
+  const size_t per_sys = size_t(nfreq) * 6 * cb + size_t(nafreq) * 6 * cb;  // tmp + ar + ap
   const int nwg_x = (ny * nz + Rx - 1) / Rx;
 
   size_t freeb = 0, totalb = 0;
@@ -292,16 +295,16 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
     auto* d_px = static_cast<double*>(ws(ctx, "part_x", sizeof(double) * kPartX * size_t(nwg_x) * nsys));
     auto* d_pz = static_cast<double*>(ws(ctx, "part_z", sizeof(double) * size_t(nwg_z) * nsys));
     void* d_tmp = ws(ctx, "tmp", size_t(nfreq) * 6 * cb * nsys);
-    void* d_ar = ws(ctx, "ar", size_t(nfreq) * 3 * cb * nsys);
-    void* d_ap = ws(ctx, "ap", size_t(nfreq) * 3 * cb * nsys);
+    void* d_ar = ws(ctx, "ar", size_t(nafreq) * 3 * cb * nsys);
+    void* d_ap = ws(ctx, "ap", size_t(nafreq) * 3 * cb * nsys);
     auto* d_out = static_cast<double*>(ws(ctx, "cout", sizeof(double) * 72 * nw));
     auto* d_ist = static_cast<int*>(ws(ctx, "istatus", sizeof(int) * nw));
     auto* d_cnt = static_cast<int*>(ws(ctx, "count", sizeof(int)));
     HIPCHK(hipMemcpyAsync(d_items, idesc.data(), sizeof(ItemDesc) * nw, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(d_sys, sdesc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemsetAsync(d_state, 0, sizeof(SysState) * nsys, ctx->stream));
-    HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nfreq) * 3 * cb * nsys, ctx->stream));
-    if (o.scheme == 1) HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nfreq) * 3 * cb * nsys, ctx->stream));
+    HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nafreq) * 3 * cb * nsys, ctx->stream));
+    if (o.scheme == 1) HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nafreq) * 3 * cb * nsys, ctx->stream));
 
     GroupArgs g;
     std::memset(&g, 0, sizeof(g));
@@ -309,6 +312,7 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
     g.ny = ny;
     g.nz = nz;
     g.hx = hx;
+    g.hxp = hxp;
     g.nsys = nsys;
     g.nyq_zero = o.nyquist;
     g.max_iter = o.max_iter;
@@ -330,7 +334,7 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
     g.ar = d_ar;
     g.ap = d_ap;
     g.tmp_stride = nfreq * 6;
-    g.a_stride = nfreq * 3;
+    g.a_stride = nafreq * 3;
     g.state = d_state;
     g.part_x = d_px;
     g.part_z = d_pz;
@@ -469,7 +473,7 @@ const unsigned char* device_labels(hh_ctx* ctx, const uint8_t* labels, long long
     auto* d_max = static_cast<int*>(ws(ctx, "lm_max", sizeof(int) * n));
     HIPCHK(hipMemcpyAsync(d_off, off.data(), sizeof(long long) * n, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(d_cnt, cnt.data(), sizeof(long long) * n, hipMemcpyHostToDevice, ctx->stream));
-    launch_label_max(d, d_off, d_cnt, n, d_max, ctx->stream);
+    launch_label_max(d, d_off, d_cnt, n, *std::max_element(cnt.begin(), cnt.end()), d_max, ctx->stream);
     HIPCHK(hipGetLastError());
     std::vector<int> mx(n);
     HIPCHK(hipMemcpyAsync(mx.data(), d_max, sizeof(int) * n, hipMemcpyDeviceToHost, ctx->stream));

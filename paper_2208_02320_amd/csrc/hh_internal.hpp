@@ -48,6 +48,8 @@ struct SysState {
   double ce2;      // (C:E, C:E), scale of the right-hand side
   double sig[6];   // running < sigma >_R (tensor components 11 22 33 23 13 12)
   double eps[6];   // running < eps >_R
+  double sig_best[6];  // averages at the smallest residual seen
+  double eps_best[6];
   int iter;
   int status;
   int stall;
@@ -57,6 +59,7 @@ struct SysState {
 // Everything a pass kernel needs about its group of systems.
 struct GroupArgs {
   int nx, ny, nz, hx;      // grid and half-spectrum length along x
+  int hxp;                 // row pitch of the spectrum (hx rounded up to a multiple of 4)
   int nsys;                // systems in this launch
   int nyq_zero;            // 1: operator zero at frequencies with a Nyquist component
   int max_iter;

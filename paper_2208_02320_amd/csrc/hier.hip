@@ -32,22 +32,28 @@ __global__ void k_gather_pad(const unsigned char* __restrict__ img, int nx, int 
   }
 }
 
-// Largest label of each item (one block per item).
+// Largest label of each item: blockIdx.y = item, blocks along x split it.
 __global__ void k_label_max(const unsigned char* __restrict__ labels, const long long* __restrict__ off,
                             const long long* __restrict__ count, int* __restrict__ out) {
   __shared__ int smax[256];
-  const int item = blockIdx.x;
+  const int item = blockIdx.y;
   const unsigned char* p = labels + off[item];
   const long long n = count[item];
   int m = 0;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = max(m, int(p[i]));
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = max(m, int(p[i]));
   smax[threadIdx.x] = m;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[item] = smax[0];
+  if (threadIdx.x == 0) atomicMax(out + item, smax[0]);
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
 // Number of systems still iterating.
@@ -82,8 +88,14 @@ void launch_gather_pad(const unsigned char* img, int nx, int ny, int nz, int n, 
 }
 
 void launch_label_max(const unsigned char* labels, const long long* off, const long long* count, int nitems,
-                      int* out, hipStream_t st) {
-  k_label_max<<<nitems, 256, 0, st>>>(labels, off, count, out);
+                      long long max_count, int* out, hipStream_t st) {
+  k_fill_int<<<(nitems + 255) / 256, 256, 0, st>>>(out, nitems, 0);
+  long long bx = (max_count + 256 * 16 - 1) / (256 * 16);
+  bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
+  for (int i0 = 0; i0 < nitems; i0 += 65535) {
+    const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
+    k_label_max<<<dim3(unsigned(bx), unsigned(ni)), 256, 0, st>>>(labels, off + i0, count + i0, out + i0);
+  }
 }
 
 void launch_count_running(const SysState* st, int n, int* count, hipStream_t s) {

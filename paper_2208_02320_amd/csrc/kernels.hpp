@@ -32,7 +32,7 @@ void launch_stiffness(int precision, const SysState* state, int nitems, double* 
 void launch_gather_pad(const unsigned char* img, int nx, int ny, int nz, int n, int p, unsigned char* out,
                        hipStream_t st);
 void launch_label_max(const unsigned char* labels, const long long* off, const long long* count, int nitems,
-                      int* out, hipStream_t st);
+                      long long max_count, int* out, hipStream_t st);
 void launch_count_running(const SysState* st, int n, int* count, hipStream_t s);
 void launch_convert_field(int precision, const double* src, void* dst, long long n, hipStream_t st);
 

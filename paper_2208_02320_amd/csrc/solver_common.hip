@@ -33,6 +33,10 @@ __global__ void __launch_bounds__(256) k_fin_x(GroupArgs g, int mode) {
       st->sig[c] = v[7 + c] * inv;
       st->eps[c] = g.loads[g.sys[s].load][c];
     }
+    for (int c = 0; c < 6; ++c) {
+      st->sig_best[c] = st->sig[c];
+      st->eps_best[c] = st->eps[c];
+    }
     st->ce2 = v[0];
     st->bb = 0.0;
     st->rr = 0.0;
@@ -100,15 +104,26 @@ __global__ void __launch_bounds__(256) k_fin_z(GroupArgs g, int mode) {
   if (rr < st->best_rr) {
     st->best_rr = rr;
     st->stall = 0;
+    for (int c = 0; c < 6; ++c) {
+      st->sig_best[c] = st->sig[c];
+      st->eps_best[c] = st->eps[c];
+    }
   } else {
     st->stall += 1;
   }
   if (rr <= g.tol2 * st->bb) {
     st->status = kConverged;
-  } else if (st->stall >= g.stall_limit) {
-    st->status = kStagnated;
+  } else if (st->stall >= g.stall_limit || rr > 1e4 * st->best_rr) {
+    st->status = kStagnated;  // FP32 floor or divergence: keep the best iterate
   } else if (st->iter >= g.max_iter) {
     st->status = kNoConv;
+  }
+  if (st->status == kStagnated || st->status == kNoConv) {
+    for (int c = 0; c < 6; ++c) {
+      st->sig[c] = st->sig_best[c];
+      st->eps[c] = st->eps_best[c];
+    }
+    st->rr = st->best_rr;
   }
   if (mode == kZFwdFp && st->status == kRunning) st->iter += 1;
 }

@@ -35,7 +35,11 @@
 
 namespace hh {
 
-inline constexpr int kLdsTile = 48 * 1024;
+// LDS budget of one tile.  y/z passes: at least 4 kx columns per tile so
+// that every tile row is a whole number of 64-byte sectors (no partial
+// writes); x pass: full spectrum rows.
+inline constexpr int kLdsTile = 24 * 1024;
+inline constexpr int kLdsTileYZ = 48 * 1024;
 
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
@@ -45,7 +49,7 @@ template <int N, class T>
 struct AxisCfg {
   static constexpr int N1 = split_n1(N), N2 = N / N1;
   static constexpr int CB = int(sizeof(cx<T>));
-  static constexpr int M = clampi(kLdsTile / (N * 6 * CB), 1, 16);
+  static constexpr int M = clampi(kLdsTileYZ / (N * 6 * CB), CB == 8 ? 4 : 2, 16);
   static constexpr int L = 6 * M;
   static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);
   static constexpr int LDS = (N * L + N) * CB;
@@ -147,10 +151,77 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
   }
 }
 
+// Sum NV doubles over a block of TH threads through LDS (no cross-lane
+// shuffles); result valid in thread 0.  scratch holds TH * NV doubles.
+template <int NV, int TH>
+__device__ __forceinline__ void block_sum_lds(double (&v)[NV], double* scratch) {
+  constexpr int G = 8;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) scratch[i * TH + threadIdx.x] = v[i];
+  __syncthreads();
+  double part = 0.0;
+  if (threadIdx.x < NV * G) {
+    const int i = threadIdx.x / G, gi = threadIdx.x % G;
+    for (int j = gi; j < TH; j += G) part += scratch[i * TH + j];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV * G) scratch[threadIdx.x] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double t = 0.0;
+      for (int gi = 0; gi < G; ++gi) t += scratch[i * G + gi];
+      v[i] = t;
+    }
+  }
+}
+
 template <class T>
 __device__ __forceinline__ cx<T>* cptr(void* p, long long off) {
   return reinterpret_cast<cx<T>*>(p) + off;
 }
+
+// ---------------------------------------------------------------------------
+// Batched tile movement.  Every thread first issues all of its 16-byte
+// global loads into registers and only then writes LDS, so a wave keeps
+// many requests in flight; LDS row r holds `rowU` 16-byte units.
+// ---------------------------------------------------------------------------
+template <int ROWS, int ROWU, int THREADS, class RowMap>
+__device__ __forceinline__ void tile_load(uint4* __restrict__ lds, const uint4* __restrict__ src, int validU,
+                                          long long gstride, RowMap map) {
+  constexpr int TOTAL = ROWS * ROWU, KMAX = (TOTAL + THREADS - 1) / THREADS;
+  uint4 v[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int idx = threadIdx.x + k * THREADS;
+    const int r = idx / ROWU, j = idx - r * ROWU;
+    v[k] = make_uint4(0u, 0u, 0u, 0u);
+    if ((TOTAL % THREADS == 0 || idx < TOTAL) && j < validU) v[k] = src[(long long)map(r) * gstride + j];
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int idx = threadIdx.x + k * THREADS;
+    if (TOTAL % THREADS == 0 || idx < TOTAL) lds[idx] = v[k];
+  }
+}
+
+template <int ROWS, int ROWU, int THREADS, class RowMap>
+__device__ __forceinline__ void tile_store(const uint4* __restrict__ lds, uint4* __restrict__ dst, int validU,
+                                           long long gstride, RowMap map) {
+  constexpr int TOTAL = ROWS * ROWU, KMAX = (TOTAL + THREADS - 1) / THREADS;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int idx = threadIdx.x + k * THREADS;
+    const int r = idx / ROWU, j = idx - r * ROWU;
+    if ((TOTAL % THREADS == 0 || idx < TOTAL) && j < validU) dst[(long long)map(r) * gstride + j] = lds[idx];
+  }
+}
+
+template <class T>
+struct alignas(2 * sizeof(cx<T>)) cpair {
+  cx<T> a, b;
+};
 
 // ---------------------------------------------------------------------------
 // z pass
@@ -158,7 +229,10 @@ __device__ __forceinline__ cx<T>* cptr(void* p, long long off) {
 template <int N, class T, int MODE>
 __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g) {
   using Cf = AxisCfg<N, T>;
-  constexpr int N1 = Cf::N1, N2 = Cf::N2;
+  constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS;
+  constexpr int CB = Cf::CB;
+  constexpr int M = Cf::M, L = 6 * M, ROWU = L * CB / 16;
+  constexpr int KT = (N * M + TH - 1) / TH;  // (z, kx) tasks per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + N;
@@ -169,96 +243,128 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g)
   const int ntx = (g.hx + Cf::M - 1) / Cf::M;
   const int y = blockIdx.x / ntx;
   const int kx0 = (blockIdx.x % ntx) * Cf::M;
-  const int mk = min(Cf::M, g.hx - kx0);
-  const int L = 6 * mk;
+  const int mk = min(M, g.hx - kx0);  // valid columns of this tile
+  const int validU = 6 * mk * CB / 16;
   cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride);
   cx<T>* ar = cptr<T>(g.ar, s * g.a_stride);
   cx<T>* ap = cptr<T>(g.ap, s * g.a_stride);
-  const long long plane = (long long)g.ny * g.hx;  // frequencies per z plane
+  const long long plane = (long long)g.ny * g.hxp;  // frequencies per z plane (padded rows)
+  uint4* tile_g = reinterpret_cast<uint4*>(tmp + ((long long)y * g.hxp + kx0) * 6);
+  const long long gstride = plane * 6 * CB / 16;
+  constexpr int ntask = N * M;
+  // 3-vector fields are stored tile-major: [tile = blockIdx.x][z][kxl][3]
+  const long long atile = (long long)blockIdx.x * N * M * 3;
 
   fill_twiddles<N, T>(tw);
 
   if constexpr (MODE == kZInvCg || MODE == kZInvFp) {
     const T beta = T(st->beta);
-    for (int task = threadIdx.x; task < N * mk; task += blockDim.x) {
-      const int kxl = task % mk, z = task / mk, kx = kx0 + kxl;
-      const long long off = ((long long)z * plane + (long long)y * g.hx + kx) * 3;
-      cx<T> a[3];
-      if constexpr (MODE == kZInvCg) {
+    cx<T> ra[KT][3], pa[KT][3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          a[i] = ar[off + i] + beta * ap[off + i];
-          ap[off + i] = a[i];
+    for (int k = 0; k < KT; ++k) {
+      const int task = threadIdx.x + k * TH;
+      const int kxl = task % M, z = task / M;
+      if (task < ntask && kxl < mk) {
+        const long long off = atile + (z * M + kxl) * 3;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ra[k][i] = ar[off + i];
+        if constexpr (MODE == kZInvCg) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) pa[k][i] = ap[off + i];
         }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) a[i] = ar[off + i];
       }
-      T n[3];
-      unit_k<T>(g, kx, y, z, n);
-      cx<T> e[6];
-      expand_sym(n, a, e);
+    }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) buf[z * L + kxl * 6 + c] = e[c];
+    for (int k = 0; k < KT; ++k) {
+      const int task = threadIdx.x + k * TH;
+      const int kxl = task % M, z = task / M, kx = kx0 + kxl;
+      if (task < ntask && kxl >= mk) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) buf[z * L + kxl * 6 + c] = cx<T>{T(0), T(0)};
+      } else if (task < ntask) {
+        cx<T> a[3];
+        if constexpr (MODE == kZInvCg) {
+          const long long off = atile + (z * M + kxl) * 3;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            a[i] = ra[k][i] + beta * pa[k][i];
+            ap[off + i] = a[i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) a[i] = ra[k][i];
+        }
+        T n[3];
+        unit_k<T>(g, kx, y, z, n);
+        cx<T> e[6];
+        expand_sym(n, a, e);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) buf[z * L + kxl * 6 + c] = e[c];
+      }
     }
     __syncthreads();
     fft_nat2perm<N1, N2, +1, T>(buf, L, tw);
-    for (int f = threadIdx.x; f < N * L; f += blockDim.x) {
-      const int l = f % L, pos = f / L;
-      const int z = perm_idx<N1, N2>(pos);
-      tmp[((long long)z * plane + (long long)y * g.hx + kx0) * 6 + l] = buf[pos * L + l];
-    }
+    tile_store<N, ROWU, TH>(reinterpret_cast<const uint4*>(buf), tile_g, validU, gstride,
+                            [](int pos) { return perm_idx<N1, N2>(pos); });
   } else {
-    for (int f = threadIdx.x; f < N * L; f += blockDim.x) {
-      const int l = f % L, z = f / L;
-      buf[z * L + l] = tmp[((long long)z * plane + (long long)y * g.hx + kx0) * 6 + l];
+    // prefetch the residual for the epilogue together with the tile
+    cx<T> ra[KT][3];
+    if constexpr (MODE != kZFwdRhs) {
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const int task = threadIdx.x + k * TH;
+        const int kxl = task % M, kz = perm_idx<N1, N2>(task / M);
+        if (task < ntask && kxl < mk) {
+          const long long off = atile + (kz * M + kxl) * 3;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) ra[k][i] = ar[off + i];
+        }
+      }
     }
+    tile_load<N, ROWU, TH>(reinterpret_cast<uint4*>(buf), tile_g, validU, gstride, [](int r) { return r; });
     __syncthreads();
     fft_nat2perm<N1, N2, -1, T>(buf, L, tw);
     const T alpha = T(st->alpha);
     const T g1 = T(0.5 / g.ref_mu);
     const T g2 = T((g.ref_lam + g.ref_mu) / (g.ref_lam + 2.0 * g.ref_mu));
     double acc[1] = {0.0};
-    for (int task = threadIdx.x; task < N * mk; task += blockDim.x) {
-      const int kxl = task % mk, pos = task / mk, kx = kx0 + kxl;
-      const int kz = perm_idx<N1, N2>(pos);
-      cx<T> sg[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sg[c] = buf[pos * L + kxl * 6 + c];
-      T n[3];
-      const bool live = unit_k<T>(g, kx, y, kz, n);
-      cx<T> t[3];
-      const cx<T> ntn = sym_dot_n(sg, n, t);
-      cx<T> q[3];  // 3-vector form of the projection of sigma
+    for (int k = 0; k < KT; ++k) {
+      const int task = threadIdx.x + k * TH;
+      const int kxl = task % M, pos = task / M, kx = kx0 + kxl;
+      if (task < ntask && kxl < mk) {
+        const int kz = perm_idx<N1, N2>(pos);
+        cx<T> sg[6];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) q[i] = live ? t[i] - (T(0.5) * n[i]) * ntn : cx<T>{T(0), T(0)};
-      const long long off = ((long long)kz * plane + (long long)y * g.hx + kx) * 3;
-      const double w = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
-      if constexpr (MODE == kZFwdCg) {
+        for (int c = 0; c < 6; ++c) sg[c] = buf[pos * L + kxl * 6 + c];
+        T n[3];
+        const bool live = unit_k<T>(g, kx, y, kz, n);
+        cx<T> t[3];
+        const cx<T> ntn = sym_dot_n(sg, n, t);
+        cx<T> q[3];  // 3-vector form of the projection of sigma
+#pragma unroll
+        for (int i = 0; i < 3; ++i) q[i] = live ? t[i] - (T(0.5) * n[i]) * ntn : cx<T>{T(0), T(0)};
+        const long long off = atile + (kz * M + kxl) * 3;
+        const double w = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
         cx<T> r[3];
+        if constexpr (MODE == kZFwdCg) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          r[i] = ar[off + i] - alpha * q[i];
-          ar[off + i] = r[i];
-        }
-        acc[0] += w * sym_norm2(n, r);
-      } else if constexpr (MODE == kZFwdRhs) {
-        cx<T> r[3];
+          for (int i = 0; i < 3; ++i) r[i] = ra[k][i] - alpha * q[i];
+          acc[0] += w * sym_norm2(n, r);
+        } else if constexpr (MODE == kZFwdRhs) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          r[i] = cx<T>{-q[i].re, -q[i].im};
-          ar[off + i] = r[i];
-        }
-        acc[0] += w * sym_norm2(n, r);
-      } else {  // basic fixed point: eps* <- eps* - Gamma0 sigma
-        cx<T> x[3];
+          for (int i = 0; i < 3; ++i) r[i] = cx<T>{-q[i].re, -q[i].im};
+          acc[0] += w * sym_norm2(n, r);
+        } else {  // basic fixed point: eps* <- eps* - Gamma0 sigma
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const cx<T> gi = live ? g1 * (t[i] - (g2 * n[i]) * ntn) : cx<T>{T(0), T(0)};
-          x[i] = ar[off + i] - gi;
-          ar[off + i] = x[i];
+          for (int i = 0; i < 3; ++i) {
+            const cx<T> gi = live ? g1 * (t[i] - (g2 * n[i]) * ntn) : cx<T>{T(0), T(0)};
+            r[i] = ra[k][i] - gi;
+          }
+          acc[0] += w * sym_norm2(n, q);
         }
-        acc[0] += w * sym_norm2(n, q);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ar[off + i] = r[i];
       }
     }
     __syncthreads();
@@ -273,7 +379,8 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g)
 template <int N, class T, int S>
 __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_ypass(GroupArgs g) {
   using Cf = AxisCfg<N, T>;
-  constexpr int N1 = Cf::N1, N2 = Cf::N2;
+  constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS, CB = Cf::CB;
+  constexpr int M = Cf::M, L = 6 * M, ROWU = L * CB / 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + N;
@@ -282,21 +389,17 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_ypass(GroupArgs g)
   const int ntx = (g.hx + Cf::M - 1) / Cf::M;
   const int z = blockIdx.x / ntx;
   const int kx0 = (blockIdx.x % ntx) * Cf::M;
-  const int mk = min(Cf::M, g.hx - kx0);
-  const int L = 6 * mk;
-  cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride) + ((long long)z * g.ny * g.hx + kx0) * 6;
-  const long long stride = (long long)g.hx * 6;
+  const int mk = min(M, g.hx - kx0);
+  const int validU = 6 * mk * CB / 16;
+  uint4* tile_g = reinterpret_cast<uint4*>(cptr<T>(g.tmp, s * g.tmp_stride) +
+                                           ((long long)z * g.ny * g.hxp + kx0) * 6);
+  const long long gstride = (long long)g.hxp * 6 * CB / 16;
   fill_twiddles<N, T>(tw);
-  for (int f = threadIdx.x; f < N * L; f += blockDim.x) {
-    const int l = f % L, y = f / L;
-    buf[y * L + l] = tmp[y * stride + l];
-  }
+  tile_load<N, ROWU, TH>(reinterpret_cast<uint4*>(buf), tile_g, validU, gstride, [](int r) { return r; });
   __syncthreads();
   fft_nat2perm<N1, N2, S, T>(buf, L, tw);
-  for (int f = threadIdx.x; f < N * L; f += blockDim.x) {
-    const int l = f % L, pos = f / L;
-    tmp[perm_idx<N1, N2>(pos) * stride + l] = buf[pos * L + l];
-  }
+  tile_store<N, ROWU, TH>(reinterpret_cast<const uint4*>(buf), tile_g, validU, gstride,
+                          [](int pos) { return perm_idx<N1, N2>(pos); });
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +408,11 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_ypass(GroupArgs g)
 template <int N, class T, int MODE>
 __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
   using Cf = XCfg<N, T>;
-  constexpr int N1 = Cf::N1, N2 = Cf::N2;
+  constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS;
+  constexpr int R = Cf::R, L = 3 * R;
+  constexpr int HX = N / 2 + 1, HXP = (HX + 3) / 4 * 4;  // spectrum row length and pitch
+  constexpr int NU = R * HX * 3;                          // (row, kx, pair) units per tile
+  constexpr int KX = (NU + TH - 1) / TH;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + N;
@@ -317,11 +424,10 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
   const SysDesc sd = g.sys[s];
   const ItemDesc& it = g.items[sd.item];
   const int rows = g.ny * g.nz;
-  const int r0 = blockIdx.x * Cf::R;
-  const int nr = min(Cf::R, rows - r0);
-  const int L = 3 * nr;
-  const int hx = g.hx;
-  cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride) + (long long)r0 * hx * 6;
+  const int r0 = blockIdx.x * R;
+  const int nr = min(R, rows - r0);  // rows of this tile; the rest are zero lines
+  cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride) + (long long)r0 * HXP * 6;
+  cpair<T>* tmpp = reinterpret_cast<cpair<T>*>(tmp);  // 3 pairs per frequency
 
   fill_twiddles<N, T>(tw);
   if (threadIdx.x < kMaxPhase) {
@@ -330,18 +436,41 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
     s_mu[threadIdx.x] = T(it.mu[i]);
   }
 
+  // labels of this thread's voxels, fetched before anything waits on memory
+  constexpr int KE = (R * N + TH - 1) / TH;
+  int lab_pre[KE];
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int task = threadIdx.x + k * TH;
+    const int rl = task % R, pos = task / R;
+    lab_pre[k] = 0;
+    if (!g.aniso && (R * N % TH == 0 || task < R * N) && rl < nr)
+      lab_pre[k] = g.labels[it.lab_off + (long long)(r0 + rl) * N + perm_idx<N1, N2>(pos)];
+  }
+
   if constexpr (MODE != kXRhs) {
     // unpack: complex line (pair) = A + i B with A, B the spectra of two real lines
-    for (int f = threadIdx.x; f < nr * hx * 3; f += blockDim.x) {
-      const int pr = f % 3, kx = (f / 3) % hx, rl = f / (3 * hx);
-      const cx<T> A = tmp[((long long)rl * hx + kx) * 6 + 2 * pr];
-      const cx<T> B = tmp[((long long)rl * hx + kx) * 6 + 2 * pr + 1];
-      const int l = rl * 3 + pr;
-      if (kx == 0 || 2 * kx == N) {
-        buf[kx * L + l] = cx<T>{A.re, B.re};
-      } else {
-        buf[kx * L + l] = cx<T>{A.re - B.im, A.im + B.re};
-        buf[(N - kx) * L + l] = cx<T>{A.re + B.im, B.re - A.im};
+    cpair<T> v[KX];
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+      const int f = threadIdx.x + k * TH;
+      const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
+      if ((NU % TH == 0 || f < NU) && rl < nr) v[k] = tmpp[(rl * HXP + kx) * 3 + pr];
+    }
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+      const int f = threadIdx.x + k * TH;
+      const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
+      if (NU % TH == 0 || f < NU) {
+        cx<T> A = v[k].a, B = v[k].b;
+        if (rl >= nr) A = B = cx<T>{T(0), T(0)};
+        const int l = rl * 3 + pr;
+        if (kx == 0 || 2 * kx == N) {
+          buf[kx * L + l] = cx<T>{A.re, B.re};
+        } else {
+          buf[kx * L + l] = cx<T>{A.re - B.im, A.im + B.re};
+          buf[(N - kx) * L + l] = cx<T>{A.re + B.im, B.re - A.im};
+        }
       }
     }
     __syncthreads();
@@ -360,14 +489,18 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
   double acc[kPartX];
 #pragma unroll
   for (int i = 0; i < kPartX; ++i) acc[i] = 0.0;
-  for (int task = threadIdx.x; task < nr * N; task += blockDim.x) {
-    const int rl = task % nr, pos = task / nr;
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int task = threadIdx.x + k * TH;
+    if (R * N % TH != 0 && task >= R * N) break;
+    const int rl = task % R, pos = task / R;
     const int x = perm_idx<N1, N2>(pos);
     const int row = r0 + rl, z = row / g.ny, y = row - z * g.ny;
+    const bool valid = rl < nr;
     T p[6];
     if constexpr (MODE == kXRhs) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) p[c] = E[c];
+      for (int c = 0; c < 6; ++c) p[c] = valid ? E[c] : T(0);
     } else {
 #pragma unroll
       for (int pr = 0; pr < 3; ++pr) {
@@ -377,17 +510,20 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
       }
       if constexpr (MODE == kXFp) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) p[c] += E[c];
+        for (int c = 0; c < 6; ++c) p[c] += valid ? E[c] : T(0);
       }
     }
     const long long vox = (long long)row * N + x;
     T sg[6];
-    if (g.aniso) {
+    if (!valid) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sg[c] = T(0);
+    } else if (g.aniso) {
       const T* Cv = reinterpret_cast<const T*>(g.cfield) + it.cf_off + vox * 21;
       // sigma_V = C_V eps_eng with eps_eng = (e11 e22 e33 2e23 2e13 2e12)
       const T ee[6] = {p[0], p[1], p[2], T(2) * p[3], T(2) * p[4], T(2) * p[5]};
-      int k = 0;
       T Cm[6][6];
+      int k = 0;
 #pragma unroll
       for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -404,28 +540,30 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
         sg[i] = a;
       }
     } else {
-      const int lab = g.labels[it.lab_off + vox];
+      const int lab = lab_pre[k];
       const T lam = s_lam[lab], mu2 = T(2) * s_mu[lab];
       const T tr = lam * (p[0] + p[1] + p[2]);
 #pragma unroll
       for (int c = 0; c < 6; ++c) sg[c] = mu2 * p[c] + (c < 3 ? tr : T(0));
     }
-    if constexpr (MODE == kXRhs) {
-      double ss = 0.0;
+    if (valid) {
+      if constexpr (MODE == kXRhs) {
+        double ss = 0.0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ss += (c < 3 ? 1.0 : 2.0) * double(sg[c]) * sg[c];
-      acc[0] += ss;
-    } else if constexpr (MODE == kXCg) {
-      double ps = 0.0;
+        for (int c = 0; c < 6; ++c) ss += (c < 3 ? 1.0 : 2.0) * double(sg[c]) * sg[c];
+        acc[0] += ss;
+      } else if constexpr (MODE == kXCg) {
+        double ps = 0.0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ps += (c < 3 ? 1.0 : 2.0) * double(p[c]) * sg[c];
-      acc[0] += ps;
-    }
-    if (x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1) {
+        for (int c = 0; c < 6; ++c) ps += (c < 3 ? 1.0 : 2.0) * double(p[c]) * sg[c];
+        acc[0] += ps;
+      }
+      if (x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        acc[1 + c] += double(p[c]);
-        acc[7 + c] += double(sg[c]);
+        for (int c = 0; c < 6; ++c) {
+          acc[1 + c] += double(p[c]);
+          acc[7 + c] += double(sg[c]);
+        }
       }
     }
 #pragma unroll
@@ -433,18 +571,23 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
   }
   __syncthreads();
   fft_perm2nat<N1, N2, -1, T>(buf, L, tw);
-  for (int f = threadIdx.x; f < nr * hx * 3; f += blockDim.x) {
-    const int pr = f % 3, kx = (f / 3) % hx, rl = f / (3 * hx);
+  for (int f = threadIdx.x; f < NU; f += TH) {
+    const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
+    if (rl >= nr) continue;
     const int l = rl * 3 + pr;
     const cx<T> zk = buf[kx * L + l];
     const cx<T> zm = buf[((N - kx) % N) * L + l];
-    const cx<T> A{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
-    const cx<T> B{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
-    tmp[((long long)rl * hx + kx) * 6 + 2 * pr] = A;
-    tmp[((long long)rl * hx + kx) * 6 + 2 * pr + 1] = B;
+    cpair<T> o;
+    o.a = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
+    o.b = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
+    tmpp[(rl * HXP + kx) * 3 + pr] = o;
   }
   __syncthreads();
-  block_sum<kPartX>(acc, reinterpret_cast<double*>(buf));
+  if constexpr (TH * kPartX * 8 <= N * L * int(sizeof(cx<T>))) {
+    block_sum_lds<kPartX, TH>(acc, reinterpret_cast<double*>(buf));
+  } else {
+    block_sum<kPartX>(acc, reinterpret_cast<double*>(buf));
+  }
   if (threadIdx.x == 0) {
     double* out = g.part_x + ((long long)s * g.nwg_x + blockIdx.x) * kPartX;
 #pragma unroll

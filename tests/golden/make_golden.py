@@ -1,0 +1,55 @@
+"""Writes the stored expected values used by the GPU parity tests.
+
+Calls only the FP64 CPU oracle (oracle/) and the seeded input generator.
+Usage:  python tests/golden/make_golden.py four_phase_256
+        python tests/golden/make_golden.py hier_512_items
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import galerkin as g, hier  # noqa: E402
+from paper_2208_02320_amd import synth  # noqa: E402
+
+
+def four_phase_256():
+    """256^3 four-phase image (seed 1, sigma 2), six unit loads, CG to 1e-9."""
+    lab = synth.four_phase(256, sigma=2.0, seed=1)
+    t = time.time()
+    r = g.homogenize(g.IsotropicMedium(lab, synth.FOUR_PHASE["phases"]), tol=1e-9, form="sym6")
+    out = dict(image="synth.four_phase(256, sigma=2.0, seed=1)", tol=1e-9, form="sym6",
+               C=r.C.tolist(), C_sym=r.C_sym.tolist(), iters=r.iters, seconds=time.time() - t)
+    json.dump(out, open(os.path.join(HERE, "four_phase_256_seed1.json"), "w"), indent=1)
+
+
+def hier_512_items(count=6):
+    """Sampled subimages of the 512^3 four-phase image (seed 2) cut with
+    n = 64 and 8 voxels of padding (80^3 boxes), homogenized over the
+    central 64^3; items spread over the image."""
+    lab = synth.four_phase(512, sigma=2.0, seed=2)
+    origins = hier.partition(lab, 64)
+    rng = np.random.default_rng(0)
+    pick = sorted(rng.choice(len(origins), size=count, replace=False).tolist())
+    items = []
+    for i in pick:
+        t = time.time()
+        box = hier.padded_box(lab, origins[i], 64, 8)
+        r = g.homogenize(g.IsotropicMedium(box, synth.FOUR_PHASE["phases"]),
+                         region=(8, 8, 8, 72, 72, 72), tol=1e-9, form="sym6")
+        items.append(dict(index=i, origin=list(origins[i]), C=r.C.tolist(), C_sym=r.C_sym.tolist(),
+                          iters=r.iters, seconds=time.time() - t))
+        print("item", i, time.time() - t, flush=True)
+    out = dict(image="synth.four_phase(512, sigma=2.0, seed=2)", n=64, pad=8, tol=1e-9,
+               form="sym6", items=items)
+    json.dump(out, open(os.path.join(HERE, "four_phase_512_n64_p8_items.json"), "w"), indent=1)
+
+
+if __name__ == "__main__":
+    {"four_phase_256": four_phase_256, "hier_512_items": hier_512_items}[sys.argv[1]]()
