@@ -43,6 +43,35 @@ def algorithmic_bytes(nx, ny, nz, cbytes=8):
     }
 
 
+def kernel_source_hash():
+    """Short hash of the HIP sources; profile-derived figures are used only
+    while it matches the hash recorded with them."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2208_02320_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, n):
+    """HBM bytes per dispatch of a pass class from the committed counter
+    profile (FETCH_SIZE/WRITE_SIZE scaled by the copy-kernel calibration),
+    or None if the profile is missing, for another size, or stale."""
+    path = os.path.join(ROOT, "profiles", "solver_passes_256cube_counters.md")
+    if n != 256 or not os.path.exists(path):
+        return None
+    sha, val = None, None
+    for line in open(path):
+        w = line.split()
+        if len(w) == 2 and w[0] == "source_sha256_16":
+            sha = w[1]
+        if len(w) == 3 and w[0] == "traffic_bytes_per_dispatch" and w[1] == kernel:
+            val = float(w[2])
+    return val if sha == kernel_source_hash() else None
+
+
 def cpu_baseline(lab, phases, iters=2):
     """FP64 oracle on a bounded sample: load 1 of the same image, the right-hand
     side plus the first ``iters`` CG iterations."""
@@ -130,7 +159,9 @@ def main():
                    "voxel_iters_per_step": vi / args.steps},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "algorithmic_bytes_per_system_iter": ab[dom],
+                     "traffic": profiled_traffic(dom, n),
+                     "algorithmic_bytes_per_launch": round(bytes_dom / max(launches[dom], 1)),
+                     "algorithmic_bytes_per_system_iter": ab[dom],
                      "mean_launch_ms": round(ms[dom] / max(launches[dom], 1), 4)},
         "cpu_baseline": cpu,
     }

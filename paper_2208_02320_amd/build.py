@@ -2,7 +2,8 @@
 
 Every ``csrc/*.hip`` translation unit is compiled by ``hipcc`` for gfx950 in
 parallel, then linked into one shared library that exports the C ABI of
-``include/hh.h``.  Run as ``python -m paper_2208_02320_amd.build``.
+``include/hh.h``.  Also builds ``calib/copy``, the plain copy kernel used to
+calibrate profiler byte counters.  Run as ``python -m paper_2208_02320_amd.build``.
 """
 from __future__ import annotations
 
@@ -16,8 +17,8 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(ROOT, "_build")
-LIB = os.path.join(HERE, "libhh.so")
+BUILD = os.environ.get("HH_BUILD_DIR", os.path.join(ROOT, "_build"))
+LIB = os.environ.get("HH_LIB_OUT", os.path.join(HERE, "libhh.so"))
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
@@ -25,7 +26,7 @@ HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wno-unused-command-line-argument",
-          "-I", os.path.join(ROOT, "include")]
+          "-I", os.path.join(ROOT, "include")] + os.environ.get("HH_EXTRA_FLAGS", "").split()
 
 
 def _compile(src, obj):
@@ -56,6 +57,13 @@ def build(jobs=None, verbose=True):
     if p.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), p.stderr))
     os.replace(tmp, LIB)
+    calib = os.path.join(HERE, "calib", "copy.cpp")
+    exe = os.path.join(HERE, "calib", "copy")
+    cmd = [HIPCC, "-x", "hip"] + COMMON + DEVICE_FLAGS + [calib, "-o", exe + ".tmp"]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("calibration kernel build failed: %s\n%s" % (" ".join(cmd), p.stderr))
+    os.replace(exe + ".tmp", exe)
     if verbose:
         print("built %s in %.1fs" % (LIB, time.time() - t0), flush=True)
     return LIB

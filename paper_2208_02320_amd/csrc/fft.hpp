@@ -205,7 +205,15 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* tw, int m) {
   return {w.re, T(S) * w.im};
 }
 
-template <int N1, int N2, int S, class T>
+// Element e of line l sits at buf[e * L + (e / N1) * P + l]: P extra
+// complex words after every block of N1 elements shift the blocks across
+// LDS banks (P = 0 is the plain layout).
+template <int N1, int P>
+__device__ __forceinline__ int lds_at(int e, int L) {
+  return e * L + (P ? (e / N1) * P : 0);
+}
+
+template <int N1, int N2, int S, class T, int P = 0>
 __device__ __forceinline__ void fft_nat2perm(cx<T>* buf, int L, const cx<T>* tw) {
   constexpr int N = N1 * N2;
   if constexpr (N2 > 1) {
@@ -213,12 +221,12 @@ __device__ __forceinline__ void fft_nat2perm(cx<T>* buf, int L, const cx<T>* tw)
       const int l = task % L, j1 = task / L;
       cx<T> v[N2];
 #pragma unroll
-      for (int j2 = 0; j2 < N2; ++j2) v[j2] = buf[(j1 + N1 * j2) * L + l];
+      for (int j2 = 0; j2 < N2; ++j2) v[j2] = buf[(j1 + N1 * j2) * L + j2 * P + l];
       dft<N2, S, T>(v);
 #pragma unroll
       for (int k2 = 1; k2 < N2; ++k2) v[k2] = cmul(v[k2], twiddle<N, S>(tw, (j1 * k2) % N));
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) buf[(j1 + N1 * k2) * L + l] = v[k2];
+      for (int k2 = 0; k2 < N2; ++k2) buf[(j1 + N1 * k2) * L + k2 * P + l] = v[k2];
     }
     __syncthreads();
   }
@@ -226,15 +234,15 @@ __device__ __forceinline__ void fft_nat2perm(cx<T>* buf, int L, const cx<T>* tw)
     const int l = task % L, k2 = task / L;
     cx<T> v[N1];
 #pragma unroll
-    for (int j1 = 0; j1 < N1; ++j1) v[j1] = buf[(j1 + N1 * k2) * L + l];
+    for (int j1 = 0; j1 < N1; ++j1) v[j1] = buf[(j1 + N1 * k2) * L + k2 * P + l];
     dft<N1, S, T>(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) buf[(k1 + N1 * k2) * L + l] = v[k1];
+    for (int k1 = 0; k1 < N1; ++k1) buf[(k1 + N1 * k2) * L + k2 * P + l] = v[k1];
   }
   __syncthreads();
 }
 
-template <int N1, int N2, int S, class T>
+template <int N1, int N2, int S, class T, int P = 0>
 __device__ __forceinline__ void fft_perm2nat(cx<T>* buf, int L, const cx<T>* tw) {
   constexpr int N = N1 * N2;
   // factors (A, B) = (N2, N1): step one runs DFT_N1 over contiguous runs
@@ -242,14 +250,14 @@ __device__ __forceinline__ void fft_perm2nat(cx<T>* buf, int L, const cx<T>* tw)
     const int l = task % L, j1 = task / L;  // j1 in [0, N2)
     cx<T> v[N1];
 #pragma unroll
-    for (int j2 = 0; j2 < N1; ++j2) v[j2] = buf[(N1 * j1 + j2) * L + l];
+    for (int j2 = 0; j2 < N1; ++j2) v[j2] = buf[(N1 * j1 + j2) * L + j1 * P + l];
     dft<N1, S, T>(v);
     if constexpr (N2 > 1) {
 #pragma unroll
       for (int k2 = 1; k2 < N1; ++k2) v[k2] = cmul(v[k2], twiddle<N, S>(tw, (j1 * k2) % N));
     }
 #pragma unroll
-    for (int k2 = 0; k2 < N1; ++k2) buf[(N1 * j1 + k2) * L + l] = v[k2];
+    for (int k2 = 0; k2 < N1; ++k2) buf[(N1 * j1 + k2) * L + j1 * P + l] = v[k2];
   }
   __syncthreads();
   if constexpr (N2 > 1) {
@@ -257,10 +265,10 @@ __device__ __forceinline__ void fft_perm2nat(cx<T>* buf, int L, const cx<T>* tw)
       const int l = task % L, k2 = task / L;  // k2 in [0, N1)
       cx<T> v[N2];
 #pragma unroll
-      for (int j1 = 0; j1 < N2; ++j1) v[j1] = buf[(N1 * j1 + k2) * L + l];
+      for (int j1 = 0; j1 < N2; ++j1) v[j1] = buf[(N1 * j1 + k2) * L + j1 * P + l];
       dft<N2, S, T>(v);
 #pragma unroll
-      for (int k1 = 0; k1 < N2; ++k1) buf[(N1 * k1 + k2) * L + l] = v[k1];
+      for (int k1 = 0; k1 < N2; ++k1) buf[(N1 * k1 + k2) * L + k1 * P + l] = v[k1];
     }
     __syncthreads();
   }

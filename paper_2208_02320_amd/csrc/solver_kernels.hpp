@@ -38,12 +38,24 @@ namespace hh {
 // LDS budget of one tile.  y/z passes: at least 4 kx columns per tile so
 // that every tile row is a whole number of 64-byte sectors (no partial
 // writes); x pass: full spectrum rows.
-inline constexpr int kLdsTile = 24 * 1024;
-inline constexpr int kLdsTileYZ = 48 * 1024;
+#ifndef HH_LDS_TILE_X
+#define HH_LDS_TILE_X (24 * 1024)
+#endif
+#ifndef HH_LDS_TILE_YZ
+#define HH_LDS_TILE_YZ (48 * 1024)
+#endif
+inline constexpr int kLdsTile = HH_LDS_TILE_X;
+inline constexpr int kLdsTileYZ = HH_LDS_TILE_YZ;
 
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
 constexpr int maxi(int a, int b) { return a > b ? a : b; }
+// LDS padding (complex words per block of N1 tile rows): when successive
+// blocks would start on the same bank (64 banks of 4 bytes), shift each by
+// one row so that the second DFT step of a wave spreads over the banks.
+constexpr int lds_pad(int n1, int n2, int L, int cb) {
+  return (n2 > 1 && (n1 * L * (cb / 4)) % 64 == 0) ? L : 0;
+}
 
 template <int N, class T>
 struct AxisCfg {
@@ -51,8 +63,9 @@ struct AxisCfg {
   static constexpr int CB = int(sizeof(cx<T>));
   static constexpr int M = clampi(kLdsTileYZ / (N * 6 * CB), CB == 8 ? 4 : 2, 16);
   static constexpr int L = 6 * M;
+  static constexpr int P = lds_pad(N1, N2, L, CB);
   static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);
-  static constexpr int LDS = (N * L + N) * CB;
+  static constexpr int LDS = (N * L + N2 * P + N) * CB;
 };
 
 template <int N, class T>
@@ -61,8 +74,9 @@ struct XCfg {
   static constexpr int CB = int(sizeof(cx<T>));
   static constexpr int R = clampi(kLdsTile / (N * 3 * CB), 1, 32);
   static constexpr int L = 3 * R;
+  static constexpr int P = lds_pad(N1, N2, L, CB);
   static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);
-  static constexpr int LDS = (N * L + N) * CB;
+  static constexpr int LDS = (N * L + N2 * P + N) * CB;
 };
 
 // ---------------------------------------------------------------------------
@@ -187,7 +201,7 @@ __device__ __forceinline__ cx<T>* cptr(void* p, long long off) {
 // global loads into registers and only then writes LDS, so a wave keeps
 // many requests in flight; LDS row r holds `rowU` 16-byte units.
 // ---------------------------------------------------------------------------
-template <int ROWS, int ROWU, int THREADS, class RowMap>
+template <int ROWS, int ROWU, int THREADS, int N1, int PU, class RowMap>
 __device__ __forceinline__ void tile_load(uint4* __restrict__ lds, const uint4* __restrict__ src, int validU,
                                           long long gstride, RowMap map) {
   constexpr int TOTAL = ROWS * ROWU, KMAX = (TOTAL + THREADS - 1) / THREADS;
@@ -202,11 +216,12 @@ __device__ __forceinline__ void tile_load(uint4* __restrict__ lds, const uint4* 
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     const int idx = threadIdx.x + k * THREADS;
-    if (TOTAL % THREADS == 0 || idx < TOTAL) lds[idx] = v[k];
+    const int r = idx / ROWU;
+    if (TOTAL % THREADS == 0 || idx < TOTAL) lds[idx + (PU ? (r / N1) * PU : 0)] = v[k];
   }
 }
 
-template <int ROWS, int ROWU, int THREADS, class RowMap>
+template <int ROWS, int ROWU, int THREADS, int N1, int PU, class RowMap>
 __device__ __forceinline__ void tile_store(const uint4* __restrict__ lds, uint4* __restrict__ dst, int validU,
                                            long long gstride, RowMap map) {
   constexpr int TOTAL = ROWS * ROWU, KMAX = (TOTAL + THREADS - 1) / THREADS;
@@ -214,7 +229,8 @@ __device__ __forceinline__ void tile_store(const uint4* __restrict__ lds, uint4*
   for (int k = 0; k < KMAX; ++k) {
     const int idx = threadIdx.x + k * THREADS;
     const int r = idx / ROWU, j = idx - r * ROWU;
-    if ((TOTAL % THREADS == 0 || idx < TOTAL) && j < validU) dst[(long long)map(r) * gstride + j] = lds[idx];
+    if ((TOTAL % THREADS == 0 || idx < TOTAL) && j < validU)
+      dst[(long long)map(r) * gstride + j] = lds[idx + (PU ? (r / N1) * PU : 0)];
   }
 }
 
@@ -231,7 +247,7 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g)
   using Cf = AxisCfg<N, T>;
   constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS;
   constexpr int CB = Cf::CB;
-  constexpr int M = Cf::M, L = 6 * M, ROWU = L * CB / 16;
+  constexpr int M = Cf::M, L = 6 * M, ROWU = L * CB / 16, P = Cf::P, PU = P * CB / 16;
   constexpr int KT = (N * M + TH - 1) / TH;  // (z, kx) tasks per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -280,7 +296,7 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g)
       const int kxl = task % M, z = task / M, kx = kx0 + kxl;
       if (task < ntask && kxl >= mk) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) buf[z * L + kxl * 6 + c] = cx<T>{T(0), T(0)};
+        for (int c = 0; c < 6; ++c) buf[lds_at<N1, P>(z, L) + kxl * 6 + c] = cx<T>{T(0), T(0)};
       } else if (task < ntask) {
         cx<T> a[3];
         if constexpr (MODE == kZInvCg) {
@@ -299,12 +315,12 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g)
         cx<T> e[6];
         expand_sym(n, a, e);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) buf[z * L + kxl * 6 + c] = e[c];
+        for (int c = 0; c < 6; ++c) buf[lds_at<N1, P>(z, L) + kxl * 6 + c] = e[c];
       }
     }
     __syncthreads();
-    fft_nat2perm<N1, N2, +1, T>(buf, L, tw);
-    tile_store<N, ROWU, TH>(reinterpret_cast<const uint4*>(buf), tile_g, validU, gstride,
+    fft_nat2perm<N1, N2, +1, T, P>(buf, L, tw);
+    tile_store<N, ROWU, TH, N1, PU>(reinterpret_cast<const uint4*>(buf), tile_g, validU, gstride,
                             [](int pos) { return perm_idx<N1, N2>(pos); });
   } else {
     // prefetch the residual for the epilogue together with the tile
@@ -321,9 +337,10 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g)
         }
       }
     }
-    tile_load<N, ROWU, TH>(reinterpret_cast<uint4*>(buf), tile_g, validU, gstride, [](int r) { return r; });
+    tile_load<N, ROWU, TH, N1, PU>(reinterpret_cast<uint4*>(buf), tile_g, validU, gstride,
+                                   [](int r) { return r; });
     __syncthreads();
-    fft_nat2perm<N1, N2, -1, T>(buf, L, tw);
+    fft_nat2perm<N1, N2, -1, T, P>(buf, L, tw);
     const T alpha = T(st->alpha);
     const T g1 = T(0.5 / g.ref_mu);
     const T g2 = T((g.ref_lam + g.ref_mu) / (g.ref_lam + 2.0 * g.ref_mu));
@@ -336,7 +353,7 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g)
         const int kz = perm_idx<N1, N2>(pos);
         cx<T> sg[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) sg[c] = buf[pos * L + kxl * 6 + c];
+        for (int c = 0; c < 6; ++c) sg[c] = buf[lds_at<N1, P>(pos, L) + kxl * 6 + c];
         T n[3];
         const bool live = unit_k<T>(g, kx, y, kz, n);
         cx<T> t[3];
@@ -380,7 +397,7 @@ template <int N, class T, int S>
 __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_ypass(GroupArgs g) {
   using Cf = AxisCfg<N, T>;
   constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS, CB = Cf::CB;
-  constexpr int M = Cf::M, L = 6 * M, ROWU = L * CB / 16;
+  constexpr int M = Cf::M, L = 6 * M, ROWU = L * CB / 16, P = Cf::P, PU = P * CB / 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + N;
@@ -395,10 +412,11 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_ypass(GroupArgs g)
                                            ((long long)z * g.ny * g.hxp + kx0) * 6);
   const long long gstride = (long long)g.hxp * 6 * CB / 16;
   fill_twiddles<N, T>(tw);
-  tile_load<N, ROWU, TH>(reinterpret_cast<uint4*>(buf), tile_g, validU, gstride, [](int r) { return r; });
+  tile_load<N, ROWU, TH, N1, PU>(reinterpret_cast<uint4*>(buf), tile_g, validU, gstride,
+                                 [](int r) { return r; });
   __syncthreads();
-  fft_nat2perm<N1, N2, S, T>(buf, L, tw);
-  tile_store<N, ROWU, TH>(reinterpret_cast<const uint4*>(buf), tile_g, validU, gstride,
+  fft_nat2perm<N1, N2, S, T, P>(buf, L, tw);
+  tile_store<N, ROWU, TH, N1, PU>(reinterpret_cast<const uint4*>(buf), tile_g, validU, gstride,
                           [](int pos) { return perm_idx<N1, N2>(pos); });
 }
 
@@ -409,7 +427,7 @@ template <int N, class T, int MODE>
 __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
   using Cf = XCfg<N, T>;
   constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS;
-  constexpr int R = Cf::R, L = 3 * R;
+  constexpr int R = Cf::R, L = 3 * R, P = Cf::P;
   constexpr int HX = N / 2 + 1, HXP = (HX + 3) / 4 * 4;  // spectrum row length and pitch
   constexpr int NU = R * HX * 3;                          // (row, kx, pair) units per tile
   constexpr int KX = (NU + TH - 1) / TH;
@@ -429,6 +447,16 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
   cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride) + (long long)r0 * HXP * 6;
   cpair<T>* tmpp = reinterpret_cast<cpair<T>*>(tmp);  // 3 pairs per frequency
 
+  // issue this tile's global loads first: nothing they need waits on memory
+  cpair<T> v[KX];
+  if constexpr (MODE != kXRhs) {
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+      const int f = threadIdx.x + k * TH;
+      const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
+      if ((NU % TH == 0 || f < NU) && rl < nr) v[k] = tmpp[(rl * HXP + kx) * 3 + pr];
+    }
+  }
   fill_twiddles<N, T>(tw);
   if (threadIdx.x < kMaxPhase) {
     const int i = threadIdx.x < it.nphase ? threadIdx.x : 0;
@@ -450,13 +478,6 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
 
   if constexpr (MODE != kXRhs) {
     // unpack: complex line (pair) = A + i B with A, B the spectra of two real lines
-    cpair<T> v[KX];
-#pragma unroll
-    for (int k = 0; k < KX; ++k) {
-      const int f = threadIdx.x + k * TH;
-      const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
-      if ((NU % TH == 0 || f < NU) && rl < nr) v[k] = tmpp[(rl * HXP + kx) * 3 + pr];
-    }
 #pragma unroll
     for (int k = 0; k < KX; ++k) {
       const int f = threadIdx.x + k * TH;
@@ -466,15 +487,15 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
         if (rl >= nr) A = B = cx<T>{T(0), T(0)};
         const int l = rl * 3 + pr;
         if (kx == 0 || 2 * kx == N) {
-          buf[kx * L + l] = cx<T>{A.re, B.re};
+          buf[lds_at<N1, P>(kx, L) + l] = cx<T>{A.re, B.re};
         } else {
-          buf[kx * L + l] = cx<T>{A.re - B.im, A.im + B.re};
-          buf[(N - kx) * L + l] = cx<T>{A.re + B.im, B.re - A.im};
+          buf[lds_at<N1, P>(kx, L) + l] = cx<T>{A.re - B.im, A.im + B.re};
+          buf[lds_at<N1, P>(N - kx, L) + l] = cx<T>{A.re + B.im, B.re - A.im};
         }
       }
     }
     __syncthreads();
-    fft_nat2perm<N1, N2, +1, T>(buf, L, tw);
+    fft_nat2perm<N1, N2, +1, T, P>(buf, L, tw);
   } else {
     __syncthreads();
   }
@@ -486,6 +507,9 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
   for (int c = 0; c < 6; ++c) E[c] = T(g.loads[sd.load][c]);
   const int x0 = it.region[0], y0 = it.region[1], z0 = it.region[2];
   const int x1 = it.region[3], y1 = it.region[4], z1 = it.region[5];
+  // Whole-box region: sum p = 0 (p is zero-mean) and the row sums of sigma
+  // are the kx = 0 outputs of the forward transform, so no per-voxel sums.
+  const bool whole = x0 == 0 && x1 == N && y0 == 0 && y1 == g.ny && z0 == 0 && z1 == g.nz;
   double acc[kPartX];
 #pragma unroll
   for (int i = 0; i < kPartX; ++i) acc[i] = 0.0;
@@ -504,7 +528,7 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
     } else {
 #pragma unroll
       for (int pr = 0; pr < 3; ++pr) {
-        const cx<T> v = buf[pos * L + rl * 3 + pr];
+        const cx<T> v = buf[lds_at<N1, P>(pos, L) + rl * 3 + pr];
         p[2 * pr] = v.re * invV;
         p[2 * pr + 1] = v.im * invV;
       }
@@ -553,12 +577,13 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
         for (int c = 0; c < 6; ++c) ss += (c < 3 ? 1.0 : 2.0) * double(sg[c]) * sg[c];
         acc[0] += ss;
       } else if constexpr (MODE == kXCg) {
-        double ps = 0.0;
+        // p : C : p >= 0 per voxel, formed in T and accumulated in double
+        T ps = T(0);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) ps += (c < 3 ? 1.0 : 2.0) * double(p[c]) * sg[c];
-        acc[0] += ps;
+        for (int c = 0; c < 6; ++c) ps += (c < 3 ? T(1) : T(2)) * p[c] * sg[c];
+        acc[0] += double(ps);
       }
-      if (x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1) {
+      if (!whole && x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
           acc[1 + c] += double(p[c]);
@@ -567,23 +592,48 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
       }
     }
 #pragma unroll
-    for (int pr = 0; pr < 3; ++pr) buf[pos * L + rl * 3 + pr] = cx<T>{sg[2 * pr], sg[2 * pr + 1]};
+    for (int pr = 0; pr < 3; ++pr) buf[lds_at<N1, P>(pos, L) + rl * 3 + pr] = cx<T>{sg[2 * pr], sg[2 * pr + 1]};
   }
   __syncthreads();
-  fft_perm2nat<N1, N2, -1, T>(buf, L, tw);
+  fft_perm2nat<N1, N2, -1, T, P>(buf, L, tw);
+  if (whole && threadIdx.x < 64) {
+    // tile sums of sigma from the kx = 0 outputs (lines: row * 3 + pair)
+    double sre[3] = {0.0, 0.0, 0.0}, sim[3] = {0.0, 0.0, 0.0};
+    for (int l = threadIdx.x; l < 3 * nr; l += 64) {
+      const cx<T> z0v = buf[lds_at<N1, P>(0, L) + l];
+      const int pr = l % 3;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        sre[q] += pr == q ? double(z0v.re) : 0.0;
+        sim[q] += pr == q ? double(z0v.im) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double a = wave_sum(sre[q]), b = wave_sum(sim[q]);
+      if (threadIdx.x == 0) {
+        acc[7 + 2 * q] = a;
+        acc[8 + 2 * q] = b;
+      }
+    }
+    if (threadIdx.x == 0 && MODE == kXFp) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[1 + c] = double(nr) * N * double(E[c]);
+    }
+  }
   for (int f = threadIdx.x; f < NU; f += TH) {
     const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
     if (rl >= nr) continue;
     const int l = rl * 3 + pr;
-    const cx<T> zk = buf[kx * L + l];
-    const cx<T> zm = buf[((N - kx) % N) * L + l];
+    const cx<T> zk = buf[lds_at<N1, P>(kx, L) + l];
+    const cx<T> zm = buf[lds_at<N1, P>((N - kx) % N, L) + l];
     cpair<T> o;
     o.a = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
     o.b = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
     tmpp[(rl * HXP + kx) * 3 + pr] = o;
   }
   __syncthreads();
-  if constexpr (TH * kPartX * 8 <= N * L * int(sizeof(cx<T>))) {
+  if constexpr (TH * kPartX * 8 <= (N * L + N2 * P) * int(sizeof(cx<T>))) {
     block_sum_lds<kPartX, TH>(acc, reinterpret_cast<double*>(buf));
   } else {
     block_sum<kPartX>(acc, reinterpret_cast<double*>(buf));
