@@ -165,6 +165,77 @@ int hh_hierarchical(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, 
                     const hh_opts *opts, double C_out[36], double *C_sub, hh_report *report);
 
 /*
+ * Partition + padding of the two-level scheme (Sec. 3; Sec. 4, Fig. 4) on
+ * its own: copies every n_sub^3 block of the [nz][ny][nx] image, extended by
+ * `pad` voxels of surrounding material (periodic wrap at the image edge),
+ * into pack_device as (nz/n)(ny/n)(nx/n) consecutive boxes of
+ * (n_sub + 2 pad)^3 bytes, blocks in C order.  pack_device: device buffer
+ * owned by the caller of at least that size.
+ */
+int hh_gather_subimages(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, int labels_on_device,
+                        int n_sub, int pad, uint8_t *pack_device);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the subimage stiffness (an addition to the paper's
+ * method: it replaces the FFT solve of Sec. 4 for subimages a gate accepts,
+ * and the FFT solve stays the fallback and the judge of its error).
+ * A 3-D CNN maps the one-hot phase labels of an n^3 subimage to its 21
+ * stiffness components: four 3x3x3 stride-2 convolutions (8 -> 32 -> 32 ->
+ * 64 -> 64 channels, ReLU), a global mean and a linear map to 21 outputs,
+ * trained on FFT-solver labels.  Convolutions run on BF16 MFMA with FP32
+ * accumulation; parameters are FP32.
+ *
+ * Inputs of every call: `batch` boxes of box^3 uint8 labels stored back to
+ * back; the network reads the n^3 window at (offset, offset, offset) of each
+ * box (n = input edge given at creation, offset + n <= box).
+ * Outputs are "normalized" (y = (C21 - mean) / scale per component, see
+ * hh_net_set_scaling) except hh_net_predict, which returns C21 in GPa.
+ * ------------------------------------------------------------------------ */
+typedef struct hh_net hh_net;
+
+/* New network for nphase (1..8) phases and input edge n (multiple of 16,
+ * <= 256); He-normal weights from `seed`, identity scaling. */
+int hh_net_create(hh_ctx *ctx, int nphase, int n, unsigned long long seed, hh_net **net);
+void hh_net_destroy(hh_net *net);
+long long hh_net_num_params(const hh_net *net);
+/* FP32 parameters (host copies); setting also resets the optimizer state. */
+int hh_net_get_params(hh_ctx *ctx, hh_net *net, float *params, long long n);
+int hh_net_set_params(hh_ctx *ctx, hh_net *net, const float *params, long long n);
+/* Output scaling: C21 = mean + scale * y (scale > 0). */
+int hh_net_set_scaling(hh_ctx *ctx, hh_net *net, const double mean[21], const double scale[21]);
+int hh_net_get_scaling(const hh_net *net, double mean[21], double scale[21]);
+/* Normalized outputs y (host, batch x 21). */
+int hh_net_forward(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_on_device, int batch, int box,
+                   int offset, float *out);
+/* Mean squared error against normalized targets (host, batch x 21) and its
+ * gradient w.r.t. every parameter (host, hh_net_num_params floats; may be
+ * NULL).  Parameters are not changed. */
+int hh_net_gradient(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_on_device, int batch, int box,
+                    int offset, const float *target, float *loss, float *grad);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on that loss. */
+int hh_net_train_step(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_on_device, int batch, int box,
+                      int offset, const float *target, int target_on_device, float lr, float *loss);
+/* Predicted stiffness C21 in GPa (host, batch x 21). */
+int hh_net_predict(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_on_device, int batch, int box,
+                   int offset, double *C21);
+
+/*
+ * Two-level scheme with the surrogate: the subimage stiffnesses come from
+ * the network(s) on the n_sub^3 core of every padded box, a gate sends an
+ * item to the FFT solver (the hh_hierarchical path) when the mean prediction
+ * is not positive definite, leaves the Voigt-Reuss bracket of the core's
+ * phase fractions by more than bound_tol (relative, Mandel norm), or - with
+ * two networks - when the two predictions differ by more than spread_tol
+ * (relative).  net_b may be NULL.  fallback: (N/n)^3 flags (may be NULL);
+ * C_sub as in hh_hierarchical.  report.items counts subimages,
+ * report.voxel_iters the fallback and level-2 solves.
+ */
+int hh_hierarchical_surrogate(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, int labels_on_device,
+                              const hh_phase *phases, int nphase, int n_sub, int pad, hh_net *net_a,
+                              hh_net *net_b, double spread_tol, double bound_tol, const hh_opts *opts,
+                              double C_out[36], double *C_sub, int *fallback, hh_report *report);
+
+/*
  * Least-squares fit M(n) = M_inf + slope / n of each of the 36 entries over
  * m >= 2 distinct subimage sizes (Sec. 5, eq_fit_power_law).  C: m x 36
  * (row i belongs to n[i]).  Host only.

@@ -1,0 +1,75 @@
+"""FP64 reference of the surrogate's acceptance gate.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The gate is not part of the paper: it decides when a network prediction of
+a subimage stiffness may replace the FFT solve of Sec. 4.  Written out from
+its definition, with eigenvalues (the kernel uses Cholesky pivots):
+
+* the prediction is the mean of the two networks' outputs (or the one
+  output);
+* in Mandel form M(C) = D C D, D = diag(1, 1, 1, sqrt2, sqrt2, sqrt2), the
+  prediction must be positive definite;
+* with t = bound_tol * ||M(C_a)||_F, both M(C_V) - M(C) + t I and
+  M(C) - M(C_R) + t I must be positive definite, where C_V and C_R are the
+  Voigt and Reuss stiffnesses of the subimage's phase fractions (the
+  bracket of Sec. 1's classical bounds);
+* with two networks, ||M(C_a) - M(C_b)||_F <= spread_tol ||M(C_a)||_F.
+
+Any failed condition flags the item for the FFT solver.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import bounds
+from .hier import from21
+
+_D = np.diag([1.0, 1.0, 1.0, np.sqrt(2.0), np.sqrt(2.0), np.sqrt(2.0)])
+
+
+def mandel(C):
+    return _D @ np.asarray(C, dtype=np.float64) @ _D
+
+
+def _pd(A):
+    return bool(np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0.0)
+
+
+def gate(c21a, c21b, CV, CR, spread_tol, bound_tol):
+    """True when the item goes to the FFT solver.  c21a/c21b: 21 upper-
+    triangle components (c21b may be None); CV, CR: 6x6 Voigt matrices."""
+    Ma = mandel(from21(c21a))
+    Mb = Ma if c21b is None else mandel(from21(c21b))
+    M = 0.5 * (Ma + Mb)
+    nrm = np.linalg.norm(Ma)
+    if not _pd(M):
+        return True
+    t = bound_tol * nrm
+    if not _pd(mandel(CV) - M + t * np.eye(6)):
+        return True
+    if not _pd(M - mandel(CR) + t * np.eye(6)):
+        return True
+    if c21b is not None and np.linalg.norm(Ma - Mb) > spread_tol * nrm:
+        return True
+    return False
+
+
+def gate_margin(c21a, c21b, CV, CR, bound_tol):
+    """Smallest eigenvalue over the three definiteness tests, relative to
+    ||M(C_a)||_F: items with a margin near zero may go either way."""
+    Ma = mandel(from21(c21a))
+    Mb = Ma if c21b is None else mandel(from21(c21b))
+    M = 0.5 * (Ma + Mb)
+    nrm = np.linalg.norm(Ma)
+    t = bound_tol * nrm
+    ev = [np.linalg.eigvalsh(M).min(),
+          np.linalg.eigvalsh(mandel(CV) - M + t * np.eye(6)).min(),
+          np.linalg.eigvalsh(M - mandel(CR) + t * np.eye(6)).min()]
+    return min(abs(e) for e in ev) / nrm
+
+
+def core_bounds(box_labels, pad, n, phases):
+    """Voigt and Reuss stiffness of the n^3 core of a padded box."""
+    core = np.asarray(box_labels)[pad:pad + n, pad:pad + n, pad:pad + n]
+    return bounds.voigt_reuss(core, phases)

@@ -1,0 +1,432 @@
+// Host side of the CNN surrogate: parameters, training step, inference, gate.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "cnn.hpp"
+#include "cnn_kernels.hpp"
+
+using namespace hh::cnn;
+
+namespace {
+
+constexpr int kLayers = 4;
+constexpr int kCin[kLayers] = {8, 32, 32, 64};
+constexpr int kCout[kLayers] = {32, 32, 64, 64};
+constexpr int kFeat = 64, kOut = 21;
+
+struct Buf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct hh_net {
+  int device = 0;
+  int nphase = 0;
+  int n = 0;  // input edge
+  long long woff[kLayers], boff[kLayers], fcw_off, fcb_off, nparam;
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  __bf16* W[kLayers] = {};
+  __bf16* Wt[kLayers] = {};
+  double mean[kOut], scale[kOut];
+  double *d_mean = nullptr, *d_scale = nullptr;
+  long long step = 0;
+  int cap = 0;  // batch capacity of the activation buffers
+  __bf16* x0 = nullptr;
+  __bf16* a[kLayers] = {};
+  float* ga[kLayers] = {};  // gradient w.r.t. output of layer l
+  float *out = nullptr, *tgt = nullptr, *hw = nullptr, *loss = nullptr;
+  float* part = nullptr;
+  size_t part_n = 0;
+  float* pbias = nullptr;
+};
+
+namespace {
+
+int edge(const hh_net* net, int l) { return net->n >> l; }  // input edge of layer l
+
+void free_acts(hh_net* net) {
+  (void)hipFree(net->x0);
+  net->x0 = nullptr;
+  for (int l = 0; l < kLayers; ++l) {
+    (void)hipFree(net->a[l]);
+    (void)hipFree(net->ga[l]);
+    net->a[l] = nullptr;
+    net->ga[l] = nullptr;
+  }
+  (void)hipFree(net->out);
+  (void)hipFree(net->tgt);
+  (void)hipFree(net->hw);
+  (void)hipFree(net->loss);
+  (void)hipFree(net->part);
+  (void)hipFree(net->pbias);
+  net->out = net->tgt = net->hw = net->loss = net->part = net->pbias = nullptr;
+  net->cap = 0;
+}
+
+template <class T>
+T* dalloc(hh_ctx* ctx, size_t count) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(count * sizeof(T), 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(ctx, HH_ENOMEM, "surrogate: device allocation failed");
+  }
+  return static_cast<T*>(p);
+}
+
+int wgrad_chunk(long long total) {
+  long long c = (total + 127) / 128;
+  c = (c + 31) / 32 * 32;
+  return int(std::max<long long>(c, 32));
+}
+
+void ensure_acts(hh_ctx* ctx, hh_net* net, int batch) {
+  if (batch <= net->cap) return;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  free_acts(net);
+  const long long n = net->n;
+  net->x0 = dalloc<__bf16>(ctx, size_t(batch) * n * n * n * 8);
+  size_t pmax = 0, bmax = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    const long long Do = edge(net, l) / 2, nv = Do * Do * Do;
+    net->a[l] = dalloc<__bf16>(ctx, size_t(batch) * nv * kCout[l]);
+    net->ga[l] = dalloc<float>(ctx, size_t(batch) * nv * kCout[l]);
+    const long long total = nv * batch;
+    const long long nch = (total + wgrad_chunk(total) - 1) / wgrad_chunk(total);
+    pmax = std::max<size_t>(pmax, size_t(nch) * 27 * kCout[l] * kCin[l]);
+    bmax = std::max<size_t>(bmax, size_t(nch) * kCout[l]);
+  }
+  net->out = dalloc<float>(ctx, size_t(batch) * kOut);
+  net->tgt = dalloc<float>(ctx, size_t(batch) * kOut);
+  net->hw = dalloc<float>(ctx, size_t(batch) * (kOut * kFeat + kOut));
+  net->loss = dalloc<float>(ctx, size_t(batch));
+  pmax = std::max<size_t>(pmax, size_t(batch) * (kOut * kFeat + kOut));
+  net->part = dalloc<float>(ctx, pmax);
+  net->part_n = pmax;
+  net->pbias = dalloc<float>(ctx, bmax);
+  net->cap = batch;
+}
+
+void cast_all(hh_ctx* ctx, hh_net* net) {
+  for (int l = 0; l < kLayers; ++l)
+    k_cast_weights<<<256, 256, 0, ctx->stream>>>(net->p + net->woff[l], kCin[l], kCout[l], net->W[l], net->Wt[l]);
+  HIPCHK(hipGetLastError());
+}
+
+template <int CI, int CO>
+void conv_fwd(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float* b, __bf16* Y, int D, int batch) {
+  const long long nvo = (long long)(D / 2) * (D / 2) * (D / 2) * batch;
+  k_conv_fwd<CI, CO><<<unsigned((nvo + 63) / 64), 256, 0, ctx->stream>>>(X, W, b, Y, D, batch);
+}
+
+void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o) {
+  const long long n = net->n, nv = n * n * n;
+  k_onehot<<<unsigned(std::min<long long>((nv * batch + 255) / 256, 65536)), 256, 0, ctx->stream>>>(
+      labels, (long long)box * box * box, box, o, net->n, batch, net->x0);
+  conv_fwd<8, 32>(ctx, net->x0, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
+  conv_fwd<32, 32>(ctx, net->a[0], net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
+  conv_fwd<32, 64>(ctx, net->a[1], net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
+  conv_fwd<64, 64>(ctx, net->a[2], net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch);
+  HIPCHK(hipGetLastError());
+}
+
+template <int CI, int CO>
+void conv_bwd(hh_ctx* ctx, hh_net* net, int l, const __bf16* X, int batch, float* dX) {
+  const int D = edge(net, l), Do = D / 2;
+  const long long total = (long long)Do * Do * Do * batch;
+  const int chunk = wgrad_chunk(total);
+  const int nch = int((total + chunk - 1) / chunk);
+  k_conv_wgrad<CI, CO><<<dim3(nch, 27), 256, 0, ctx->stream>>>(net->ga[l], net->a[l], X, net->part, net->pbias, D,
+                                                               batch, chunk);
+  const long long nw = 27LL * CO * CI;
+  k_reduce_parts<<<unsigned(std::min<long long>((nw + 255) / 256, 4096)), 256, 0, ctx->stream>>>(
+      net->part, nch, nw, net->g + net->woff[l]);
+  k_reduce_parts<<<1, 256, 0, ctx->stream>>>(net->pbias, nch, CO, net->g + net->boff[l]);
+  if constexpr (CI >= 16) {
+    if (dX) {
+      const long long ncls = (long long)(D / 2) * (D / 2) * (D / 2) * batch;
+      for (int c = 0; c < 8; ++c)
+        k_conv_dgrad<CI, CO><<<unsigned((ncls + 63) / 64), 256, 0, ctx->stream>>>(net->ga[l], net->a[l], net->Wt[l],
+                                                                                 dX, D, batch, c);
+    }
+  }
+  HIPCHK(hipGetLastError());
+}
+
+// loss and gradient into net->g; returns the mean squared error
+float backward(hh_ctx* ctx, hh_net* net, int batch) {
+  const int V = edge(net, 3) / 2;
+  const int nvl = V * V * V;
+  const float inv = 1.0f / float(batch * kOut);
+  k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], nvl, net->p + net->fcw_off, net->p + net->fcb_off, net->out,
+                                        net->tgt, net->ga[3], net->hw, net->loss, inv);
+  k_reduce_parts<<<8, 256, 0, ctx->stream>>>(net->hw, batch, kOut * kFeat + kOut, net->g + net->fcw_off);
+  conv_bwd<64, 64>(ctx, net, 3, net->a[2], batch, net->ga[2]);
+  conv_bwd<32, 64>(ctx, net, 2, net->a[1], batch, net->ga[1]);
+  conv_bwd<32, 32>(ctx, net, 1, net->a[0], batch, net->ga[0]);
+  conv_bwd<8, 32>(ctx, net, 0, net->x0, batch, nullptr);
+  std::vector<float> lh(batch);
+  HIPCHK(hipMemcpyAsync(lh.data(), net->loss, sizeof(float) * batch, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double s = 0.0;
+  for (float x : lh) s += x;
+  return float(s);
+}
+
+const unsigned char* labels_to_device(hh_ctx* ctx, const uint8_t* labels, int on_device, long long bytes) {
+  if (on_device) return labels;
+  auto* d = static_cast<unsigned char*>(ws(ctx, "net_labels", size_t(bytes)));
+  HIPCHK(hipMemcpyAsync(d, labels, size_t(bytes), hipMemcpyHostToDevice, ctx->stream));
+  return d;
+}
+
+void check_input(hh_ctx* ctx, hh_net* net, int batch, int box, int o) {
+  if (!net) fail(ctx, HH_EINVAL, "null network");
+  if (batch < 1) fail(ctx, HH_EINVAL, "batch must be >= 1");
+  if (o < 0 || o + net->n > box) fail(ctx, HH_EINVAL, "input window outside the boxes");
+}
+
+}  // namespace
+
+void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
+                           double* c21) {
+  const int step = 64;
+  for (int b0 = 0; b0 < batch; b0 += step) {
+    const int nb = std::min(step, batch - b0);
+    ensure_acts(ctx, net, step);
+    forward(ctx, net, labels + (long long)b0 * box * box * box, nb, box, o);
+    const int V = edge(net, 3) / 2;
+    k_head<<<nb, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->p + net->fcw_off, net->p + net->fcb_off, net->out,
+                                       nullptr, nullptr, nullptr, nullptr, 0.0f);
+    k_denorm<<<(nb * kOut + 255) / 256, 256, 0, ctx->stream>>>(net->out, net->d_mean, net->d_scale, nb,
+                                                               c21 + (long long)b0 * kOut);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+void hh_launch_bounds(const unsigned char* labels, int nitems, int box, int o, int n, int nphase, const double* Cp21,
+                      const double* Sp21, double* cv21, double* cr21, hipStream_t st) {
+  k_phase_bounds<<<nitems, 256, 0, st>>>(labels, box, o, n, nphase, Cp21, Sp21, cv21, cr21);
+}
+
+void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,
+                    double spread_tol, double bound_tol, int* flag, hipStream_t st) {
+  k_gate<<<(nitems + 63) / 64, 64, 0, st>>>(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, flag);
+}
+
+int hh_net_input_size(const hh_net* net) { return net ? net->n : 0; }
+
+extern "C" {
+
+int hh_net_create(hh_ctx* ctx, int nphase, int n, unsigned long long seed, hh_net** out) {
+  return guarded(ctx, [&]() -> int {
+    if (!out) fail(ctx, HH_EINVAL, "null output");
+    *out = nullptr;
+    if (nphase < 1 || nphase > 8) fail(ctx, HH_EINVAL, "the surrogate takes 1..8 phases");
+    if (n < 16 || n % 16 != 0 || n > 256) fail(ctx, HH_EINVAL, "input edge must be a multiple of 16 in [16, 256]");
+    auto* net = new hh_net();
+    net->device = ctx->device;
+    net->nphase = nphase;
+    net->n = n;
+    long long off = 0;
+    for (int l = 0; l < kLayers; ++l) {
+      net->woff[l] = off;
+      off += 27LL * kCout[l] * kCin[l];
+      net->boff[l] = off;
+      off += kCout[l];
+    }
+    net->fcw_off = off;
+    off += kOut * kFeat;
+    net->fcb_off = off;
+    off += kOut;
+    net->nparam = off;
+    try {
+      net->p = dalloc<float>(ctx, off);
+      net->g = dalloc<float>(ctx, off);
+      net->m = dalloc<float>(ctx, off);
+      net->v = dalloc<float>(ctx, off);
+      for (int l = 0; l < kLayers; ++l) {
+        net->W[l] = dalloc<__bf16>(ctx, 27LL * kCout[l] * kCin[l]);
+        net->Wt[l] = dalloc<__bf16>(ctx, 27LL * kCout[l] * kCin[l]);
+      }
+      net->d_mean = dalloc<double>(ctx, kOut);
+      net->d_scale = dalloc<double>(ctx, kOut);
+    } catch (...) {
+      hh_net_destroy(net);
+      throw;
+    }
+    // He initialisation (fan-in of the real input channels); padded input
+    // channels of the first layer start (and stay) at zero
+    std::vector<float> h(off, 0.0f);
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < kLayers; ++l) {
+      const int cin_real = l == 0 ? nphase : kCin[l];
+      std::normal_distribution<float> nd(0.0f, std::sqrt(2.0f / (27.0f * cin_real)));
+      for (int t = 0; t < 27; ++t)
+        for (int co = 0; co < kCout[l]; ++co)
+          for (int ci = 0; ci < kCin[l]; ++ci)
+            h[net->woff[l] + ((long long)t * kCout[l] + co) * kCin[l] + ci] = ci < cin_real ? nd(rng) : 0.0f;
+    }
+    std::normal_distribution<float> nf(0.0f, std::sqrt(1.0f / kFeat));
+    for (int i = 0; i < kOut * kFeat; ++i) h[net->fcw_off + i] = nf(rng);
+    for (int i = 0; i < kOut; ++i) {
+      net->mean[i] = 0.0;
+      net->scale[i] = 1.0;
+    }
+    HIPCHK(hipMemcpyAsync(net->p, h.data(), sizeof(float) * off, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemsetAsync(net->m, 0, sizeof(float) * off, ctx->stream));
+    HIPCHK(hipMemsetAsync(net->v, 0, sizeof(float) * off, ctx->stream));
+    HIPCHK(hipMemcpyAsync(net->d_mean, net->mean, sizeof(double) * kOut, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(net->d_scale, net->scale, sizeof(double) * kOut, hipMemcpyHostToDevice, ctx->stream));
+    cast_all(ctx, net);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *out = net;
+    return HH_OK;
+  });
+}
+
+void hh_net_destroy(hh_net* net) {
+  if (!net) return;
+  (void)hipSetDevice(net->device);
+  (void)hipDeviceSynchronize();
+  free_acts(net);
+  (void)hipFree(net->p);
+  (void)hipFree(net->g);
+  (void)hipFree(net->m);
+  (void)hipFree(net->v);
+  for (int l = 0; l < kLayers; ++l) {
+    (void)hipFree(net->W[l]);
+    (void)hipFree(net->Wt[l]);
+  }
+  (void)hipFree(net->d_mean);
+  (void)hipFree(net->d_scale);
+  delete net;
+}
+
+long long hh_net_num_params(const hh_net* net) { return net ? net->nparam : 0; }
+
+int hh_net_get_params(hh_ctx* ctx, hh_net* net, float* params, long long n) {
+  return guarded(ctx, [&]() -> int {
+    if (!net || !params || n != net->nparam) fail(ctx, HH_EINVAL, "parameter count mismatch");
+    HIPCHK(hipMemcpyAsync(params, net->p, sizeof(float) * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+  });
+}
+
+int hh_net_set_params(hh_ctx* ctx, hh_net* net, const float* params, long long n) {
+  return guarded(ctx, [&]() -> int {
+    if (!net || !params || n != net->nparam) fail(ctx, HH_EINVAL, "parameter count mismatch");
+    HIPCHK(hipMemcpyAsync(net->p, params, sizeof(float) * n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemsetAsync(net->m, 0, sizeof(float) * n, ctx->stream));
+    HIPCHK(hipMemsetAsync(net->v, 0, sizeof(float) * n, ctx->stream));
+    net->step = 0;
+    cast_all(ctx, net);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+  });
+}
+
+int hh_net_set_scaling(hh_ctx* ctx, hh_net* net, const double mean[21], const double scale[21]) {
+  return guarded(ctx, [&]() -> int {
+    if (!net || !mean || !scale) fail(ctx, HH_EINVAL, "null argument");
+    for (int i = 0; i < kOut; ++i) {
+      if (!(scale[i] > 0.0) || !std::isfinite(mean[i])) fail(ctx, HH_EINVAL, "scales must be positive");
+      net->mean[i] = mean[i];
+      net->scale[i] = scale[i];
+    }
+    HIPCHK(hipMemcpyAsync(net->d_mean, net->mean, sizeof(double) * kOut, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(net->d_scale, net->scale, sizeof(double) * kOut, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+  });
+}
+
+int hh_net_get_scaling(const hh_net* net, double mean[21], double scale[21]) {
+  if (!net || !mean || !scale) return HH_EINVAL;
+  for (int i = 0; i < kOut; ++i) {
+    mean[i] = net->mean[i];
+    scale[i] = net->scale[i];
+  }
+  return HH_OK;
+}
+
+int hh_net_forward(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_on_device, int batch, int box,
+                   int offset, float* out) {
+  return guarded(ctx, [&]() -> int {
+    check_input(ctx, net, batch, box, offset);
+    if (!labels || !out) fail(ctx, HH_EINVAL, "null argument");
+    const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
+    ensure_acts(ctx, net, batch);
+    forward(ctx, net, d, batch, box, offset);
+    const int V = edge(net, 3) / 2;
+    k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->p + net->fcw_off, net->p + net->fcb_off,
+                                          net->out, nullptr, nullptr, nullptr, nullptr, 0.0f);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, net->out, sizeof(float) * batch * kOut, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+  });
+}
+
+int hh_net_gradient(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_on_device, int batch, int box,
+                    int offset, const float* target, float* loss, float* grad) {
+  return guarded(ctx, [&]() -> int {
+    check_input(ctx, net, batch, box, offset);
+    if (!labels || !target) fail(ctx, HH_EINVAL, "null argument");
+    const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
+    ensure_acts(ctx, net, batch);
+    HIPCHK(hipMemcpyAsync(net->tgt, target, sizeof(float) * batch * kOut, hipMemcpyHostToDevice, ctx->stream));
+    forward(ctx, net, d, batch, box, offset);
+    const float l = backward(ctx, net, batch);
+    if (loss) *loss = l;
+    if (grad) {
+      HIPCHK(hipMemcpyAsync(grad, net->g, sizeof(float) * net->nparam, hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return HH_OK;
+  });
+}
+
+int hh_net_train_step(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_on_device, int batch, int box,
+                      int offset, const float* target, int target_on_device, float lr, float* loss) {
+  return guarded(ctx, [&]() -> int {
+    check_input(ctx, net, batch, box, offset);
+    if (!labels || !target || !(lr > 0.0f)) fail(ctx, HH_EINVAL, "bad argument");
+    const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
+    ensure_acts(ctx, net, batch);
+    HIPCHK(hipMemcpyAsync(net->tgt, target, sizeof(float) * batch * kOut,
+                          target_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+    forward(ctx, net, d, batch, box, offset);
+    const float l = backward(ctx, net, batch);
+    net->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, float(net->step)), c2 = 1.0f - std::pow(b2, float(net->step));
+    k_adam<<<unsigned(std::min<long long>((net->nparam + 255) / 256, 4096)), 256, 0, ctx->stream>>>(
+        net->p, net->g, net->m, net->v, net->nparam, lr, b1, b2, 1e-8f, c1, c2);
+    cast_all(ctx, net);
+    if (loss) *loss = l;
+    return HH_OK;
+  });
+}
+
+int hh_net_predict(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_on_device, int batch, int box,
+                   int offset, double* C21) {
+  return guarded(ctx, [&]() -> int {
+    check_input(ctx, net, batch, box, offset);
+    if (!labels || !C21) fail(ctx, HH_EINVAL, "null argument");
+    const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
+    auto* c = static_cast<double*>(ws(ctx, "net_c21", sizeof(double) * batch * kOut));
+    hh_net_predict_device(ctx, net, d, batch, box, offset, c);
+    HIPCHK(hipMemcpyAsync(C21, c, sizeof(double) * batch * kOut, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+  });
+}
+
+}  // extern "C"

@@ -12,58 +12,14 @@
 #include <vector>
 
 #include "../../include/hh.h"
+#include "cnn.hpp"
+#include "ctx.hpp"
 #include "hh_internal.hpp"
 #include "kernels.hpp"
 
 using namespace hh;
 
-struct hh_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  std::map<std::string, std::pair<void*, size_t>> bufs;
-  std::vector<hipEvent_t> evpool;
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-};
-
 namespace {
-
-struct Fail {
-  int code;
-};
-
-#define HIPCHK(expr)                                                                       \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess) {                                                                \
-      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                       \
-      throw Fail{e_ == hipErrorOutOfMemory ? HH_ENOMEM : HH_EDEVICE};                      \
-    }                                                                                      \
-  } while (0)
-
-[[noreturn]] void fail(hh_ctx* ctx, int code, const std::string& msg) {
-  ctx->err = msg;
-  throw Fail{code};
-}
-
-void* ws(hh_ctx* ctx, const std::string& name, size_t bytes) {
-  auto it = ctx->bufs.find(name);
-  if (it != ctx->bufs.end() && it->second.second >= bytes) return it->second.first;
-  if (it != ctx->bufs.end()) {
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    HIPCHK(hipFree(it->second.first));
-    ctx->bufs.erase(it);
-  }
-  void* p = nullptr;
-  const size_t sz = std::max<size_t>(bytes, 256);
-  hipError_t e = hipMalloc(&p, sz);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    fail(ctx, HH_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes for " + name + " failed");
-  }
-  ctx->bufs[name] = {p, sz};
-  return p;
-}
 
 int status_code(int s) {
   switch (s) {
@@ -399,26 +355,6 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
     }
   }
   return res;
-}
-
-int finish(hh_ctx* ctx, int rc) { return rc; }
-
-template <class F>
-int guarded(hh_ctx* ctx, F&& f) {
-  if (!ctx) return HH_EINVAL;
-  ctx->err.clear();
-  try {
-    HIPCHK(hipSetDevice(ctx->device));
-    return f();
-  } catch (const Fail& e) {
-    return e.code;
-  } catch (const std::exception& e) {
-    ctx->err = e.what();
-    return HH_EDEVICE;
-  } catch (...) {
-    ctx->err = "unknown error";
-    return HH_EDEVICE;
-  }
 }
 
 void begin_report(hh_ctx* ctx, hh_report* rep) {
@@ -807,6 +743,173 @@ int hh_hierarchical(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, 
     if (report) {
       fill_item_report(report, r2, 0);
       report->voxel_iters = r1.voxel_iters + r2.voxel_iters;
+      report->items = nitems;
+      report->status = rc;
+    }
+    return rc;
+  });
+}
+
+int hh_gather_subimages(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, int labels_on_device, int n_sub,
+                        int pad, uint8_t* pack_device) {
+  return guarded(ctx, [&]() -> int {
+    if (!labels || !pack_device) fail(ctx, HH_EINVAL, "labels and pack_device are required");
+    if (nx < 1 || ny < 1 || nz < 1 || n_sub < 1) fail(ctx, HH_EINVAL, "sizes must be positive");
+    if (nx % n_sub || ny % n_sub || nz % n_sub) fail(ctx, HH_EINVAL, "the subimage size must divide the image size");
+    if (pad < 0 || 2 * pad >= std::min(nx, std::min(ny, nz)))
+      fail(ctx, HH_EINVAL, "padding must satisfy 0 <= 2 pad < image size");
+    const long long nvox = (long long)nx * ny * nz;
+    const unsigned char* d = labels;
+    if (!labels_on_device) {
+      auto* buf = static_cast<unsigned char*>(ws(ctx, "image", size_t(nvox)));
+      HIPCHK(hipMemcpyAsync(buf, labels, size_t(nvox), hipMemcpyHostToDevice, ctx->stream));
+      d = buf;
+    }
+    launch_gather_pad(d, nx, ny, nz, n_sub, pad, pack_device, ctx->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return HH_OK;
+  });
+}
+
+int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, int labels_on_device,
+                              const hh_phase* phases, int nphase, int n_sub, int pad, hh_net* net_a, hh_net* net_b,
+                              double spread_tol, double bound_tol, const hh_opts* opts, double C_out[36],
+                              double* C_sub, int* fallback, hh_report* report) {
+  return guarded(ctx, [&]() -> int {
+    hh_opts o;
+    hh_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(ctx, o);
+    if (!labels || !C_out || !net_a) fail(ctx, HH_EINVAL, "labels, net_a and C_out are required");
+    if (nx < 1 || ny < 1 || nz < 1 || n_sub < 1) fail(ctx, HH_EINVAL, "sizes must be positive");
+    if (nx % n_sub || ny % n_sub || nz % n_sub) fail(ctx, HH_EINVAL, "the subimage size must divide the image size");
+    if (pad < 0 || 2 * pad >= std::min(nx, std::min(ny, nz)))
+      fail(ctx, HH_EINVAL, "padding must satisfy 0 <= 2 pad < image size");
+    if (hh_net_input_size(net_a) != n_sub || (net_b && hh_net_input_size(net_b) != n_sub))
+      fail(ctx, HH_EINVAL, "the network input edge must equal the subimage size");
+    if (!(spread_tol > 0.0) || !(bound_tol >= 0.0)) fail(ctx, HH_EINVAL, "bad gate tolerances");
+    const int b = n_sub + 2 * pad;
+    const int mx = nx / n_sub, my = ny / n_sub, mz = nz / n_sub;
+    check_shape(ctx, b, b, b, o.precision);
+    check_shape(ctx, mx, my, mz, o.precision);
+    check_phases(ctx, phases, nphase);
+    if (nphase > 8) fail(ctx, HH_EINVAL, "the surrogate takes at most 8 phases");
+    const long long nvox = (long long)nx * ny * nz;
+    const int nitems = mx * my * mz;
+    begin_report(ctx, report);
+    const hipStream_t st = ctx->stream;
+    const unsigned char* d_img = device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "image");
+    const long long box = (long long)b * b * b;
+    auto* d_pack = static_cast<unsigned char*>(ws(ctx, "pack", size_t(box * nitems)));
+    Profile prof{ctx, o.profile != 0, {}, 0, report};
+    prof.run(HH_K_SETUP, [&] { launch_gather_pad(d_img, nx, ny, nz, n_sub, pad, d_pack, st); });
+    // predictions of the network(s) on the n_sub^3 cores
+    auto* c21a = static_cast<double*>(ws(ctx, "sur_c21a", sizeof(double) * 21 * nitems));
+    double* c21b = net_b ? static_cast<double*>(ws(ctx, "sur_c21b", sizeof(double) * 21 * nitems)) : nullptr;
+    prof.run(HH_K_OTHER, [&] {
+      hh_net_predict_device(ctx, net_a, d_pack, nitems, b, pad, c21a);
+      if (net_b) hh_net_predict_device(ctx, net_b, d_pack, nitems, b, pad, c21b);
+    });
+    // Voigt and Reuss stiffness of each core's phase fractions
+    std::vector<double> cp(21 * nphase), sp(21 * nphase);
+    for (int q = 0; q < nphase; ++q) {
+      const double K = phases[q].K, G = phases[q].G;
+      double C[6][6] = {}, S[6][6] = {};
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          C[i][j] = (i == j) ? K + 4.0 * G / 3.0 : K - 2.0 * G / 3.0;
+          S[i][j] = (i == j) ? 1.0 / (9.0 * K) + 1.0 / (3.0 * G) : 1.0 / (9.0 * K) - 1.0 / (6.0 * G);
+        }
+      for (int i = 3; i < 6; ++i) {
+        C[i][i] = G;
+        S[i][i] = 1.0 / G;
+      }
+      int k = 0;
+      for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+          cp[q * 21 + k] = C[i][j];
+          sp[q * 21 + k] = S[i][j];
+          ++k;
+        }
+    }
+    auto* d_cp = static_cast<double*>(ws(ctx, "sur_cp", sizeof(double) * 21 * nphase));
+    auto* d_sp = static_cast<double*>(ws(ctx, "sur_sp", sizeof(double) * 21 * nphase));
+    auto* cv21 = static_cast<double*>(ws(ctx, "sur_cv", sizeof(double) * 21 * nitems));
+    auto* cr21 = static_cast<double*>(ws(ctx, "sur_cr", sizeof(double) * 21 * nitems));
+    auto* d_flag = static_cast<int*>(ws(ctx, "sur_flag", sizeof(int) * nitems));
+    HIPCHK(hipMemcpyAsync(d_cp, cp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_sp, sp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
+    prof.run(HH_K_OTHER, [&] {
+      hh_launch_bounds(d_pack, nitems, b, pad, n_sub, nphase, d_cp, d_sp, cv21, cr21, st);
+      hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, d_flag, st);
+    });
+    HIPCHK(hipGetLastError());
+    std::vector<int> flag(nitems);
+    std::vector<double> ha(21 * size_t(nitems)), hb;
+    HIPCHK(hipMemcpyAsync(flag.data(), d_flag, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ha.data(), c21a, sizeof(double) * 21 * nitems, hipMemcpyDeviceToHost, st));
+    if (net_b) {
+      hb.resize(ha.size());
+      HIPCHK(hipMemcpyAsync(hb.data(), c21b, sizeof(double) * 21 * nitems, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    prof.flush();
+    // FFT solves of the gated items
+    std::vector<int> fb;
+    for (int i = 0; i < nitems; ++i)
+      if (flag[i]) fb.push_back(i);
+    std::vector<double> field(21 * size_t(nitems));
+    for (size_t i = 0; i < field.size(); ++i) field[i] = net_b ? 0.5 * (ha[i] + hb[i]) : ha[i];
+    double vi = 0.0;
+    int rc = HH_OK;
+    double L[6][6];
+    unit_loads(L);
+    if (!fb.empty()) {
+      std::vector<Item> items(fb.size());
+      for (size_t k = 0; k < fb.size(); ++k) {
+        Item& it = items[k];
+        it.nx = it.ny = it.nz = b;
+        it.lab_off = box * fb[k];
+        it.cf_off = -1;
+        const int r[6] = {pad, pad, pad, pad + n_sub, pad + n_sub, pad + n_sub};
+        std::memcpy(it.region, r, sizeof(r));
+        it.phases.assign(phases, phases + nphase);
+      }
+      GroupResult r1 = solve_group(ctx, items, d_pack, nullptr, false, o, L, prof, nullptr);
+      vi += r1.voxel_iters;
+      for (size_t k = 0; k < fb.size(); ++k) {
+        rc = worse(rc, r1.status[k]);
+        const double* S = r1.C72.data() + k * 72 + 36;
+        int q = 0;
+        for (int i = 0; i < 6; ++i)
+          for (int j = i; j < 6; ++j) field[size_t(fb[k]) * 21 + q++] = S[i * 6 + j];
+      }
+    }
+    if (C_sub) std::memcpy(C_sub, field.data(), sizeof(double) * field.size());
+    if (fallback) std::memcpy(fallback, flag.data(), sizeof(int) * nitems);
+    // level 2
+    auto* d_field = static_cast<double*>(ws(ctx, "sur_field", sizeof(double) * field.size()));
+    HIPCHK(hipMemcpyAsync(d_field, field.data(), sizeof(double) * field.size(), hipMemcpyHostToDevice, st));
+    void* cf = ws(ctx, "cfield", field.size() * (o.precision == 0 ? 4 : 8));
+    launch_convert_field(o.precision, d_field, cf, (long long)field.size(), st);
+    HIPCHK(hipGetLastError());
+    Item l2;
+    l2.nx = mx;
+    l2.ny = my;
+    l2.nz = mz;
+    l2.lab_off = 0;
+    l2.cf_off = 0;
+    const int whole[6] = {0, 0, 0, mx, my, mz};
+    std::memcpy(l2.region, whole, sizeof(l2.region));
+    l2.phases.assign(1, hh_phase{1.0, 1.0});
+    GroupResult r2 = solve_group(ctx, {l2}, nullptr, cf, true, o, L, prof, nullptr);
+    end_report(ctx, report);
+    write_C(r2, 0, C_out, nullptr);
+    rc = worse(rc, r2.status[0]);
+    if (report) {
+      fill_item_report(report, r2, 0);
+      report->voxel_iters = vi + r2.voxel_iters;
       report->items = nitems;
       report->status = rc;
     }

@@ -28,8 +28,11 @@ NKERNEL = len(KERNEL_CLASSES)
 # Exported symbols (checked by the CPU test suite against include/hh.h).
 SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_last_error",
            "hh_workspace_bytes", "hh_release_workspace", "hh_size_supported", "hh_homogenize",
-           "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_richardson",
-           "hh_moduli")
+           "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_gather_subimages",
+           "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_get_params",
+           "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_forward",
+           "hh_net_gradient", "hh_net_train_step", "hh_net_predict", "hh_hierarchical_surrogate",
+           "hh_richardson", "hh_moduli")
 
 
 class HHError(RuntimeError):
@@ -97,6 +100,23 @@ def load_library(path=LIB_PATH):
                                         DP, DP, ct.POINTER(I), ct.POINTER(I), ct.POINTER(Report)]
     lib.hh_hierarchical.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, I, I, I, ct.POINTER(Opts),
                                     DP, DP, ct.POINTER(Report)]
+    lib.hh_gather_subimages.argtypes = [P, P, I, I, I, I, I, I, P]
+    FP = ct.POINTER(ct.c_float)
+    lib.hh_net_create.argtypes = [P, I, I, ct.c_ulonglong, ct.POINTER(P)]
+    lib.hh_net_destroy.argtypes = [P]
+    lib.hh_net_destroy.restype = None
+    lib.hh_net_num_params.argtypes = [P]
+    lib.hh_net_num_params.restype = LL
+    lib.hh_net_get_params.argtypes = [P, P, FP, LL]
+    lib.hh_net_set_params.argtypes = [P, P, FP, LL]
+    lib.hh_net_set_scaling.argtypes = [P, P, DP, DP]
+    lib.hh_net_get_scaling.argtypes = [P, DP, DP]
+    lib.hh_net_forward.argtypes = [P, P, P, I, I, I, I, FP]
+    lib.hh_net_gradient.argtypes = [P, P, P, I, I, I, I, FP, FP, FP]
+    lib.hh_net_train_step.argtypes = [P, P, P, I, I, I, I, P, I, ct.c_float, FP]
+    lib.hh_net_predict.argtypes = [P, P, P, I, I, I, I, DP]
+    lib.hh_hierarchical_surrogate.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, I, I, P, P, D, D,
+                                              ct.POINTER(Opts), DP, DP, ct.POINTER(I), ct.POINTER(Report)]
     lib.hh_richardson.argtypes = [ct.POINTER(I), DP, I, DP, DP]
     lib.hh_moduli.argtypes = [DP, DP, DP]
     for name in SYMBOLS:
@@ -120,6 +140,10 @@ def _dptr(a):
     return a.ctypes.data_as(ct.POINTER(ct.c_double))
 
 
+def _fptr(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_float))
+
+
 def _phases(phases):
     arr = (Phase * len(phases))()
     for i, (K, G) in enumerate(phases):
@@ -139,7 +163,7 @@ def _buffer(x, dtype):
     """(pointer, on_device, keepalive) for a torch tensor or array-like."""
     if _is_torch(x):
         import torch
-        want = {np.uint8: torch.uint8, np.float64: torch.float64}[dtype]
+        want = {np.uint8: torch.uint8, np.float64: torch.float64, np.float32: torch.float32}[dtype]
         if x.dtype != want:
             raise TypeError("expected a %s tensor" % want)
         if not x.is_contiguous():
@@ -311,6 +335,149 @@ class Context:
             self._check(rc)
         del keep
         return C.reshape(6, 6), Cs[:21 * m].reshape(m, 21), rep.as_dict()
+
+    def gather_subimages(self, labels, n_sub, pad=0, out=None):
+        """Padded subimage boxes of an image [z][y][x] as a device uint8 tensor
+        of shape (blocks, n_sub + 2 pad, ...), blocks in C order."""
+        import torch
+        nz, ny, nx = tuple(labels.shape)
+        b = n_sub + 2 * pad
+        m = (nx // n_sub) * (ny // n_sub) * (nz // n_sub)
+        if out is None:
+            out = torch.empty((m, b, b, b), dtype=torch.uint8, device="cuda:%d" % self.device)
+        elif out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous() or out.numel() < m * b ** 3:
+            raise ValueError("out must be a contiguous device uint8 tensor of %d bytes" % (m * b ** 3))
+        ptr, dev, keep = _buffer(labels, np.uint8)
+        self._check(self._lib.hh_gather_subimages(self._h, ptr, nx, ny, nz, dev, int(n_sub), int(pad),
+                                                  ct.c_void_p(out.data_ptr())))
+        del keep
+        return out
+
+    def hierarchical_surrogate(self, labels, phases, n_sub, pad, net_a, net_b=None, spread_tol=0.05,
+                               bound_tol=0.02, check=True, **opts):
+        """Two-level C* with network subimage stiffnesses and FFT fallback;
+        returns (C*, C_sub[(N/n)^3, 21], fallback flags, report)."""
+        nz, ny, nx = tuple(labels.shape)
+        ptr, dev, keep = _buffer(labels, np.uint8)
+        o = default_opts(**opts)
+        ph = _phases(phases)
+        m = (nx // n_sub) * (ny // n_sub) * (nz // n_sub)
+        C = np.zeros(36)
+        Cs = np.zeros(max(1, m) * 21)
+        fb = np.zeros(max(1, m), dtype=np.int32)
+        rep = Report()
+        rc = self._lib.hh_hierarchical_surrogate(
+            self._h, ptr, nx, ny, nz, dev, ph, len(phases), int(n_sub), int(pad), net_a._h,
+            None if net_b is None else net_b._h, float(spread_tol), float(bound_tol), ct.byref(o), _dptr(C),
+            _dptr(Cs), fb.ctypes.data_as(ct.POINTER(ct.c_int)), ct.byref(rep))
+        if check:
+            self._check(rc)
+        del keep
+        return C.reshape(6, 6), Cs[:21 * m].reshape(m, 21), fb[:m].astype(bool), rep.as_dict()
+
+
+class Net:
+    """CNN surrogate of the subimage stiffness (one network on one context).
+
+    Label inputs are ``batch`` boxes of edge ``box`` (an array or a device
+    uint8 tensor of shape (batch, box, box, box)); the network reads the
+    n^3 window at (offset, offset, offset) of each box."""
+
+    def __init__(self, ctx, nphase, n, seed=0):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        self.n = int(n)
+        self.nphase = int(nphase)
+        h = ct.c_void_p()
+        ctx._check(self._lib.hh_net_create(ctx._h, self.nphase, self.n, ct.c_ulonglong(seed), ct.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hh_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self):
+        return int(self._lib.hh_net_num_params(self._h))
+
+    def get_params(self):
+        p = np.zeros(self.num_params, dtype=np.float32)
+        self.ctx._check(self._lib.hh_net_get_params(self.ctx._h, self._h, _fptr(p), p.size))
+        return p
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        self.ctx._check(self._lib.hh_net_set_params(self.ctx._h, self._h, _fptr(p), p.size))
+
+    def set_scaling(self, mean, scale):
+        m = np.ascontiguousarray(np.asarray(mean, dtype=np.float64).reshape(21))
+        s = np.ascontiguousarray(np.asarray(scale, dtype=np.float64).reshape(21))
+        self.ctx._check(self._lib.hh_net_set_scaling(self.ctx._h, self._h, _dptr(m), _dptr(s)))
+
+    def get_scaling(self):
+        m, s = np.zeros(21), np.zeros(21)
+        rc = self._lib.hh_net_get_scaling(self._h, _dptr(m), _dptr(s))
+        if rc != HH_OK:
+            raise HHError(rc, "hh_net_get_scaling")
+        return m, s
+
+    def _labels(self, labels, offset):
+        shp = tuple(labels.shape)
+        if len(shp) == 3:
+            shp = (1,) + shp
+        batch, box = shp[0], shp[1]
+        if shp[1:] != (box, box, box):
+            raise ValueError("label boxes must be cubes")
+        ptr, dev, keep = _buffer(labels, np.uint8)
+        return ptr, dev, keep, int(batch), int(box), int(offset)
+
+    def forward(self, labels, offset=0):
+        """Normalized outputs (batch, 21), float32."""
+        ptr, dev, keep, batch, box, off = self._labels(labels, offset)
+        out = np.zeros((batch, 21), dtype=np.float32)
+        self.ctx._check(self._lib.hh_net_forward(self.ctx._h, self._h, ptr, dev, batch, box, off, _fptr(out)))
+        del keep
+        return out
+
+    def gradient(self, labels, target, offset=0):
+        """(loss, gradient over all parameters) of the mean squared error."""
+        ptr, dev, keep, batch, box, off = self._labels(labels, offset)
+        t = np.ascontiguousarray(np.asarray(target, dtype=np.float32).reshape(batch, 21))
+        g = np.zeros(self.num_params, dtype=np.float32)
+        loss = ct.c_float()
+        self.ctx._check(self._lib.hh_net_gradient(self.ctx._h, self._h, ptr, dev, batch, box, off, _fptr(t),
+                                                  ct.byref(loss), _fptr(g)))
+        del keep
+        return loss.value, g
+
+    def train_step(self, labels, target, lr, offset=0):
+        """One Adam step; returns the loss before the step.  ``target`` is a
+        (batch, 21) float32 array or device tensor of normalized values."""
+        ptr, dev, keep, batch, box, off = self._labels(labels, offset)
+        tptr, tdev, tkeep = _buffer(target if _is_torch(target) else
+                                    np.asarray(target, dtype=np.float32).reshape(batch, 21), np.float32)
+        if (target.numel() if _is_torch(target) else np.size(target)) != batch * 21:
+            raise ValueError("target must hold batch x 21 values")
+        loss = ct.c_float()
+        self.ctx._check(self._lib.hh_net_train_step(self.ctx._h, self._h, ptr, dev, batch, box, off, tptr, tdev,
+                                                    ct.c_float(lr), ct.byref(loss)))
+        del keep, tkeep
+        return loss.value
+
+    def predict(self, labels, offset=0):
+        """Stiffness C21 in GPa (batch, 21), float64."""
+        ptr, dev, keep, batch, box, off = self._labels(labels, offset)
+        out = np.zeros((batch, 21))
+        self.ctx._check(self._lib.hh_net_predict(self.ctx._h, self._h, ptr, dev, batch, box, off, _dptr(out)))
+        del keep
+        return out
 
 
 def richardson(ns, Cs):

@@ -1,0 +1,229 @@
+"""GPU parity of the CNN surrogate and its gate, through the C ABI.
+
+Network tolerances: the oracle rounds to bfloat16 at the same points as the
+kernels (weights, activations, masked output gradients), so the remaining
+differences come from FP32 against FP64 accumulation, which moves a value
+across a bfloat16 rounding boundary only rarely (a relative 2^-9 step).
+Outputs must agree to 2e-3 of their scale, gradients to 2e-2 (relative L2
+norm per parameter block; the bias gradients of the kernels sum FP32 values
+before their bfloat16 rounding), and the loss to 1e-3.
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn as ref
+from oracle import galerkin as g
+from oracle import hier
+from oracle import surrogate as sg
+from paper_2208_02320_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FOUR = synth.FOUR_PHASE["phases"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2208_02320_amd import hh
+    c = hh.Context(0)
+    yield c
+    c.close()
+
+
+def boxes(batch, box, nphase, seed):
+    """Label boxes cut from a rock-like image (so that windows hold
+    realistic structure), back to back."""
+    lab = synth.rocklike(max(2 * box, 32), [1.0 / nphase] * nphase, sigma=1.5, seed=seed)
+    out = np.empty((batch, box, box, box), np.uint8)
+    rng = np.random.default_rng(seed)
+    for b in range(batch):
+        z, y, x = rng.integers(0, lab.shape[0], size=3)
+        out[b] = hier.padded_box(lab, (z, y, x), box, 0)
+    return out
+
+
+def net_with(ctx, nphase, n, params):
+    from paper_2208_02320_amd import hh
+    net = hh.Net(ctx, nphase, n)
+    net.set_params(params)
+    return net
+
+
+@pytest.mark.parametrize("n,batch,nphase", [(16, 3, 3), (32, 2, 4), (16, 5, 8)])
+def test_forward_matches_oracle(ctx, n, batch, nphase):
+    pad = 2
+    lab = boxes(batch, n + 2 * pad, nphase, seed=n + batch)
+    p = ref.init_params(nphase, seed=7).astype(np.float32)
+    net = net_with(ctx, nphase, n, p)
+    y = net.forward(lab, offset=pad)
+    core = lab[:, pad:pad + n, pad:pad + n, pad:pad + n]
+    yr, _ = ref.forward(p.astype(np.float64), core, bf=True)
+    scale = max(1.0, np.abs(yr).max())
+    err = np.abs(y - yr).max() / scale
+    print("forward n=%d batch=%d err %.2e" % (n, batch, err))
+    assert err < 2e-3
+    net.close()
+
+
+def test_gradient_matches_oracle(ctx):
+    n, batch, nphase, pad = 16, 3, 4, 1
+    lab = boxes(batch, n + 2 * pad, nphase, seed=11)
+    p = ref.init_params(nphase, seed=3).astype(np.float32)
+    tgt = np.random.default_rng(4).standard_normal((batch, 21)).astype(np.float32)
+    net = net_with(ctx, nphase, n, p)
+    loss, grad = net.gradient(lab, tgt, offset=pad)
+    core = lab[:, pad:pad + n, pad:pad + n, pad:pad + n]
+    lr, gr = ref.loss_and_grad(p.astype(np.float64), core, tgt.astype(np.float64), bf=True)
+    assert abs(loss - lr) <= 1e-3 * lr
+    lay, _ = ref.layout()
+    for name, off, shp in lay:
+        sz = int(np.prod(shp))
+        a, b = grad[off:off + sz].astype(np.float64), gr[off:off + sz]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print("grad %-4s rel %.2e |g| %.3e" % (name, rel, np.linalg.norm(b)))
+        assert rel < 2e-2, name
+    # padded input channels of the first layer see no data
+    W1 = grad[:27 * 32 * 8].reshape(27, 32, 8)
+    assert np.all(W1[:, :, nphase:] == 0.0)
+    net.close()
+
+
+def test_adam_first_step(ctx):
+    """Adam's first step is lr * g / (|g| + eps) for every parameter."""
+    n, batch, nphase = 16, 2, 3
+    lab = boxes(batch, n, nphase, seed=21)
+    p0 = ref.init_params(nphase, seed=5).astype(np.float32)
+    tgt = np.random.default_rng(6).standard_normal((batch, 21)).astype(np.float32)
+    net = net_with(ctx, nphase, n, p0)
+    loss_g, gr = net.gradient(lab, tgt)
+    lr = 1e-3
+    loss_t = net.train_step(lab, tgt, lr)
+    assert loss_t == loss_g  # same kernels, same order: identical
+    p1 = net.get_params()
+    step = (p0.astype(np.float64) - p1) / lr
+    want = gr / (np.abs(gr) + 1e-8)
+    mask = np.abs(gr) > 1e-5
+    assert np.abs(step - want)[mask].max() < 2e-3
+    assert np.all(p1.reshape(-1)[:27 * 32 * 8].reshape(27, 32, 8)[:, :, nphase:] == 0.0)
+    net.close()
+
+
+def test_training_reduces_loss(ctx):
+    n, batch, nphase = 16, 8, 4
+    lab = boxes(batch, n, nphase, seed=31)
+    # targets depend on the phase fractions, plus an offset to learn
+    fr = np.stack([np.bincount(b.ravel(), minlength=nphase) / b.size for b in lab])
+    A = np.random.default_rng(8).standard_normal((nphase, 21))
+    tgt = (1.5 + 4.0 * (fr - fr.mean(axis=0)) @ A).astype(np.float32)
+    from paper_2208_02320_amd import hh
+    net = hh.Net(ctx, nphase, n, seed=1)
+    losses = [net.train_step(lab, tgt, 3e-3) for _ in range(80)]
+    print("loss %.4f -> %.4f" % (losses[0], losses[-1]))
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.3 * losses[0]
+    net.close()
+
+
+def test_predict_applies_scaling(ctx):
+    n, batch, nphase = 16, 3, 2
+    lab = boxes(batch, n, nphase, seed=41)
+    from paper_2208_02320_amd import hh
+    net = hh.Net(ctx, nphase, n, seed=2)
+    mean = np.linspace(1.0, 40.0, 21)
+    scale = np.linspace(0.5, 3.0, 21)
+    net.set_scaling(mean, scale)
+    m2, s2 = net.get_scaling()
+    assert np.array_equal(m2, mean) and np.array_equal(s2, scale)
+    y = net.forward(lab).astype(np.float64)
+    c = net.predict(lab)
+    assert np.abs(c - (y * scale + mean)).max() < 1e-12 * np.abs(c).max()
+    net.close()
+
+
+def test_gather_subimages_matches_padded_boxes(ctx):
+    lab = np.ascontiguousarray(synth.rocklike((16, 48, 32), [0.5, 0.3, 0.2], sigma=1.5, seed=9))
+    n, pad = 16, 3
+    pack = ctx.gather_subimages(lab, n, pad).cpu().numpy()
+    origins = hier.partition(lab, n)
+    assert pack.shape == (len(origins), n + 2 * pad, n + 2 * pad, n + 2 * pad)
+    for i, o in enumerate(origins):
+        assert np.array_equal(pack[i], hier.padded_box(lab, o, n, pad)), i
+
+
+def constant_net(ctx, nphase, n, c21):
+    """A network whose every prediction is c21 (all weights zero)."""
+    from paper_2208_02320_amd import hh
+    net = hh.Net(ctx, nphase, n)
+    net.set_params(np.zeros(net.num_params, np.float32))
+    net.set_scaling(c21, np.ones(21))
+    return net
+
+
+def test_gate_and_fallback_match_oracle(ctx):
+    lab = synth.four_phase(64, seed=4)
+    n, pad = 16, 4
+    CV, CR = sg.core_bounds(lab, 0, 64, FOUR)
+    # near the Voigt end of the whole image's bracket: items with less stiff
+    # phase than average fall outside their own bracket (17 of 64 here)
+    c = hier.to21(0.9 * CV + 0.1 * CR)
+    net = constant_net(ctx, 4, n, c)
+    C, Cs, fb, rep = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=0.0,
+                                                tol=1e-6)
+    origins = hier.partition(lab, n)
+    want = np.zeros(len(origins), bool)
+    tight = np.zeros(len(origins), bool)
+    for i, o in enumerate(origins):
+        box = hier.padded_box(lab, o, n, pad)
+        cv, cr = sg.core_bounds(box, pad, n, FOUR)
+        want[i] = sg.gate(c, None, cv, cr, 0.05, 0.0)
+        tight[i] = sg.gate_margin(c, None, cv, cr, 0.0) < 1e-9
+    print("fallback %d of %d (oracle %d)" % (fb.sum(), len(fb), want.sum()))
+    assert 0 < want.sum() < len(want)  # the case exercises both branches
+    assert np.array_equal(fb[~tight], want[~tight])
+    # accepted items carry the prediction, gated items the FFT solve
+    assert np.array_equal(Cs[~fb], np.broadcast_to(c, Cs[~fb].shape))
+    _, Cs_fft, _ = ctx.hierarchical(lab, FOUR, n, pad, tol=1e-6)
+    assert np.abs(Cs[fb] - Cs_fft[fb]).max() < 1e-5 * np.abs(Cs_fft).max()
+    # level 2 on the assembled field against the oracle
+    m = tuple(s // n for s in lab.shape)
+    field = np.stack([hier.from21(r) for r in Cs]).reshape(m + (6, 6))
+    l2 = g.homogenize(g.AnisotropicMedium(field), tol=1e-10, form="sym6")
+    assert g.rel_error(C, l2.C_sym) < 1e-5
+    assert rep["items"] == len(origins)
+    net.close()
+
+
+def test_spread_between_networks_sends_all_to_fft(ctx):
+    lab = synth.four_phase(32, seed=6)
+    n, pad = 16, 2
+    CV, CR = sg.core_bounds(lab, 0, 32, FOUR)
+    c = hier.to21(0.5 * (CV + CR))
+    na = constant_net(ctx, 4, n, c)
+    nb = constant_net(ctx, 4, n, 1.2 * c)
+    C, Cs, fb, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, na, nb, spread_tol=0.05, bound_tol=1.0, tol=1e-6)
+    assert fb.all()
+    C2, Cs2, _ = ctx.hierarchical(lab, FOUR, n, pad, tol=1e-6)
+    assert np.abs(Cs - Cs2).max() < 1e-5 * np.abs(Cs2).max()
+    assert g.rel_error(C, C2) < 1e-6
+    # a loose spread tolerance accepts the mean of the two
+    C3, Cs3, fb3, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, na, nb, spread_tol=0.5, bound_tol=1.0,
+                                                 tol=1e-6)
+    assert not fb3.any()
+    assert np.allclose(Cs3, np.broadcast_to(1.1 * c, Cs3.shape), rtol=1e-12)
+    na.close()
+    nb.close()
+
+
+def test_surrogate_argument_errors(ctx):
+    from paper_2208_02320_amd import hh
+    lab = synth.four_phase(32, seed=6)
+    net = hh.Net(ctx, 4, 16)
+    with pytest.raises(hh.HHError):
+        ctx.hierarchical_surrogate(lab, FOUR, 32, 0, net)  # input edge != subimage size
+    with pytest.raises(hh.HHError):
+        net.forward(np.zeros((2, 16, 16, 16), np.uint8), offset=1)  # window outside the box
+    with pytest.raises(hh.HHError):
+        hh.Net(ctx, 4, 24)  # not a multiple of 16
+    with pytest.raises(hh.HHError):
+        net.set_params(np.zeros(5, np.float32))
+    net.close()

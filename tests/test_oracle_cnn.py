@@ -1,0 +1,102 @@
+"""Pins of the FP64 CNN reference: the convolution against its definition,
+the hand-written backward against central finite differences, and the
+bfloat16 rounding against exactly representable values."""
+import numpy as np
+
+from oracle import cnn
+
+
+def test_conv_matches_definition():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 6, 6, 6, 8))
+    W = rng.standard_normal((27, 5, 8))
+    b = rng.standard_normal(5)
+    assert np.abs(cnn.conv(x, W, b) - cnn.conv_direct(x, W, b)).max() < 1e-12
+
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(1)
+    labels = rng.integers(0, 3, size=(2, 16, 16, 16))
+    flat = cnn.init_params(3, seed=2)
+    target = rng.standard_normal((2, 21))
+    loss, g = cnn.loss_and_grad(flat, labels, target)
+    lay, n = cnn.layout()
+    idx = []
+    for name, off, shp in lay:
+        size = int(np.prod(shp))
+        cand = rng.integers(0, size, size=6) + off
+        if name == "W1":  # real input channels only (padded ones never see data)
+            w = flat[off:off + size].reshape(shp)
+            real = np.flatnonzero(np.broadcast_to(np.arange(8) < 3, shp).ravel())
+            cand = off + rng.choice(real, size=6)
+        idx.extend(cand.tolist())
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(n)
+        e[i] = h
+        lp, _ = cnn.loss_and_grad(flat + e, labels, target)
+        lm, _ = cnn.loss_and_grad(flat - e, labels, target)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (i, fd, g[i])
+
+
+def test_bf16_rounding():
+    v = np.array([1.0, -2.5, 3.140625, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 65280.0])
+    r = cnn.bf16(v)
+    # representable values stay, halfway cases go to even
+    assert r[0] == 1.0 and r[1] == -2.5 and r[2] == 3.140625 and r[5] == 65280.0
+    assert r[3] == 1.0 and r[4] == 1.0 + 2 ** -6
+
+
+def test_layout_size():
+    _, n = cnn.layout()
+    assert n == 27 * 32 * 8 + 32 + 27 * 32 * 32 + 32 + 27 * 64 * 32 + 64 + 27 * 64 * 64 + 64 + 21 * 64 + 21
+
+
+# ---------------------------------------------------------------------------
+# acceptance gate of the surrogate
+# ---------------------------------------------------------------------------
+def _bracket():
+    from oracle import bounds
+    from paper_2208_02320_amd import synth
+    lab = synth.four_phase(16, seed=5)
+    return bounds.voigt_reuss(lab, synth.FOUR_PHASE["phases"])
+
+
+def test_gate_accepts_inside_the_bracket():
+    from oracle import surrogate as sg
+    from oracle.hier import to21
+    CV, CR = _bracket()
+    mid = to21(0.5 * (CV + CR))
+    assert not sg.gate(mid, None, CV, CR, 0.05, 0.0)
+    # the bracket ends pass with a small tolerance (exact ends are singular)
+    assert not sg.gate(to21(CV), None, CV, CR, 0.05, 1e-9)
+    assert not sg.gate(to21(CR), None, CV, CR, 0.05, 1e-9)
+    assert sg.gate(to21(CV), None, CV, CR, 0.05, 0.0)
+
+
+def test_gate_rejects_outside_and_indefinite():
+    from oracle import surrogate as sg
+    from oracle.hier import to21
+    CV, CR = _bracket()
+    assert sg.gate(to21(1.2 * CV), None, CV, CR, 0.05, 0.02)       # above Voigt
+    assert sg.gate(to21(0.8 * CR), None, CV, CR, 0.05, 0.02)       # below Reuss
+    assert sg.gate(to21(-0.5 * (CV + CR)), None, CV, CR, 0.05, 10.0)  # not positive definite
+    # a shear entry pushed past Voigt is caught by one direction only
+    C = 0.5 * (CV + CR)
+    C[3, 3] = CV[3, 3] * 1.5
+    assert sg.gate(to21(C), None, CV, CR, 0.05, 0.01)
+
+
+def test_gate_spread_between_networks():
+    from oracle import surrogate as sg
+    from oracle.hier import to21
+    CV, CR = _bracket()
+    a = to21(0.5 * (CV + CR))
+    assert not sg.gate(a, a * 1.01, CV, CR, 0.05, 0.0)
+    assert sg.gate(a, a * 1.10, CV, CR, 0.05, 0.0)
+    # the norm is taken in Mandel form, where C44 (component 15) carries a
+    # factor 2: a change of 3 % of the norm there is a 6 % spread
+    b = a.copy()
+    b[15] += 0.06 * np.linalg.norm(sg.mandel(0.5 * (CV + CR))) / 2.0
+    assert sg.gate(a, b, CV, CR, 0.05, 0.0)
