@@ -43,13 +43,20 @@ def algorithmic_bytes(nx, ny, nz, cbytes=8):
     }
 
 
+SOLVER_SOURCES = ("fft.hpp", "hh_internal.hpp", "kernels.hpp", "solver_kernels.hpp", "solver_common.hip",
+                  "sizes_f32_*.hip", "sizes_f64_*.hip")
+
+
 def kernel_source_hash():
-    """Short hash of the HIP sources; profile-derived figures are used only
-    while it matches the hash recorded with them."""
+    """Short hash of the solver kernels' sources; profile-derived figures are
+    used only while it matches the hash recorded with them."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2208_02320_amd", "csrc", "*"))):
+    files = set()
+    for pat in SOLVER_SOURCES:
+        files.update(glob.glob(os.path.join(ROOT, "paper_2208_02320_amd", "csrc", pat)))
+    for f in sorted(files):
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
@@ -169,9 +176,101 @@ def bench_uneven(args):
     ctx.close()
 
 
+def conv_flops_per_item(n, nphase):
+    """Multiply-adds x 2 of the four convolutions on one n^3 input (real
+    input channels for the one-hot layer)."""
+    cin, cout = (nphase, 32, 32, 64), (32, 32, 64, 64)
+    f, d = 0, n
+    for l in range(4):
+        d //= 2
+        f += 2 * d ** 3 * cout[l] * 27 * cin[l]
+    return f
+
+
+def bench_surrogate(args):
+    """Two-level scheme with the CNN surrogate: 1024^3 four-phase image (device
+    generator, seed 3) cut into 4096 subimages of 64^3 with 8 voxels of
+    padding; two shipped networks predict every subimage stiffness, the gate
+    sends doubtful ones to the FFT solver, then the 16^3 level-2 solve.  One
+    step is the whole pipeline; the plain FFT hierarchy on the same image is
+    timed once for the speed-up and is the reference of the C* error."""
+    import torch
+    from paper_2208_02320_amd import hh, surrogate, synth
+    N, n, pad = args.sur_size, 64, 8
+    phases = synth.FOUR_PHASE["phases"]
+    ctx = hh.Context(0)
+    paths = surrogate.default_weights(n, pad, args.weights_dir)
+    for pth in paths:
+        if not os.path.exists(pth):
+            raise SystemExit("surrogate weights %s missing: train them with "
+                             "python -m paper_2208_02320_amd.surrogate" % pth)
+    na, nb = (surrogate.load(ctx, pth) for pth in paths)
+    img = synth.four_phase_device(N, sigma=2.0, seed=3, device="cuda:0")
+    torch.cuda.synchronize()
+    kw = dict(spread_tol=args.spread_tol, bound_tol=args.bound_tol, tol=1e-6)
+    print("bench: surrogate %d^3, warmup %d" % (N, args.warmup), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.hierarchical_surrogate(img, phases, n, pad, na, nb, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        C, Cs, fb, rep = ctx.hierarchical_surrogate(img, phases, n, pad, na, nb, profile=1, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    items = rep["items"]
+    print("bench: surrogate step %.3f s, fallback %d of %d" % (dt, int(fb.sum()), items), file=sys.stderr,
+          flush=True)
+    # network inference alone, for the MFMA roofline of the convolutions
+    pack = ctx.gather_subimages(img, n, pad)
+    na.predict(pack[:64], offset=pad)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    na.predict(pack, offset=pad)
+    ev1.record()
+    torch.cuda.synchronize()
+    cnn_s = ev0.elapsed_time(ev1) * 1e-3
+    flops = conv_flops_per_item(n, len(phases)) * items
+    tflops = flops / cnn_s / 1e12
+    del pack
+    # the plain FFT hierarchy on the same image: speed and reference C*
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Cp, Csp, repp = ctx.hierarchical(img, phases, n, pad, tol=1e-6)
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - t1
+    err = float(surrogate.rel_error21(hh.upper21(C), hh.upper21(Cp))[0])
+    sub_err = surrogate.rel_error21(Cs, Csp)
+    line = {
+        "metric": "subimages/s of the two-level scheme with surrogate and FFT fallback",
+        "value": items / dt, "unit": "subimages/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 network / f32 solver", "data": "synthetic",
+        "config": {"workload": "hierarchical %d^3 four-phase (seed 3), n = 64, pad 8, CNN surrogate pair, "
+                               "spread_tol %g, bound_tol %g, FFT fallback tol 1e-6" % (N, args.spread_tol,
+                                                                                      args.bound_tol)},
+        "fallback_fraction": float(fb.mean()),
+        "rel_error_vs_plain": err,
+        "subimage_rel_error": {"mean": float(sub_err.mean()), "p95": float(np.quantile(sub_err, 0.95)),
+                               "max": float(sub_err.max())},
+        "plain_subimages_per_s": items / dtp, "speedup_vs_plain": dtp / dt,
+        "roofline": {"bound": "mfma", "kernel": "network forward (4 BF16 convolutions + head)",
+                     "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tflops / 2500.0, 5), "traffic": None,
+                     "algorithmic_flops_per_item": conv_flops_per_item(n, len(phases)),
+                     "seconds_for_%d_items" % items: cnn_s},
+        "kernel_ms": rep["kernel_ms"],
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("solve256", "hier", "uneven"), default="solve256")
+    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate"), default="solve256")
+    ap.add_argument("--sur-size", type=int, default=1024)
+    ap.add_argument("--weights-dir", default=None)
+    ap.add_argument("--spread-tol", type=float, default=0.02)
+    ap.add_argument("--bound-tol", type=float, default=0.0)
     ap.add_argument("--hier-size", type=int, default=512)
     ap.add_argument("--uneven-count", type=int, default=2048)
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +288,8 @@ def main():
         return bench_hier(args)
     if args.workload == "uneven":
         return bench_uneven(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
 
     import torch
     from paper_2208_02320_amd import hh, synth

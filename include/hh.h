@@ -181,8 +181,10 @@ int hh_gather_subimages(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int 
  * and the FFT solve stays the fallback and the judge of its error).
  * A 3-D CNN maps the one-hot phase labels of an n^3 subimage to its 21
  * stiffness components: four 3x3x3 stride-2 convolutions (8 -> 32 -> 32 ->
- * 64 -> 64 channels, ReLU), a global mean and a linear map to 21 outputs,
- * trained on FFT-solver labels.  Convolutions run on BF16 MFMA with FP32
+ * 64 -> 64 channels, ReLU) and a global mean give 64 features; the window's
+ * 8 phase fractions, standardized (hh_net_set_fraction_scaling), are
+ * appended, and a linear map takes the 72 features to 21 outputs.  Trained
+ * on FFT-solver labels.  Convolutions run on BF16 MFMA with FP32
  * accumulation; parameters are FP32.
  *
  * Inputs of every call: `batch` boxes of box^3 uint8 labels stored back to
@@ -204,6 +206,10 @@ int hh_net_set_params(hh_ctx *ctx, hh_net *net, const float *params, long long n
 /* Output scaling: C21 = mean + scale * y (scale > 0). */
 int hh_net_set_scaling(hh_ctx *ctx, hh_net *net, const double mean[21], const double scale[21]);
 int hh_net_get_scaling(const hh_net *net, double mean[21], double scale[21]);
+/* Phase-fraction features: feature_c = (f_c - mean[c]) * scale[c] for the
+ * fraction f_c of label c in the input window (c = 0..7; default 0 and 1). */
+int hh_net_set_fraction_scaling(hh_ctx *ctx, hh_net *net, const double mean[8], const double scale[8]);
+int hh_net_get_fraction_scaling(const hh_net *net, double mean[8], double scale[8]);
 /* Normalized outputs y (host, batch x 21). */
 int hh_net_forward(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_on_device, int batch, int box,
                    int offset, float *out);

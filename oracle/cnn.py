@@ -8,11 +8,13 @@ subimage solve of Sec. 4.  This module defines what its kernels compute:
 * input: one-hot phase labels of an n^3 window, channels padded to 8;
 * four convolutions, 3x3x3 taps (tz, ty, tx) in row-major order, stride 2,
   zero padding 1, bias, ReLU: 8 -> 32 -> 32 -> 64 -> 64 channels;
-* global mean over the last 4-D activation, linear map 64 -> 21;
+* global mean over the last 4-D activation (64 features), followed by the
+  window's 8 phase fractions f_c (the mean of the one-hot input),
+  standardized as (f_c - mu_c) s_c; linear map 72 -> 21;
 * loss: mean over batch and outputs of the squared error.
 
 Parameters use the flat layout of the library: per layer W[tap][cout][cin]
-then bias[cout]; then W_fc[21][64], b_fc[21].
+then bias[cout]; then W_fc[21][72], b_fc[21].
 
 With ``bf16=True`` values are rounded to bfloat16 (round to nearest even)
 where the kernels store or feed them in bfloat16: weights, every layer's
@@ -25,7 +27,8 @@ import numpy as np
 
 CIN = (8, 32, 32, 64)
 COUT = (32, 32, 64, 64)
-FEAT, OUT = 64, 21
+CONV_FEAT, NFRAC, OUT = 64, 8, 21
+FEAT = CONV_FEAT + NFRAC
 
 
 def layout():
@@ -105,7 +108,16 @@ def conv_direct(x, W, b):
     return out
 
 
-def forward(flat, labels, bf=False):
+def fraction_features(labels, fstats=None):
+    """(B, 8) standardized phase fractions; fstats = (mu[8], s[8])."""
+    f = onehot(labels).mean(axis=(1, 2, 3))
+    if fstats is None:
+        return f
+    mu, sc = (np.asarray(a, dtype=np.float64) for a in fstats)
+    return (f - mu) * sc
+
+
+def forward(flat, labels, bf=False, fstats=None):
     """Outputs (B, 21) and the activations needed by backward()."""
     P = unpack(flat)
     r = bf16 if bf else (lambda a: a)
@@ -114,23 +126,23 @@ def forward(flat, labels, bf=False):
     for l in range(4):
         z = conv(acts[-1], r(P["W%d" % (l + 1)]), P["b%d" % (l + 1)])
         acts.append(r(np.maximum(z, 0.0)))
-    h = acts[-1].mean(axis=(1, 2, 3))
+    h = np.concatenate([acts[-1].mean(axis=(1, 2, 3)), fraction_features(labels, fstats)], axis=1)
     y = h @ P["Wfc"].T + P["bfc"]
     return y, dict(acts=acts, h=h)
 
 
-def loss_and_grad(flat, labels, target, bf=False):
+def loss_and_grad(flat, labels, target, bf=False, fstats=None):
     """(loss, flat gradient) of the mean squared error."""
     P = unpack(flat)
     r = bf16 if bf else (lambda a: a)
-    y, c = forward(flat, labels, bf)
+    y, c = forward(flat, labels, bf, fstats)
     target = np.asarray(target, dtype=np.float64)
     B = y.shape[0]
     d = y - target
     loss = float((d * d).sum() / (B * OUT))
     dy = 2.0 * d / (B * OUT)
     G = {"Wfc": dy.T @ c["h"], "bfc": dy.sum(axis=0)}
-    dh = dy @ P["Wfc"]
+    dh = dy @ P["Wfc"][:, :CONV_FEAT]  # the fraction features take no gradient
     A = c["acts"]
     V = np.prod(A[4].shape[1:4])
     dA = np.broadcast_to(dh[:, None, None, None, :] / V, A[4].shape).copy()

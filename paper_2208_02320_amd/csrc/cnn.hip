@@ -16,7 +16,7 @@ namespace {
 constexpr int kLayers = 4;
 constexpr int kCin[kLayers] = {8, 32, 32, 64};
 constexpr int kCout[kLayers] = {32, 32, 64, 64};
-constexpr int kFeat = 64, kOut = 21;
+constexpr int kFeat = 72, kConvFeat = 64, kFrac = 8, kOut = 21;
 
 struct Buf {
   void* p = nullptr;
@@ -35,12 +35,14 @@ struct hh_net {
   __bf16* Wt[kLayers] = {};
   double mean[kOut], scale[kOut];
   double *d_mean = nullptr, *d_scale = nullptr;
+  double fmu[kFrac], fsc[kFrac];  // standardization of the phase-fraction features
+  float *d_fmu = nullptr, *d_fsc = nullptr;
   long long step = 0;
   int cap = 0;  // batch capacity of the activation buffers
   __bf16* x0 = nullptr;
   __bf16* a[kLayers] = {};
   float* ga[kLayers] = {};  // gradient w.r.t. output of layer l
-  float *out = nullptr, *tgt = nullptr, *hw = nullptr, *loss = nullptr;
+  float *out = nullptr, *tgt = nullptr, *hw = nullptr, *loss = nullptr, *frac = nullptr;
   float* part = nullptr;
   size_t part_n = 0;
   float* pbias = nullptr;
@@ -65,7 +67,8 @@ void free_acts(hh_net* net) {
   (void)hipFree(net->loss);
   (void)hipFree(net->part);
   (void)hipFree(net->pbias);
-  net->out = net->tgt = net->hw = net->loss = net->part = net->pbias = nullptr;
+  (void)hipFree(net->frac);
+  net->out = net->tgt = net->hw = net->loss = net->part = net->pbias = net->frac = nullptr;
   net->cap = 0;
 }
 
@@ -105,6 +108,7 @@ void ensure_acts(hh_ctx* ctx, hh_net* net, int batch) {
   net->tgt = dalloc<float>(ctx, size_t(batch) * kOut);
   net->hw = dalloc<float>(ctx, size_t(batch) * (kOut * kFeat + kOut));
   net->loss = dalloc<float>(ctx, size_t(batch));
+  net->frac = dalloc<float>(ctx, size_t(batch) * kFrac);
   pmax = std::max<size_t>(pmax, size_t(batch) * (kOut * kFeat + kOut));
   net->part = dalloc<float>(ctx, pmax);
   net->part_n = pmax;
@@ -128,6 +132,8 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
   const long long n = net->n, nv = n * n * n;
   k_onehot<<<unsigned(std::min<long long>((nv * batch + 255) / 256, 65536)), 256, 0, ctx->stream>>>(
       labels, (long long)box * box * box, box, o, net->n, batch, net->x0);
+  k_fractions<<<batch, 256, 0, ctx->stream>>>(labels, (long long)box * box * box, box, o, net->n, net->d_fmu,
+                                              net->d_fsc, net->frac);
   conv_fwd<8, 32>(ctx, net->x0, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
   conv_fwd<32, 32>(ctx, net->a[0], net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
   conv_fwd<32, 64>(ctx, net->a[1], net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
@@ -163,7 +169,7 @@ float backward(hh_ctx* ctx, hh_net* net, int batch) {
   const int V = edge(net, 3) / 2;
   const int nvl = V * V * V;
   const float inv = 1.0f / float(batch * kOut);
-  k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], nvl, net->p + net->fcw_off, net->p + net->fcb_off, net->out,
+  k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], nvl, net->frac, net->p + net->fcw_off, net->p + net->fcb_off, net->out,
                                         net->tgt, net->ga[3], net->hw, net->loss, inv);
   k_reduce_parts<<<8, 256, 0, ctx->stream>>>(net->hw, batch, kOut * kFeat + kOut, net->g + net->fcw_off);
   conv_bwd<64, 64>(ctx, net, 3, net->a[2], batch, net->ga[2]);
@@ -185,6 +191,17 @@ const unsigned char* labels_to_device(hh_ctx* ctx, const uint8_t* labels, int on
   return d;
 }
 
+void upload_fraction_scaling(hh_ctx* ctx, hh_net* net) {
+  float mu[kFrac], sc[kFrac];
+  for (int i = 0; i < kFrac; ++i) {
+    mu[i] = float(net->fmu[i]);
+    sc[i] = float(net->fsc[i]);
+  }
+  HIPCHK(hipMemcpyAsync(net->d_fmu, mu, sizeof(mu), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(net->d_fsc, sc, sizeof(sc), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+}
+
 void check_input(hh_ctx* ctx, hh_net* net, int batch, int box, int o) {
   if (!net) fail(ctx, HH_EINVAL, "null network");
   if (batch < 1) fail(ctx, HH_EINVAL, "batch must be >= 1");
@@ -201,7 +218,7 @@ void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels
     ensure_acts(ctx, net, step);
     forward(ctx, net, labels + (long long)b0 * box * box * box, nb, box, o);
     const int V = edge(net, 3) / 2;
-    k_head<<<nb, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->p + net->fcw_off, net->p + net->fcb_off, net->out,
+    k_head<<<nb, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->frac, net->p + net->fcw_off, net->p + net->fcb_off, net->out,
                                        nullptr, nullptr, nullptr, nullptr, 0.0f);
     k_denorm<<<(nb * kOut + 255) / 256, 256, 0, ctx->stream>>>(net->out, net->d_mean, net->d_scale, nb,
                                                                c21 + (long long)b0 * kOut);
@@ -256,6 +273,8 @@ int hh_net_create(hh_ctx* ctx, int nphase, int n, unsigned long long seed, hh_ne
       }
       net->d_mean = dalloc<double>(ctx, kOut);
       net->d_scale = dalloc<double>(ctx, kOut);
+      net->d_fmu = dalloc<float>(ctx, kFrac);
+      net->d_fsc = dalloc<float>(ctx, kFrac);
     } catch (...) {
       hh_net_destroy(net);
       throw;
@@ -278,6 +297,11 @@ int hh_net_create(hh_ctx* ctx, int nphase, int n, unsigned long long seed, hh_ne
       net->mean[i] = 0.0;
       net->scale[i] = 1.0;
     }
+    for (int i = 0; i < kFrac; ++i) {
+      net->fmu[i] = 0.0;
+      net->fsc[i] = 1.0;
+    }
+    upload_fraction_scaling(ctx, net);
     HIPCHK(hipMemcpyAsync(net->p, h.data(), sizeof(float) * off, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemsetAsync(net->m, 0, sizeof(float) * off, ctx->stream));
     HIPCHK(hipMemsetAsync(net->v, 0, sizeof(float) * off, ctx->stream));
@@ -305,6 +329,8 @@ void hh_net_destroy(hh_net* net) {
   }
   (void)hipFree(net->d_mean);
   (void)hipFree(net->d_scale);
+  (void)hipFree(net->d_fmu);
+  (void)hipFree(net->d_fsc);
   delete net;
 }
 
@@ -347,6 +373,29 @@ int hh_net_set_scaling(hh_ctx* ctx, hh_net* net, const double mean[21], const do
   });
 }
 
+int hh_net_set_fraction_scaling(hh_ctx* ctx, hh_net* net, const double mean[8], const double scale[8]) {
+  return guarded(ctx, [&]() -> int {
+    if (!net || !mean || !scale) fail(ctx, HH_EINVAL, "null argument");
+    for (int i = 0; i < kFrac; ++i)
+      if (!std::isfinite(mean[i]) || !std::isfinite(scale[i])) fail(ctx, HH_EINVAL, "non-finite scaling");
+    for (int i = 0; i < kFrac; ++i) {
+      net->fmu[i] = mean[i];
+      net->fsc[i] = scale[i];
+    }
+    upload_fraction_scaling(ctx, net);
+    return HH_OK;
+  });
+}
+
+int hh_net_get_fraction_scaling(const hh_net* net, double mean[8], double scale[8]) {
+  if (!net || !mean || !scale) return HH_EINVAL;
+  for (int i = 0; i < kFrac; ++i) {
+    mean[i] = net->fmu[i];
+    scale[i] = net->fsc[i];
+  }
+  return HH_OK;
+}
+
 int hh_net_get_scaling(const hh_net* net, double mean[21], double scale[21]) {
   if (!net || !mean || !scale) return HH_EINVAL;
   for (int i = 0; i < kOut; ++i) {
@@ -365,7 +414,7 @@ int hh_net_forward(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_o
     ensure_acts(ctx, net, batch);
     forward(ctx, net, d, batch, box, offset);
     const int V = edge(net, 3) / 2;
-    k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->p + net->fcw_off, net->p + net->fcb_off,
+    k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->frac, net->p + net->fcw_off, net->p + net->fcb_off,
                                           net->out, nullptr, nullptr, nullptr, nullptr, 0.0f);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, net->out, sizeof(float) * batch * kOut, hipMemcpyDeviceToHost, ctx->stream));

@@ -4,7 +4,9 @@
 //
 // Network (all convolutions 3x3x3, stride 2, zero padding 1, bias, ReLU):
 //   one-hot [P <= 8 channels, padded to 8] n^3 -> 32 ch (n/2)^3 -> 32 ch (n/4)^3
-//   -> 64 ch (n/8)^3 -> 64 ch (n/16)^3 -> global mean -> linear 64 -> 21.
+//   -> 64 ch (n/8)^3 -> 64 ch (n/16)^3 -> global mean (64 features), plus the
+//   window's 8 standardized phase fractions (a skip path from the input) ->
+//   linear 72 -> 21.
 // Activations are channels-last BF16 [b][z][y][x][c]; activation gradients
 // FP32; parameters FP32 master copies with BF16 working copies [tap][cout][cin]
 // (forward) and [tap][cin][cout] (data gradient).
@@ -302,27 +304,60 @@ __global__ void k_reduce_parts(const float* __restrict__ part, int nchunk, long 
 }
 
 // ---------------------------------------------------------------------------
-// head: global mean over V voxels of the last activation (C = 64 channels),
-// linear 64 -> 21, and (training) squared loss against targets with its
-// gradients.  One block of 64 threads per item.
+// phase fractions of each input window (the mean of the one-hot input), as
+// standardized features for the head: frac[b][c] = (f_c - mu_c) * sc_c.
+// One block of 256 threads per item; labels >= 8 count in no channel.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V, const float* __restrict__ Wfc,
-                                             const float* __restrict__ bfc, float* __restrict__ out,
-                                             const float* __restrict__ target, float* __restrict__ dA,
-                                             float* __restrict__ dW_item, float* __restrict__ loss_item,
-                                             float inv_count) {
-  constexpr int C = 64, O = 21;
-  __shared__ float feat[C];
+__global__ void __launch_bounds__(256) k_fractions(const unsigned char* __restrict__ labels, long long item_stride,
+                                                   int box, int o, int n, const float* __restrict__ mu,
+                                                   const float* __restrict__ sc, float* __restrict__ frac) {
+  __shared__ int cnt[8];
+  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const unsigned char* L = labels + blockIdx.x * item_stride;
+  const int nn = n * n;
+  const long long nv = (long long)nn * n;
+  int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long v = threadIdx.x; v < nv; v += blockDim.x) {
+    const int z = int(v / nn), y = int((v / n) % n), x = int(v % n);
+    const int lab = L[((long long)(z + o) * box + (y + o)) * box + (x + o)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] += (lab == k) ? 1 : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (c[k]) atomicAdd(&cnt[k], c[k]);
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int k = threadIdx.x;
+    frac[blockIdx.x * 8 + k] = (float(double(cnt[k]) / double(nv)) - mu[k]) * sc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// head: global mean over V voxels of the last activation (64 channels), the
+// 8 standardized phase fractions appended (72 features), linear 72 -> 21,
+// and (training) squared loss against targets with its gradients.  Only the
+// 64 pooled features pass a gradient back.  One block of 64 threads per item.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V, const float* __restrict__ frac,
+                                             const float* __restrict__ Wfc, const float* __restrict__ bfc,
+                                             float* __restrict__ out, const float* __restrict__ target,
+                                             float* __restrict__ dA, float* __restrict__ dW_item,
+                                             float* __restrict__ loss_item, float inv_count) {
+  constexpr int C = 64, F = 72, O = 21;
+  __shared__ float feat[F];
   __shared__ float dout[O];
   const int b = blockIdx.x, c = threadIdx.x;
   const __bf16* Ab = A + (long long)b * V * C;
   float s = 0.0f;
   for (int v = 0; v < V; ++v) s += (float)Ab[(long long)v * C + c];
   feat[c] = s / float(V);
+  if (c < F - C) feat[C + c] = frac[b * (F - C) + c];
   __syncthreads();
   if (c < O) {
     float y = bfc[c];
-    for (int k = 0; k < C; ++k) y += Wfc[c * C + k] * feat[k];
+    for (int k = 0; k < F; ++k) y += Wfc[c * F + k] * feat[k];
     out[b * O + c] = y;
     if (target) dout[c] = 2.0f * (y - target[b * O + c]) * inv_count;
   }
@@ -337,11 +372,11 @@ __global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V
     loss_item[b] = l * inv_count;
   }
   // parameter gradients of this item: dW[o][k] = dout[o] feat[k], db[o] = dout[o]
-  for (int e = c; e < O * C; e += C) dW_item[(long long)b * (O * C + O) + e] = dout[e / C] * feat[e % C];
-  if (c < O) dW_item[(long long)b * (O * C + O) + O * C + c] = dout[c];
+  for (int e = c; e < O * F; e += C) dW_item[(long long)b * (O * F + O) + e] = dout[e / F] * feat[e % F];
+  if (c < O) dW_item[(long long)b * (O * F + O) + O * F + c] = dout[c];
   // dfeat[k] = sum_o dout[o] W[o][k]; the mean spreads it evenly over V voxels
   float g = 0.0f;
-  for (int o = 0; o < O; ++o) g += dout[o] * Wfc[o * C + c];
+  for (int o = 0; o < O; ++o) g += dout[o] * Wfc[o * F + c];
   g /= float(V);
   for (int v = 0; v < V; ++v) dA[((long long)b * V + v) * C + c] = g;
 }

@@ -30,7 +30,8 @@ SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_la
            "hh_workspace_bytes", "hh_release_workspace", "hh_size_supported", "hh_homogenize",
            "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_gather_subimages",
            "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_get_params",
-           "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_forward",
+           "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling",
+           "hh_net_get_fraction_scaling", "hh_net_forward",
            "hh_net_gradient", "hh_net_train_step", "hh_net_predict", "hh_hierarchical_surrogate",
            "hh_richardson", "hh_moduli")
 
@@ -111,6 +112,8 @@ def load_library(path=LIB_PATH):
     lib.hh_net_set_params.argtypes = [P, P, FP, LL]
     lib.hh_net_set_scaling.argtypes = [P, P, DP, DP]
     lib.hh_net_get_scaling.argtypes = [P, DP, DP]
+    lib.hh_net_set_fraction_scaling.argtypes = [P, P, DP, DP]
+    lib.hh_net_get_fraction_scaling.argtypes = [P, DP, DP]
     lib.hh_net_forward.argtypes = [P, P, P, I, I, I, I, FP]
     lib.hh_net_gradient.argtypes = [P, P, P, I, I, I, I, FP, FP, FP]
     lib.hh_net_train_step.argtypes = [P, P, P, I, I, I, I, P, I, ct.c_float, FP]
@@ -426,6 +429,18 @@ class Net:
         rc = self._lib.hh_net_get_scaling(self._h, _dptr(m), _dptr(s))
         if rc != HH_OK:
             raise HHError(rc, "hh_net_get_scaling")
+        return m, s
+
+    def set_fraction_scaling(self, mean, scale):
+        m = np.ascontiguousarray(np.asarray(mean, dtype=np.float64).reshape(8))
+        s = np.ascontiguousarray(np.asarray(scale, dtype=np.float64).reshape(8))
+        self.ctx._check(self._lib.hh_net_set_fraction_scaling(self.ctx._h, self._h, _dptr(m), _dptr(s)))
+
+    def get_fraction_scaling(self):
+        m, s = np.zeros(8), np.zeros(8)
+        rc = self._lib.hh_net_get_fraction_scaling(self._h, _dptr(m), _dptr(s))
+        if rc != HH_OK:
+            raise HHError(rc, "hh_net_get_fraction_scaling")
         return m, s
 
     def _labels(self, labels, offset):

@@ -1,0 +1,302 @@
+"""Training and use of the CNN surrogate of the subimage stiffness.
+
+The surrogate stands in for the FFT solve of Sec. 4 on each padded
+subimage: a network maps the one-hot phase labels of the n^3 core to the 21
+independent components of the subimage's stiffness C_R.  Training data are
+subimages that the library's own FFT solver homogenizes (the same padding
+p as at use), so the solver remains the judge of the network's error, and
+at use a gate sends doubtful subimages back to it.
+
+Everything numeric runs in the HIP library (network kernels, solver,
+gather); this module only arranges data and calls the bindings.  Label
+boxes and targets stay in device memory; the 48 symmetries of the cube
+(axis permutations and reflections) multiply the training set, with the
+stiffness transformed alongside each box.
+
+Command line (trains and saves two networks for the spread gate):
+    python -m paper_2208_02320_amd.surrogate --out DIR [--images K ...]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import hh, synth
+
+UPPER = [(i, j) for i in range(6) for j in range(i, 6)]
+VOIGT = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]  # index pairs of 11,22,33,23,13,12
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+
+# ---------------------------------------------------------------------------
+# symmetries of the cube
+# ---------------------------------------------------------------------------
+def cube_symmetries():
+    """The 48 signed axis permutations (p, s): x'_i = s_i x_{p(i)}, with
+    physical axes 0 = x, 1 = y, 2 = z."""
+    out = []
+    for p in itertools.permutations(range(3)):
+        for s in itertools.product((1, -1), repeat=3):
+            out.append((tuple(p), tuple(s)))
+    return out
+
+
+def sym_matrix(p, s):
+    Q = np.zeros((3, 3))
+    for i in range(3):
+        Q[i, p[i]] = s[i]
+    return Q
+
+
+def _voigt_to_tensor(C):
+    T = np.zeros((3, 3, 3, 3))
+    for I, (i, j) in enumerate(VOIGT):
+        for J, (k, l) in enumerate(VOIGT):
+            for a, b in ((i, j), (j, i)):
+                for c, d in ((k, l), (l, k)):
+                    T[a, b, c, d] = C[I, J]
+    return T
+
+
+def _tensor_to_voigt(T):
+    return np.array([[T[i, j, k, l] for (k, l) in VOIGT] for (i, j) in VOIGT])
+
+
+def c21_transform(p, s):
+    """21 x 21 matrix taking the upper-triangle stiffness of a material to
+    that of the material mapped by x -> Q x (C'_ijkl = Q_ia Q_jb Q_kc Q_ld C_abcd)."""
+    Q = sym_matrix(p, s)
+    T = np.zeros((21, 21))
+    for m, (a, b) in enumerate(UPPER):
+        C = np.zeros((6, 6))
+        C[a, b] = C[b, a] = 1.0
+        R = np.einsum("ia,jb,kc,ld,abcd->ijkl", Q, Q, Q, Q, _voigt_to_tensor(C))
+        V = _tensor_to_voigt(R)
+        T[:, m] = [V[i, j] for (i, j) in UPPER]
+    return T
+
+
+def transform_boxes(boxes, p, s):
+    """Apply x -> Q x to label boxes (..., z, y, x) (a torch tensor or a
+    numpy array): new physical axis i is old axis p(i), reversed where s_i < 0."""
+    nd = boxes.ndim
+    lead = list(range(nd - 3))
+    # tensor dim of physical axis a is nd - 1 - a
+    perm = lead + [nd - 1 - p[nd - 1 - d] for d in range(nd - 3, nd)]
+    flips = [d for d in range(nd - 3, nd) if s[nd - 1 - d] < 0]
+    if type(boxes).__module__.startswith("torch"):
+        out = boxes.permute(*perm)
+        if flips:
+            out = out.flip(flips)
+        return out.contiguous()
+    out = np.transpose(boxes, perm)
+    if flips:
+        out = np.flip(out, axis=flips)
+    return np.ascontiguousarray(out)
+
+
+def mandel_weights():
+    """Weights w such that sum w c^2 is the squared Frobenius norm of the
+    Mandel-scaled matrix (the tensor norm)."""
+    w = []
+    for (i, j) in UPPER:
+        f = (np.sqrt(2.0) if i >= 3 else 1.0) * (np.sqrt(2.0) if j >= 3 else 1.0)
+        w.append(f * f * (1.0 if i == j else 2.0))
+    return np.asarray(w)
+
+
+def rel_error21(c, ref):
+    """Per-item relative tensor-norm error of (m, 21) stiffnesses."""
+    w = mandel_weights()
+    c, ref = np.atleast_2d(c), np.atleast_2d(ref)
+    return np.sqrt(((c - ref) ** 2 * w).sum(-1) / (ref ** 2 * w).sum(-1))
+
+
+# ---------------------------------------------------------------------------
+# data
+# ---------------------------------------------------------------------------
+@dataclass
+class Dataset:
+    boxes: object                 # device uint8 tensor (m, b, b, b)
+    c21: np.ndarray               # (m, 21) FFT-solver stiffness of each padded box
+    n: int                        # core edge
+    pad: int
+    seeds: list = field(default_factory=list)
+    solve_seconds: float = 0.0
+
+    @property
+    def box(self):
+        return self.n + 2 * self.pad
+
+    def split(self, count):
+        """(first m - count items, last count items)."""
+        m = self.c21.shape[0]
+        a = Dataset(self.boxes[:m - count], self.c21[:m - count], self.n, self.pad, self.seeds)
+        b = Dataset(self.boxes[m - count:], self.c21[m - count:], self.n, self.pad, self.seeds)
+        return a, b
+
+
+def label_images(ctx, seeds, size, n_sub, pad, sigma=2.0, tol=1e-5, log=print):
+    """Cut four-phase device images (one per seed, edge ``size``) into padded
+    subimages and homogenize each with the FFT solver."""
+    import torch
+    boxes, c21 = [], []
+    t_solve = 0.0
+    for k, seed in enumerate(seeds):
+        img = synth.four_phase_device(size, sigma=sigma, seed=seed, device="cuda:%d" % ctx.device)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, Cs, rep = ctx.hierarchical(img, synth.FOUR_PHASE["phases"], n_sub, pad, tol=tol)
+        t_solve += time.time() - t0
+        boxes.append(ctx.gather_subimages(img, n_sub, pad))
+        c21.append(Cs.copy())
+        del img
+        if log:
+            log("labelled image %d/%d (seed %d): %d subimages, %.1fs" % (k + 1, len(seeds), seed, Cs.shape[0],
+                                                                      time.time() - t0))
+    return Dataset(torch.cat(boxes), np.concatenate(c21), n_sub, pad, list(seeds), t_solve)
+
+
+def fraction_stats(data, nch=8):
+    """Mean and inverse standard deviation of each label's fraction in the
+    cores of the data set (scale 0 for labels that never vary)."""
+    import torch
+    p, n = data.pad, data.n
+    core = data.boxes[:, p:p + n, p:p + n, p:p + n]
+    f = torch.stack([(core == c).float().mean(dim=(1, 2, 3)) for c in range(nch)], dim=1).double().cpu().numpy()
+    mu, sd = f.mean(axis=0), f.std(axis=0)
+    return mu, np.where(sd > 1e-6, 1.0 / np.maximum(sd, 1e-6), 0.0)
+
+
+def symmetric_scaling(c21, syms=None):
+    """Mean and standard deviation per component over the data set and all
+    its symmetric images (floor 1e-3 of the largest)."""
+    syms = syms or cube_symmetries()
+    allc = np.concatenate([c21 @ c21_transform(p, s).T for p, s in syms])
+    mean = allc.mean(axis=0)
+    sd = allc.std(axis=0)
+    return mean, np.maximum(sd, 1e-3 * sd.max())
+
+
+# ---------------------------------------------------------------------------
+# training
+# ---------------------------------------------------------------------------
+def train(ctx, data, nphase, epochs=20, batch=32, lr=1e-3, lr_final=2e-5, seed=0, augment=True, log=print,
+          log_every=200, val=None):
+    """Train a network on ``data``; returns (net, history)."""
+    import torch
+    syms = cube_symmetries() if augment else [((0, 1, 2), (1, 1, 1))]
+    mats = [c21_transform(p, s) for p, s in syms]
+    mean, scale = symmetric_scaling(data.c21, syms)
+    net = hh.Net(ctx, nphase, data.n, seed=seed)
+    net.set_scaling(mean, scale)
+    net.set_fraction_scaling(*fraction_stats(data))
+    dev = "cuda:%d" % ctx.device
+    m = data.c21.shape[0]
+    steps_per_epoch = max(1, m // batch)
+    total = epochs * steps_per_epoch
+    rng = np.random.default_rng(seed)
+    hist = []
+    step = 0
+    t0 = time.time()
+    for ep in range(epochs):
+        order = rng.permutation(m)
+        run = 0.0
+        for j in range(steps_per_epoch):
+            idx = order[j * batch:(j + 1) * batch]
+            k = int(rng.integers(len(syms)))
+            p, s = syms[k]
+            ti = torch.from_numpy(idx).to(dev)
+            lab = transform_boxes(data.boxes.index_select(0, ti), p, s)
+            tgt = (data.c21[idx] @ mats[k].T - mean) / scale
+            tdev = torch.from_numpy(tgt.astype(np.float32)).to(dev)
+            frac = step / max(1, total - 1)
+            rate = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * frac))
+            loss = net.train_step(lab, tdev, rate, offset=data.pad)
+            run += loss
+            step += 1
+            if log and log_every and step % log_every == 0:
+                log("step %d/%d epoch %d loss %.4e lr %.2e (%.0fs)" % (step, total, ep, loss, rate,
+                                                                     time.time() - t0))
+        rec = dict(epoch=ep, loss=run / steps_per_epoch, seconds=time.time() - t0)
+        if val is not None:
+            e = rel_error21(predict(net, val), val.c21)
+            rec.update(val_mean=float(e.mean()), val_p95=float(np.quantile(e, 0.95)))
+        hist.append(rec)
+        if log:
+            log("epoch %d: %s" % (ep, json.dumps(rec)))
+    return net, hist
+
+
+def predict(net, data, chunk=512):
+    out = []
+    for a in range(0, data.c21.shape[0], chunk):
+        out.append(net.predict(data.boxes[a:a + chunk], offset=data.pad))
+    return np.concatenate(out)
+
+
+def save(net, path, meta=None):
+    mean, scale = net.get_scaling()
+    fmu, fsc = net.get_fraction_scaling()
+    np.savez_compressed(path, params=net.get_params(), mean=mean, scale=scale, fmu=fmu, fsc=fsc, n=net.n,
+                        nphase=net.nphase, meta=json.dumps(meta or {}))
+
+
+def load(ctx, path):
+    z = np.load(path, allow_pickle=False)
+    net = hh.Net(ctx, int(z["nphase"]), int(z["n"]))
+    net.set_params(z["params"])
+    net.set_scaling(z["mean"], z["scale"])
+    net.set_fraction_scaling(z["fmu"], z["fsc"])
+    net.meta = json.loads(str(z["meta"]))
+    return net
+
+
+def default_weights(n=64, pad=8, directory=None):
+    """Paths of the two shipped networks for four-phase subimages."""
+    return [os.path.join(directory or WEIGHTS_DIR, "four_phase_n%d_p%d_%s.npz" % (n, pad, t)) for t in ("a", "b")]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", default=WEIGHTS_DIR)
+    ap.add_argument("--images", type=int, default=40, help="training images (seeds 10000, 10001, ...)")
+    ap.add_argument("--val-images", type=int, default=2)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--pad", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--nets", type=int, default=2)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    ctx = hh.Context(0)
+    seeds = list(range(10000, 10000 + a.images))
+    vseeds = list(range(20000, 20000 + a.val_images))
+    data = label_images(ctx, seeds, a.size, a.n, a.pad, tol=a.tol, log=log)
+    val = label_images(ctx, vseeds, a.size, a.n, a.pad, tol=a.tol, log=log)
+    os.makedirs(a.out, exist_ok=True)
+    for k in range(a.nets):
+        net, hist = train(ctx, data, 4, epochs=a.epochs, batch=a.batch, lr=a.lr, seed=k + 1, log=log, val=val)
+        err = rel_error21(predict(net, val), val.c21)
+        meta = dict(images=seeds, val_images=vseeds, size=a.size, n=a.n, pad=a.pad, epochs=a.epochs,
+                    batch=a.batch, lr=a.lr, tol=a.tol, seed=k + 1, items=int(data.c21.shape[0]),
+                    val_mean=float(err.mean()), val_p95=float(np.quantile(err, 0.95)), history=hist)
+        path = os.path.join(a.out, "four_phase_n%d_p%d_%s.npz" % (a.n, a.pad, "ab"[k] if k < 2 else str(k)))
+        save(net, path, meta)
+        log("saved %s: validation error mean %.3e p95 %.3e" % (path, err.mean(), np.quantile(err, 0.95)))
+
+
+if __name__ == "__main__":
+    main()

@@ -145,3 +145,69 @@ def correlation_x(labels, solid_label=0, max_lag=10):
     for l in range(max_lag + 1):
         out.append(((m * np.roll(m, -l, axis=2)).mean() - mean * mean) / var)
     return np.asarray(out)
+
+
+# ---------------------------------------------------------------------------
+# The same recipe on a torch device, for images too large to make quickly on
+# the host (the 1024^3 surrogate workload and its training images).  Same
+# steps - standard-normal noise, periodic Gaussian smoothing with the kernel
+# sampled at integer offsets up to 4 sigma and normalised to sum 1, quantile
+# thresholds with linear interpolation - but a different random stream, so the
+# images are statistically, not bitwise, equal to the host generator's.
+# ---------------------------------------------------------------------------
+def smoothed_noise_device(shape, sigma, seed, device="cuda"):
+    import torch
+    shape = tuple(int(s) for s in shape)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    w = torch.randn(shape, generator=gen, device=device, dtype=torch.float32)
+    if sigma > 0:
+        r = int(4.0 * sigma + 0.5)
+        x = np.arange(-r, r + 1, dtype=np.float64)
+        k = np.exp(-0.5 * (x / sigma) ** 2)
+        k /= k.sum()
+        for axis in range(3):
+            acc = torch.zeros_like(w)
+            for j, kj in enumerate(k):
+                acc.add_(torch.roll(w, shifts=r - j, dims=axis), alpha=float(kj))
+            w = acc
+    return w
+
+
+def threshold_device(values, fracs, low_to_high):
+    import torch
+    fracs = np.asarray(fracs, dtype=np.float64)
+    if np.any(fracs < 0) or abs(fracs.sum() - 1.0) > 1e-9:
+        raise ValueError("fractions must be non-negative and sum to 1")
+    order = list(low_to_high)
+    if sorted(order) != list(range(len(fracs))):
+        raise ValueError("low_to_high must be a permutation of the labels")
+    cum = np.cumsum([fracs[l] for l in order])[:-1]
+    flat = values.reshape(-1)
+    srt = torch.sort(flat).values
+    n = flat.numel()
+    cuts = []
+    for q in cum:
+        pos = q * (n - 1)
+        lo = int(np.floor(pos))
+        hi = min(lo + 1, n - 1)
+        a, b = float(srt[lo]), float(srt[hi])
+        cuts.append(a + (pos - lo) * (b - a))
+    del srt
+    bins = torch.bucketize(flat, torch.tensor(cuts, dtype=flat.dtype, device=flat.device), right=True)
+    lut = torch.tensor(order, dtype=torch.uint8, device=flat.device)
+    return lut[bins].reshape(values.shape)
+
+
+def rocklike_device(shape, fracs, sigma=2.0, seed=0, low_to_high=None, device="cuda"):
+    """Rock-like periodic label image as a uint8 torch tensor on ``device``."""
+    if np.isscalar(shape):
+        shape = (int(shape),) * 3
+    if low_to_high is None:
+        low_to_high = list(range(len(fracs)))[::-1]
+    v = smoothed_noise_device(shape, sigma, seed, device)
+    return threshold_device(v, fracs, low_to_high).contiguous()
+
+
+def four_phase_device(n, sigma=2.0, seed=1, device="cuda"):
+    return rocklike_device(n, FOUR_PHASE["fracs"], sigma, seed, FOUR_PHASE["low_to_high"], device)

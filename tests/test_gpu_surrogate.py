@@ -42,10 +42,15 @@ def boxes(batch, box, nphase, seed):
     return out
 
 
-def net_with(ctx, nphase, n, params):
+FSTATS = (np.linspace(0.05, 0.4, 8), np.linspace(3.0, 25.0, 8))
+
+
+def net_with(ctx, nphase, n, params, fstats=FSTATS):
     from paper_2208_02320_amd import hh
     net = hh.Net(ctx, nphase, n)
     net.set_params(params)
+    if fstats is not None:
+        net.set_fraction_scaling(*fstats)
     return net
 
 
@@ -57,7 +62,7 @@ def test_forward_matches_oracle(ctx, n, batch, nphase):
     net = net_with(ctx, nphase, n, p)
     y = net.forward(lab, offset=pad)
     core = lab[:, pad:pad + n, pad:pad + n, pad:pad + n]
-    yr, _ = ref.forward(p.astype(np.float64), core, bf=True)
+    yr, _ = ref.forward(p.astype(np.float64), core, bf=True, fstats=FSTATS)
     scale = max(1.0, np.abs(yr).max())
     err = np.abs(y - yr).max() / scale
     print("forward n=%d batch=%d err %.2e" % (n, batch, err))
@@ -73,7 +78,7 @@ def test_gradient_matches_oracle(ctx):
     net = net_with(ctx, nphase, n, p)
     loss, grad = net.gradient(lab, tgt, offset=pad)
     core = lab[:, pad:pad + n, pad:pad + n, pad:pad + n]
-    lr, gr = ref.loss_and_grad(p.astype(np.float64), core, tgt.astype(np.float64), bf=True)
+    lr, gr = ref.loss_and_grad(p.astype(np.float64), core, tgt.astype(np.float64), bf=True, fstats=FSTATS)
     assert abs(loss - lr) <= 1e-3 * lr
     lay, _ = ref.layout()
     for name, off, shp in lay:
@@ -134,6 +139,9 @@ def test_predict_applies_scaling(ctx):
     net.set_scaling(mean, scale)
     m2, s2 = net.get_scaling()
     assert np.array_equal(m2, mean) and np.array_equal(s2, scale)
+    net.set_fraction_scaling(*FSTATS)
+    f2, g2 = net.get_fraction_scaling()
+    assert np.array_equal(f2, FSTATS[0]) and np.array_equal(g2, FSTATS[1])
     y = net.forward(lab).astype(np.float64)
     c = net.predict(lab)
     assert np.abs(c - (y * scale + mean)).max() < 1e-12 * np.abs(c).max()
@@ -227,3 +235,36 @@ def test_surrogate_argument_errors(ctx):
     with pytest.raises(hh.HHError):
         net.set_params(np.zeros(5, np.float32))
     net.close()
+
+
+def test_trained_network_gains_over_the_method_without_it(ctx):
+    """Train on FFT-labelled subimages, then compare on held-out subimages:
+    the trained network must beat the best constant stiffness and the Hill
+    average of each subimage's phase fractions, and the surrogate hierarchy
+    must replace most FFT work while staying close to the plain hierarchy."""
+    from paper_2208_02320_amd import surrogate as sur
+    n, pad = 16, 4
+    data = sur.label_images(ctx, [10000, 10001, 10002, 10003], 64, n, pad, tol=1e-5, log=None)
+    val = sur.label_images(ctx, [20000], 64, n, pad, tol=1e-5, log=None)
+    nets = [sur.train(ctx, data, 4, epochs=60, batch=16, lr=2e-3, seed=s, log=None)[0] for s in (1, 2)]
+    e_net = sur.rel_error21(sur.predict(nets[0], val), val.c21)
+    e_const = sur.rel_error21(np.broadcast_to(data.c21.mean(axis=0), val.c21.shape), val.c21)
+    boxes_h = val.boxes.cpu().numpy()
+    hill = []
+    for b in boxes_h:
+        cv, cr = sg.core_bounds(b, pad, n, FOUR)
+        hill.append(hier.to21(0.5 * (cv + cr)))
+    e_hill = sur.rel_error21(np.array(hill), val.c21)
+    print("held-out error: network %.4f, constant %.4f, Hill %.4f" % (e_net.mean(), e_const.mean(), e_hill.mean()))
+    assert e_net.mean() < 0.75 * min(e_const.mean(), e_hill.mean())
+    img = synth.four_phase_device(64, seed=20000, device="cuda:0")
+    Cp, Csp, rp = ctx.hierarchical(img, FOUR, n, pad, tol=1e-5)
+    C, Cs, fb, rs = ctx.hierarchical_surrogate(img, FOUR, n, pad, nets[0], nets[1], spread_tol=0.1,
+                                               bound_tol=0.0, tol=1e-5)
+    err = g.rel_error(C, Cp)
+    print("surrogate hierarchy: fallback %d/%d, FFT voxel-iters %.3g vs %.3g, C* error %.2e" %
+          (fb.sum(), fb.size, rs["voxel_iters"], rp["voxel_iters"], err))
+    assert rs["voxel_iters"] < 0.8 * rp["voxel_iters"]
+    assert err < 1e-2
+    for net in nets:
+        net.close()

@@ -19,7 +19,8 @@ def test_gradient_matches_finite_differences():
     labels = rng.integers(0, 3, size=(2, 16, 16, 16))
     flat = cnn.init_params(3, seed=2)
     target = rng.standard_normal((2, 21))
-    loss, g = cnn.loss_and_grad(flat, labels, target)
+    fst = (rng.random(8) * 0.5, 1.0 + rng.random(8) * 20.0)
+    loss, g = cnn.loss_and_grad(flat, labels, target, fstats=fst)
     lay, n = cnn.layout()
     idx = []
     for name, off, shp in lay:
@@ -34,10 +35,21 @@ def test_gradient_matches_finite_differences():
     for i in idx:
         e = np.zeros(n)
         e[i] = h
-        lp, _ = cnn.loss_and_grad(flat + e, labels, target)
-        lm, _ = cnn.loss_and_grad(flat - e, labels, target)
+        lp, _ = cnn.loss_and_grad(flat + e, labels, target, fstats=fst)
+        lm, _ = cnn.loss_and_grad(flat - e, labels, target, fstats=fst)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (i, fd, g[i])
+
+
+def test_fraction_features_are_phase_fractions():
+    rng = np.random.default_rng(3)
+    labels = rng.integers(0, 9, size=(3, 8, 8, 8))  # label 8 lies outside the 8 channels
+    f = cnn.fraction_features(labels)
+    for b in range(3):
+        cnt = np.bincount(labels[b].ravel(), minlength=9)[:8]
+        assert np.array_equal(f[b], cnt / 512.0)
+    mu, sc = np.full(8, 0.1), np.arange(8.0)
+    assert np.allclose(cnn.fraction_features(labels, (mu, sc)), (f - 0.1) * sc)
 
 
 def test_bf16_rounding():
@@ -50,7 +62,7 @@ def test_bf16_rounding():
 
 def test_layout_size():
     _, n = cnn.layout()
-    assert n == 27 * 32 * 8 + 32 + 27 * 32 * 32 + 32 + 27 * 64 * 32 + 64 + 27 * 64 * 64 + 64 + 21 * 64 + 21
+    assert n == 27 * 32 * 8 + 32 + 27 * 32 * 32 + 32 + 27 * 64 * 32 + 64 + 27 * 64 * 64 + 64 + 21 * 72 + 21
 
 
 # ---------------------------------------------------------------------------
