@@ -264,9 +264,60 @@ def bench_surrogate(args):
     ctx.close()
 
 
+def bench_cnn(args):
+    """Network kernels alone: inference over the 4096 padded 64^3 subimages of
+    the 1024^3 surrogate workload, and Adam training steps at batch 32."""
+    import torch
+    from paper_2208_02320_amd import hh, surrogate, synth
+    n, pad = 64, 8
+    ctx = hh.Context(0)
+    net = surrogate.load(ctx, surrogate.default_weights(n, pad, args.weights_dir)[0])
+    img = synth.four_phase_device(args.sur_size, sigma=2.0, seed=3, device="cuda:0")
+    pack = ctx.gather_subimages(img, n, pad)
+    del img
+    items = pack.shape[0]
+    fl = conv_flops_per_item(n, 4)
+    net.predict(pack[:64], offset=pad)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(args.steps):
+        net.predict(pack, offset=pad)
+    ev[1].record()
+    torch.cuda.synchronize()
+    inf_s = ev[0].elapsed_time(ev[1]) * 1e-3 / args.steps
+    B = 32
+    tgt = torch.zeros((B, 21), dtype=torch.float32, device="cuda:0")
+    lab = pack[:B].contiguous()
+    for _ in range(3):
+        net.train_step(lab, tgt, 1e-6, offset=pad)
+    nsteps = 20 * args.steps
+    torch.cuda.synchronize()
+    ev[2].record()
+    for _ in range(nsteps):
+        net.train_step(lab, tgt, 1e-6, offset=pad)
+    ev[3].record()
+    torch.cuda.synchronize()
+    tr_s = ev[2].elapsed_time(ev[3]) * 1e-3 / nsteps
+    inf_tf = fl * items / inf_s / 1e12
+    line = {
+        "metric": "subimages/s of network inference", "value": items / inf_s, "unit": "subimages/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": inf_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "CNN surrogate on %d padded 64^3 four-phase subimages (core input)" % items},
+        "train_ms_per_step_batch32": tr_s * 1e3,
+        "train_items_per_s": B / tr_s,
+        "roofline": {"bound": "mfma", "kernel": "network forward (4 BF16 convolutions + head)",
+                     "achieved": round(inf_tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(inf_tf / 2500.0, 5), "traffic": None, "algorithmic_flops_per_item": fl},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate"), default="solve256")
+    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "cnn"), default="solve256")
     ap.add_argument("--sur-size", type=int, default=1024)
     ap.add_argument("--weights-dir", default=None)
     ap.add_argument("--spread-tol", type=float, default=0.02)
@@ -290,6 +341,8 @@ def main():
         return bench_uneven(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "cnn":
+        return bench_cnn(args)
 
     import torch
     from paper_2208_02320_amd import hh, synth

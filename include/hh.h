@@ -227,7 +227,8 @@ int hh_net_predict(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_o
 
 /*
  * Two-level scheme with the surrogate: the subimage stiffnesses come from
- * the network(s) on the n_sub^3 core of every padded box, a gate sends an
+ * the network(s) on every padded box, each network reading the n_sub^3 core
+ * or the whole (n_sub + 2 pad)^3 box as its input edge says; a gate sends an
  * item to the FFT solver (the hh_hierarchical path) when the mean prediction
  * is not positive definite, leaves the Voigt-Reuss bracket of the core's
  * phase fractions by more than bound_tol (relative, Mandel norm), or - with

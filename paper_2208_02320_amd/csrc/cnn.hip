@@ -39,10 +39,11 @@ struct hh_net {
   float *d_fmu = nullptr, *d_fsc = nullptr;
   long long step = 0;
   int cap = 0;  // batch capacity of the activation buffers
-  __bf16* x0 = nullptr;
+  LabelWindow lw{};  // input of the last forward pass (read again by the first layer's weight gradient)
+  int* cnt = nullptr;  // label counts per item [cap][8]
   __bf16* a[kLayers] = {};
   float* ga[kLayers] = {};  // gradient w.r.t. output of layer l
-  float *out = nullptr, *tgt = nullptr, *hw = nullptr, *loss = nullptr, *frac = nullptr;
+  float *out = nullptr, *tgt = nullptr, *hw = nullptr, *loss = nullptr;
   float* part = nullptr;
   size_t part_n = 0;
   float* pbias = nullptr;
@@ -53,8 +54,8 @@ namespace {
 int edge(const hh_net* net, int l) { return net->n >> l; }  // input edge of layer l
 
 void free_acts(hh_net* net) {
-  (void)hipFree(net->x0);
-  net->x0 = nullptr;
+  (void)hipFree(net->cnt);
+  net->cnt = nullptr;
   for (int l = 0; l < kLayers; ++l) {
     (void)hipFree(net->a[l]);
     (void)hipFree(net->ga[l]);
@@ -67,8 +68,7 @@ void free_acts(hh_net* net) {
   (void)hipFree(net->loss);
   (void)hipFree(net->part);
   (void)hipFree(net->pbias);
-  (void)hipFree(net->frac);
-  net->out = net->tgt = net->hw = net->loss = net->part = net->pbias = net->frac = nullptr;
+  net->out = net->tgt = net->hw = net->loss = net->part = net->pbias = nullptr;
   net->cap = 0;
 }
 
@@ -82,8 +82,12 @@ T* dalloc(hh_ctx* ctx, size_t count) {
   return static_cast<T*>(p);
 }
 
+// Voxels per weight-gradient chunk: at most kMaxChunks chunks for any total
+// (chunk >= total / kMaxChunks), each a multiple of the 32-voxel MFMA step.
+constexpr int kMaxChunks = 128;
+
 int wgrad_chunk(long long total) {
-  long long c = (total + 127) / 128;
+  long long c = (total + kMaxChunks - 1) / kMaxChunks;
   c = (c + 31) / 32 * 32;
   return int(std::max<long long>(c, 32));
 }
@@ -92,23 +96,20 @@ void ensure_acts(hh_ctx* ctx, hh_net* net, int batch) {
   if (batch <= net->cap) return;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   free_acts(net);
-  const long long n = net->n;
-  net->x0 = dalloc<__bf16>(ctx, size_t(batch) * n * n * n * 8);
+  net->cnt = dalloc<int>(ctx, size_t(batch) * kFrac);
   size_t pmax = 0, bmax = 0;
   for (int l = 0; l < kLayers; ++l) {
     const long long Do = edge(net, l) / 2, nv = Do * Do * Do;
     net->a[l] = dalloc<__bf16>(ctx, size_t(batch) * nv * kCout[l]);
     net->ga[l] = dalloc<float>(ctx, size_t(batch) * nv * kCout[l]);
-    const long long total = nv * batch;
-    const long long nch = (total + wgrad_chunk(total) - 1) / wgrad_chunk(total);
-    pmax = std::max<size_t>(pmax, size_t(nch) * 27 * kCout[l] * kCin[l]);
-    bmax = std::max<size_t>(bmax, size_t(nch) * kCout[l]);
+    // any batch up to the capacity needs at most kMaxChunks partials
+    pmax = std::max<size_t>(pmax, size_t(kMaxChunks) * 27 * kCout[l] * kCin[l]);
+    bmax = std::max<size_t>(bmax, size_t(kMaxChunks) * kCout[l]);
   }
   net->out = dalloc<float>(ctx, size_t(batch) * kOut);
   net->tgt = dalloc<float>(ctx, size_t(batch) * kOut);
   net->hw = dalloc<float>(ctx, size_t(batch) * (kOut * kFeat + kOut));
   net->loss = dalloc<float>(ctx, size_t(batch));
-  net->frac = dalloc<float>(ctx, size_t(batch) * kFrac);
   pmax = std::max<size_t>(pmax, size_t(batch) * (kOut * kFeat + kOut));
   net->part = dalloc<float>(ctx, pmax);
   net->part_n = pmax;
@@ -122,33 +123,42 @@ void cast_all(hh_ctx* ctx, hh_net* net) {
   HIPCHK(hipGetLastError());
 }
 
-template <int CI, int CO>
-void conv_fwd(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float* b, __bf16* Y, int D, int batch) {
+template <int CI, int CO, bool LAB>
+void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16* W, const float* b, __bf16* Y, int D,
+              int batch) {
   const long long nvo = (long long)(D / 2) * (D / 2) * (D / 2) * batch;
-  k_conv_fwd<CI, CO><<<unsigned((nvo + 63) / 64), 256, 0, ctx->stream>>>(X, W, b, Y, D, batch);
+  k_conv_fwd<CI, CO, LAB><<<unsigned((nvo + 63) / 64), 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, batch);
 }
 
 void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o) {
-  const long long n = net->n, nv = n * n * n;
-  k_onehot<<<unsigned(std::min<long long>((nv * batch + 255) / 256, 65536)), 256, 0, ctx->stream>>>(
-      labels, (long long)box * box * box, box, o, net->n, batch, net->x0);
-  k_fractions<<<batch, 256, 0, ctx->stream>>>(labels, (long long)box * box * box, box, o, net->n, net->d_fmu,
-                                              net->d_fsc, net->frac);
-  conv_fwd<8, 32>(ctx, net->x0, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
-  conv_fwd<32, 32>(ctx, net->a[0], net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
-  conv_fwd<32, 64>(ctx, net->a[1], net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
-  conv_fwd<64, 64>(ctx, net->a[2], net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch);
+  const int n = net->n;
+  net->lw = LabelWindow{labels, (long long)box * box * box, box, o};
+  k_zero_int<<<(batch * kFrac + 255) / 256, 256, 0, ctx->stream>>>(net->cnt, batch * kFrac);
+  k_count_labels<<<dim3((n * n + kCountRows - 1) / kCountRows, batch), 256, 0, ctx->stream>>>(net->lw, n, net->cnt);
+  conv_fwd<8, 32, true>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
+  conv_fwd<32, 32, false>(ctx, net->a[0], net->lw, net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
+  conv_fwd<32, 64, false>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
+  conv_fwd<64, 64, false>(ctx, net->a[2], net->lw, net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch);
   HIPCHK(hipGetLastError());
 }
 
-template <int CI, int CO>
+void head(hh_ctx* ctx, hh_net* net, int batch, const float* target, float* dA, float* dW, float* loss, float inv) {
+  const int V = edge(net, 3) / 2;
+  const double nv = double(net->n) * net->n * net->n;
+  k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->cnt, 1.0 / nv, net->d_fmu, net->d_fsc,
+                                        net->p + net->fcw_off, net->p + net->fcb_off, net->out, target, dA, dW, loss,
+                                        inv);
+}
+
+template <int CI, int CO, bool LAB>
 void conv_bwd(hh_ctx* ctx, hh_net* net, int l, const __bf16* X, int batch, float* dX) {
   const int D = edge(net, l), Do = D / 2;
   const long long total = (long long)Do * Do * Do * batch;
   const int chunk = wgrad_chunk(total);
   const int nch = int((total + chunk - 1) / chunk);
-  k_conv_wgrad<CI, CO><<<dim3(nch, 27), 256, 0, ctx->stream>>>(net->ga[l], net->a[l], X, net->part, net->pbias, D,
-                                                               batch, chunk);
+  if (nch > kMaxChunks) fail(ctx, HH_EINVAL, "internal: weight-gradient chunk count");
+  k_conv_wgrad<CI, CO, LAB><<<dim3(nch, 27), 256, 0, ctx->stream>>>(net->ga[l], net->a[l], X, net->lw, net->part,
+                                                                    net->pbias, D, batch, chunk);
   const long long nw = 27LL * CO * CI;
   k_reduce_parts<<<unsigned(std::min<long long>((nw + 255) / 256, 4096)), 256, 0, ctx->stream>>>(
       net->part, nch, nw, net->g + net->woff[l]);
@@ -166,16 +176,13 @@ void conv_bwd(hh_ctx* ctx, hh_net* net, int l, const __bf16* X, int batch, float
 
 // loss and gradient into net->g; returns the mean squared error
 float backward(hh_ctx* ctx, hh_net* net, int batch) {
-  const int V = edge(net, 3) / 2;
-  const int nvl = V * V * V;
   const float inv = 1.0f / float(batch * kOut);
-  k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], nvl, net->frac, net->p + net->fcw_off, net->p + net->fcb_off, net->out,
-                                        net->tgt, net->ga[3], net->hw, net->loss, inv);
+  head(ctx, net, batch, net->tgt, net->ga[3], net->hw, net->loss, inv);
   k_reduce_parts<<<8, 256, 0, ctx->stream>>>(net->hw, batch, kOut * kFeat + kOut, net->g + net->fcw_off);
-  conv_bwd<64, 64>(ctx, net, 3, net->a[2], batch, net->ga[2]);
-  conv_bwd<32, 64>(ctx, net, 2, net->a[1], batch, net->ga[1]);
-  conv_bwd<32, 32>(ctx, net, 1, net->a[0], batch, net->ga[0]);
-  conv_bwd<8, 32>(ctx, net, 0, net->x0, batch, nullptr);
+  conv_bwd<64, 64, false>(ctx, net, 3, net->a[2], batch, net->ga[2]);
+  conv_bwd<32, 64, false>(ctx, net, 2, net->a[1], batch, net->ga[1]);
+  conv_bwd<32, 32, false>(ctx, net, 1, net->a[0], batch, net->ga[0]);
+  conv_bwd<8, 32, true>(ctx, net, 0, nullptr, batch, nullptr);
   std::vector<float> lh(batch);
   HIPCHK(hipMemcpyAsync(lh.data(), net->loss, sizeof(float) * batch, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -212,14 +219,12 @@ void check_input(hh_ctx* ctx, hh_net* net, int batch, int box, int o) {
 
 void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
                            double* c21) {
-  const int step = 64;
+  const int step = 256;
+  ensure_acts(ctx, net, std::min(step, batch));
   for (int b0 = 0; b0 < batch; b0 += step) {
     const int nb = std::min(step, batch - b0);
-    ensure_acts(ctx, net, step);
     forward(ctx, net, labels + (long long)b0 * box * box * box, nb, box, o);
-    const int V = edge(net, 3) / 2;
-    k_head<<<nb, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->frac, net->p + net->fcw_off, net->p + net->fcb_off, net->out,
-                                       nullptr, nullptr, nullptr, nullptr, 0.0f);
+    head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f);
     k_denorm<<<(nb * kOut + 255) / 256, 256, 0, ctx->stream>>>(net->out, net->d_mean, net->d_scale, nb,
                                                                c21 + (long long)b0 * kOut);
     HIPCHK(hipGetLastError());
@@ -413,9 +418,7 @@ int hh_net_forward(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_o
     const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
     ensure_acts(ctx, net, batch);
     forward(ctx, net, d, batch, box, offset);
-    const int V = edge(net, 3) / 2;
-    k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->frac, net->p + net->fcw_off, net->p + net->fcb_off,
-                                          net->out, nullptr, nullptr, nullptr, nullptr, 0.0f);
+    head(ctx, net, batch, nullptr, nullptr, nullptr, nullptr, 0.0f);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, net->out, sizeof(float) * batch * kOut, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -46,24 +46,60 @@ __device__ __forceinline__ bf16x8 zero8() {
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
 // ---------------------------------------------------------------------------
-// one-hot input: labels (uint8, items of n^3 with byte stride `stride`, first
-// voxel at offset `off0`, sub-box origin `o` inside a box of edge `box`) ->
-// [b][n^3][8] bf16
+// The network input: the n^3 window at (o, o, o) of each of `batch` label
+// boxes of edge `box` (uint8, `stride` bytes apart).  The first layer reads
+// the labels and forms their one-hot code (8 channels) in registers.
 // ---------------------------------------------------------------------------
-__global__ void k_onehot(const unsigned char* __restrict__ labels, long long item_stride, int box, int o, int n,
-                         int batch, __bf16* __restrict__ x) {
-  const long long nv = (long long)n * n * n;
-  const long long total = nv * batch;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long b = i / nv, v = i - b * nv;
-    const int z = int(v / (n * n)), y = int((v / n) % n), xx = int(v % n);
-    const int lab = labels[b * item_stride + ((long long)(z + o) * box + (y + o)) * box + (xx + o)];
-    bf16x8 h;
+struct LabelWindow {
+  const unsigned char* labels;
+  long long stride;
+  int box, o;
+};
+
+__device__ __forceinline__ int label_at(const LabelWindow& w, long long b, int z, int y, int x) {
+  return w.labels[b * w.stride + ((long long)(z + w.o) * w.box + (y + w.o)) * w.box + (x + w.o)];
+}
+
+__device__ __forceinline__ bf16x8 onehot8(int lab) {
+  bf16x8 h;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) h[c] = (__bf16)(c == lab ? 1.0f : 0.0f);
-    *reinterpret_cast<bf16x8*>(x + i * 8) = h;
+  for (int c = 0; c < 8; ++c) h[c] = (__bf16)(c == lab ? 1.0f : 0.0f);
+  return h;
+}
+
+// Label counts of each window: cnt[b][c] += number of voxels with label c
+// (c < 8).  Grid (row blocks, batch); each wave takes whole x-rows (lanes
+// along x), counts in registers, then one atomic per block and label.
+constexpr int kCountRows = 64;
+
+__global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, int* __restrict__ cnt) {
+  const int b = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * kCountRows, r1 = min(n * n, r0 + kCountRows);
+  int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int r = r0 + wave; r < r1; r += 4) {
+    const int z = r / n, y = r - z * n;
+    for (int x = lane; x < n; x += 64) {
+      const int lab = label_at(w, b, z, y, x);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) c[k] += (lab == k) ? 1 : 0;
+    }
   }
+  __shared__ int s[8];
+  if (threadIdx.x < 8) s[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int v = c[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0 && v) atomicAdd(&s[k], v);
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && s[threadIdx.x]) atomicAdd(&cnt[b * 8 + threadIdx.x], s[threadIdx.x]);
+}
+
+__global__ void k_zero_int(int* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // Input voxel of output voxel (oz, oy, ox) under tap t (stride 2, pad 1);
@@ -77,13 +113,15 @@ __device__ __forceinline__ long long in_voxel(int oz, int oy, int ox, int t, int
 
 // ---------------------------------------------------------------------------
 // forward convolution + bias + ReLU.  256 threads = 4 waves, each wave 16
-// output voxels x COUT channels.  X: [b][D^3][CIN], Y: [b][Do^3][COUT].
+// output voxels x COUT channels.  X: [b][D^3][CIN] (or, with LAB, the label
+// window, CIN = 8), Y: [b][Do^3][COUT].
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT>
-__global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, const __bf16* __restrict__ W,
-                                                  const float* __restrict__ bias, __bf16* __restrict__ Y, int D,
-                                                  int batch) {
+template <int CIN, int COUT, bool LAB>
+__global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
+                                                  const __bf16* __restrict__ W, const float* __restrict__ bias,
+                                                  __bf16* __restrict__ Y, int D, int batch) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
+  static_assert(!LAB || CIN == 8, "label input has 8 channels");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
   const int Do = D / 2;
   const long long nvo = (long long)Do * Do * Do;
@@ -94,7 +132,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   const bool valid_a = va < nvo * batch;
   const long long ba = valid_a ? va / nvo : 0, ra = valid_a ? va - ba * nvo : 0;
   const int oz = int(ra / ((long long)Do * Do)), oy = int((ra / Do) % Do), ox = int(ra % Do);
-  const __bf16* Xb = X + ba * (long long)D * D * D * CIN;
+  const __bf16* Xb = LAB ? nullptr : X + ba * (long long)D * D * D * CIN;
   f32x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -103,8 +141,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
     const int tap = k / CIN, c0 = k % CIN;
     bf16x8 a = zero8();
     if (valid_a && tap < 27) {
-      const long long iv = in_voxel(oz, oy, ox, tap, D);
-      if (iv >= 0) a = ld8(Xb + iv * CIN + c0);
+      const int iz = 2 * oz + tap / 9 - 1, iy = 2 * oy + (tap / 3) % 3 - 1, ix = 2 * ox + tap % 3 - 1;
+      if (iz >= 0 && iy >= 0 && ix >= 0 && iz < D && iy < D && ix < D) {
+        if constexpr (LAB)
+          a = onehot8(label_at(lw, ba, iz, iy, ix));
+        else
+          a = ld8(Xb + (((long long)iz * D + iy) * D + ix) * CIN + c0);
+      }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -203,11 +246,13 @@ __global__ void __launch_bounds__(256) k_conv_dgrad(const float* __restrict__ dY
 // (K = voxels) are 16-byte LDS reads.  The bias gradient rides on tap 13.
 // Partials: part[chunk][tap][COUT][CIN], bias partials pb[chunk][COUT].
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT>
+template <int CIN, int COUT, bool LAB>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY, const __bf16* __restrict__ Y,
-                                                    const __bf16* __restrict__ X, float* __restrict__ part,
-                                                    float* __restrict__ pb, int D, int batch, int chunk) {
+                                                    const __bf16* __restrict__ X, LabelWindow lw,
+                                                    float* __restrict__ part, float* __restrict__ pb, int D,
+                                                    int batch, int chunk) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0 && 256 % COUT == 0, "channel counts");
+  static_assert(!LAB || CIN == 8, "label input has 8 channels");
   constexpr int MT = COUT / 16, NTN = (CIN + 15) / 16;  // output tiles (cout x cin)
   constexpr int VS = 32;                                 // voxels per staged step (= MFMA K)
   __shared__ __bf16 sZ[COUT][VS + 8];
@@ -248,7 +293,14 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY
         const long long b = v / nvo, r = v - b * nvo;
         const int oz = int(r / ((long long)Do * Do)), oy = int((r / Do) % Do), ox = int(r % Do);
         const long long iv = in_voxel(oz, oy, ox, tap, D);
-        if (iv >= 0) xv = (float)X[(b * (long long)D * D * D + iv) * CIN + ci];
+        if (iv >= 0) {
+          if constexpr (LAB) {
+            const int iz = int(iv / ((long long)D * D)), iy = int((iv / D) % D), ix = int(iv % D);
+            xv = label_at(lw, b, iz, iy, ix) == ci ? 1.0f : 0.0f;
+          } else {
+            xv = (float)X[(b * (long long)D * D * D + iv) * CIN + ci];
+          }
+        }
       }
       sX[ci][vl] = (__bf16)xv;
     }
@@ -304,44 +356,16 @@ __global__ void k_reduce_parts(const float* __restrict__ part, int nchunk, long 
 }
 
 // ---------------------------------------------------------------------------
-// phase fractions of each input window (the mean of the one-hot input), as
-// standardized features for the head: frac[b][c] = (f_c - mu_c) * sc_c.
-// One block of 256 threads per item; labels >= 8 count in no channel.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_fractions(const unsigned char* __restrict__ labels, long long item_stride,
-                                                   int box, int o, int n, const float* __restrict__ mu,
-                                                   const float* __restrict__ sc, float* __restrict__ frac) {
-  __shared__ int cnt[8];
-  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const unsigned char* L = labels + blockIdx.x * item_stride;
-  const int nn = n * n;
-  const long long nv = (long long)nn * n;
-  int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (long long v = threadIdx.x; v < nv; v += blockDim.x) {
-    const int z = int(v / nn), y = int((v / n) % n), x = int(v % n);
-    const int lab = L[((long long)(z + o) * box + (y + o)) * box + (x + o)];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) c[k] += (lab == k) ? 1 : 0;
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if (c[k]) atomicAdd(&cnt[k], c[k]);
-  __syncthreads();
-  if (threadIdx.x < 8) {
-    const int k = threadIdx.x;
-    frac[blockIdx.x * 8 + k] = (float(double(cnt[k]) / double(nv)) - mu[k]) * sc[k];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // head: global mean over V voxels of the last activation (64 channels), the
-// 8 standardized phase fractions appended (72 features), linear 72 -> 21,
+// 8 standardized phase fractions (f_c - mu_c) sc_c appended, f_c from the
+// label counts (72 features), linear 72 -> 21,
 // and (training) squared loss against targets with its gradients.  Only the
 // 64 pooled features pass a gradient back.  One block of 64 threads per item.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V, const float* __restrict__ frac,
-                                             const float* __restrict__ Wfc, const float* __restrict__ bfc,
+__global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V, const int* __restrict__ cnt,
+                                             double inv_nv, const float* __restrict__ fmu,
+                                             const float* __restrict__ fsc, const float* __restrict__ Wfc,
+                                             const float* __restrict__ bfc,
                                              float* __restrict__ out, const float* __restrict__ target,
                                              float* __restrict__ dA, float* __restrict__ dW_item,
                                              float* __restrict__ loss_item, float inv_count) {
@@ -353,7 +377,7 @@ __global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V
   float s = 0.0f;
   for (int v = 0; v < V; ++v) s += (float)Ab[(long long)v * C + c];
   feat[c] = s / float(V);
-  if (c < F - C) feat[C + c] = frac[b * (F - C) + c];
+  if (c < F - C) feat[C + c] = (float(double(cnt[b * (F - C) + c]) * inv_nv) - fmu[c]) * fsc[c];
   __syncthreads();
   if (c < O) {
     float y = bfc[c];

@@ -786,8 +786,11 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     if (nx % n_sub || ny % n_sub || nz % n_sub) fail(ctx, HH_EINVAL, "the subimage size must divide the image size");
     if (pad < 0 || 2 * pad >= std::min(nx, std::min(ny, nz)))
       fail(ctx, HH_EINVAL, "padding must satisfy 0 <= 2 pad < image size");
-    if (hh_net_input_size(net_a) != n_sub || (net_b && hh_net_input_size(net_b) != n_sub))
-      fail(ctx, HH_EINVAL, "the network input edge must equal the subimage size");
+    // a network reads either the n_sub^3 core (offset pad) or the whole box
+    const int in_a = hh_net_input_size(net_a), in_b = net_b ? hh_net_input_size(net_b) : in_a;
+    auto window_ok = [&](int e) { return e == n_sub || e == n_sub + 2 * pad; };
+    if (!window_ok(in_a) || !window_ok(in_b))
+      fail(ctx, HH_EINVAL, "the network input edge must be the subimage size or the padded box size");
     if (!(spread_tol > 0.0) || !(bound_tol >= 0.0)) fail(ctx, HH_EINVAL, "bad gate tolerances");
     const int b = n_sub + 2 * pad;
     const int mx = nx / n_sub, my = ny / n_sub, mz = nz / n_sub;
@@ -808,8 +811,8 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     auto* c21a = static_cast<double*>(ws(ctx, "sur_c21a", sizeof(double) * 21 * nitems));
     double* c21b = net_b ? static_cast<double*>(ws(ctx, "sur_c21b", sizeof(double) * 21 * nitems)) : nullptr;
     prof.run(HH_K_OTHER, [&] {
-      hh_net_predict_device(ctx, net_a, d_pack, nitems, b, pad, c21a);
-      if (net_b) hh_net_predict_device(ctx, net_b, d_pack, nitems, b, pad, c21b);
+      hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a);
+      if (net_b) hh_net_predict_device(ctx, net_b, d_pack, nitems, b, in_b == n_sub ? pad : 0, c21b);
     });
     // Voigt and Reuss stiffness of each core's phase fractions
     std::vector<double> cp(21 * nphase), sp(21 * nphase);

@@ -7,14 +7,29 @@ namespace hh {
 // ---------------------------------------------------------------------------
 // finalize kernels: one block per system, fixed-order FP64 reductions
 // ---------------------------------------------------------------------------
+// Sum of the per-workgroup partials of one system: each thread runs a
+// Neumaier-compensated sum over its strided share (the running sum and the
+// rounding error lost at each step, added back at the end), then a fixed
+// tree over the block.
 template <int NV>
 __device__ __forceinline__ void reduce_parts(const double* part, int n, double (&v)[NV], double* scratch) {
+  double comp[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = 0.0;
+  for (int i = 0; i < NV; ++i) {
+    v[i] = 0.0;
+    comp[i] = 0.0;
+  }
   for (int w = threadIdx.x; w < n; w += blockDim.x) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] += part[(long long)w * NV + i];
+    for (int i = 0; i < NV; ++i) {
+      const double x = part[(long long)w * NV + i];
+      const double t = v[i] + x;
+      comp[i] += fabs(v[i]) >= fabs(x) ? (v[i] - t) + x : (x - t) + v[i];
+      v[i] = t;
+    }
   }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] += comp[i];
   block_sum<NV>(v, scratch);
 }
 

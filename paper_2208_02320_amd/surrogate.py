@@ -134,6 +134,15 @@ class Dataset:
     def box(self):
         return self.n + 2 * self.pad
 
+    def window(self, edge):
+        """Offset of a network input window of ``edge`` in the boxes: the
+        core (edge n) or the whole box (edge n + 2 pad)."""
+        if edge == self.n:
+            return self.pad
+        if edge == self.box:
+            return 0
+        raise ValueError("network input edge %d fits neither the core nor the box" % edge)
+
     def split(self, count):
         """(first m - count items, last count items)."""
         m = self.c21.shape[0]
@@ -142,32 +151,40 @@ class Dataset:
         return a, b
 
 
-def label_images(ctx, seeds, size, n_sub, pad, sigma=2.0, tol=1e-5, log=print):
+def label_images(ctx, seeds, size, n_sub, pad, sigma=2.0, tol=1e-5, log=print, labels=None):
     """Cut four-phase device images (one per seed, edge ``size``) into padded
-    subimages and homogenize each with the FFT solver."""
+    subimages and homogenize each with the FFT solver.  With ``labels`` (the
+    c21 array of an earlier call with the same arguments) the images are only
+    regenerated and cut: the device generator is deterministic."""
     import torch
     boxes, c21 = [], []
     t_solve = 0.0
+    per = (size // n_sub) ** 3
+    if labels is not None and labels.shape != (per * len(seeds), 21):
+        raise ValueError("cached labels do not match the image recipe")
     for k, seed in enumerate(seeds):
         img = synth.four_phase_device(size, sigma=sigma, seed=seed, device="cuda:%d" % ctx.device)
         torch.cuda.synchronize()
         t0 = time.time()
-        _, Cs, rep = ctx.hierarchical(img, synth.FOUR_PHASE["phases"], n_sub, pad, tol=tol)
+        if labels is None:
+            _, Cs, rep = ctx.hierarchical(img, synth.FOUR_PHASE["phases"], n_sub, pad, tol=tol)
+            c21.append(Cs.copy())
         t_solve += time.time() - t0
         boxes.append(ctx.gather_subimages(img, n_sub, pad))
-        c21.append(Cs.copy())
         del img
-        if log:
-            log("labelled image %d/%d (seed %d): %d subimages, %.1fs" % (k + 1, len(seeds), seed, Cs.shape[0],
+        if log and labels is None:
+            log("labelled image %d/%d (seed %d): %d subimages, %.1fs" % (k + 1, len(seeds), seed, per,
                                                                       time.time() - t0))
-    return Dataset(torch.cat(boxes), np.concatenate(c21), n_sub, pad, list(seeds), t_solve)
+    c21 = labels if labels is not None else np.concatenate(c21)
+    return Dataset(torch.cat(boxes), c21, n_sub, pad, list(seeds), t_solve)
 
 
-def fraction_stats(data, nch=8):
+def fraction_stats(data, edge=None, nch=8):
     """Mean and inverse standard deviation of each label's fraction in the
-    cores of the data set (scale 0 for labels that never vary)."""
+    input windows of the data set (scale 0 for labels that never vary)."""
     import torch
-    p, n = data.pad, data.n
+    n = edge or data.n
+    p = data.window(n)
     core = data.boxes[:, p:p + n, p:p + n, p:p + n]
     f = torch.stack([(core == c).float().mean(dim=(1, 2, 3)) for c in range(nch)], dim=1).double().cpu().numpy()
     mu, sd = f.mean(axis=0), f.std(axis=0)
@@ -188,15 +205,18 @@ def symmetric_scaling(c21, syms=None):
 # training
 # ---------------------------------------------------------------------------
 def train(ctx, data, nphase, epochs=20, batch=32, lr=1e-3, lr_final=2e-5, seed=0, augment=True, log=print,
-          log_every=200, val=None):
-    """Train a network on ``data``; returns (net, history)."""
+          log_every=200, val=None, window="core"):
+    """Train a network on ``data`` whose input is the core of each box
+    (``window="core"``) or the whole box; returns (net, history)."""
     import torch
     syms = cube_symmetries() if augment else [((0, 1, 2), (1, 1, 1))]
     mats = [c21_transform(p, s) for p, s in syms]
     mean, scale = symmetric_scaling(data.c21, syms)
-    net = hh.Net(ctx, nphase, data.n, seed=seed)
+    edge = data.n if window == "core" else data.box
+    offset = data.window(edge)
+    net = hh.Net(ctx, nphase, edge, seed=seed)
     net.set_scaling(mean, scale)
-    net.set_fraction_scaling(*fraction_stats(data))
+    net.set_fraction_scaling(*fraction_stats(data, edge))
     dev = "cuda:%d" % ctx.device
     m = data.c21.shape[0]
     steps_per_epoch = max(1, m // batch)
@@ -218,7 +238,7 @@ def train(ctx, data, nphase, epochs=20, batch=32, lr=1e-3, lr_final=2e-5, seed=0
             tdev = torch.from_numpy(tgt.astype(np.float32)).to(dev)
             frac = step / max(1, total - 1)
             rate = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * frac))
-            loss = net.train_step(lab, tdev, rate, offset=data.pad)
+            loss = net.train_step(lab, tdev, rate, offset=offset)
             run += loss
             step += 1
             if log and log_every and step % log_every == 0:
@@ -235,9 +255,10 @@ def train(ctx, data, nphase, epochs=20, batch=32, lr=1e-3, lr_final=2e-5, seed=0
 
 
 def predict(net, data, chunk=512):
+    off = data.window(net.n)
     out = []
     for a in range(0, data.c21.shape[0], chunk):
-        out.append(net.predict(data.boxes[a:a + chunk], offset=data.pad))
+        out.append(net.predict(data.boxes[a:a + chunk], offset=off))
     return np.concatenate(out)
 
 
@@ -267,7 +288,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default=WEIGHTS_DIR)
     ap.add_argument("--images", type=int, default=40, help="training images (seeds 10000, 10001, ...)")
-    ap.add_argument("--val-images", type=int, default=2)
+    ap.add_argument("--val-images", type=int, default=2, help="validation images (seeds 20000, ...)")
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--pad", type=int, default=8)
@@ -275,7 +296,9 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--nets", type=int, default=2)
+    ap.add_argument("--seeds", default="1,2", help="one network per seed")
+    ap.add_argument("--window", choices=("core", "box"), default="core")
+    ap.add_argument("--labels", default=None, help="npz cache of the FFT labels (read if present, else written)")
     a = ap.parse_args(argv)
 
     def log(msg):
@@ -284,18 +307,33 @@ def main(argv=None):
     ctx = hh.Context(0)
     seeds = list(range(10000, 10000 + a.images))
     vseeds = list(range(20000, 20000 + a.val_images))
-    data = label_images(ctx, seeds, a.size, a.n, a.pad, tol=a.tol, log=log)
-    val = label_images(ctx, vseeds, a.size, a.n, a.pad, tol=a.tol, log=log)
+    cached = None
+    if a.labels and os.path.exists(a.labels):
+        z = np.load(a.labels, allow_pickle=False)
+        key = [a.size, a.n, a.pad, a.images, a.val_images]
+        if list(z["key"]) != key or float(z["tol"]) != a.tol:
+            raise SystemExit("label cache %s was made for another recipe" % a.labels)
+        cached = (z["train"], z["val"])
+        log("labels from %s" % a.labels)
+    data = label_images(ctx, seeds, a.size, a.n, a.pad, tol=a.tol, log=log,
+                        labels=None if cached is None else cached[0])
+    val = label_images(ctx, vseeds, a.size, a.n, a.pad, tol=a.tol, log=log,
+                       labels=None if cached is None else cached[1])
+    if a.labels and cached is None:
+        np.savez_compressed(a.labels, train=data.c21, val=val.c21, tol=a.tol,
+                            key=np.array([a.size, a.n, a.pad, a.images, a.val_images]))
     os.makedirs(a.out, exist_ok=True)
-    for k in range(a.nets):
-        net, hist = train(ctx, data, 4, epochs=a.epochs, batch=a.batch, lr=a.lr, seed=k + 1, log=log, val=val)
+    for sd in [int(x) for x in a.seeds.split(",")]:
+        net, hist = train(ctx, data, 4, epochs=a.epochs, batch=a.batch, lr=a.lr, seed=sd, log=log, val=val,
+                          window=a.window)
         err = rel_error21(predict(net, val), val.c21)
-        meta = dict(images=seeds, val_images=vseeds, size=a.size, n=a.n, pad=a.pad, epochs=a.epochs,
-                    batch=a.batch, lr=a.lr, tol=a.tol, seed=k + 1, items=int(data.c21.shape[0]),
+        meta = dict(images=seeds, val_images=vseeds, size=a.size, n=a.n, pad=a.pad, window=a.window,
+                    epochs=a.epochs, batch=a.batch, lr=a.lr, tol=a.tol, seed=sd, items=int(data.c21.shape[0]),
                     val_mean=float(err.mean()), val_p95=float(np.quantile(err, 0.95)), history=hist)
-        path = os.path.join(a.out, "four_phase_n%d_p%d_%s.npz" % (a.n, a.pad, "ab"[k] if k < 2 else str(k)))
+        path = os.path.join(a.out, "four_phase_n%d_p%d_%s_s%d.npz" % (a.n, a.pad, a.window, sd))
         save(net, path, meta)
         log("saved %s: validation error mean %.3e p95 %.3e" % (path, err.mean(), np.quantile(err, 0.95)))
+        net.close()
 
 
 if __name__ == "__main__":
