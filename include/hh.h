@@ -42,6 +42,7 @@ extern "C" {
 #define HH_EBREAKDOWN (-8)    /* (p, A p) <= 0 or non-finite values in the iteration */
 
 #define HH_NKERNEL 8          /* kernel classes timed in hh_report.kernel_ms */
+#define HH_NVARIANT 3         /* compiled tile variants per FP32 axis length */
 /* kernel class indices */
 #define HH_K_ZINV 0
 #define HH_K_YINV 1
@@ -74,6 +75,14 @@ typedef struct {
                         HH_ESTAGNATED; default 100 */
   int chunk;         /* iterations launched between convergence polls; default 8 */
   double ref_lambda, ref_mu; /* basic scheme reference medium; <= 0: mid-range of the phases */
+  int tune;          /* FP32: 1 = the first solve of a shape in a context times the compiled
+                        tile variants of each pass (on that group's own buffers, before its
+                        right-hand side) and the context keeps the fastest; 0 = default
+                        tiles; default 1 */
+  int graph;         /* 1 = each chunk of iterations is captured once as a hipGraph and
+                        replayed (not with profile); 0 = plain launches; default 1 */
+  int plan[3];       /* tile variant forced for the z, y and x passes (0..HH_NVARIANT-1,
+                        FP64: 0 only); -1 = tuned or default; default -1 */
 } hh_opts;
 
 /* Per-call report. */
@@ -87,6 +96,9 @@ typedef struct {
   long long items;              /* images homogenized by the call */
   double kernel_ms[HH_NKERNEL]; /* with opts.profile: summed device time per class */
   int kernel_launches[HH_NKERNEL];
+  int plan[3];                  /* tile variants (z, y, x) of the last group solved */
+  double setup_ms;              /* host time spent tuning and building graphs in the call
+                                   (one-time per shape / argument set; part of seconds) */
 } hh_report;
 
 /* Fills *opts with the defaults listed in hh_opts. */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -16,8 +17,22 @@ struct hh_ctx {
   std::string err;
   std::map<std::string, std::pair<void*, size_t>> bufs;
   std::vector<hipEvent_t> evpool;
-  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;  // call timing
+  hipEvent_t e0 = nullptr, e1 = nullptr;  // autotuner timing
+  hipStream_t cap = nullptr;              // stream used only to capture graphs
+  int max_lds = 65536;                    // LDS bytes a workgroup may use
+  // tuned tile variants (z, y, x) per (nx, ny, nz, precision, aniso, systems bucket)
+  std::map<std::array<int, 6>, std::array<int, 3>> plans;
+  // instantiated graphs of iteration chunks, keyed by their launch arguments
+  std::map<std::string, hipGraphExec_t> graphs;
+  double setup_ms = 0.0;                  // tuning and graph construction of the current call
+  std::array<int, 3> last_plan{{0, 0, 0}};
 };
+
+inline void clear_graphs(hh_ctx* ctx) {
+  for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+  ctx->graphs.clear();
+}
 
 
 struct Fail {

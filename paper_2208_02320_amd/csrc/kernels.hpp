@@ -9,21 +9,23 @@ namespace hh {
 
 enum : int { kZInvCg = 0, kZFwdCg = 1, kZFwdRhs = 2, kZInvFp = 3, kZFwdFp = 4 };
 enum : int { kXCg = 0, kXRhs = 1, kXFp = 2 };
-enum : int { kOpZ = 0, kOpY = 1, kOpX = 2, kOpInfoZ = 3, kOpInfoX = 4 };
+enum : int { kOpZ = 0, kOpY = 1, kOpX = 2, kOpInfoZ = 3, kOpInfoX = 4, kOpInfoLdsZ = 5, kOpInfoLdsX = 6 };
+// Number of compiled tile variants per FP32 size (see variant_budget).
+constexpr int kNVariant = 3;
 
 using SizeOpsFn = void (*)(int what, int mode, const GroupArgs* g, hipStream_t st, int* info);
 
-SizeOpsFn size_ops(int n, int precision);
+SizeOpsFn size_ops(int n, int precision, int variant = 0);
 // per-file size tables (sizes_f32_*.hip, sizes_f64_*.hip)
-SizeOpsFn size_ops_f32_0(int n);
-SizeOpsFn size_ops_f32_1(int n);
-SizeOpsFn size_ops_f32_2(int n);
-SizeOpsFn size_ops_f32_3(int n);
-SizeOpsFn size_ops_f32_4(int n);
-SizeOpsFn size_ops_f32_5(int n);
-SizeOpsFn size_ops_f64_0(int n);
-SizeOpsFn size_ops_f64_1(int n);
-SizeOpsFn size_ops_f64_2(int n);
+SizeOpsFn size_ops_f32_0(int n, int v);
+SizeOpsFn size_ops_f32_1(int n, int v);
+SizeOpsFn size_ops_f32_2(int n, int v);
+SizeOpsFn size_ops_f32_3(int n, int v);
+SizeOpsFn size_ops_f32_4(int n, int v);
+SizeOpsFn size_ops_f32_5(int n, int v);
+SizeOpsFn size_ops_f64_0(int n, int v);
+SizeOpsFn size_ops_f64_1(int n, int v);
+SizeOpsFn size_ops_f64_2(int n, int v);
 void launch_fin_x(int mode, const GroupArgs& g, hipStream_t st);
 void launch_fin_z(int mode, const GroupArgs& g, hipStream_t st);
 void launch_stiffness(int precision, const SysState* state, int nitems, double* out, void* cfield_out,

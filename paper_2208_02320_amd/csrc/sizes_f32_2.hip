@@ -3,7 +3,7 @@
 
 namespace hh {
 
-SizeOpsFn size_ops_f32_2(int n) {
+SizeOpsFn size_ops_f32_2(int n, int v) {
   switch (n) {
     HH_CASE_F(60) HH_CASE_F(64) HH_CASE_F(72) HH_CASE_F(75) HH_CASE_F(80) HH_CASE_F(90)
   }

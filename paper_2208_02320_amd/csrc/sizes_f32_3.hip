@@ -3,7 +3,7 @@
 
 namespace hh {
 
-SizeOpsFn size_ops_f32_3(int n) {
+SizeOpsFn size_ops_f32_3(int n, int v) {
   switch (n) {
     HH_CASE_F(96) HH_CASE_F(100) HH_CASE_F(120) HH_CASE_F(128)
   }

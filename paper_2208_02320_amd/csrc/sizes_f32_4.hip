@@ -3,7 +3,7 @@
 
 namespace hh {
 
-SizeOpsFn size_ops_f32_4(int n) {
+SizeOpsFn size_ops_f32_4(int n, int v) {
   switch (n) {
     HH_CASE_F(144) HH_CASE_F(150) HH_CASE_F(160) HH_CASE_F(180)
   }

@@ -3,7 +3,7 @@
 
 namespace hh {
 
-SizeOpsFn size_ops_f64_2(int n) {
+SizeOpsFn size_ops_f64_2(int n, int v) {
   switch (n) {
     HH_CASE_D(64) HH_CASE_D(80) HH_CASE_D(96) HH_CASE_D(128)
   }

@@ -215,17 +215,18 @@ __global__ void k_stiffness(const SysState* state, int nitems, double* out, T* c
   if (status_out) status_out[item] = singular ? kSingularStatus : worst;
 }
 
-SizeOpsFn size_ops(int n, int precision) {
-  using Part = SizeOpsFn (*)(int);
+SizeOpsFn size_ops(int n, int precision, int variant) {
+  using Part = SizeOpsFn (*)(int, int);
+  if (variant < 0 || variant >= kNVariant) return nullptr;
   static const Part f32[] = {size_ops_f32_0, size_ops_f32_1, size_ops_f32_2, size_ops_f32_3,
                              size_ops_f32_4, size_ops_f32_5};
   static const Part f64[] = {size_ops_f64_0, size_ops_f64_1, size_ops_f64_2};
   if (precision == 0) {
     for (Part p : f32)
-      if (SizeOpsFn f = p(n)) return f;
+      if (SizeOpsFn f = p(n, variant)) return f;
   } else if (precision == 1) {
     for (Part p : f64)
-      if (SizeOpsFn f = p(n)) return f;
+      if (SizeOpsFn f = p(n, variant)) return f;
   }
   return nullptr;
 }

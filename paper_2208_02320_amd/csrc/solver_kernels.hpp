@@ -47,6 +47,12 @@ namespace hh {
 inline constexpr int kLdsTile = HH_LDS_TILE_X;
 inline constexpr int kLdsTileYZ = HH_LDS_TILE_YZ;
 
+// Tile variants: the same kernels compiled for three LDS budgets (default,
+// half, double), i.e. narrower or wider tiles and more or fewer resident
+// workgroups per CU.  The context times the distinct ones per shape and keeps
+// the fastest.
+constexpr int variant_budget(int base, int v) { return v == 1 ? base / 2 : (v == 2 ? base * 2 : base); }
+
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
 constexpr int maxi(int a, int b) { return a > b ? a : b; }
@@ -57,22 +63,22 @@ constexpr int lds_pad(int n1, int n2, int L, int cb) {
   return (n2 > 1 && (n1 * L * (cb / 4)) % 64 == 0) ? L : 0;
 }
 
-template <int N, class T>
+template <int N, class T, int V = 0>
 struct AxisCfg {
   static constexpr int N1 = split_n1(N), N2 = N / N1;
   static constexpr int CB = int(sizeof(cx<T>));
-  static constexpr int M = clampi(kLdsTileYZ / (N * 6 * CB), CB == 8 ? 4 : 2, 16);
+  static constexpr int M = clampi(variant_budget(kLdsTileYZ, V) / (N * 6 * CB), CB == 8 ? 4 : 2, 16);
   static constexpr int L = 6 * M;
   static constexpr int P = lds_pad(N1, N2, L, CB);
   static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);
   static constexpr int LDS = (N * L + N2 * P + N) * CB;
 };
 
-template <int N, class T>
+template <int N, class T, int V = 0>
 struct XCfg {
   static constexpr int N1 = split_n1(N), N2 = N / N1;
   static constexpr int CB = int(sizeof(cx<T>));
-  static constexpr int R = clampi(kLdsTile / (N * 3 * CB), 1, 32);
+  static constexpr int R = clampi(variant_budget(kLdsTile, V) / (N * 3 * CB), 1, 32);
   static constexpr int L = 3 * R;
   static constexpr int P = lds_pad(N1, N2, L, CB);
   static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);
@@ -242,9 +248,9 @@ struct alignas(2 * sizeof(cx<T>)) cpair {
 // ---------------------------------------------------------------------------
 // z pass
 // ---------------------------------------------------------------------------
-template <int N, class T, int MODE>
-__global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g) {
-  using Cf = AxisCfg<N, T>;
+template <int N, class T, int MODE, int V>
+__global__ void __launch_bounds__((AxisCfg<N, T, V>::THREADS)) k_zpass(GroupArgs g) {
+  using Cf = AxisCfg<N, T, V>;
   constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS;
   constexpr int CB = Cf::CB;
   constexpr int M = Cf::M, L = 6 * M, ROWU = L * CB / 16, P = Cf::P, PU = P * CB / 16;
@@ -393,9 +399,9 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_zpass(GroupArgs g)
 // ---------------------------------------------------------------------------
 // y pass (plain FFT along y of the 6-component spectrum, in place)
 // ---------------------------------------------------------------------------
-template <int N, class T, int S>
-__global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_ypass(GroupArgs g) {
-  using Cf = AxisCfg<N, T>;
+template <int N, class T, int S, int V>
+__global__ void __launch_bounds__((AxisCfg<N, T, V>::THREADS)) k_ypass(GroupArgs g) {
+  using Cf = AxisCfg<N, T, V>;
   constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS, CB = Cf::CB;
   constexpr int M = Cf::M, L = 6 * M, ROWU = L * CB / 16, P = Cf::P, PU = P * CB / 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -423,9 +429,9 @@ __global__ void __launch_bounds__((AxisCfg<N, T>::THREADS)) k_ypass(GroupArgs g)
 // ---------------------------------------------------------------------------
 // x pass: C2R, constitutive law, reductions, R2C
 // ---------------------------------------------------------------------------
-template <int N, class T, int MODE>
-__global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
-  using Cf = XCfg<N, T>;
+template <int N, class T, int MODE, int V>
+__global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g) {
+  using Cf = XCfg<N, T, V>;
   constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS;
   constexpr int R = Cf::R, L = 3 * R, P = Cf::P;
   constexpr int HX = N / 2 + 1, HXP = (HX + 3) / 4 * 4;  // spectrum row length and pitch
@@ -648,54 +654,57 @@ __global__ void __launch_bounds__((XCfg<N, T>::THREADS)) k_xpass(GroupArgs g) {
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-template <int N, class T>
+template <int N, class T, int V>
 struct Ops {
-  static int zm() { return AxisCfg<N, T>::M; }
-  static int xr() { return XCfg<N, T>::R; }
   static void z(int mode, const GroupArgs& g, hipStream_t st) {
-    using Cf = AxisCfg<N, T>;
+    using Cf = AxisCfg<N, T, V>;
     const dim3 grid(g.ny * ((g.hx + Cf::M - 1) / Cf::M), g.nsys);
     switch (mode) {
-      case kZInvCg: k_zpass<N, T, kZInvCg><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
-      case kZFwdCg: k_zpass<N, T, kZFwdCg><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
-      case kZFwdRhs: k_zpass<N, T, kZFwdRhs><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
-      case kZInvFp: k_zpass<N, T, kZInvFp><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
-      case kZFwdFp: k_zpass<N, T, kZFwdFp><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZInvCg: k_zpass<N, T, kZInvCg, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZFwdCg: k_zpass<N, T, kZFwdCg, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZFwdRhs: k_zpass<N, T, kZFwdRhs, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZInvFp: k_zpass<N, T, kZInvFp, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kZFwdFp: k_zpass<N, T, kZFwdFp, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
     }
   }
   static void y(int dir, const GroupArgs& g, hipStream_t st) {
-    using Cf = AxisCfg<N, T>;
+    using Cf = AxisCfg<N, T, V>;
     const dim3 grid(g.nz * ((g.hx + Cf::M - 1) / Cf::M), g.nsys);
-    if (dir < 0) k_ypass<N, T, -1><<<grid, Cf::THREADS, Cf::LDS, st>>>(g);
-    else k_ypass<N, T, +1><<<grid, Cf::THREADS, Cf::LDS, st>>>(g);
+    if (dir < 0) k_ypass<N, T, -1, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g);
+    else k_ypass<N, T, +1, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g);
   }
   static void x(int mode, const GroupArgs& g, hipStream_t st) {
-    using Cf = XCfg<N, T>;
+    using Cf = XCfg<N, T, V>;
     const dim3 grid((g.ny * g.nz + Cf::R - 1) / Cf::R, g.nsys);
     switch (mode) {
-      case kXCg: k_xpass<N, T, kXCg><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
-      case kXRhs: k_xpass<N, T, kXRhs><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
-      case kXFp: k_xpass<N, T, kXFp><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kXCg: k_xpass<N, T, kXCg, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kXRhs: k_xpass<N, T, kXRhs, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
+      case kXFp: k_xpass<N, T, kXFp, V><<<grid, Cf::THREADS, Cf::LDS, st>>>(g); break;
     }
   }
 };
 
-#define HH_CASE_F(N) \
-  case N:            \
-    return &size_ops_impl<N, float>;
-#define HH_CASE_D(N) \
-  case N:            \
-    return &size_ops_impl<N, double>;
-
-template <int N, class T>
+template <int N, class T, int V>
 void size_ops_impl(int what, int mode, const GroupArgs* g, hipStream_t st, int* info) {
   switch (what) {
-    case kOpZ: Ops<N, T>::z(mode, *g, st); break;
-    case kOpY: Ops<N, T>::y(mode, *g, st); break;
-    case kOpX: Ops<N, T>::x(mode, *g, st); break;
-    case kOpInfoZ: *info = Ops<N, T>::zm(); break;
-    case kOpInfoX: *info = Ops<N, T>::xr(); break;
+    case kOpZ: Ops<N, T, V>::z(mode, *g, st); break;
+    case kOpY: Ops<N, T, V>::y(mode, *g, st); break;
+    case kOpX: Ops<N, T, V>::x(mode, *g, st); break;
+    case kOpInfoZ: *info = AxisCfg<N, T, V>::M; break;
+    case kOpInfoX: *info = XCfg<N, T, V>::R; break;
+    case kOpInfoLdsZ: *info = AxisCfg<N, T, V>::LDS; break;
+    case kOpInfoLdsX: *info = XCfg<N, T, V>::LDS; break;
   }
 }
+
+// FP32 sizes have the three tile variants, FP64 sizes the default one.
+#define HH_CASE_F(N)                            \
+  case N:                                       \
+    return v == 1   ? &size_ops_impl<N, float, 1> \
+           : v == 2 ? &size_ops_impl<N, float, 2> \
+                    : &size_ops_impl<N, float, 0>;
+#define HH_CASE_D(N) \
+  case N:            \
+    return v == 0 ? &size_ops_impl<N, double, 0> : nullptr;
 
 }  // namespace hh

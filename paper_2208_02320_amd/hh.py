@@ -50,19 +50,20 @@ class Opts(ct.Structure):
     _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int), ("scheme", ct.c_int),
                 ("precision", ct.c_int), ("nyquist", ct.c_int), ("profile", ct.c_int),
                 ("stall_limit", ct.c_int), ("chunk", ct.c_int),
-                ("ref_lambda", ct.c_double), ("ref_mu", ct.c_double)]
+                ("ref_lambda", ct.c_double), ("ref_mu", ct.c_double),
+                ("tune", ct.c_int), ("graph", ct.c_int), ("plan", ct.c_int * 3)]
 
 
 class Report(ct.Structure):
     _fields_ = [("status", ct.c_int), ("iters", ct.c_int * 6), ("rel_resid", ct.c_double * 6),
                 ("asym", ct.c_double), ("seconds", ct.c_double), ("voxel_iters", ct.c_double),
                 ("items", ct.c_longlong), ("kernel_ms", ct.c_double * NKERNEL),
-                ("kernel_launches", ct.c_int * NKERNEL)]
+                ("kernel_launches", ct.c_int * NKERNEL), ("plan", ct.c_int * 3), ("setup_ms", ct.c_double)]
 
     def as_dict(self):
         return dict(status=self.status, iters=list(self.iters), rel_resid=list(self.rel_resid),
                     asym=self.asym, seconds=self.seconds, voxel_iters=self.voxel_iters,
-                    items=self.items,
+                    items=self.items, plan=list(self.plan), setup_ms=self.setup_ms,
                     kernel_ms={k: self.kernel_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
                     kernel_launches={k: self.kernel_launches[i] for i, k in enumerate(KERNEL_CLASSES)})
 
@@ -135,6 +136,8 @@ def default_opts(**kw):
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError("unknown option %r" % k)
+        if k == "plan":
+            v = (ct.c_int * 3)(*[int(x) for x in v])
         setattr(o, k, v)
     return o
 
