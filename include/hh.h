@@ -42,7 +42,7 @@ extern "C" {
 #define HH_EBREAKDOWN (-8)    /* (p, A p) <= 0 or non-finite values in the iteration */
 
 #define HH_NKERNEL 8          /* kernel classes timed in hh_report.kernel_ms */
-#define HH_NVARIANT 3         /* compiled tile variants per FP32 axis length */
+#define HH_NVARIANT 5         /* compiled tile variants per FP32 axis length */
 /* kernel class indices */
 #define HH_K_ZINV 0
 #define HH_K_YINV 1

@@ -181,28 +181,31 @@ void check_region(hh_ctx* ctx, const int* r, int nx, int ny, int nz) {
 // Compiled tile variants of one axis pass that fit the device's LDS.
 struct PassVariants {
   SizeOpsFn f[kNVariant] = {};
-  int geom[kNVariant] = {};  // columns per tile (z, y) or rows per tile (x)
+  int geom[kNVariant] = {};     // columns per tile (z, y) or rows per tile (x)
+  int threads[kNVariant] = {};  // workgroup size
   bool ok[kNVariant] = {};
   // variant v is worth timing: available and unlike every earlier one
   bool distinct(int v) const {
     if (!ok[v]) return false;
     for (int u = 0; u < v; ++u)
-      if (ok[u] && geom[u] == geom[v]) return false;
+      if (ok[u] && geom[u] == geom[v] && threads[u] == threads[v]) return false;
     return true;
   }
 };
 
-PassVariants pass_variants(hh_ctx* ctx, int n, int P, int info_geom, int info_lds) {
+PassVariants pass_variants(hh_ctx* ctx, int n, int P, int info_geom, int info_lds, int info_threads) {
   PassVariants pv;
   for (int v = 0; v < kNVariant; ++v) {
     SizeOpsFn f = size_ops(n, P, v);
     if (!f) continue;
-    int lds = 0, gm = 0;
+    int lds = 0, gm = 0, th = 0;
     f(info_lds, 0, nullptr, nullptr, &lds);
     f(info_geom, 0, nullptr, nullptr, &gm);
+    f(info_threads, 0, nullptr, nullptr, &th);
     if (lds > ctx->max_lds) continue;
     pv.f[v] = f;
     pv.geom[v] = gm;
+    pv.threads[v] = th;
     pv.ok[v] = true;
   }
   return pv;
@@ -217,9 +220,9 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
                         Profile& prof, void* cfield_out) {
   const int nx = items[0].nx, ny = items[0].ny, nz = items[0].nz;
   const int P = o.precision;
-  const PassVariants vz = pass_variants(ctx, nz, P, kOpInfoZ, kOpInfoLdsZ);
-  const PassVariants vy = pass_variants(ctx, ny, P, kOpInfoZ, kOpInfoLdsZ);
-  const PassVariants vx = pass_variants(ctx, nx, P, kOpInfoX, kOpInfoLdsX);
+  const PassVariants vz = pass_variants(ctx, nz, P, kOpInfoZ, kOpInfoLdsZ, kOpInfoThreadsZ);
+  const PassVariants vy = pass_variants(ctx, ny, P, kOpInfoZ, kOpInfoLdsZ, kOpInfoThreadsZ);
+  const PassVariants vx = pass_variants(ctx, nx, P, kOpInfoX, kOpInfoLdsX, kOpInfoThreadsX);
   if (!vz.ok[0] || !vy.ok[0] || !vx.ok[0]) fail(ctx, HH_EUNSUPPORTED, "unsupported axis length");
   const PassVariants* pvs[3] = {&vz, &vy, &vx};
   const int hx = nx / 2 + 1;

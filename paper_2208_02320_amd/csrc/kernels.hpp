@@ -9,9 +9,19 @@ namespace hh {
 
 enum : int { kZInvCg = 0, kZFwdCg = 1, kZFwdRhs = 2, kZInvFp = 3, kZFwdFp = 4 };
 enum : int { kXCg = 0, kXRhs = 1, kXFp = 2 };
-enum : int { kOpZ = 0, kOpY = 1, kOpX = 2, kOpInfoZ = 3, kOpInfoX = 4, kOpInfoLdsZ = 5, kOpInfoLdsX = 6 };
+enum : int {
+  kOpZ = 0,
+  kOpY = 1,
+  kOpX = 2,
+  kOpInfoZ = 3,
+  kOpInfoX = 4,
+  kOpInfoLdsZ = 5,
+  kOpInfoLdsX = 6,
+  kOpInfoThreadsZ = 7,
+  kOpInfoThreadsX = 8
+};
 // Number of compiled tile variants per FP32 size (see variant_budget).
-constexpr int kNVariant = 3;
+constexpr int kNVariant = 5;
 
 using SizeOpsFn = void (*)(int what, int mode, const GroupArgs* g, hipStream_t st, int* info);
 
@@ -23,6 +33,16 @@ SizeOpsFn size_ops_f32_2(int n, int v);
 SizeOpsFn size_ops_f32_3(int n, int v);
 SizeOpsFn size_ops_f32_4(int n, int v);
 SizeOpsFn size_ops_f32_5(int n, int v);
+SizeOpsFn size_ops_f32_6(int n, int v);
+SizeOpsFn size_ops_f32_7(int n, int v);
+SizeOpsFn size_ops_f32_8(int n, int v);
+SizeOpsFn size_ops_f32_9(int n, int v);
+SizeOpsFn size_ops_f32_10(int n, int v);
+SizeOpsFn size_ops_f32_11(int n, int v);
+SizeOpsFn size_ops_f32_12(int n, int v);
+SizeOpsFn size_ops_f32_13(int n, int v);
+SizeOpsFn size_ops_f32_14(int n, int v);
+SizeOpsFn size_ops_f32_15(int n, int v);
 SizeOpsFn size_ops_f64_0(int n, int v);
 SizeOpsFn size_ops_f64_1(int n, int v);
 SizeOpsFn size_ops_f64_2(int n, int v);

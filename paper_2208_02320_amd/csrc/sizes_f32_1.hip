@@ -5,7 +5,7 @@ namespace hh {
 
 SizeOpsFn size_ops_f32_1(int n, int v) {
   switch (n) {
-    HH_CASE_F(30) HH_CASE_F(32) HH_CASE_F(36) HH_CASE_F(40) HH_CASE_F(45) HH_CASE_F(48) HH_CASE_F(50)
+    HH_CASE_F(8) HH_CASE_F(9) HH_CASE_F(10) HH_CASE_F(12)
   }
   return nullptr;
 }

@@ -5,7 +5,7 @@ namespace hh {
 
 SizeOpsFn size_ops_f32_2(int n, int v) {
   switch (n) {
-    HH_CASE_F(60) HH_CASE_F(64) HH_CASE_F(72) HH_CASE_F(75) HH_CASE_F(80) HH_CASE_F(90)
+    HH_CASE_F(15) HH_CASE_F(16) HH_CASE_F(18) HH_CASE_F(20)
   }
   return nullptr;
 }

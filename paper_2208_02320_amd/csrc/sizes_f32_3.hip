@@ -5,7 +5,7 @@ namespace hh {
 
 SizeOpsFn size_ops_f32_3(int n, int v) {
   switch (n) {
-    HH_CASE_F(96) HH_CASE_F(100) HH_CASE_F(120) HH_CASE_F(128)
+    HH_CASE_F(24) HH_CASE_F(25) HH_CASE_F(27)
   }
   return nullptr;
 }

@@ -5,7 +5,7 @@ namespace hh {
 
 SizeOpsFn size_ops_f32_4(int n, int v) {
   switch (n) {
-    HH_CASE_F(144) HH_CASE_F(150) HH_CASE_F(160) HH_CASE_F(180)
+    HH_CASE_F(30) HH_CASE_F(32) HH_CASE_F(36)
   }
   return nullptr;
 }

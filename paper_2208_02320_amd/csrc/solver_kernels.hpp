@@ -47,11 +47,18 @@ namespace hh {
 inline constexpr int kLdsTile = HH_LDS_TILE_X;
 inline constexpr int kLdsTileYZ = HH_LDS_TILE_YZ;
 
-// Tile variants: the same kernels compiled for three LDS budgets (default,
-// half, double), i.e. narrower or wider tiles and more or fewer resident
-// workgroups per CU.  The context times the distinct ones per shape and keeps
-// the fastest.
-constexpr int variant_budget(int base, int v) { return v == 1 ? base / 2 : (v == 2 ? base * 2 : base); }
+// Tile variants: the same kernels compiled for several LDS budgets and
+// workgroup sizes.  Variants 0, 1, 2: the default, half and double budget
+// (narrower or wider tiles, more or fewer resident workgroups per CU);
+// 3 and 4: the default and half budget with at least 256 threads per
+// workgroup in the x pass (fewer loads in flight per thread).  The y and z
+// passes run variants 3 and 4 as 0 and 1.  The context times the distinct
+// ones per shape and keeps the fastest.
+constexpr int variant_budget(int base, int v) {
+  return (v == 1 || v == 4) ? base / 2 : (v == 2 ? base * 2 : base);
+}
+constexpr int variant_min_threads(int v) { return v >= 3 ? 256 : 64; }
+constexpr int yz_variant(int v) { return v >= 3 ? v - 3 : v; }
 
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 constexpr int round64(int v) { return (v + 63) / 64 * 64; }
@@ -81,7 +88,7 @@ struct XCfg {
   static constexpr int R = clampi(variant_budget(kLdsTile, V) / (N * 3 * CB), 1, 32);
   static constexpr int L = 3 * R;
   static constexpr int P = lds_pad(N1, N2, L, CB);
-  static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);
+  static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), variant_min_threads(V), 512);
   static constexpr int LDS = (N * L + N2 * P + N) * CB;
 };
 
@@ -684,24 +691,54 @@ struct Ops {
   }
 };
 
-template <int N, class T, int V>
-void size_ops_impl(int what, int mode, const GroupArgs* g, hipStream_t st, int* info) {
-  switch (what) {
-    case kOpZ: Ops<N, T, V>::z(mode, *g, st); break;
-    case kOpY: Ops<N, T, V>::y(mode, *g, st); break;
-    case kOpX: Ops<N, T, V>::x(mode, *g, st); break;
-    case kOpInfoZ: *info = AxisCfg<N, T, V>::M; break;
-    case kOpInfoX: *info = XCfg<N, T, V>::R; break;
-    case kOpInfoLdsZ: *info = AxisCfg<N, T, V>::LDS; break;
-    case kOpInfoLdsX: *info = XCfg<N, T, V>::LDS; break;
+// The lowest-numbered variant with the same tile configuration as V, so
+// that variants which coincide at a size share one set of kernels.
+template <int N, class T, int V, int U = 0>
+constexpr int canon_x() {
+  if constexpr (U >= V) {
+    return V;
+  } else if constexpr (XCfg<N, T, U>::R == XCfg<N, T, V>::R && XCfg<N, T, U>::THREADS == XCfg<N, T, V>::THREADS) {
+    return U;
+  } else {
+    return canon_x<N, T, V, U + 1>();
+  }
+}
+template <int N, class T, int V, int U = 0>
+constexpr int canon_yz() {
+  if constexpr (U >= V) {
+    return V;
+  } else if constexpr (AxisCfg<N, T, U>::M == AxisCfg<N, T, V>::M &&
+                       AxisCfg<N, T, U>::THREADS == AxisCfg<N, T, V>::THREADS) {
+    return U;
+  } else {
+    return canon_yz<N, T, V, U + 1>();
   }
 }
 
-// FP32 sizes have the three tile variants, FP64 sizes the default one.
-#define HH_CASE_F(N)                            \
-  case N:                                       \
+template <int N, class T, int V>
+void size_ops_impl(int what, int mode, const GroupArgs* g, hipStream_t st, int* info) {
+  constexpr int VZ = canon_yz<N, T, yz_variant(V)>();
+  constexpr int VX = canon_x<N, T, V>();
+  switch (what) {
+    case kOpZ: Ops<N, T, VZ>::z(mode, *g, st); break;
+    case kOpY: Ops<N, T, VZ>::y(mode, *g, st); break;
+    case kOpX: Ops<N, T, VX>::x(mode, *g, st); break;
+    case kOpInfoZ: *info = AxisCfg<N, T, VZ>::M; break;
+    case kOpInfoX: *info = XCfg<N, T, VX>::R; break;
+    case kOpInfoLdsZ: *info = AxisCfg<N, T, VZ>::LDS; break;
+    case kOpInfoLdsX: *info = XCfg<N, T, VX>::LDS; break;
+    case kOpInfoThreadsZ: *info = AxisCfg<N, T, VZ>::THREADS; break;
+    case kOpInfoThreadsX: *info = XCfg<N, T, VX>::THREADS; break;
+  }
+}
+
+// FP32 sizes have all tile variants, FP64 sizes the default one.
+#define HH_CASE_F(N)                              \
+  case N:                                         \
     return v == 1   ? &size_ops_impl<N, float, 1> \
            : v == 2 ? &size_ops_impl<N, float, 2> \
+           : v == 3 ? &size_ops_impl<N, float, 3> \
+           : v == 4 ? &size_ops_impl<N, float, 4> \
                     : &size_ops_impl<N, float, 0>;
 #define HH_CASE_D(N) \
   case N:            \
