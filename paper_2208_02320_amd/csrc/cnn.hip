@@ -123,11 +123,18 @@ void cast_all(hh_ctx* ctx, hh_net* net) {
   HIPCHK(hipGetLastError());
 }
 
-template <int CI, int CO, bool LAB>
+template <int CI, int CO, bool LAB, int RB>
 void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16* W, const float* b, __bf16* Y, int D,
               int batch) {
   const long long nvo = (long long)(D / 2) * (D / 2) * (D / 2) * batch;
-  k_conv_fwd<CI, CO, LAB><<<unsigned((nvo + 63) / 64), 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, batch);
+  k_conv_fwd<CI, CO, LAB, RB><<<unsigned((nvo + 64 * RB - 1) / (64 * RB)), 256, 0, ctx->stream>>>(X, lw, W, b, Y, D,
+                                                                                                  batch);
+}
+
+template <int CI, int CO>
+void conv_fwd_splitk(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float* b, __bf16* Y, int D, int batch) {
+  const long long nvo = (long long)(D / 2) * (D / 2) * (D / 2) * batch;
+  k_conv_fwd_splitk<CI, CO><<<unsigned((nvo + 15) / 16), 256, 0, ctx->stream>>>(X, W, b, Y, D, batch);
 }
 
 void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o) {
@@ -135,10 +142,10 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
   net->lw = LabelWindow{labels, (long long)box * box * box, box, o};
   k_zero_int<<<(batch * kFrac + 255) / 256, 256, 0, ctx->stream>>>(net->cnt, batch * kFrac);
   k_count_labels<<<dim3((n * n + kCountRows - 1) / kCountRows, batch), 256, 0, ctx->stream>>>(net->lw, n, net->cnt);
-  conv_fwd<8, 32, true>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
-  conv_fwd<32, 32, false>(ctx, net->a[0], net->lw, net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
-  conv_fwd<32, 64, false>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
-  conv_fwd<64, 64, false>(ctx, net->a[2], net->lw, net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch);
+  conv_fwd<8, 32, true, 4>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
+  conv_fwd<32, 32, false, 4>(ctx, net->a[0], net->lw, net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
+  conv_fwd<32, 64, false, 2>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
+  conv_fwd_splitk<64, 64>(ctx, net->a[2], net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch);
   HIPCHK(hipGetLastError());
 }
 

@@ -112,11 +112,12 @@ __device__ __forceinline__ long long in_voxel(int oz, int oy, int ox, int t, int
 }
 
 // ---------------------------------------------------------------------------
-// forward convolution + bias + ReLU.  256 threads = 4 waves, each wave 16
-// output voxels x COUT channels.  X: [b][D^3][CIN] (or, with LAB, the label
-// window, CIN = 8), Y: [b][Do^3][COUT].
+// forward convolution + bias + ReLU.  256 threads = 4 waves; each wave
+// computes RB row blocks of 16 output voxels x COUT channels, so that every
+// B fragment (weights) it loads serves RB MFMAs.  X: [b][D^3][CIN] (or, with
+// LAB, the label window, CIN = 8), Y: [b][Do^3][COUT].
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, bool LAB>
+template <int CIN, int COUT, bool LAB, int RB>
 __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
                                                   const __bf16* __restrict__ W, const float* __restrict__ bias,
                                                   __bf16* __restrict__ Y, int D, int batch) {
@@ -124,30 +125,98 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   static_assert(!LAB || CIN == 8, "label input has 8 channels");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
   const int Do = D / 2;
-  const long long nvo = (long long)Do * Do * Do;
+  const long long nvo = (long long)Do * Do * Do, total = nvo * batch;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long v0 = (long long)blockIdx.x * 64 + wave * 16;
-  // the voxel whose A row this lane loads
-  const long long va = v0 + (lane & 15);
-  const bool valid_a = va < nvo * batch;
-  const long long ba = valid_a ? va / nvo : 0, ra = valid_a ? va - ba * nvo : 0;
-  const int oz = int(ra / ((long long)Do * Do)), oy = int((ra / Do) % Do), ox = int(ra % Do);
-  const __bf16* Xb = LAB ? nullptr : X + ba * (long long)D * D * D * CIN;
-  f32x4 acc[NT];
+  const long long v0 = (long long)blockIdx.x * (64 * RB) + wave * (16 * RB);
+  // the voxel whose A row this lane loads, per row block
+  bool valid[RB];
+  long long bidx[RB];
+  int oz[RB], oy[RB], ox[RB];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < RB; ++r) {
+    const long long va = v0 + r * 16 + (lane & 15);
+    valid[r] = va < total;
+    const long long ba = valid[r] ? va / nvo : 0, ra = valid[r] ? va - ba * nvo : 0;
+    bidx[r] = ba;
+    oz[r] = int(ra / ((long long)Do * Do));
+    oy[r] = int((ra / Do) % Do);
+    ox[r] = int(ra % Do);
+  }
+  f32x4 acc[RB][NT];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int ks = 0; ks < KS; ++ks) {
     const int k = ks * 32 + (lane >> 4) * 8;
     const int tap = k / CIN, c0 = k % CIN;
-    bf16x8 a = zero8();
-    if (valid_a && tap < 27) {
-      const int iz = 2 * oz + tap / 9 - 1, iy = 2 * oy + (tap / 3) % 3 - 1, ix = 2 * ox + tap % 3 - 1;
-      if (iz >= 0 && iy >= 0 && ix >= 0 && iz < D && iy < D && ix < D) {
-        if constexpr (LAB)
-          a = onehot8(label_at(lw, ba, iz, iy, ix));
-        else
-          a = ld8(Xb + (((long long)iz * D + iy) * D + ix) * CIN + c0);
+    bf16x8 b[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      b[t] = zero8();
+      if (tap < 27) b[t] = ld8(W + ((long long)tap * COUT + t * 16 + (lane & 15)) * CIN + c0);
+    }
+    const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      bf16x8 a = zero8();
+      if (valid[r] && tap < 27) {
+        const int iz = 2 * oz[r] + tz - 1, iy = 2 * oy[r] + ty - 1, ix = 2 * ox[r] + tx - 1;
+        if (iz >= 0 && iy >= 0 && ix >= 0 && iz < D && iy < D && ix < D) {
+          if constexpr (LAB)
+            a = onehot8(label_at(lw, bidx[r], iz, iy, ix));
+          else
+            a = ld8(X + (bidx[r] * (long long)D * D * D + ((long long)iz * D + iy) * D + ix) * CIN + c0);
+        }
       }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a, b[t], acc[r][t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = t * 16 + (lane & 15);
+    const float bb = bias[co];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long v = v0 + r * 16 + (lane >> 4) * 4 + i;
+        if (v < total) Y[v * COUT + co] = (__bf16)fmaxf(acc[r][t][i] + bb, 0.0f);
+      }
+  }
+}
+
+// Forward convolution with the K steps of one 16-voxel row block split over
+// the 4 waves of a workgroup (for the deep layers with few voxels and long
+// K), partial sums reduced through LDS.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_conv_fwd_splitk(const __bf16* __restrict__ X, const __bf16* __restrict__ W,
+                                                         const float* __restrict__ bias, __bf16* __restrict__ Y, int D,
+                                                         int batch) {
+  static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
+  constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
+  __shared__ float red[3][NT][64][4];
+  const int Do = D / 2;
+  const long long nvo = (long long)Do * Do * Do, total = nvo * batch;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long v0 = (long long)blockIdx.x * 16;
+  const long long va = v0 + (lane & 15);
+  const bool valid = va < total;
+  const long long ba = valid ? va / nvo : 0, ra = valid ? va - ba * nvo : 0;
+  const int oz = int(ra / ((long long)Do * Do)), oy = int((ra / Do) % Do), ox = int(ra % Do);
+  const __bf16* Xb = X + ba * (long long)D * D * D * CIN;
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = wave; ks < KS; ks += 4) {
+    const int k = ks * 32 + (lane >> 4) * 8;
+    const int tap = k / CIN, c0 = k % CIN;
+    bf16x8 a = zero8();
+    if (valid && tap < 27) {
+      const int iz = 2 * oz + tap / 9 - 1, iy = 2 * oy + (tap / 3) % 3 - 1, ix = 2 * ox + tap % 3 - 1;
+      if (iz >= 0 && iy >= 0 && ix >= 0 && iz < D && iy < D && ix < D)
+        a = ld8(Xb + (((long long)iz * D + iy) * D + ix) * CIN + c0);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -156,14 +225,24 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
       acc[t] = mfma(a, b, acc[t]);
     }
   }
+  if (wave > 0) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = t * 16 + (lane & 15);
-    const float bb = bias[co];
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long long v = v0 + (lane >> 4) * 4 + i;
-      if (v < nvo * batch) Y[v * COUT + co] = (__bf16)fmaxf(acc[t][i] + bb, 0.0f);
+      for (int i = 0; i < 4; ++i) red[wave - 1][t][lane][i] = acc[t][i];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + (lane & 15);
+      const float bb = bias[co];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float sum = acc[t][i] + red[0][t][lane][i] + red[1][t][lane][i] + red[2][t][lane][i];
+        const long long v = v0 + (lane >> 4) * 4 + i;
+        if (v < total) Y[v * COUT + co] = (__bf16)fmaxf(sum + bb, 0.0f);
+      }
     }
   }
 }

@@ -222,12 +222,38 @@ def test_spread_between_networks_sends_all_to_fft(ctx):
     nb.close()
 
 
+def test_network_reading_the_whole_padded_box(ctx):
+    """A network whose input edge is n + 2 pad reads each whole box: with a
+    constant prediction the gate and level 2 behave as for a core network."""
+    lab = synth.four_phase(48, seed=12)
+    n, pad = 16, 8  # boxes of 32^3
+    CV, CR = sg.core_bounds(lab, 0, 48, FOUR)
+    c = hier.to21(0.5 * (CV + CR))
+    box_net = constant_net(ctx, 4, n + 2 * pad, c)
+    core_net = constant_net(ctx, 4, n, c)
+    Cb, Csb, fbb, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, box_net, None, spread_tol=0.05, bound_tol=0.5,
+                                                 tol=1e-6)
+    Cc, Csc, fbc, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, core_net, None, spread_tol=0.05, bound_tol=0.5,
+                                                 tol=1e-6)
+    assert np.array_equal(fbb, fbc) and np.array_equal(Csb, Csc) and np.array_equal(Cb, Cc)
+    # and a trained-style forward on the box matches the oracle on the box
+    from paper_2208_02320_amd import hh
+    p = ref.init_params(4, seed=9).astype(np.float32)
+    net = net_with(ctx, 4, 32, p)
+    boxes_ = ctx.gather_subimages(lab, n, pad)[:3].contiguous()
+    y = net.forward(boxes_, offset=0)
+    yr, _ = ref.forward(p.astype(np.float64), boxes_.cpu().numpy(), bf=True, fstats=FSTATS)
+    assert np.abs(y - yr).max() < 2e-3 * max(1.0, np.abs(yr).max())
+    for x in (box_net, core_net, net):
+        x.close()
+
+
 def test_surrogate_argument_errors(ctx):
     from paper_2208_02320_amd import hh
     lab = synth.four_phase(32, seed=6)
     net = hh.Net(ctx, 4, 16)
     with pytest.raises(hh.HHError):
-        ctx.hierarchical_surrogate(lab, FOUR, 32, 0, net)  # input edge != subimage size
+        ctx.hierarchical_surrogate(lab, FOUR, 32, 0, net)  # input edge fits neither core nor box
     with pytest.raises(hh.HHError):
         net.forward(np.zeros((2, 16, 16, 16), np.uint8), offset=1)  # window outside the box
     with pytest.raises(hh.HHError):
