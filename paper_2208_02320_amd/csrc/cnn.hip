@@ -126,15 +126,16 @@ void cast_all(hh_ctx* ctx, hh_net* net) {
 template <int CI, int CO, bool LAB, int RB>
 void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16* W, const float* b, __bf16* Y, int D,
               int batch) {
-  const long long nvo = (long long)(D / 2) * (D / 2) * (D / 2) * batch;
-  k_conv_fwd<CI, CO, LAB, RB><<<unsigned((nvo + 64 * RB - 1) / (64 * RB)), 256, 0, ctx->stream>>>(X, lw, W, b, Y, D,
-                                                                                                  batch);
+  const int Do = D / 2, nvo = Do * Do * Do;
+  k_conv_fwd<CI, CO, LAB, RB><<<dim3(unsigned((nvo + 64 * RB - 1) / (64 * RB)), unsigned(batch)), 256, 0, ctx->stream>>>(
+      X, lw, W, b, Y, D, make_grid3(Do));
 }
 
 template <int CI, int CO>
 void conv_fwd_splitk(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float* b, __bf16* Y, int D, int batch) {
-  const long long nvo = (long long)(D / 2) * (D / 2) * (D / 2) * batch;
-  k_conv_fwd_splitk<CI, CO><<<unsigned((nvo + 15) / 16), 256, 0, ctx->stream>>>(X, W, b, Y, D, batch);
+  const int Do = D / 2, nvo = Do * Do * Do;
+  k_conv_fwd_splitk<CI, CO><<<dim3(unsigned((nvo + 15) / 16), unsigned(batch)), 256, 0, ctx->stream>>>(
+      X, W, b, Y, D, make_grid3(Do));
 }
 
 void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o) {
@@ -165,17 +166,17 @@ void conv_bwd(hh_ctx* ctx, hh_net* net, int l, const __bf16* X, int batch, float
   const int nch = int((total + chunk - 1) / chunk);
   if (nch > kMaxChunks) fail(ctx, HH_EINVAL, "internal: weight-gradient chunk count");
   k_conv_wgrad<CI, CO, LAB><<<dim3(nch, 27), 256, 0, ctx->stream>>>(net->ga[l], net->a[l], X, net->lw, net->part,
-                                                                    net->pbias, D, batch, chunk);
+                                                                    net->pbias, D, make_grid3(D / 2), batch, chunk);
   const long long nw = 27LL * CO * CI;
   k_reduce_parts<<<unsigned(std::min<long long>((nw + 255) / 256, 4096)), 256, 0, ctx->stream>>>(
       net->part, nch, nw, net->g + net->woff[l]);
   k_reduce_parts<<<1, 256, 0, ctx->stream>>>(net->pbias, nch, CO, net->g + net->boff[l]);
   if constexpr (CI >= 16) {
     if (dX) {
-      const long long ncls = (long long)(D / 2) * (D / 2) * (D / 2) * batch;
+      const int h = D / 2, ncls = h * h * h;  // voxels of one parity class per item
       for (int c = 0; c < 8; ++c)
-        k_conv_dgrad<CI, CO><<<unsigned((ncls + 63) / 64), 256, 0, ctx->stream>>>(net->ga[l], net->a[l], net->Wt[l],
-                                                                                 dX, D, batch, c);
+        k_conv_dgrad<CI, CO><<<dim3(unsigned((ncls + 63) / 64), unsigned(batch)), 256, 0, ctx->stream>>>(
+            net->ga[l], net->a[l], net->Wt[l], dX, D, make_grid3(h), c);
     }
   }
   HIPCHK(hipGetLastError());
@@ -218,7 +219,7 @@ void upload_fraction_scaling(hh_ctx* ctx, hh_net* net) {
 
 void check_input(hh_ctx* ctx, hh_net* net, int batch, int box, int o) {
   if (!net) fail(ctx, HH_EINVAL, "null network");
-  if (batch < 1) fail(ctx, HH_EINVAL, "batch must be >= 1");
+  if (batch < 1 || batch > 65535) fail(ctx, HH_EINVAL, "batch must be in [1, 65535]");
   if (o < 0 || o + net->n > box) fail(ctx, HH_EINVAL, "input window outside the boxes");
 }
 

@@ -60,6 +60,33 @@ __device__ __forceinline__ int label_at(const LabelWindow& w, long long b, int z
   return w.labels[b * w.stride + ((long long)(z + w.o) * w.box + (y + w.o)) * w.box + (x + w.o)];
 }
 
+// floor(a / d) for 0 <= a < 2^23 and d >= 1, given inv = 1.0f / d: the
+// float quotient is within one of the true one, and one integer step fixes it.
+__device__ __forceinline__ int fdiv(int a, int d, float inv) {
+  int q = int(float(a) * inv);
+  const int r = a - q * d;
+  q += (r >= d ? 1 : 0) - (r < 0 ? 1 : 0);
+  return q;
+}
+
+// Output voxel v (< Do^3) of one item -> (oz, oy, ox).
+struct Grid3 {
+  int D, D2;         // edge and edge^2
+  float inv, inv2;   // their reciprocals
+};
+__host__ inline Grid3 make_grid3(int D) { return Grid3{D, D * D, 1.0f / float(D), 1.0f / float(D * D)}; }
+__device__ __forceinline__ void split3(const Grid3& g, int v, int& z, int& y, int& x) {
+  z = fdiv(v, g.D2, g.inv2);
+  const int r = v - z * g.D2;
+  y = fdiv(r, g.D, g.inv);
+  x = r - y * g.D;
+}
+
+// labels of item b as a base pointer at window origin (o, o, o)
+__device__ __forceinline__ const unsigned char* window_base(const LabelWindow& w, int b) {
+  return w.labels + (long long)b * w.stride + ((long long)w.o * w.box + w.o) * w.box + w.o;
+}
+
 __device__ __forceinline__ bf16x8 onehot8(int lab) {
   bf16x8 h;
 #pragma unroll
@@ -102,15 +129,6 @@ __global__ void k_zero_int(int* __restrict__ p, int n) {
   if (i < n) p[i] = 0;
 }
 
-// Input voxel of output voxel (oz, oy, ox) under tap t (stride 2, pad 1);
-// returns -1 when it falls in the zero padding.
-__device__ __forceinline__ long long in_voxel(int oz, int oy, int ox, int t, int D) {
-  const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
-  const int iz = 2 * oz + tz - 1, iy = 2 * oy + ty - 1, ix = 2 * ox + tx - 1;
-  if (iz < 0 || iy < 0 || ix < 0 || iz >= D || iy >= D || ix >= D) return -1;
-  return ((long long)iz * D + iy) * D + ix;
-}
-
 // ---------------------------------------------------------------------------
 // forward convolution + bias + ReLU.  256 threads = 4 waves; each wave
 // computes RB row blocks of 16 output voxels x COUT channels, so that every
@@ -120,27 +138,36 @@ __device__ __forceinline__ long long in_voxel(int oz, int oy, int ox, int t, int
 template <int CIN, int COUT, bool LAB, int RB>
 __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
                                                   const __bf16* __restrict__ W, const float* __restrict__ bias,
-                                                  __bf16* __restrict__ Y, int D, int batch) {
+                                                  __bf16* __restrict__ Y, int D, Grid3 go) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
   static_assert(!LAB || CIN == 8, "label input has 8 channels");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
-  const int Do = D / 2;
-  const long long nvo = (long long)Do * Do * Do, total = nvo * batch;
+  constexpr int VW = 16 * RB;  // output voxels of one wave
+  // one-hot codes of labels 0..7 and a zero row (index 8) for padding and labels >= 8
+  __shared__ bf16x8 sOne[9];
+  // first layer (large output): each wave's output tile, [voxel][channel],
+  // goes out as whole 16-byte chunks; deeper layers store straight from the
+  // MFMA result layout
+  constexpr bool STAGE = LAB;
+  __shared__ __align__(16) __bf16 sOut[STAGE ? 4 : 1][STAGE ? VW * COUT : 8];
+  const int nvo = go.D2 * go.D;  // output voxels per item
+  const int b = blockIdx.y;      // item
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long v0 = (long long)blockIdx.x * (64 * RB) + wave * (16 * RB);
+  const int v0 = blockIdx.x * (64 * RB) + wave * VW;
+  if constexpr (LAB) {
+    if (threadIdx.x < 9) sOne[threadIdx.x] = threadIdx.x < 8 ? onehot8(threadIdx.x) : zero8();
+    __syncthreads();
+  }
+  const __bf16* Xb = LAB ? nullptr : X + (long long)b * D * D * D * CIN;
+  const unsigned char* Lb = LAB ? window_base(lw, b) : nullptr;
   // the voxel whose A row this lane loads, per row block
   bool valid[RB];
-  long long bidx[RB];
   int oz[RB], oy[RB], ox[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    const long long va = v0 + r * 16 + (lane & 15);
-    valid[r] = va < total;
-    const long long ba = valid[r] ? va / nvo : 0, ra = valid[r] ? va - ba * nvo : 0;
-    bidx[r] = ba;
-    oz[r] = int(ra / ((long long)Do * Do));
-    oy[r] = int((ra / Do) % Do);
-    ox[r] = int(ra % Do);
+    const int va = v0 + r * 16 + (lane & 15);
+    valid[r] = va < nvo;
+    split3(go, valid[r] ? va : 0, oz[r], oy[r], ox[r]);
   }
   f32x4 acc[RB][NT];
 #pragma unroll
@@ -150,40 +177,67 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   for (int ks = 0; ks < KS; ++ks) {
     const int k = ks * 32 + (lane >> 4) * 8;
     const int tap = k / CIN, c0 = k % CIN;
-    bf16x8 b[NT];
+    bf16x8 bw[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      b[t] = zero8();
-      if (tap < 27) b[t] = ld8(W + ((long long)tap * COUT + t * 16 + (lane & 15)) * CIN + c0);
+      bw[t] = zero8();
+      if (tap < 27) bw[t] = ld8(W + (tap * COUT + t * 16 + (lane & 15)) * CIN + c0);
     }
     const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      bf16x8 a = zero8();
-      if (valid[r] && tap < 27) {
-        const int iz = 2 * oz[r] + tz - 1, iy = 2 * oy[r] + ty - 1, ix = 2 * ox[r] + tx - 1;
-        if (iz >= 0 && iy >= 0 && ix >= 0 && iz < D && iy < D && ix < D) {
-          if constexpr (LAB)
-            a = onehot8(label_at(lw, bidx[r], iz, iy, ix));
-          else
-            a = ld8(X + (bidx[r] * (long long)D * D * D + ((long long)iz * D + iy) * D + ix) * CIN + c0);
-        }
+      // input 2o + t - 1 is never >= D (D even); only the low side can fall in the padding
+      const int iz = 2 * oz[r] + tz - 1, iy = 2 * oy[r] + ty - 1, ix = 2 * ox[r] + tx - 1;
+      const bool in = valid[r] && tap < 27 && iz >= 0 && iy >= 0 && ix >= 0;
+      bf16x8 a;
+      if constexpr (LAB) {
+        int lab = 8;
+        if (in) lab = min(int(Lb[(iz * lw.box + iy) * lw.box + ix]), 8);
+        a = sOne[lab];
+      } else {
+        a = zero8();
+        if (in) a = ld8(Xb + ((iz * D + iy) * D + ix) * CIN + c0);
       }
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a, b[t], acc[r][t]);
+      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a, bw[t], acc[r][t]);
     }
   }
+  if constexpr (STAGE) {
+    // bias + ReLU into the wave's LDS tile (row = voxel, col = channel) ...
+    __bf16* so = sOut[wave];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int co = t * 16 + (lane & 15);
-    const float bb = bias[co];
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + (lane & 15);
+      const float bb = bias[co];
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+      for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const long long v = v0 + r * 16 + (lane >> 4) * 4 + i;
-        if (v < total) Y[v * COUT + co] = (__bf16)fmaxf(acc[r][t][i] + bb, 0.0f);
-      }
+        for (int i = 0; i < 4; ++i)
+          so[(r * 16 + (lane >> 4) * 4 + i) * COUT + co] = (__bf16)fmaxf(acc[r][t][i] + bb, 0.0f);
+    }
+    __syncthreads();
+    // ... then out as contiguous 16-byte chunks (the wave's voxels are consecutive)
+    constexpr int CH = VW * COUT * 2 / 16;  // chunks per wave
+    const int nv = min(VW, nvo - v0);       // valid voxels of this wave (may be <= 0)
+    uint4* dst = reinterpret_cast<uint4*>(Y + ((long long)b * nvo + v0) * COUT);
+    const uint4* src = reinterpret_cast<const uint4*>(so);
+#pragma unroll
+    for (int c = lane; c < CH; c += 64)
+      if (c * 16 < nv * COUT * 2) dst[c] = src[c];
+  } else {
+    __bf16* Yb = Y + (long long)b * nvo * COUT;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int co = t * 16 + (lane & 15);
+      const float bb = bias[co];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int v = v0 + r * 16 + (lane >> 4) * 4 + i;
+          if (v < nvo) Yb[v * COUT + co] = (__bf16)fmaxf(acc[r][t][i] + bb, 0.0f);
+        }
+    }
   }
 }
 
@@ -193,19 +247,19 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_conv_fwd_splitk(const __bf16* __restrict__ X, const __bf16* __restrict__ W,
                                                          const float* __restrict__ bias, __bf16* __restrict__ Y, int D,
-                                                         int batch) {
+                                                         Grid3 go) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
   __shared__ float red[3][NT][64][4];
-  const int Do = D / 2;
-  const long long nvo = (long long)Do * Do * Do, total = nvo * batch;
+  const int nvo = go.D2 * go.D;
+  const int b = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long v0 = (long long)blockIdx.x * 16;
-  const long long va = v0 + (lane & 15);
-  const bool valid = va < total;
-  const long long ba = valid ? va / nvo : 0, ra = valid ? va - ba * nvo : 0;
-  const int oz = int(ra / ((long long)Do * Do)), oy = int((ra / Do) % Do), ox = int(ra % Do);
-  const __bf16* Xb = X + ba * (long long)D * D * D * CIN;
+  const int v0 = blockIdx.x * 16;
+  const int va = v0 + (lane & 15);
+  const bool valid = va < nvo;
+  int oz, oy, ox;
+  split3(go, valid ? va : 0, oz, oy, ox);
+  const __bf16* Xb = X + (long long)b * D * D * D * CIN;
   f32x4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -213,16 +267,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd_splitk(const __bf16* __restric
     const int k = ks * 32 + (lane >> 4) * 8;
     const int tap = k / CIN, c0 = k % CIN;
     bf16x8 a = zero8();
-    if (valid && tap < 27) {
-      const int iz = 2 * oz + tap / 9 - 1, iy = 2 * oy + (tap / 3) % 3 - 1, ix = 2 * ox + tap % 3 - 1;
-      if (iz >= 0 && iy >= 0 && ix >= 0 && iz < D && iy < D && ix < D)
-        a = ld8(Xb + (((long long)iz * D + iy) * D + ix) * CIN + c0);
-    }
+    const int iz = 2 * oz + tap / 9 - 1, iy = 2 * oy + (tap / 3) % 3 - 1, ix = 2 * ox + tap % 3 - 1;
+    if (valid && tap < 27 && iz >= 0 && iy >= 0 && ix >= 0) a = ld8(Xb + ((iz * D + iy) * D + ix) * CIN + c0);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      bf16x8 b = zero8();
-      if (tap < 27) b = ld8(W + ((long long)tap * COUT + t * 16 + (lane & 15)) * CIN + c0);
-      acc[t] = mfma(a, b, acc[t]);
+      bf16x8 bw = zero8();
+      if (tap < 27) bw = ld8(W + (tap * COUT + t * 16 + (lane & 15)) * CIN + c0);
+      acc[t] = mfma(a, bw, acc[t]);
     }
   }
   if (wave > 0) {
@@ -233,6 +284,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_splitk(const __bf16* __restric
   }
   __syncthreads();
   if (wave == 0) {
+    __bf16* Yb = Y + (long long)b * nvo * COUT;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int co = t * 16 + (lane & 15);
@@ -240,8 +292,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd_splitk(const __bf16* __restric
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float sum = acc[t][i] + red[0][t][lane][i] + red[1][t][lane][i] + red[2][t][lane][i];
-        const long long v = v0 + (lane >> 4) * 4 + i;
-        if (v < total) Y[v * COUT + co] = (__bf16)fmaxf(sum + bb, 0.0f);
+        const int v = v0 + (lane >> 4) * 4 + i;
+        if (v < nvo) Yb[v * COUT + co] = (__bf16)fmaxf(sum + bb, 0.0f);
       }
     }
   }
@@ -257,22 +309,22 @@ __global__ void __launch_bounds__(256) k_conv_fwd_splitk(const __bf16* __restric
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_conv_dgrad(const float* __restrict__ dY, const __bf16* __restrict__ Y,
                                                     const __bf16* __restrict__ Wt, float* __restrict__ dX, int D,
-                                                    int batch, int cls) {
+                                                    Grid3 gh, int cls) {
   static_assert(CIN % 16 == 0 && COUT % 32 == 0, "channel counts");
   constexpr int NT = CIN / 16, KC = COUT / 32;
   const int Do = D / 2;
   const int pz = (cls >> 2) & 1, py = (cls >> 1) & 1, px = cls & 1;
-  const int h = D / 2;  // voxels per axis in a parity class
-  const long long ncls = (long long)h * h * h;
+  const int ncls = gh.D2 * gh.D;  // voxels of one parity class in one item (h = D / 2 per axis)
+  const int b = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long v0 = (long long)blockIdx.x * 64 + wave * 16;
-  const long long va = v0 + (lane & 15);
-  const bool valid_a = va < ncls * batch;
-  const long long ba = valid_a ? va / ncls : 0, ra = valid_a ? va - ba * ncls : 0;
-  const int jz = int(ra / ((long long)h * h)), jy = int((ra / h) % h), jx = int(ra % h);
-  const long long nvo = (long long)Do * Do * Do;
-  const float* dYb = dY + ba * nvo * COUT;
-  const __bf16* Yb = Y + ba * nvo * COUT;
+  const int v0 = blockIdx.x * 64 + wave * 16;
+  const int va = v0 + (lane & 15);
+  const bool valid_a = va < ncls;
+  int jz, jy, jx;
+  split3(gh, valid_a ? va : 0, jz, jy, jx);
+  const int nvo = Do * Do * Do;
+  const float* dYb = dY + (long long)b * nvo * COUT;
+  const __bf16* Yb = Y + (long long)b * nvo * COUT;
   // taps along each axis for this parity: even -> {1}, odd -> {0, 2}
   const int nz_t = pz ? 2 : 1, ny_t = py ? 2 : 1, nx_t = px ? 2 : 1;
   f32x4 acc[NT];
@@ -285,35 +337,34 @@ __global__ void __launch_bounds__(256) k_conv_dgrad(const float* __restrict__ dY
         const int tap = (tz * 3 + ty) * 3 + tx;
         // i = 2 j + p = 2 o + t - 1  ->  o = j + (p + 1 - t) / 2
         const int oz = jz + (pz + 1 - tz) / 2, oy = jy + (py + 1 - ty) / 2, ox = jx + (px + 1 - tx) / 2;
-        const bool in = valid_a && oz >= 0 && oy >= 0 && ox >= 0 && oz < Do && oy < Do && ox < Do;
-        const long long ov = ((long long)oz * Do + oy) * Do + ox;
+        const bool in = valid_a && oz < Do && oy < Do && ox < Do;
+        const int ov = (oz * Do + oy) * Do + ox;
         for (int kc = 0; kc < KC; ++kc) {
           const int co0 = kc * 32 + (lane >> 4) * 8;
           bf16x8 a = zero8();
           if (in) {
-            const float* g = dYb + ov * COUT + co0;
+            const float* gp = dYb + ov * COUT + co0;
             const bf16x8 yv = ld8(Yb + ov * COUT + co0);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = (__bf16)((float)yv[j] > 0.0f ? g[j] : 0.0f);
+            for (int j = 0; j < 8; ++j) a[j] = (__bf16)((float)yv[j] > 0.0f ? gp[j] : 0.0f);
           }
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
-            const bf16x8 b = ld8(Wt + ((long long)tap * CIN + t * 16 + (lane & 15)) * COUT + co0);
-            acc[t] = mfma(a, b, acc[t]);
+            const bf16x8 bw = ld8(Wt + (tap * CIN + t * 16 + (lane & 15)) * COUT + co0);
+            acc[t] = mfma(a, bw, acc[t]);
           }
         }
       }
+  float* dXb = dX + (long long)b * D * D * D * CIN;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int ci = t * 16 + (lane & 15);
+  for (int i = 0; i < 4; ++i) {
+    const int v = v0 + (lane >> 4) * 4 + i;
+    if (v < ncls) {
+      int z, y, x;
+      split3(gh, v, z, y, x);
+      const int base = (((2 * z + pz) * D + 2 * y + py) * D + 2 * x + px) * CIN;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long long v = v0 + (lane >> 4) * 4 + i;
-      if (v < ncls * batch) {
-        const long long b = v / ncls, r = v - b * ncls;
-        const int z = 2 * int(r / ((long long)h * h)) + pz, y = 2 * int((r / h) % h) + py, x = 2 * int(r % h) + px;
-        dX[(b * (long long)D * D * D + ((long long)z * D + y) * D + x) * CIN + ci] = acc[t][i];
-      }
+      for (int t = 0; t < NT; ++t) dXb[base + t * 16 + (lane & 15)] = acc[t][i];
     }
   }
 }
@@ -328,7 +379,7 @@ __global__ void __launch_bounds__(256) k_conv_dgrad(const float* __restrict__ dY
 template <int CIN, int COUT, bool LAB>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY, const __bf16* __restrict__ Y,
                                                     const __bf16* __restrict__ X, LabelWindow lw,
-                                                    float* __restrict__ part, float* __restrict__ pb, int D,
+                                                    float* __restrict__ part, float* __restrict__ pb, int D, Grid3 go,
                                                     int batch, int chunk) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0 && 256 % COUT == 0, "channel counts");
   static_assert(!LAB || CIN == 8, "label input has 8 channels");
@@ -336,9 +387,12 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY
   constexpr int VS = 32;                                 // voxels per staged step (= MFMA K)
   __shared__ __bf16 sZ[COUT][VS + 8];
   __shared__ __bf16 sX[NTN * 16][VS + 8];
+  __shared__ int sPos[VS][4];  // item, iz0, iy0, ix0 (input corner 2o - 1) of each staged voxel; item -1 if none
   const int tap = blockIdx.y;
-  const int Do = D / 2;
-  const long long nvo = (long long)Do * Do * Do, total = nvo * batch;
+  const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
+  const int nvo = go.D2 * go.D;
+  const float inv_nvo = 1.0f / float(nvo);
+  const long long total = (long long)nvo * batch;
   const long long vbeg = (long long)blockIdx.x * chunk;
   const long long vend = vbeg + chunk < total ? vbeg + chunk : total;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -349,36 +403,48 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY
   for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.0f;  // bias partial for cout = threadIdx.x % COUT (tap 13 blocks)
   __shared__ float sB[256];
+  // (item, voxel) of the first staged voxel, carried from step to step
+  int b0 = int(vbeg / nvo), r0 = int(vbeg - (long long)b0 * nvo);
   for (long long vs = vbeg; vs < vend; vs += VS) {
+    __syncthreads();
+    if (threadIdx.x < VS) {
+      const int vl = threadIdx.x;
+      int bi = -1, z = 0, y = 0, x = 0;
+      if (vs + vl < vend) {
+        const int q = fdiv(r0 + vl, nvo, inv_nvo);
+        bi = b0 + q;
+        split3(go, r0 + vl - q * nvo, z, y, x);
+      }
+      sPos[vl][0] = bi;
+      sPos[vl][1] = 2 * z - 1;
+      sPos[vl][2] = 2 * y - 1;
+      sPos[vl][3] = 2 * x - 1;
+    }
     __syncthreads();
     // stage dZ^T: COUT x VS
     for (int e = threadIdx.x; e < COUT * VS; e += 256) {
       const int co = e % COUT, vl = e / COUT;
-      const long long v = vs + vl;
-      float z = 0.0f;
-      if (v < vend) {
-        const float g = dY[v * COUT + co];
-        z = (float)Y[v * COUT + co] > 0.0f ? g : 0.0f;
+      float zv = 0.0f;
+      if (vs + vl < vend) {
+        const long long v = vs + vl;
+        const float gv = dY[v * COUT + co];
+        zv = (float)Y[v * COUT + co] > 0.0f ? gv : 0.0f;
       }
-      sZ[co][vl] = (__bf16)z;
-      if (tap == 13) bsum += z;  // co == threadIdx.x % COUT since 256 % COUT == 0
+      sZ[co][vl] = (__bf16)zv;
+      if (tap == 13) bsum += zv;  // co == threadIdx.x % COUT since 256 % COUT == 0
     }
     // stage X^T for this tap: CIN x VS (zero rows beyond CIN)
     for (int e = threadIdx.x; e < NTN * 16 * VS; e += 256) {
       const int ci = e % (NTN * 16), vl = e / (NTN * 16);
-      const long long v = vs + vl;
       float xv = 0.0f;
-      if (v < vend && ci < CIN) {
-        const long long b = v / nvo, r = v - b * nvo;
-        const int oz = int(r / ((long long)Do * Do)), oy = int((r / Do) % Do), ox = int(r % Do);
-        const long long iv = in_voxel(oz, oy, ox, tap, D);
-        if (iv >= 0) {
-          if constexpr (LAB) {
-            const int iz = int(iv / ((long long)D * D)), iy = int((iv / D) % D), ix = int(iv % D);
-            xv = label_at(lw, b, iz, iy, ix) == ci ? 1.0f : 0.0f;
-          } else {
-            xv = (float)X[(b * (long long)D * D * D + iv) * CIN + ci];
-          }
+      const int bi = sPos[vl][0];
+      if (bi >= 0 && ci < CIN) {
+        const int iz = sPos[vl][1] + tz, iy = sPos[vl][2] + ty, ix = sPos[vl][3] + tx;
+        if (iz >= 0 && iy >= 0 && ix >= 0) {  // 2 o + t - 1 < D always
+          if constexpr (LAB)
+            xv = window_base(lw, bi)[(iz * lw.box + iy) * lw.box + ix] == ci ? 1.0f : 0.0f;
+          else
+            xv = (float)X[((long long)bi * D * D * D + (iz * D + iy) * D + ix) * CIN + ci];
         }
       }
       sX[ci][vl] = (__bf16)xv;
@@ -389,15 +455,20 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY
       const int tile = wave + 4 * q;
       if (tile < TILES) {
         const int mt = tile / NTN, nt = tile % NTN;
-        bf16x8 a, b;
+        bf16x8 a, bw;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           a[j] = sZ[mt * 16 + (lane & 15)][(lane >> 4) * 8 + j];
-          b[j] = sX[nt * 16 + (lane & 15)][(lane >> 4) * 8 + j];
+          bw[j] = sX[nt * 16 + (lane & 15)][(lane >> 4) * 8 + j];
         }
-        acc[q] = mfma(a, b, acc[q]);
+        acc[q] = mfma(a, bw, acc[q]);
       }
     }
+    // advance the carried (item, voxel) by one step
+    r0 += VS;
+    const int q = fdiv(r0, nvo, inv_nvo);
+    b0 += q;
+    r0 -= q * nvo;
   }
   // D tile rows = cout (A rows), cols = cin (B cols)
   float* out = part + ((long long)blockIdx.x * 27 + tap) * COUT * CIN;

@@ -11,24 +11,33 @@
 
 namespace hh {
 
-__global__ void k_gather_pad(const unsigned char* __restrict__ img, int nx, int ny, int nz, int n, int p,
-                             int mx, int my, long long nitems, unsigned char* __restrict__ out) {
+// Row-wise copy: grid (row blocks of kGatherRows rows, items); each wave
+// takes whole rows of the (n + 2p)^3 box, lanes along x.  The source row
+// (z, y) wraps once per row, x once per byte (p < nx, so one step suffices).
+constexpr int kGatherRows = 64;
+
+__global__ void __launch_bounds__(256) k_gather_pad(const unsigned char* __restrict__ img, int nx, int ny, int nz,
+                                                    int n, int p, int mx, int my, int item0,
+                                                    unsigned char* __restrict__ out) {
   const int b = n + 2 * p;
-  const long long box = (long long)b * b * b;
-  const long long total = nitems * box;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long item = i / box;
-    const long long r = i - item * box;
-    const int zz = int(r / ((long long)b * b));
-    const int yy = int((r / b) % b);
-    const int xx = int(r % b);
-    const int bx = int(item % mx), by = int((item / mx) % my), bz = int(item / ((long long)mx * my));
-    int z = bz * n - p + zz, y = by * n - p + yy, x = bx * n - p + xx;
-    z = ((z % nz) + nz) % nz;
-    y = ((y % ny) + ny) % ny;
-    x = ((x % nx) + nx) % nx;
-    out[i] = img[((long long)z * ny + y) * nx + x];
+  const int item = item0 + blockIdx.y;
+  const int bx = item % mx, by = (item / mx) % my, bz = item / (mx * my);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * kGatherRows, r1 = min(b * b, r0 + kGatherRows);
+  const int x0 = bx * n - p;
+  unsigned char* dst_item = out + (long long)item * b * b * b;
+  for (int r = r0 + wave; r < r1; r += 4) {
+    const int zz = r / b, yy = r - zz * b;
+    int z = bz * n - p + zz, y = by * n - p + yy;
+    z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    const unsigned char* src = img + ((long long)z * ny + y) * nx;
+    unsigned char* dst = dst_item + (long long)r * b;
+    for (int xx = lane; xx < b; xx += 64) {
+      int x = x0 + xx;
+      x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+      dst[xx] = src[x];
+    }
   }
 }
 
@@ -80,11 +89,13 @@ __global__ void k_convert_field(const double* __restrict__ src, T* __restrict__ 
 void launch_gather_pad(const unsigned char* img, int nx, int ny, int nz, int n, int p, unsigned char* out,
                        hipStream_t st) {
   const int mx = nx / n, my = ny / n, mz = nz / n;
-  const long long nitems = (long long)mx * my * mz;
-  const long long total = nitems * (long long)(n + 2 * p) * (n + 2 * p) * (n + 2 * p);
-  const long long blocks = (total + 255) / 256;
-  k_gather_pad<<<int(blocks < 65536 ? blocks : 65536), 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, nitems,
-                                                                      out);
+  const int nitems = mx * my * mz;
+  const int b = n + 2 * p;
+  const unsigned rb = unsigned((b * b + kGatherRows - 1) / kGatherRows);
+  for (int i0 = 0; i0 < nitems; i0 += 65535) {
+    const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
+    k_gather_pad<<<dim3(rb, unsigned(ni)), 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, i0, out);
+  }
 }
 
 void launch_label_max(const unsigned char* labels, const long long* off, const long long* count, int nitems,

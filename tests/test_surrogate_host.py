@@ -76,3 +76,22 @@ def test_device_generator_fractions():
     lab = synth.four_phase_device(32, seed=3, device="cpu").numpy()
     f = np.bincount(lab.ravel(), minlength=4) / lab.size
     assert np.abs(f - synth.FOUR_PHASE["fracs"]).max() < 1.0 / lab.size
+
+
+def test_float_reciprocal_division_is_exact():
+    """The network kernels split voxel indices with q = int(a * (1/d)) plus one
+    integer correction step, in float32; exact for 0 <= a < 2^23, d >= 1."""
+    rng = np.random.default_rng(0)
+    ds = set([1, 2, 3, 7, 8, 15, 16, 17, 31, 32, 33, 64, 100, 127, 128, 129, 4095, 4096, 4097, 32767, 32768,
+              32769, 2 ** 21 - 1, 2 ** 21])
+    ds |= set(int(x) for x in rng.integers(1, 2 ** 21, size=300))
+    for d in sorted(ds):
+        inv = np.float32(1.0) / np.float32(d)
+        ks = np.unique(np.concatenate([np.arange(0, 5), (2 ** 23 - 1) // d - np.arange(0, 3),
+                                       rng.integers(0, (2 ** 23 - 1) // d + 1, size=40)]))
+        a = np.concatenate([ks * d - 1, ks * d, ks * d + 1, rng.integers(0, 2 ** 23, size=200)])
+        a = a[(a >= 0) & (a < 2 ** 23)].astype(np.int64)
+        q = (a.astype(np.float32) * inv).astype(np.int64)  # truncation, as the float-to-int conversion
+        r = a - q * d
+        q = q + (r >= d) - (r < 0)
+        assert np.array_equal(q, a // d), d
