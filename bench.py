@@ -31,7 +31,8 @@ KCLS = ("zinv", "yinv", "x", "yfwd", "zfwd")
 
 
 def algorithmic_bytes(nx, ny, nz, cbytes=8):
-    """Bytes each pass class must move per system-iteration."""
+    """Bytes each pass class must move per system-iteration: the CG vectors as 3-vectors, the
+    6-component spectrum in FP32 complex (cbytes per value), labels once per voxel."""
     nf = (nx // 2 + 1) * ny * nz  # half-spectrum frequencies
     V = nx * ny * nz
     return {

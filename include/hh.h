@@ -190,7 +190,7 @@ int hh_gather_subimages(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int 
 /* ------------------------------------------------------------------------
  * Learned surrogate of the subimage stiffness (an addition to the paper's
  * method: it replaces the FFT solve of Sec. 4 for subimages a gate accepts,
- * and the FFT solve stays the fallback and the judge of its error).
+ * and the FFT solve stays the fallback and the reference for its error).
  * A 3-D CNN maps the one-hot phase labels of an n^3 subimage to its 21
  * stiffness components: four 3x3x3 stride-2 convolutions (8 -> 32 -> 32 ->
  * 64 -> 64 channels, ReLU) and a global mean give 64 features; the window's

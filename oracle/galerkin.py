@@ -18,7 +18,7 @@ What it computes (paper, Sec. 4 and Appendix A):
   G * (C : eps*) = - G * (C : E), solved by conjugate gradients.
 * Averages over the region Omega_R and C_R = Sigma_R E_R^-1 (Sec. 4).
 
-Readings where the paper is silent or garbled (each also listed in the design doc):
+Readings where the paper is silent or garbled:
 
 * Grid/frequency: arrays are indexed [z][y][x]; tensor index 0/1/2 is x/y/z;
   k_d = m_d / N_d with integer m_d in FFT order (unit voxel; the projection

@@ -1,4 +1,4 @@
-// Internal interface of the CNN surrogate used by the hierarchical driver.
+// Internal interface of the CNN surrogate used by the two-level scheme.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -1,5 +1,5 @@
 // Host side of the C ABI declared in include/hh.h: validation, workspace,
-// the per-group solve loop, and the hierarchical driver.
+// the per-group solve loop, and the two-level scheme.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -96,28 +96,32 @@ struct XCfg {
 // helpers
 // ---------------------------------------------------------------------------
 
-// Wave number component of FFT index i on an n-point axis (unit voxel);
-// the Nyquist component is zero.  Sets nyq when i is the Nyquist index.
-__device__ __forceinline__ double kcomp(int i, int n, bool& nyq) {
+// Signed wave number of FFT index i on an n-point axis; 0 at the Nyquist
+// index (nyq set there).
+__device__ __forceinline__ int kint(int i, int n, bool& nyq) {
   nyq = (2 * i == n);
-  const int m = (2 * i <= n) ? i : i - n;
-  return nyq ? 0.0 : double(m) / double(n);
+  return nyq ? 0 : ((2 * i <= n) ? i : i - n);
 }
 
-// Unit wave vector of frequency (kx, ky, kz); false where the operator is zero.
+__device__ __forceinline__ float inv_sqrt(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
+// Unit wave vector of frequency (kx, ky, kz) in the field precision T, from
+// k_d = m_d / N_d; false where the operator is zero.
 template <class T>
 __device__ __forceinline__ bool unit_k(const GroupArgs& g, int kx, int ky, int kz, T n[3]) {
   bool qx, qy, qz;
-  const double a = kcomp(kx, g.nx, qx), b = kcomp(ky, g.ny, qy), c = kcomp(kz, g.nz, qz);
-  const double k2 = a * a + b * b + c * c;
-  if (k2 == 0.0 || (g.nyq_zero && (qx || qy || qz))) {
+  const int mx = kint(kx, g.nx, qx), my = kint(ky, g.ny, qy), mz = kint(kz, g.nz, qz);
+  if ((mx == 0 && my == 0 && mz == 0) || (g.nyq_zero && (qx || qy || qz))) {
     n[0] = n[1] = n[2] = T(0);
     return false;
   }
-  const double inv = 1.0 / sqrt(k2);
-  n[0] = T(a * inv);
-  n[1] = T(b * inv);
-  n[2] = T(c * inv);
+  // reciprocals of the axis lengths are loop invariants of every caller
+  const T a = T(mx) * (T(1) / T(g.nx)), b = T(my) * (T(1) / T(g.ny)), c = T(mz) * (T(1) / T(g.nz));
+  const T inv = inv_sqrt(a * a + b * b + c * c);
+  n[0] = a * inv;
+  n[1] = b * inv;
+  n[2] = c * inv;
   return true;
 }
 

@@ -4,7 +4,7 @@ The surrogate stands in for the FFT solve of Sec. 4 on each padded
 subimage: a network maps the one-hot phase labels of the n^3 core to the 21
 independent components of the subimage's stiffness C_R.  Training data are
 subimages that the library's own FFT solver homogenizes (the same padding
-p as at use), so the solver remains the judge of the network's error, and
+p as at use), so the solver remains the reference for the network's error, and
 at use a gate sends doubtful subimages back to it.
 
 Everything numeric runs in the HIP library (network kernels, solver,

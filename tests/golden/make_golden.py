@@ -3,6 +3,7 @@
 Calls only the FP64 CPU oracle (oracle/) and the seeded input generator.
 Usage:  python tests/golden/make_golden.py four_phase_256
         python tests/golden/make_golden.py hier_512_items
+        python tests/golden/make_golden.py uneven_2048_items
 """
 import json
 import os
@@ -51,5 +52,27 @@ def hier_512_items(count=6):
     json.dump(out, open(os.path.join(HERE, "four_phase_512_n64_p8_items.json"), "w"), indent=1)
 
 
+def uneven_2048_items(per_size=2):
+    """Stratified sample of the uneven batch recipe (2048 items, sizes 32, 48,
+    64, 96, seed 1234): the first ``per_size`` items of each size, six loads,
+    whole box."""
+    recipe = synth.uneven_batch(2048, seed=1234)
+    picked = []
+    for size in (32, 48, 64, 96):
+        picked += [i for i, it in enumerate(recipe) if it["size"] == size][:per_size]
+    items = []
+    for i in picked:
+        t = time.time()
+        it = recipe[i]
+        lab = synth.item_image(it)
+        r = g.homogenize(g.IsotropicMedium(lab, it["phases"]), tol=1e-9, form="sym6")
+        items.append(dict(index=i, size=it["size"], C=r.C.tolist(), C_sym=r.C_sym.tolist(), iters=r.iters,
+                          seconds=time.time() - t))
+        print("item", i, it["size"], time.time() - t, flush=True)
+    out = dict(recipe="synth.uneven_batch(2048, seed=1234)", tol=1e-9, form="sym6", items=items)
+    json.dump(out, open(os.path.join(HERE, "uneven_2048_items.json"), "w"), indent=1)
+
+
 if __name__ == "__main__":
-    {"four_phase_256": four_phase_256, "hier_512_items": hier_512_items}[sys.argv[1]]()
+    {"four_phase_256": four_phase_256, "hier_512_items": hier_512_items,
+     "uneven_2048_items": uneven_2048_items}[sys.argv[1]]()

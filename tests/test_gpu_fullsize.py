@@ -61,3 +61,41 @@ def test_512cube_hierarchy_sampled_items_match_stored_oracle(ctx):
         err = g.rel_error(got, want)
         print("item %d origin %s: %.3e" % (it["index"], it["origin"], err))
         assert err < 1e-5, it["index"]
+
+
+def test_uneven_2048_batch_sampled_items_match_stored_oracle(ctx):
+    """The uneven batched launch: all 2048 items (sizes 32-96, 2-4 phases) in
+    one call; a stratified sample (two per size) against the oracle."""
+    ref = golden("uneven_2048_items.json")
+    recipe = synth.uneven_batch(2048, seed=1234)
+    imgs = [synth.item_image(it) for it in recipe]
+    C, Craw, st, iters, rep = ctx.homogenize_batch(imgs, [it["phases"] for it in recipe], tol=1e-6)
+    assert (st == 0).all()
+    for it in ref["items"]:
+        err = g.rel_error(C[it["index"]], np.array(it["C_sym"]))
+        print("item %d (%d^3): %.3e" % (it["index"], it["size"], err))
+        assert err < 1e-5, it["index"]
+
+
+def test_surrogate_1024_within_budget_of_plain_hierarchy(ctx):
+    """The surrogate workload at full size: 1024^3 four-phase image (device
+    generator, seed 3), 4096 padded subimages, the shipped network pair; the
+    final C* against the plain FFT hierarchy on the same image."""
+    import os
+    from paper_2208_02320_amd import hh, surrogate
+    paths = surrogate.default_weights(64, 8)
+    if not all(os.path.exists(p) for p in paths):
+        pytest.skip("shipped surrogate weights missing")
+    na, nb = (surrogate.load(ctx, p) for p in paths)
+    img = synth.four_phase_device(1024, sigma=2.0, seed=3, device="cuda:0")
+    C, Cs, fb, rs = ctx.hierarchical_surrogate(img, FOUR, 64, 8, na, nb, spread_tol=0.02, bound_tol=0.0, tol=1e-6)
+    Cp, Csp, rp = ctx.hierarchical(img, FOUR, 64, 8, tol=1e-6)
+    err = g.rel_error(C, Cp)
+    sub = surrogate.rel_error21(Cs, Csp)
+    print("1024^3 surrogate: C* error %.2e, fallback %d/%d, subimage error mean %.3e max %.3e, %.3f s vs %.1f s" %
+          (err, fb.sum(), fb.size, sub.mean(), sub.max(), rs["seconds"], rp["seconds"]))
+    assert err < 1e-3
+    assert fb.mean() < 0.1
+    assert rs["seconds"] * 10 < rp["seconds"]
+    na.close()
+    nb.close()
