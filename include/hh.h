@@ -170,7 +170,11 @@ int hh_homogenize_batch(hh_ctx *ctx, int nitems, const int *dims, const uint8_t 
  * image edge) and averaged over the block; the symmetrized block stiffnesses
  * form the intermediate image, which is solved with anisotropic voxels.
  * C_out: final C* (36).  C_sub: (nz/n)(ny/n)(nx/n) x 21 symmetrized block
- * stiffnesses, C order (may be NULL).  use_surrogate must be 0.
+ * stiffnesses, C order (may be NULL).  use_surrogate must be 0 (the learned
+ * path is hh_hierarchical_surrogate).  With one subimage (n = image size)
+ * the intermediate image is a single voxel and C* is its stiffness; an
+ * intermediate image with some axes of length 1 and others longer returns
+ * HH_EUNSUPPORTED.
  */
 int hh_hierarchical(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, int labels_on_device,
                     const hh_phase *phases, int nphase, int n_sub, int pad, int use_surrogate,

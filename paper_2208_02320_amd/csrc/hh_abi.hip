@@ -887,7 +887,9 @@ int hh_hierarchical(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, 
     const int b = n_sub + 2 * pad;
     const int mx = nx / n_sub, my = ny / n_sub, mz = nz / n_sub;
     check_shape(ctx, b, b, b, o.precision);
-    check_shape(ctx, mx, my, mz, o.precision);
+    // one subimage: the intermediate image is a single voxel, whose solve is the identity
+    const bool single = mx == 1 && my == 1 && mz == 1;
+    if (!single) check_shape(ctx, mx, my, mz, o.precision);
     check_phases(ctx, phases, nphase);
     const long long nvox = (long long)nx * ny * nz;
     const int nitems = mx * my * mz;
@@ -922,6 +924,17 @@ int hh_hierarchical(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, 
         for (int p = 0; p < 6; ++p)
           for (int q = p; q < 6; ++q) C_sub[size_t(i) * 21 + k++] = S[p * 6 + q];
       }
+    }
+    if (single) {
+      end_report(ctx, report);
+      const double* S = r1.C72.data() + 36;
+      for (int i = 0; i < 36; ++i) C_out[i] = S[i];
+      if (report) {
+        report->voxel_iters = r1.voxel_iters;
+        report->items = nitems;
+        report->status = rc;
+      }
+      return rc;
     }
     Item l2;
     l2.nx = mx;
@@ -991,7 +1004,9 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     const int b = n_sub + 2 * pad;
     const int mx = nx / n_sub, my = ny / n_sub, mz = nz / n_sub;
     check_shape(ctx, b, b, b, o.precision);
-    check_shape(ctx, mx, my, mz, o.precision);
+    // one subimage: the intermediate image is a single voxel, whose solve is the identity
+    const bool single = mx == 1 && my == 1 && mz == 1;
+    if (!single) check_shape(ctx, mx, my, mz, o.precision);
     check_phases(ctx, phases, nphase);
     if (nphase > 8) fail(ctx, HH_EINVAL, "the surrogate takes at most 8 phases");
     const long long nvox = (long long)nx * ny * nz;
@@ -1087,6 +1102,18 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     }
     if (C_sub) std::memcpy(C_sub, field.data(), sizeof(double) * field.size());
     if (fallback) std::memcpy(fallback, flag.data(), sizeof(int) * nitems);
+    if (single) {
+      end_report(ctx, report);
+      int q = 0;
+      for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) C_out[i * 6 + j] = C_out[j * 6 + i] = field[q++];
+      if (report) {
+        report->voxel_iters = vi;
+        report->items = nitems;
+        report->status = rc;
+      }
+      return rc;
+    }
     // level 2
     auto* d_field = static_cast<double*>(ws(ctx, "sur_field", sizeof(double) * field.size()));
     HIPCHK(hipMemcpyAsync(d_field, field.data(), sizeof(double) * field.size(), hipMemcpyHostToDevice, st));

@@ -153,6 +153,20 @@ def test_hierarchical_fp32(ctx):
     assert g.rel_error(C, ref.C) < TOL32
 
 
+def test_hierarchical_single_subimage(ctx):
+    """n = N: one padded subimage; the intermediate image is a single voxel,
+    so C* is that subimage's symmetrized stiffness."""
+    lab = synth.rocklike(24, [0.7, 0.3], sigma=1.5, seed=5, low_to_high=[1, 0])
+    C, Cs, rep = ctx.hierarchical(lab, QP, 24, 4, tol=1e-11, precision=1)
+    ref = hier.hierarchical(lab, QP, 24, 4, tol=1e-12, form="sym6")
+    assert Cs.shape == (1, 21)
+    assert g.rel_error(C, ref.C) < TOL64
+    assert np.array_equal(hier.to21(C), Cs[0])
+    from paper_2208_02320_amd import hh
+    with pytest.raises(hh.HHError):  # 1 x 1 x 2 intermediate image
+        ctx.hierarchical(np.zeros((48, 24, 24), np.uint8), QP, 24, 0)
+
+
 def test_batch_mixed_sizes(ctx):
     recipe = synth.uneven_batch(6, sizes=(8, 12, 16), seed=77)
     imgs = [synth.item_image(it) for it in recipe]

@@ -248,6 +248,18 @@ def test_network_reading_the_whole_padded_box(ctx):
         x.close()
 
 
+def test_surrogate_single_subimage(ctx):
+    lab = synth.four_phase(32, seed=13)
+    n, pad = 32, 4
+    CV, CR = sg.core_bounds(lab, 0, 32, FOUR)
+    c = hier.to21(0.5 * (CV + CR))
+    net = constant_net(ctx, 4, n, c)
+    C, Cs, fb, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=0.5, tol=1e-6)
+    assert not fb.any()
+    assert np.array_equal(Cs[0], c) and np.array_equal(hier.to21(C), c)
+    net.close()
+
+
 def test_surrogate_argument_errors(ctx):
     from paper_2208_02320_amd import hh
     lab = synth.four_phase(32, seed=6)
