@@ -142,7 +142,7 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
   const int n = net->n;
   net->lw = LabelWindow{labels, (long long)box * box * box, box, o};
   k_zero_int<<<(batch * kFrac + 255) / 256, 256, 0, ctx->stream>>>(net->cnt, batch * kFrac);
-  k_count_labels<<<dim3((n * n + kCountRows - 1) / kCountRows, batch), 256, 0, ctx->stream>>>(net->lw, n, net->cnt);
+  k_count_labels<<<dim3((n * n + kCountRows - 1) / kCountRows, batch), 256, 0, ctx->stream>>>(net->lw, n, 0, net->cnt);
   conv_fwd<8, 32, true, 4>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
   conv_fwd<32, 32, false, 4>(ctx, net->a[0], net->lw, net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
   conv_fwd<32, 64, false, 2>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
@@ -240,8 +240,16 @@ void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels
 }
 
 void hh_launch_bounds(const unsigned char* labels, int nitems, int box, int o, int n, int nphase, const double* Cp21,
-                      const double* Sp21, double* cv21, double* cr21, hipStream_t st) {
-  k_phase_bounds<<<nitems, 256, 0, st>>>(labels, box, o, n, nphase, Cp21, Sp21, cv21, cr21);
+                      const double* Sp21, int* counts, double* cv21, double* cr21, hipStream_t st) {
+  k_zero_int<<<(nitems * 8 + 255) / 256, 256, 0, st>>>(counts, nitems * 8);
+  const LabelWindow lw{labels, (long long)box * box * box, box, o};
+  const unsigned rb = unsigned((n * n + kCountRows - 1) / kCountRows);
+  for (int i0 = 0; i0 < nitems; i0 += 65535) {
+    const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
+    k_count_labels<<<dim3(rb, unsigned(ni)), 256, 0, st>>>(lw, n, i0, counts);
+  }
+  k_bounds_from_counts<<<(nitems + 63) / 64, 64, 0, st>>>(counts, nitems, 1.0 / (double(n) * n * n), nphase, Cp21,
+                                                          Sp21, cv21, cr21);
 }
 
 void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,

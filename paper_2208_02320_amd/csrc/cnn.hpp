@@ -14,7 +14,7 @@ void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels
 // stiffness (21 components each, device).  Cp21/Sp21: per phase stiffness
 // and compliance (21 components, device).
 void hh_launch_bounds(const unsigned char* labels, int nitems, int box, int o, int n, int nphase, const double* Cp21,
-                      const double* Sp21, double* cv21, double* cr21, hipStream_t st);
+                      const double* Sp21, int* counts, double* cv21, double* cr21, hipStream_t st);
 void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,
                     double spread_tol, double bound_tol, int* flag, hipStream_t st);
 int hh_net_input_size(const hh_net* net);

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -99,14 +100,16 @@ __device__ __forceinline__ bf16x8 onehot8(int lab) {
 // along x), counts in registers, then one atomic per block and label.
 constexpr int kCountRows = 64;
 
-__global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, int* __restrict__ cnt) {
-  const int b = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, int item0, int* __restrict__ cnt) {
+  const int b = item0 + blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = blockIdx.x * kCountRows, r1 = min(n * n, r0 + kCountRows);
+  const unsigned char* base = window_base(w, b);
   int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int r = r0 + wave; r < r1; r += 4) {
     const int z = r / n, y = r - z * n;
+    const unsigned char* row = base + (z * w.box + y) * w.box;
     for (int x = lane; x < n; x += 64) {
-      const int lab = label_at(w, b, z, y, x);
+      const int lab = row[x];
 #pragma unroll
       for (int k = 0; k < 8; ++k) c[k] += (lab == k) ? 1 : 0;
     }
@@ -160,47 +163,80 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   }
   const __bf16* Xb = LAB ? nullptr : X + (long long)b * D * D * D * CIN;
   const unsigned char* Lb = LAB ? window_base(lw, b) : nullptr;
-  // the voxel whose A row this lane loads, per row block
-  bool valid[RB];
-  int oz[RB], oy[RB], ox[RB];
+  const int rs = LAB ? lw.box : D;  // row stride of the input, in voxels
+  // per row block: offset of input corner (2o - 1) and which axes sit at o = 0
+  // (their tap 0 falls in the zero padding; 2o + t - 1 never reaches D)
+  int base[RB];
+  unsigned lowm[RB];  // bit 0: z, 1: y, 2: x at the low edge; bit 3: voxel past the end
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     const int va = v0 + r * 16 + (lane & 15);
-    valid[r] = va < nvo;
-    split3(go, valid[r] ? va : 0, oz[r], oy[r], ox[r]);
+    int oz, oy, ox;
+    split3(go, va < nvo ? va : 0, oz, oy, ox);
+    base[r] = ((2 * oz - 1) * rs + 2 * oy - 1) * rs + 2 * ox - 1;
+    lowm[r] = (oz == 0 ? 1u : 0u) | (oy == 0 ? 2u : 0u) | (ox == 0 ? 4u : 0u) | (va < nvo ? 0u : 8u);
   }
+  // input of k-step ks for row block r: a zero fragment where the tap falls
+  // in the padding; loads are issued without branches from a safe address
+  auto tap_of = [&](int ks) { return (ks * 32 + (lane >> 4) * 8) / CIN; };
+  auto tap_mask = [&](int tap) {
+    const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
+    return (tz == 0 ? 1u : 0u) | (ty == 0 ? 2u : 0u) | (tx == 0 ? 4u : 0u);
+  };
+  auto tap_off = [&](int tap) { return ((tap / 9) * rs + (tap / 3) % 3) * rs + tap % 3; };
+  using Raw = typename std::conditional<LAB, int, bf16x8>::type;
+  auto load_a = [&](int ks, int r, bool& ok) -> Raw {
+    const int tap = tap_of(ks);
+    ok = tap < 27 && (lowm[r] & (tap_mask(tap) | 8u)) == 0u;
+    const int off = ok ? base[r] + tap_off(tap) : 0;
+    if constexpr (LAB) {
+      return int(Lb[off]);
+    } else {
+      const int c0 = (ks * 32 + (lane >> 4) * 8) % CIN;
+      return ld8(Xb + off * CIN + c0);
+    }
+  };
+  auto load_b = [&](int ks, int t) {
+    const int k = ks * 32 + (lane >> 4) * 8;
+    const int tap = k / CIN, c0 = k % CIN;
+    return ld8(W + ((tap < 27 ? tap : 0) * COUT + t * 16 + (lane & 15)) * CIN + c0);
+  };
   f32x4 acc[RB][NT];
 #pragma unroll
   for (int r = 0; r < RB; ++r)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ks = 0; ks < KS; ++ks) {
-    const int k = ks * 32 + (lane >> 4) * 8;
-    const int tap = k / CIN, c0 = k % CIN;
-    bf16x8 bw[NT];
+  // software pipeline: the loads of k-step ks + 1 are in flight during the MFMAs of ks
+  Raw ra[RB];
+  bool rok[RB];
+  bf16x8 rb_[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      bw[t] = zero8();
-      if (tap < 27) bw[t] = ld8(W + (tap * COUT + t * 16 + (lane & 15)) * CIN + c0);
-    }
-    const int tz = tap / 9, ty = (tap / 3) % 3, tx = tap % 3;
+  for (int r = 0; r < RB; ++r) ra[r] = load_a(0, r, rok[r]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) rb_[t] = load_b(0, t);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    bf16x8 a[RB], bw[NT];
+    const bool btap = tap_of(ks) < 27;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bw[t] = btap ? rb_[t] : zero8();
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      // input 2o + t - 1 is never >= D (D even); only the low side can fall in the padding
-      const int iz = 2 * oz[r] + tz - 1, iy = 2 * oy[r] + ty - 1, ix = 2 * ox[r] + tx - 1;
-      const bool in = valid[r] && tap < 27 && iz >= 0 && iy >= 0 && ix >= 0;
-      bf16x8 a;
-      if constexpr (LAB) {
-        int lab = 8;
-        if (in) lab = min(int(Lb[(iz * lw.box + iy) * lw.box + ix]), 8);
-        a = sOne[lab];
-      } else {
-        a = zero8();
-        if (in) a = ld8(Xb + ((iz * D + iy) * D + ix) * CIN + c0);
-      }
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a, bw[t], acc[r][t]);
+      if constexpr (LAB)
+        a[r] = sOne[rok[r] ? min(ra[r], 8) : 8];
+      else
+        a[r] = rok[r] ? ra[r] : zero8();
     }
+    if (ks + 1 < KS) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) ra[r] = load_a(ks + 1, r, rok[r]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) rb_[t] = load_b(ks + 1, t);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a[r], bw[t], acc[r][t]);
   }
   if constexpr (STAGE) {
     // bias + ReLU into the wave's LDS tile (row = voxel, col = channel) ...
@@ -638,32 +674,16 @@ __global__ void k_gate(const double* __restrict__ c21a, const double* __restrict
   flag[it] = bad;
 }
 
-// Phase fractions of the n^3 core of each box (one block per item) and the
 // Voigt (arithmetic mean of stiffness) and Reuss (inverse of the mean
-// compliance) stiffnesses of that mixture, 21 components each.
-__global__ void __launch_bounds__(256) k_phase_bounds(const unsigned char* __restrict__ labels, int box, int o, int n,
-                                                      int nphase, const double* __restrict__ Cp21,
-                                                      const double* __restrict__ Sp21, double* __restrict__ cv21,
-                                                      double* __restrict__ cr21) {
-  __shared__ int cnt[16];
-  const int it = blockIdx.x;
-  if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const unsigned char* L = labels + (long long)it * box * box * box;
-  const long long nv = (long long)n * n * n;
-  int local[16];
-  for (int p = 0; p < 16; ++p) local[p] = 0;
-  for (long long v = threadIdx.x; v < nv; v += blockDim.x) {
-    const int z = int(v / (n * n)) + o, y = int((v / n) % n) + o, x = int(v % n) + o;
-    const int lab = L[((long long)z * box + y) * box + x];
-    if (lab < 16) local[lab] += 1;
-  }
-  for (int p = 0; p < nphase; ++p)
-    if (local[p]) atomicAdd(&cnt[p], local[p]);
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double f[16];
-  for (int p = 0; p < nphase; ++p) f[p] = double(cnt[p]) / double(nv);
+// compliance) stiffnesses of each item's phase mixture, 21 components each,
+// from its label counts (k_count_labels over the n^3 core).  One thread per item.
+__global__ void k_bounds_from_counts(const int* __restrict__ cnt, int nitems, double inv_nv, int nphase,
+                                     const double* __restrict__ Cp21, const double* __restrict__ Sp21,
+                                     double* __restrict__ cv21, double* __restrict__ cr21) {
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= nitems) return;
+  double f[8];
+  for (int p = 0; p < 8; ++p) f[p] = p < nphase ? double(cnt[it * 8 + p]) * inv_nv : 0.0;
   double S[6][6], Ci[6][6];
   int k = 0;
   for (int i = 0; i < 6; ++i)

@@ -274,14 +274,24 @@ __device__ __forceinline__ void fft_perm2nat(cx<T>* buf, int L, const cx<T>* tw)
   }
 }
 
-// Fill tw[0..N) with exp(2 pi i m / N) (double-precision sincospi, rounded).
+// Twiddle table exp(2 pi i m / N), m in [0, N), evaluated at compile time
+// (the series above in double, then rounded to T) and placed in read-only
+// device memory, one per (N, T).
+template <class T, int N>
+struct TwTable {
+  cx<T> v[N];
+};
+template <class T, int N, int... I>
+constexpr TwTable<T, N> make_twiddles(std::integer_sequence<int, I...>) {
+  return TwTable<T, N>{{cx<T>{T(cos2pi(I, N)), T(sin2pi(I, N))}...}};
+}
+template <int N, class T>
+__device__ const TwTable<T, N> kTwiddles = make_twiddles<T, N>(std::make_integer_sequence<int, N>{});
+
+// Copy the table into tw[0..N) (LDS); the caller's next barrier publishes it.
 template <int N, class T>
 __device__ __forceinline__ void fill_twiddles(cx<T>* tw) {
-  for (int m = threadIdx.x; m < N; m += blockDim.x) {
-    double s, c;
-    sincospi(2.0 * double(m) / double(N), &s, &c);
-    tw[m] = cx<T>{T(c), T(s)};
-  }
+  for (int m = threadIdx.x; m < N; m += blockDim.x) tw[m] = kTwiddles<N, T>.v[m];
 }
 
 // Split of N for the two-step DFT: N <= 16 in one register step, otherwise

@@ -1052,10 +1052,11 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     auto* cv21 = static_cast<double*>(ws(ctx, "sur_cv", sizeof(double) * 21 * nitems));
     auto* cr21 = static_cast<double*>(ws(ctx, "sur_cr", sizeof(double) * 21 * nitems));
     auto* d_flag = static_cast<int*>(ws(ctx, "sur_flag", sizeof(int) * nitems));
+    auto* d_counts = static_cast<int*>(ws(ctx, "sur_counts", sizeof(int) * 8 * size_t(nitems)));
     HIPCHK(hipMemcpyAsync(d_cp, cp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_sp, sp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
     prof.run(HH_K_OTHER, [&] {
-      hh_launch_bounds(d_pack, nitems, b, pad, n_sub, nphase, d_cp, d_sp, cv21, cr21, st);
+      hh_launch_bounds(d_pack, nitems, b, pad, n_sub, nphase, d_cp, d_sp, d_counts, cv21, cr21, st);
       hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, d_flag, st);
     });
     HIPCHK(hipGetLastError());

@@ -452,6 +452,7 @@ __global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g)
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + N;
   __shared__ T s_lam[kMaxPhase], s_mu[kMaxPhase];
+  __shared__ double s_sig[6];
 
   const int s = blockIdx.y;
   SysState* st = g.state + s;
@@ -613,29 +614,14 @@ __global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g)
   }
   __syncthreads();
   fft_perm2nat<N1, N2, -1, T, P>(buf, L, tw);
-  if (whole && threadIdx.x < 64) {
-    // tile sums of sigma from the kx = 0 outputs (lines: row * 3 + pair)
-    double sre[3] = {0.0, 0.0, 0.0}, sim[3] = {0.0, 0.0, 0.0};
-    for (int l = threadIdx.x; l < 3 * nr; l += 64) {
-      const cx<T> z0v = buf[lds_at<N1, P>(0, L) + l];
-      const int pr = l % 3;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        sre[q] += pr == q ? double(z0v.re) : 0.0;
-        sim[q] += pr == q ? double(z0v.im) : 0.0;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const double a = wave_sum(sre[q]), b = wave_sum(sim[q]);
-      if (threadIdx.x == 0) {
-        acc[7 + 2 * q] = a;
-        acc[8 + 2 * q] = b;
-      }
-    }
-    if (threadIdx.x == 0 && MODE == kXFp) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) acc[1 + c] = double(nr) * N * double(E[c]);
+  // whole box: tile sums of sigma are the kx = 0 outputs (lines row * 3 + pair);
+  // thread 2 * pair + (0 re, 1 im) sums its component over the tile rows
+  double sig_sum = 0.0;
+  if (whole && threadIdx.x < 6) {
+    const int pr = threadIdx.x >> 1;
+    for (int rl = 0; rl < nr; ++rl) {
+      const cx<T> z0v = buf[lds_at<N1, P>(0, L) + rl * 3 + pr];
+      sig_sum += double((threadIdx.x & 1) ? z0v.im : z0v.re);
     }
   }
   for (int f = threadIdx.x; f < NU; f += TH) {
@@ -650,7 +636,20 @@ __global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g)
     tmpp[(rl * HXP + kx) * 3 + pr] = o;
   }
   __syncthreads();
-  if constexpr (TH * kPartX * 8 <= (N * L + N2 * P) * int(sizeof(cx<T>))) {
+  if (whole) {
+    // only (p, C:p) is spread over the threads
+    if (threadIdx.x < 6) s_sig[threadIdx.x] = sig_sum;
+    double a0[1] = {acc[0]};
+    block_sum_lds<1, TH>(a0, reinterpret_cast<double*>(buf));
+    if (threadIdx.x == 0) {
+      acc[0] = a0[0];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        acc[1 + c] = MODE == kXFp ? double(nr) * N * double(E[c]) : 0.0;
+        acc[7 + c] = s_sig[c];
+      }
+    }
+  } else if constexpr (TH * kPartX * 8 <= (N * L + N2 * P) * int(sizeof(cx<T>))) {
     block_sum_lds<kPartX, TH>(acc, reinterpret_cast<double*>(buf));
   } else {
     block_sum<kPartX>(acc, reinterpret_cast<double*>(buf));
