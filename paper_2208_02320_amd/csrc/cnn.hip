@@ -41,6 +41,7 @@ struct hh_net {
   int cap = 0;  // batch capacity of the activation buffers
   LabelWindow lw{};  // input of the last forward pass (read again by the first layer's weight gradient)
   int* cnt = nullptr;  // label counts per item [cap][8]
+  const int* cnt_in = nullptr;  // the counts the head reads (cnt or the caller's)
   __bf16* a[kLayers] = {};
   float* ga[kLayers] = {};  // gradient w.r.t. output of layer l
   float *out = nullptr, *tgt = nullptr, *hw = nullptr, *loss = nullptr;
@@ -138,11 +139,19 @@ void conv_fwd_splitk(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float*
       X, W, b, Y, D, make_grid3(Do));
 }
 
-void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o) {
+// counts: label counts of the batch's input windows when the caller has them
+// (the fraction features), else counted here into net->cnt
+void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
+             const int* counts = nullptr) {
   const int n = net->n;
   net->lw = LabelWindow{labels, (long long)box * box * box, box, o};
-  k_zero_int<<<(batch * kFrac + 255) / 256, 256, 0, ctx->stream>>>(net->cnt, batch * kFrac);
-  k_count_labels<<<dim3((n * n + kCountRows - 1) / kCountRows, batch), 256, 0, ctx->stream>>>(net->lw, n, 0, net->cnt);
+  if (counts) {
+    net->cnt_in = counts;
+  } else {
+    k_zero_int<<<(batch * kFrac + 255) / 256, 256, 0, ctx->stream>>>(net->cnt, batch * kFrac);
+    launch_count_labels(labels, (long long)box * box * box, box, o, n, 0, batch, net->cnt, ctx->stream);
+    net->cnt_in = net->cnt;
+  }
   conv_fwd<8, 32, true, 4>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
   conv_fwd<32, 32, false, 4>(ctx, net->a[0], net->lw, net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
   conv_fwd<32, 64, false, 2>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
@@ -153,7 +162,7 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
 void head(hh_ctx* ctx, hh_net* net, int batch, const float* target, float* dA, float* dW, float* loss, float inv) {
   const int V = edge(net, 3) / 2;
   const double nv = double(net->n) * net->n * net->n;
-  k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->cnt, 1.0 / nv, net->d_fmu, net->d_fsc,
+  k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->cnt_in, 1.0 / nv, net->d_fmu, net->d_fsc,
                                         net->p + net->fcw_off, net->p + net->fcb_off, net->out, target, dA, dW, loss,
                                         inv);
 }
@@ -226,12 +235,13 @@ void check_input(hh_ctx* ctx, hh_net* net, int batch, int box, int o) {
 }  // namespace
 
 void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
-                           double* c21) {
+                           double* c21, const int* counts) {
   const int step = 256;
   ensure_acts(ctx, net, std::min(step, batch));
   for (int b0 = 0; b0 < batch; b0 += step) {
     const int nb = std::min(step, batch - b0);
-    forward(ctx, net, labels + (long long)b0 * box * box * box, nb, box, o);
+    forward(ctx, net, labels + (long long)b0 * box * box * box, nb, box, o,
+            counts ? counts + (long long)b0 * kFrac : nullptr);
     head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f);
     k_denorm<<<(nb * kOut + 255) / 256, 256, 0, ctx->stream>>>(net->out, net->d_mean, net->d_scale, nb,
                                                                c21 + (long long)b0 * kOut);
@@ -239,15 +249,13 @@ void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels
   }
 }
 
-void hh_launch_bounds(const unsigned char* labels, int nitems, int box, int o, int n, int nphase, const double* Cp21,
-                      const double* Sp21, int* counts, double* cv21, double* cr21, hipStream_t st) {
+void hh_launch_counts(const unsigned char* labels, int nitems, int box, int o, int n, int* counts, hipStream_t st) {
   k_zero_int<<<(nitems * 8 + 255) / 256, 256, 0, st>>>(counts, nitems * 8);
-  const LabelWindow lw{labels, (long long)box * box * box, box, o};
-  const unsigned rb = unsigned((n * n + kCountRows - 1) / kCountRows);
-  for (int i0 = 0; i0 < nitems; i0 += 65535) {
-    const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
-    k_count_labels<<<dim3(rb, unsigned(ni)), 256, 0, st>>>(lw, n, i0, counts);
-  }
+  launch_count_labels(labels, (long long)box * box * box, box, o, n, 0, nitems, counts, st);
+}
+
+void hh_launch_bounds(const int* counts, int nitems, int n, int nphase, const double* Cp21, const double* Sp21,
+                      double* cv21, double* cr21, hipStream_t st) {
   k_bounds_from_counts<<<(nitems + 63) / 64, 64, 0, st>>>(counts, nitems, 1.0 / (double(n) * n * n), nphase, Cp21,
                                                           Sp21, cv21, cr21);
 }
@@ -490,7 +498,7 @@ int hh_net_predict(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_o
     if (!labels || !C21) fail(ctx, HH_EINVAL, "null argument");
     const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
     auto* c = static_cast<double*>(ws(ctx, "net_c21", sizeof(double) * batch * kOut));
-    hh_net_predict_device(ctx, net, d, batch, box, offset, c);
+    hh_net_predict_device(ctx, net, d, batch, box, offset, c, nullptr);
     HIPCHK(hipMemcpyAsync(C21, c, sizeof(double) * batch * kOut, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return HH_OK;

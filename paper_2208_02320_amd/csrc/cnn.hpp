@@ -7,14 +7,18 @@
 
 // Predicted stiffness (21 components, denormalized, FP64, device) of `batch`
 // items; item i is the n^3 box at offset (o, o, o) of the box^3 labels at
-// labels + i * box^3 (device).
+// labels + i * box^3 (device).  counts: label counts of those windows
+// ([batch][8], device), or null to count them here.
 void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
-                           double* c21);
-// Phase fractions of the n^3 core (offset o) of each box -> Voigt and Reuss
-// stiffness (21 components each, device).  Cp21/Sp21: per phase stiffness
-// and compliance (21 components, device).
-void hh_launch_bounds(const unsigned char* labels, int nitems, int box, int o, int n, int nphase, const double* Cp21,
-                      const double* Sp21, int* counts, double* cv21, double* cr21, hipStream_t st);
+                           double* c21, const int* counts);
+// counts[i][c] = voxels with label c (< 8) in the n^3 window at offset
+// (o, o, o) of box i (box^3 labels, device).
+void hh_launch_counts(const unsigned char* labels, int nitems, int box, int o, int n, int* counts, hipStream_t st);
+// Phase fractions counts / n^3 -> Voigt and Reuss stiffness (21 components
+// each, device).  Cp21/Sp21: per phase stiffness and compliance (21
+// components, device).
+void hh_launch_bounds(const int* counts, int nitems, int n, int nphase, const double* Cp21, const double* Sp21,
+                      double* cv21, double* cr21, hipStream_t st);
 void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,
                     double spread_tol, double bound_tol, int* flag, hipStream_t st);
 int hh_net_input_size(const hh_net* net);

@@ -24,6 +24,8 @@
 #include <string>
 #include <vector>
 
+#include "intdiv.hpp"
+
 #pragma once
 
 namespace hh {
@@ -61,14 +63,6 @@ __device__ __forceinline__ int label_at(const LabelWindow& w, long long b, int z
   return w.labels[b * w.stride + ((long long)(z + w.o) * w.box + (y + w.o)) * w.box + (x + w.o)];
 }
 
-// floor(a / d) for 0 <= a < 2^23 and d >= 1, given inv = 1.0f / d: the
-// float quotient is within one of the true one, and one integer step fixes it.
-__device__ __forceinline__ int fdiv(int a, int d, float inv) {
-  int q = int(float(a) * inv);
-  const int r = a - q * d;
-  q += (r >= d ? 1 : 0) - (r < 0 ? 1 : 0);
-  return q;
-}
 
 // Output voxel v (< Do^3) of one item -> (oz, oy, ox).
 struct Grid3 {
@@ -96,35 +90,77 @@ __device__ __forceinline__ bf16x8 onehot8(int lab) {
 }
 
 // Label counts of each window: cnt[b][c] += number of voxels with label c
-// (c < 8).  Grid (row blocks, batch); each wave takes whole x-rows (lanes
-// along x), counts in registers, then one atomic per block and label.
-constexpr int kCountRows = 64;
+// (c < 8).  Grid (row blocks, batch).  The block's window rows are cut into
+// W-byte chunks (cw per row; the launcher picks W so that every chunk is an
+// aligned word).  Per chunk, each label adds 1 to its 4-bit field of a word
+// (label 8 and above shift out of it); the fields then go to two words of
+// byte counters (even and odd labels).  The launcher bounds the bytes per
+// thread by count_rows_per_block, so no byte counter overflows.  Wave sums
+// in 16-bit fields, then one atomic per block and label.
+inline int count_rows_per_block(int n) {
+  const int r = 61440 / n;  // at most 240 + W bytes per thread
+  return r < 1 ? 1 : (r > n * n ? n * n : r);
+}
 
-__global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, int item0, int* __restrict__ cnt) {
-  const int b = item0 + blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * kCountRows, r1 = min(n * n, r0 + kCountRows);
+template <int W>
+__global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, float inv_n, int cw, float inv_cw,
+                                                      int rows, int item0, int* __restrict__ cnt) {
+  using CT = typename Chunk<W>::type;
+  const int b = item0 + blockIdx.y, lane = threadIdx.x & 63;
+  const int r0 = blockIdx.x * rows, nr = min(rows, n * n - r0);
   const unsigned char* base = window_base(w, b);
-  int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int r = r0 + wave; r < r1; r += 4) {
-    const int z = r / n, y = r - z * n;
-    const unsigned char* row = base + (z * w.box + y) * w.box;
-    for (int x = lane; x < n; x += 64) {
-      const int lab = row[x];
+  const int tasks = nr * cw;
+  unsigned ev = 0u, od = 0u;  // byte counters of labels 0 2 4 6 and 1 3 5 7
+  for (int t = threadIdx.x; t < tasks; t += 256) {
+    const int rl = fdiv(t, cw, inv_cw), k = t - rl * cw;
+    const int r = r0 + rl, z = fdiv(r, n, inv_n), y = r - z * n;
+    const CT v = *reinterpret_cast<const CT*>(base + (z * w.box + y) * w.box + k * W);
+    unsigned nib = 0u;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) c[k] += (lab == k) ? 1 : 0;
-    }
+    for (int j = 0; j < W; ++j) nib += unsigned(1ull << (4u * min(chunk_byte(v, j), 8u)));
+    ev += nib & 0x0F0F0F0Fu;
+    od += (nib >> 4) & 0x0F0F0F0Fu;
   }
+  // 16-bit fields: (0, 1), (2, 3), (4, 5), (6, 7)
+  unsigned pr[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) pr[i] = ((ev >> (8 * i)) & 0xFFu) | (((od >> (8 * i)) & 0xFFu) << 16);
   __shared__ int s[8];
   if (threadIdx.x < 8) s[threadIdx.x] = 0;
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    int v = c[k];
+  for (int i = 0; i < 4; ++i) {
+    unsigned v = pr[i];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0 && v) atomicAdd(&s[k], v);
+    if (lane == 0) {
+      if (v & 0xFFFFu) atomicAdd(&s[2 * i], int(v & 0xFFFFu));
+      if (v >> 16) atomicAdd(&s[2 * i + 1], int(v >> 16));
+    }
   }
   __syncthreads();
   if (threadIdx.x < 8 && s[threadIdx.x]) atomicAdd(&cnt[b * 8 + threadIdx.x], s[threadIdx.x]);
+}
+
+// cnt[item0 .. item0 + nitems) += label counts of the n^3 windows at (o, o, o)
+// of the box^3 label boxes; the caller zeroes cnt.
+inline void launch_count_labels(const unsigned char* labels, long long stride, int box, int o, int n, int item0,
+                                int nitems, int* cnt, hipStream_t st) {
+  const LabelWindow lw{labels, stride, box, o};
+  const unsigned char* first = labels + ((long long)o * box + o) * box + o;
+  const int W = chunk_width({stride, (long long)box, (long long)n}, first, first);
+  const int cw = n / W, rows = count_rows_per_block(n);
+  const unsigned gx = unsigned((n * n + rows - 1) / rows);
+  const float inv_n = 1.0f / float(n), inv_cw = 1.0f / float(cw);
+  for (int i0 = 0; i0 < nitems; i0 += 65535) {
+    const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
+    const dim3 g(gx, unsigned(ni));
+    if (W == 8)
+      k_count_labels<8><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
+    else if (W == 4)
+      k_count_labels<4><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
+    else
+      k_count_labels<1><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
+  }
 }
 
 __global__ void k_zero_int(int* __restrict__ p, int n) {

@@ -1018,12 +1018,21 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     auto* d_pack = static_cast<unsigned char*>(ws(ctx, "pack", size_t(box * nitems)));
     Profile prof{ctx, o.profile != 0, {}, 0, report};
     prof.run(HH_K_SETUP, [&] { launch_gather_pad(d_img, nx, ny, nz, n_sub, pad, d_pack, st); });
-    // predictions of the network(s) on the n_sub^3 cores
+    // label counts of the cores (bounds, core-input networks) and, for a
+    // network that reads the whole box, of the boxes; then the predictions
     auto* c21a = static_cast<double*>(ws(ctx, "sur_c21a", sizeof(double) * 21 * nitems));
     double* c21b = net_b ? static_cast<double*>(ws(ctx, "sur_c21b", sizeof(double) * 21 * nitems)) : nullptr;
+    auto* d_counts = static_cast<int*>(ws(ctx, "sur_counts", sizeof(int) * 8 * size_t(nitems)));
+    const bool box_in = in_a != n_sub || (net_b && in_b != n_sub);
+    int* d_counts_box = box_in ? static_cast<int*>(ws(ctx, "sur_counts_box", sizeof(int) * 8 * size_t(nitems))) : nullptr;
     prof.run(HH_K_OTHER, [&] {
-      hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a);
-      if (net_b) hh_net_predict_device(ctx, net_b, d_pack, nitems, b, in_b == n_sub ? pad : 0, c21b);
+      hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
+      if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
+      hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a,
+                            in_a == n_sub ? d_counts : d_counts_box);
+      if (net_b)
+        hh_net_predict_device(ctx, net_b, d_pack, nitems, b, in_b == n_sub ? pad : 0, c21b,
+                              in_b == n_sub ? d_counts : d_counts_box);
     });
     // Voigt and Reuss stiffness of each core's phase fractions
     std::vector<double> cp(21 * nphase), sp(21 * nphase);
@@ -1052,11 +1061,10 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     auto* cv21 = static_cast<double*>(ws(ctx, "sur_cv", sizeof(double) * 21 * nitems));
     auto* cr21 = static_cast<double*>(ws(ctx, "sur_cr", sizeof(double) * 21 * nitems));
     auto* d_flag = static_cast<int*>(ws(ctx, "sur_flag", sizeof(int) * nitems));
-    auto* d_counts = static_cast<int*>(ws(ctx, "sur_counts", sizeof(int) * 8 * size_t(nitems)));
     HIPCHK(hipMemcpyAsync(d_cp, cp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_sp, sp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
     prof.run(HH_K_OTHER, [&] {
-      hh_launch_bounds(d_pack, nitems, b, pad, n_sub, nphase, d_cp, d_sp, d_counts, cv21, cr21, st);
+      hh_launch_bounds(d_counts, nitems, n_sub, nphase, d_cp, d_sp, cv21, cr21, st);
       hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, d_flag, st);
     });
     HIPCHK(hipGetLastError());

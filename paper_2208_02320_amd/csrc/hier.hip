@@ -7,37 +7,52 @@
 #include <hip/hip_runtime.h>
 
 #include "hh_internal.hpp"
+#include "intdiv.hpp"
 #include "kernels.hpp"
 
 namespace hh {
 
-// Row-wise copy: grid (row blocks of kGatherRows rows, items); each wave
-// takes whole rows of the (n + 2p)^3 box, lanes along x.  The source row
-// (z, y) wraps once per row, x once per byte (p < nx, so one step suffices).
-constexpr int kGatherRows = 64;
+// Copy of the boxes: grid (row blocks of kGatherRows box rows, items).  The
+// block's rows are cut into W-byte chunks (cw per row); W is chosen by the
+// launcher so that every chunk maps to W aligned, contiguous source bytes
+// (no wrap inside a chunk).  The source row (z, y) wraps once per row and x
+// once per chunk (p < nx, so one step suffices).  Each thread issues kGatherU
+// chunk loads before their stores.
+constexpr int kGatherRows = 256, kGatherU = 4;
 
+template <int W>
 __global__ void __launch_bounds__(256) k_gather_pad(const unsigned char* __restrict__ img, int nx, int ny, int nz,
-                                                    int n, int p, int mx, int my, int item0,
-                                                    unsigned char* __restrict__ out) {
+                                                    int n, int p, int mx, int my, int item0, int cw, float inv_cw,
+                                                    float inv_b, unsigned char* __restrict__ out) {
+  using CT = typename Chunk<W>::type;
   const int b = n + 2 * p;
   const int item = item0 + blockIdx.y;
   const int bx = item % mx, by = (item / mx) % my, bz = item / (mx * my);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * kGatherRows, r1 = min(b * b, r0 + kGatherRows);
+  const int r0 = blockIdx.x * kGatherRows, nr = min(kGatherRows, b * b - r0);
+  const int tasks = nr * cw;
   const int x0 = bx * n - p;
   unsigned char* dst_item = out + (long long)item * b * b * b;
-  for (int r = r0 + wave; r < r1; r += 4) {
-    const int zz = r / b, yy = r - zz * b;
-    int z = bz * n - p + zz, y = by * n - p + yy;
-    z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
-    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-    const unsigned char* src = img + ((long long)z * ny + y) * nx;
-    unsigned char* dst = dst_item + (long long)r * b;
-    for (int xx = lane; xx < b; xx += 64) {
-      int x = x0 + xx;
-      x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
-      dst[xx] = src[x];
+  for (int t0 = threadIdx.x; t0 < tasks; t0 += 256 * kGatherU) {
+    CT v[kGatherU];
+    long long d[kGatherU];
+#pragma unroll
+    for (int u = 0; u < kGatherU; ++u) {
+      const int t = t0 + u * 256;
+      d[u] = -1;
+      if (t < tasks) {
+        const int rl = fdiv(t, cw, inv_cw), k = t - rl * cw;
+        const int r = r0 + rl, zz = fdiv(r, b, inv_b), yy = r - zz * b;
+        int z = bz * n - p + zz, y = by * n - p + yy, x = x0 + k * W;
+        z = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+        y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+        v[u] = *reinterpret_cast<const CT*>(img + ((long long)z * ny + y) * nx + x);
+        d[u] = (long long)r * b + k * W;
+      }
     }
+#pragma unroll
+    for (int u = 0; u < kGatherU; ++u)
+      if (d[u] >= 0) *reinterpret_cast<CT*>(dst_item + d[u]) = v[u];
   }
 }
 
@@ -91,10 +106,19 @@ void launch_gather_pad(const unsigned char* img, int nx, int ny, int nz, int n, 
   const int mx = nx / n, my = ny / n, mz = nz / n;
   const int nitems = mx * my * mz;
   const int b = n + 2 * p;
+  const int W = chunk_width({(long long)n, (long long)p, (long long)nx}, img, out);
+  const int cw = b / W;
+  const float inv_cw = 1.0f / float(cw), inv_b = 1.0f / float(b);
   const unsigned rb = unsigned((b * b + kGatherRows - 1) / kGatherRows);
   for (int i0 = 0; i0 < nitems; i0 += 65535) {
     const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
-    k_gather_pad<<<dim3(rb, unsigned(ni)), 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, i0, out);
+    const dim3 grid(rb, unsigned(ni));
+    if (W == 8)
+      k_gather_pad<8><<<grid, 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, i0, cw, inv_cw, inv_b, out);
+    else if (W == 4)
+      k_gather_pad<4><<<grid, 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, i0, cw, inv_cw, inv_b, out);
+    else
+      k_gather_pad<1><<<grid, 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, i0, cw, inv_cw, inv_b, out);
   }
 }
 

@@ -54,9 +54,10 @@ def net_with(ctx, nphase, n, params, fstats=FSTATS):
     return net
 
 
-@pytest.mark.parametrize("n,batch,nphase", [(16, 3, 3), (32, 2, 4), (16, 5, 8)])
-def test_forward_matches_oracle(ctx, n, batch, nphase):
-    pad = 2
+# pad 2: byte-wise label counts; pad 4 and 8: 4- and 8-byte chunks
+@pytest.mark.parametrize("n,batch,nphase,pad", [(16, 3, 3, 2), (32, 2, 4, 2), (16, 5, 8, 2), (16, 3, 4, 4),
+                                                (16, 2, 5, 8)])
+def test_forward_matches_oracle(ctx, n, batch, nphase, pad):
     lab = boxes(batch, n + 2 * pad, nphase, seed=n + batch)
     p = ref.init_params(nphase, seed=7).astype(np.float32)
     net = net_with(ctx, nphase, n, p)
@@ -67,6 +68,22 @@ def test_forward_matches_oracle(ctx, n, batch, nphase):
     err = np.abs(y - yr).max() / scale
     print("forward n=%d batch=%d err %.2e" % (n, batch, err))
     assert err < 2e-3
+    net.close()
+
+
+def test_forward_ignores_labels_outside_the_channels(ctx):
+    """Labels 8..255 have no one-hot channel and no phase fraction."""
+    n, batch, pad = 16, 2, 8
+    lab = boxes(batch, n + 2 * pad, 8, seed=21)
+    rng = np.random.default_rng(22)
+    high = rng.random(lab.shape) < 0.3
+    lab[high] = rng.integers(8, 256, size=int(high.sum()))
+    p = ref.init_params(8, seed=9).astype(np.float32)
+    net = net_with(ctx, 8, n, p)
+    y = net.forward(lab, offset=pad)
+    core = lab[:, pad:pad + n, pad:pad + n, pad:pad + n]
+    yr, _ = ref.forward(p.astype(np.float64), core, bf=True, fstats=FSTATS)
+    assert np.abs(y - yr).max() / max(1.0, np.abs(yr).max()) < 2e-3
     net.close()
 
 
@@ -148,12 +165,19 @@ def test_predict_applies_scaling(ctx):
     net.close()
 
 
-def test_gather_subimages_matches_padded_boxes(ctx):
-    lab = np.ascontiguousarray(synth.rocklike((16, 48, 32), [0.5, 0.3, 0.2], sigma=1.5, seed=9))
-    n, pad = 16, 3
-    pack = ctx.gather_subimages(lab, n, pad).cpu().numpy()
+# the copy moves 1-, 4- or 8-byte chunks, as the sizes and addresses allow
+@pytest.mark.parametrize("shape,n,pad,shift", [((16, 48, 32), 16, 3, 0), ((32, 48, 64), 16, 4, 0),
+                                               ((32, 48, 64), 16, 8, 0), ((16, 48, 32), 8, 0, 0),
+                                               ((32, 48, 64), 16, 8, 1)])
+def test_gather_subimages_matches_padded_boxes(ctx, shape, n, pad, shift):
+    import torch
+    lab = np.ascontiguousarray(synth.rocklike(shape, [0.5, 0.3, 0.2], sigma=1.5, seed=9))
     origins = hier.partition(lab, n)
-    assert pack.shape == (len(origins), n + 2 * pad, n + 2 * pad, n + 2 * pad)
+    b = n + 2 * pad
+    out = None
+    if shift:  # an output address that is not 4-byte aligned
+        out = torch.full((len(origins) * b ** 3 + shift,), 255, dtype=torch.uint8, device="cuda")[shift:]
+    pack = ctx.gather_subimages(lab, n, pad, out=out).cpu().numpy().reshape(len(origins), b, b, b)
     for i, o in enumerate(origins):
         assert np.array_equal(pack[i], hier.padded_box(lab, o, n, pad)), i
 
