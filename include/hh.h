@@ -33,7 +33,7 @@ extern "C" {
 
 #define HH_OK 0
 #define HH_EINVAL (-1)        /* bad sizes / arguments, label >= nphase, N % n != 0, ... */
-#define HH_EUNSUPPORTED (-2)  /* axis length without compiled FFT passes (not 5-smooth, too large) */
+#define HH_EUNSUPPORTED (-2)  /* axis length without compiled FFT passes (see hh_size_supported) */
 #define HH_ENOMEM (-3)        /* device allocation failed */
 #define HH_EDEVICE (-4)       /* HIP runtime error or not a gfx950 device */
 #define HH_ESINGULAR (-5)     /* averaged strain matrix E_R not invertible */
@@ -118,7 +118,13 @@ const char *hh_last_error(const hh_ctx *ctx);
 long long hh_workspace_bytes(const hh_ctx *ctx);
 /* Releases the context's workspace (it is re-allocated on demand). */
 void hh_release_workspace(hh_ctx *ctx);
-/* 1 if axis length n has compiled FFT passes at `precision`, else 0. */
+/* 1 if axis length n has compiled FFT passes at `precision`, else 0.  The
+ * list is fixed at build time.  FP32 (precision 0): 2 3 4 5 6 8 9 10 12 15 16
+ * 18 20 24 25 27 30 32 36 40 45 48 50 60 64 72 75 80 85 90 95 96 100 110 120
+ * 128 144 150 160 170 180 190 192 200 225 235 240 245 256 300 310 320 512
+ * (among them the boxes of the paper's subimage sizes of Sec. 5 with 5 or 10
+ * voxels of padding).  FP64 (precision 1): 2 3 4 5 6 8 9 10 12 15 16 18 20
+ * 24 25 27 30 32 36 40 45 48 60 64 80 85 95 96 110 128. */
 int hh_size_supported(int n, int precision);
 
 /*

@@ -85,16 +85,24 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-constexpr int first_radix(int r) {
-  return (r % 4 == 0 && r != 8) ? 4 : (r % 2 == 0) ? 2 : (r % 3 == 0) ? 3 : (r % 5 == 0) ? 5 : r;
+constexpr int smallest_factor(int r) {
+  for (int p = 2; p * p <= r; ++p)
+    if (r % p == 0) return p;
+  return r;
 }
+constexpr bool is_prime(int r) { return r > 1 && smallest_factor(r) == r; }
+constexpr int first_radix(int r) { return (r % 4 == 0 && r != 8) ? 4 : smallest_factor(r); }
 
-constexpr bool smooth5(int n) {
+// Lengths whose register DFT is built here: every prime factor at most kMaxPrime.
+constexpr int kMaxPrime = 47;
+constexpr bool dft_length_ok(int n) {
   if (n < 1) return false;
-  while (n % 2 == 0) n /= 2;
-  while (n % 3 == 0) n /= 3;
-  while (n % 5 == 0) n /= 5;
-  return n == 1;
+  while (n > 1) {
+    const int p = smallest_factor(n);
+    if (p > kMaxPrime) return false;
+    n /= p;
+  }
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -103,7 +111,7 @@ constexpr bool smooth5(int n) {
 // ---------------------------------------------------------------------------
 template <int R, int S, class T>
 __device__ __forceinline__ void dft(cx<T>* v) {
-  static_assert(smooth5(R), "register DFT length must be 5-smooth");
+  static_assert(dft_length_ok(R), "register DFT length has a prime factor above kMaxPrime");
   if constexpr (R == 1) {
   } else if constexpr (R == 2) {
     const cx<T> a = v[0], b = v[1];
@@ -138,6 +146,34 @@ __device__ __forceinline__ void dft(cx<T>* v) {
     v[4] = r1 - i1;
     v[2] = r2 + i2;
     v[3] = r2 - i2;
+  } else if constexpr (is_prime(R)) {
+    // odd prime R: pair j with R - j; with a_j = v_j + v_{R-j} and
+    // b_j = v_j - v_{R-j} (j = 1 .. H),
+    //   X_k     = v_0 + sum_j cos(2 pi jk/R) a_j + S i sum_j sin(2 pi jk/R) b_j
+    //   X_{R-k} = the same with the sine sum subtracted
+    constexpr int H = (R - 1) / 2;
+    cx<T> a[H], b[H];
+    cx<T> x0 = v[0];
+    static_for<1, H + 1>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      a[j - 1] = v[j] + v[R - j];
+      b[j - 1] = v[j] - v[R - j];
+      x0 = x0 + a[j - 1];
+    });
+    static_for<1, H + 1>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      cx<T> re = v[0], im = {T(0), T(0)};
+      static_for<1, H + 1>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        constexpr T c = T(cos2pi(j * k, R)), sn = T(sin2pi(j * k, R));
+        re = re + c * a[j - 1];
+        im = im + sn * b[j - 1];
+      });
+      const cx<T> t = mul_si<S>(im);
+      v[k] = re + t;
+      v[R - k] = re - t;
+    });
+    v[0] = x0;
   } else {
     // R = A * B:  j = j1 + A j2,  k = k2 + B k1
     constexpr int A = first_radix(R), B = R / A;

@@ -43,9 +43,17 @@ SizeOpsFn size_ops_f32_12(int n, int v);
 SizeOpsFn size_ops_f32_13(int n, int v);
 SizeOpsFn size_ops_f32_14(int n, int v);
 SizeOpsFn size_ops_f32_15(int n, int v);
+SizeOpsFn size_ops_f32_16(int n, int v);
+SizeOpsFn size_ops_f32_17(int n, int v);
+SizeOpsFn size_ops_f32_18(int n, int v);
+SizeOpsFn size_ops_f32_19(int n, int v);
+SizeOpsFn size_ops_f32_20(int n, int v);
+SizeOpsFn size_ops_f32_21(int n, int v);
+SizeOpsFn size_ops_f32_22(int n, int v);
 SizeOpsFn size_ops_f64_0(int n, int v);
 SizeOpsFn size_ops_f64_1(int n, int v);
 SizeOpsFn size_ops_f64_2(int n, int v);
+SizeOpsFn size_ops_f64_3(int n, int v);
 void launch_fin_x(int mode, const GroupArgs& g, hipStream_t st);
 void launch_fin_z(int mode, const GroupArgs& g, hipStream_t st);
 void launch_stiffness(int precision, const SysState* state, int nitems, double* out, void* cfield_out,

@@ -1,0 +1,13 @@
+// Instantiation of the pass kernels for one set of axis lengths (F32).
+#include "solver_kernels.hpp"
+
+namespace hh {
+
+SizeOpsFn size_ops_f32_22(int n, int v) {
+  switch (n) {
+    HH_CASE_F(512)
+  }
+  return nullptr;
+}
+
+}  // namespace hh

@@ -41,6 +41,18 @@ def test_binding_loads():
     assert lib.hh_size_supported(80, 1) == 1 and lib.hh_size_supported(80, 2) == 0
 
 
+def test_supported_sizes_are_the_documented_ones():
+    """hh_size_supported answers exactly the lists of the header."""
+    from paper_2208_02320_amd import hh
+    lib = hh.load_library()
+    text = open(os.path.join(ROOT, "include", "hh.h")).read()
+    doc = text[text.index("1 if axis length n has compiled FFT passes"):text.index("int hh_size_supported")]
+    f32 = [int(x) for x in re.search(r"FP32 \(precision 0\):([\d\s*]+)", doc).group(1).replace("*", " ").split()]
+    f64 = [int(x) for x in re.search(r"FP64 \(precision 1\):([\d\s*]+)", doc).group(1).replace("*", " ").split()]
+    assert [n for n in range(1, 1100) if lib.hh_size_supported(n, 0)] == f32
+    assert [n for n in range(1, 1100) if lib.hh_size_supported(n, 1)] == f64
+
+
 def test_moduli_host_entry_point():
     from paper_2208_02320_amd import hh
     C = bounds.iso_voigt_matrix(37.0, 44.0)

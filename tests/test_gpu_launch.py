@@ -36,7 +36,7 @@ def image_and_oracle(shape):
     return _cache[shape]
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (20, 24, 30), (48, 48, 48), (64, 64, 64)])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (20, 24, 30), (48, 48, 48), (64, 64, 64), (6, 85, 95)])
 @pytest.mark.parametrize("plan", [(0, 0, 0), (1, 1, 1), (2, 2, 2), (1, 2, 0), (2, 0, 1), (0, 0, 3), (3, 4, 4)])
 def test_every_tile_variant_matches_oracle(ctx, shape, plan):
     lab, ref = image_and_oracle(shape)

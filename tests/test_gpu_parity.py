@@ -84,6 +84,40 @@ def test_sizes_fp32(ctx, n):
     assert g.rel_error(r.C, ref.C_sym) < TOL32
 
 
+# Lengths with prime factors above 5 (padded boxes of the paper's subimage
+# sizes 75, 90, 150, 180, 225, 300 with 5 or 10 voxels of padding) and the
+# longest FP32 axis, each on every axis in turn of a thin image.
+LONG32 = [85, 95, 110, 170, 190, 225, 235, 245, 300, 310, 320, 512]
+
+
+def thin(n, axis, seed):
+    shape = [6, 4, 5]
+    shape[axis] = n
+    return synth.rocklike(tuple(shape), [0.6, 0.25, 0.15], sigma=1.0, seed=seed, low_to_high=[2, 1, 0])
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", LONG32)
+def test_long_and_prime_axes_fp32(ctx, n, axis):
+    lab = thin(n, axis, seed=n + axis)
+    ph = [synth.QUARTZ, synth.FELDSPAR, synth.PORE]
+    r = ctx.homogenize(lab, ph, tol=1e-6, tune=0)
+    ref = oracle(lab, ph)
+    err = g.rel_error(r.C, ref.C_sym)
+    print("n=%d axis %d err %.2e" % (n, axis, err))
+    assert err < TOL32
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [85, 95, 110])
+def test_prime_axes_fp64(ctx, n, axis):
+    lab = thin(n, axis, seed=2 * n + axis)
+    ph = [synth.QUARTZ, synth.FELDSPAR, synth.PORE]
+    r = ctx.homogenize(lab, ph, tol=1e-11, precision=1)
+    ref = oracle(lab, ph, tol=1e-12)
+    assert g.rel_error(r.C, ref.C_sym) < TOL64
+
+
 def test_laminate_backus_fp32(ctx):
     lab = synth.laminate(16, 4, axis=0)
     r = ctx.homogenize(lab, QP, tol=1e-7)
