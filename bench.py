@@ -141,6 +141,72 @@ def bench_hier(args):
     ctx.close()
 
 
+def _full36(c21):
+    C = np.zeros((6, 6))
+    k = 0
+    for i in range(6):
+        for j in range(i, 6):
+            C[i, j] = C[j, i] = c21[k]
+            k += 1
+    return C
+
+
+def bench_study(args):
+    """The error study of Sec. 5 on a synthetic stand-in: a 300^3 four-phase
+    image with a correlation length near the paper's rocks (smoothing sigma 8,
+    seed 5), homogenized directly (the reference) and by the two-level scheme
+    for subimage sizes 50, 60, 75, 100 with 0, 5 and 10 voxels of padding per
+    side; the arithmetic mean of the subimage stiffnesses beside each, and the
+    n^-1 extrapolation per padding.  Only sizes with at least three subimages
+    per axis: with two, the intermediate image has only the mean and Nyquist
+    frequencies, and its solve returns the arithmetic mean."""
+    import torch
+    from paper_2208_02320_amd import hh, synth
+    N, sigma, seed = args.study_size, 8.0, 5
+    phases = synth.FOUR_PHASE["phases"]
+    lab = synth.four_phase_device(N, sigma=sigma, seed=seed)
+    torch.cuda.synchronize()
+    ctx = hh.Context(0)
+    t0 = time.perf_counter()
+    ref = ctx.homogenize(lab, phases, tol=1e-6)
+    t_ref = time.perf_counter() - t0
+    Kr, Gr = hh.moduli(ref.C)
+    print("bench: study %d^3 reference K %.4f G %.4f in %.2f s (iters %s)" % (N, Kr, Gr, t_ref, ref.report["iters"]),
+          file=sys.stderr, flush=True)
+    ns = [n for n in (50, 60, 75, 100) if N % n == 0 and N // n >= 3]
+    runs = {}
+    for pad in (0, 5, 10):
+        for n in ns:
+            t = time.perf_counter()
+            C, Cs, rep = ctx.hierarchical(lab, phases, n, pad, tol=1e-6)
+            dt = time.perf_counter() - t
+            K, G = hh.moduli(C)
+            Ka, Ga = hh.moduli(_full36(Cs.reshape(-1, 21).mean(axis=0)))
+            runs[(n, pad)] = dict(C=C, K=K, G=G, K_am=Ka, G_am=Ga, seconds=dt)
+            print("bench: study n=%d pad %d: K %.4f (%+.3f %%) G %.4f (%+.3f %%); mean of subimages K %+.3f %% "
+                  "G %+.3f %%; %.2f s" % (n, pad, K, 100 * (K / Kr - 1), G, 100 * (G / Gr - 1),
+                                         100 * (Ka / Kr - 1), 100 * (Ga / Gr - 1), dt), file=sys.stderr, flush=True)
+    fits = {}
+    for pad in (0, 5, 10):
+        Cinf, _ = hh.richardson(ns, [runs[(n, pad)]["C"] for n in ns])
+        Ki, Gi = hh.moduli(Cinf)
+        fits[pad] = {"K_inf": Ki, "G_inf": Gi, "K_err_pct": 100 * (Ki / Kr - 1), "G_err_pct": 100 * (Gi / Gr - 1)}
+    total = time.perf_counter() - t0
+    line = {
+        "metric": "seconds for the two-level error study (reference solve + 12 hierarchies)",
+        "value": total, "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "error study, %d^3 four-phase (sigma %g, seed %d), n in %s, pad 0/5/10, tol 1e-6"
+                               % (N, sigma, seed, ns)},
+        "reference": {"K": Kr, "G": Gr, "seconds": t_ref, "iters": ref.report["iters"]},
+        "runs": [{"n": n, "pad": pad, "K_err_pct": 100 * (r["K"] / Kr - 1), "G_err_pct": 100 * (r["G"] / Gr - 1),
+                  "K_mean_err_pct": 100 * (r["K_am"] / Kr - 1), "G_mean_err_pct": 100 * (r["G_am"] / Gr - 1),
+                  "seconds": r["seconds"]} for (n, pad), r in sorted(runs.items(), key=lambda kv: (kv[0][1], kv[0][0]))],
+        "richardson": fits,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def bench_uneven(args):
     """2048 independent subimages of sizes 32/48/64/96 (seed 1234), 2-4 phases,
     contrast <= 50, six loads each, FP32, tol 1e-6, in one batched call."""
@@ -318,12 +384,14 @@ def bench_cnn(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "cnn"), default="solve256")
+    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "cnn", "study"),
+                    default="solve256")
     ap.add_argument("--sur-size", type=int, default=1024)
     ap.add_argument("--weights-dir", default=None)
     ap.add_argument("--spread-tol", type=float, default=0.02)
     ap.add_argument("--bound-tol", type=float, default=0.0)
     ap.add_argument("--hier-size", type=int, default=512)
+    ap.add_argument("--study-size", type=int, default=300)
     ap.add_argument("--uneven-count", type=int, default=2048)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -333,7 +401,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "hier":
@@ -344,6 +412,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "cnn":
         return bench_cnn(args)
+    if args.workload == "study":
+        return bench_study(args)
 
     import torch
     from paper_2208_02320_amd import hh, synth

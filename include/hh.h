@@ -120,7 +120,7 @@ long long hh_workspace_bytes(const hh_ctx *ctx);
 void hh_release_workspace(hh_ctx *ctx);
 /* 1 if axis length n has compiled FFT passes at `precision`, else 0.  The
  * list is fixed at build time.  FP32 (precision 0): 2 3 4 5 6 8 9 10 12 15 16
- * 18 20 24 25 27 30 32 36 40 45 48 50 60 64 72 75 80 85 90 95 96 100 110 120
+ * 18 20 24 25 27 30 32 36 40 45 48 50 60 64 70 72 75 80 85 90 95 96 100 110 120
  * 128 144 150 160 170 180 190 192 200 225 235 240 245 256 300 310 320 512
  * (among them the boxes of the paper's subimage sizes of Sec. 5 with 5 or 10
  * voxels of padding).  FP64 (precision 1): 2 3 4 5 6 8 9 10 12 15 16 18 20

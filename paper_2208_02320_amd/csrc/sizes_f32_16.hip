@@ -5,7 +5,7 @@ namespace hh {
 
 SizeOpsFn size_ops_f32_16(int n, int v) {
   switch (n) {
-    HH_CASE_F(85) HH_CASE_F(95) HH_CASE_F(110)
+    HH_CASE_F(70) HH_CASE_F(85) HH_CASE_F(95) HH_CASE_F(110)
   }
   return nullptr;
 }
