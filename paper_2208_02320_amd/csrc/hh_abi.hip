@@ -226,7 +226,7 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
   if (!vz.ok[0] || !vy.ok[0] || !vx.ok[0]) fail(ctx, HH_EUNSUPPORTED, "unsupported axis length");
   const PassVariants* pvs[3] = {&vz, &vy, &vx};
   const int hx = nx / 2 + 1;
-  const int hxp = (hx + 3) / 4 * 4;  // 64-byte aligned spectrum rows
+  const int hxp = spectrum_pitch(hx);
   const long long nfreq = (long long)hxp * ny * nz;
   const size_t cb = P == 0 ? 8 : 16;
   // geometry of a z variant (M columns per tile): 3-vector fields are stored

@@ -57,9 +57,13 @@ struct SysState {
 };
 
 // Everything a pass kernel needs about its group of systems.
+// Row pitch of the half spectrum: hx rounded up to a multiple of 8, so that
+// every row, and every tile of 8 columns, starts on a 128-byte line.
+__host__ __device__ constexpr int spectrum_pitch(int hx) { return (hx + 7) / 8 * 8; }
+
 struct GroupArgs {
   int nx, ny, nz, hx;      // grid and half-spectrum length along x
-  int hxp;                 // row pitch of the spectrum (hx rounded up to a multiple of 4)
+  int hxp;                 // row pitch of the spectrum (spectrum_pitch(hx))
   int nsys;                // systems in this launch
   int nyq_zero;            // 1: operator zero at frequencies with a Nyquist component
   int max_iter;

@@ -445,7 +445,7 @@ __global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g)
   using Cf = XCfg<N, T, V>;
   constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS;
   constexpr int R = Cf::R, L = 3 * R, P = Cf::P;
-  constexpr int HX = N / 2 + 1, HXP = (HX + 3) / 4 * 4;  // spectrum row length and pitch
+  constexpr int HX = N / 2 + 1, HXP = spectrum_pitch(HX);  // spectrum row length and pitch
   constexpr int NU = R * HX * 3;                          // (row, kx, pair) units per tile
   constexpr int KX = (NU + TH - 1) / TH;
   extern __shared__ __align__(16) unsigned char smem_raw[];
