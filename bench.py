@@ -207,6 +207,49 @@ def bench_study(args):
     ctx.close()
 
 
+def bench_contrast(args):
+    """Iterations and accuracy against phase contrast (Sec. 2 gives pores of
+    1e-5 GPa, chosen there for stability): a 64^3 two-phase quartz / pore
+    image (porosity 0.2, sigma 2, seed 0), pore moduli from the benchmark
+    2.25 / 1 GPa down to the paper's 1e-5 GPa; FP32 and FP64 fields at tol
+    1e-6 against FP64 at tol 1e-9."""
+    from paper_2208_02320_amd import hh, synth
+    lab = synth.two_phase(64, 0.2, 2.0, 0)
+    ctx = hh.Context(0)
+    rows = []
+    for Kp, Gp in ((2.25, 1.0), (0.1, 0.05), (1e-2, 5e-3), (1e-3, 5e-4), (1e-5, 1e-5)):
+        ph = [synth.QUARTZ, (Kp, Gp)]
+        row = {"pore_K": Kp, "pore_G": Gp, "contrast": max(synth.QUARTZ) / min(Kp, Gp)}
+        ref = ctx.homogenize(lab, ph, tol=1e-9, precision=1, max_iter=50000, stall_limit=2000, check=False)
+        row["fp64_tight"] = {"iters": max(ref.report["iters"]), "status": ref.report["status"],
+                             "K_G": hh.moduli(ref.C)}
+        for name, prec in (("fp32", 0), ("fp64", 1)):
+            t = time.perf_counter()
+            r = ctx.homogenize(lab, ph, tol=1e-6, precision=prec, max_iter=50000, stall_limit=2000, check=False)
+            dt = time.perf_counter() - t
+            err = float(np.linalg.norm(_mandel(r.C) - _mandel(ref.C)) / np.linalg.norm(_mandel(ref.C)))
+            row[name] = {"iters": max(r.report["iters"]), "status": r.report["status"], "seconds": dt,
+                         "rel_err_vs_tight": err}
+        print("bench: contrast %.1e: fp32 %d it (status %d) err %.1e; fp64 %d it err %.1e; tight %d it" % (
+            row["contrast"], row["fp32"]["iters"], row["fp32"]["status"], row["fp32"]["rel_err_vs_tight"],
+            row["fp64"]["iters"], row["fp64"]["rel_err_vs_tight"], row["fp64_tight"]["iters"]),
+            file=sys.stderr, flush=True)
+        rows.append(row)
+    line = {"metric": "CG iterations to tol 1e-6 at the paper's pore contrast (FP64 fields)",
+            "value": rows[-1]["fp64"]["iters"], "unit": "iterations", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "f32/f64", "data": "synthetic",
+            "config": {"workload": "64^3 two-phase quartz/pore (porosity 0.2, sigma 2, seed 0), pore moduli "
+                                   "2.25 GPa down to 1e-5 GPa, 6 loads"},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def _mandel(C):
+    d = np.array([1.0, 1.0, 1.0, np.sqrt(2.0), np.sqrt(2.0), np.sqrt(2.0)])
+    return np.asarray(C).reshape(6, 6) * d[:, None] * d[None, :]
+
+
 def bench_uneven(args):
     """2048 independent subimages of sizes 32/48/64/96 (seed 1234), 2-4 phases,
     contrast <= 50, six loads each, FP32, tol 1e-6, in one batched call."""
@@ -384,7 +427,7 @@ def bench_cnn(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "cnn", "study"),
+    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "cnn", "study", "contrast"),
                     default="solve256")
     ap.add_argument("--sur-size", type=int, default=1024)
     ap.add_argument("--weights-dir", default=None)
@@ -414,6 +457,8 @@ def main():
         return bench_cnn(args)
     if args.workload == "study":
         return bench_study(args)
+    if args.workload == "contrast":
+        return bench_contrast(args)
 
     import torch
     from paper_2208_02320_amd import hh, synth
