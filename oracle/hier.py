@@ -15,6 +15,8 @@ Steps in the paper's order (Sec. 3, Fig. 2; Sec. 4, Fig. 4; Sec. 5):
    not exactly symmetric and the second solve needs a self-adjoint operator).
 5. Homogenize the intermediate image with the same periodic solver and an
    anisotropic law per voxel (Sec. 4, closing paragraph) -> C*.
+   ``hierarchical_levels`` repeats steps 1-4 on the intermediate image
+   before step 5 (more than two levels).
 6. Bulk and shear moduli (reading: Voigt isotropic projection of C*) and the
    fit M(n) = M_inf + c n^-1 (Sec. 5, eq_fit_power_law) by unweighted least
    squares (reading: the fitting method is not stated).
@@ -87,6 +89,49 @@ def hierarchical(labels, phases, n, p=0, level2_kw=None, **kw):
     symm = 0.5 * (raw + np.swapaxes(raw, -1, -2))
     l2 = g.homogenize(g.AnisotropicMedium(symm), **(level2_kw or kw))
     return HierResult(C=l2.C_sym, C_sub=symm, C_sub_raw=raw, level2=l2, subs=subs)
+
+
+def padded_field_box(field, origin, n, p):
+    """Omega_B of an intermediate image (m_z, m_y, m_x, 6, 6), wrapped."""
+    z, y, x = origin
+    iz = np.arange(z - p, z + n + p) % field.shape[0]
+    iy = np.arange(y - p, y + n + p) % field.shape[1]
+    ix = np.arange(x - p, x + n + p) % field.shape[2]
+    return field[np.ix_(iz, iy, ix)]
+
+
+def hierarchical_levels(labels, phases, levels, **kw):
+    """Repeated coarse-graining (reading: Sec. 3's scheme applied again to its
+    own intermediate image, as in the renormalization it is modelled on).
+
+    ``levels`` = [(n_1, p_1), (n_2, p_2), ...]: the label image is cut into
+    n_1^3 subimages with p_1 voxels of surround (steps 1-4); each further
+    level cuts the current intermediate image into n_l^3 blocks of voxels
+    with p_l voxels of surround, homogenizes each with the anisotropic law
+    over its central n_l^3 region, and assembles the symmetric parts into the
+    next intermediate image.  The last image is homogenized whole (step 5).
+    Returns (C*, list of the intermediate images)."""
+    n1, p1 = levels[0]
+    subs = subimage_stiffness(labels, phases, n1, p1, **kw)
+    m = tuple(s // n1 for s in labels.shape)
+    raw = np.stack([s.C for s in subs]).reshape(m + (6, 6))
+    field = 0.5 * (raw + np.swapaxes(raw, -1, -2))
+    images = [field]
+    for n, p in levels[1:]:
+        if any(s % n for s in field.shape[:3]):
+            raise ValueError("the block size must divide the intermediate image")
+        out = []
+        for origin in partition(field[..., 0, 0], n):
+            box = padded_field_box(field, origin, n, p)
+            region = (p, p, p, p + n, p + n, p + n)
+            out.append(g.homogenize(g.AnisotropicMedium(box), region=region, **kw).C)
+        m = tuple(s // n for s in field.shape[:3])
+        raw = np.stack(out).reshape(m + (6, 6))
+        field = 0.5 * (raw + np.swapaxes(raw, -1, -2))
+        images.append(field)
+    if field.shape[:3] == (1, 1, 1):
+        return field[0, 0, 0].copy(), images
+    return g.homogenize(g.AnisotropicMedium(field), **kw).C_sym, images
 
 
 def arithmetic_mean_moduli(C_sub):
