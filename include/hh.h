@@ -187,6 +187,25 @@ int hh_hierarchical(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, 
                     const hh_opts *opts, double C_out[36], double *C_sub, hh_report *report);
 
 /*
+ * Repeated coarse-graining: the scheme of Sec. 3 applied again to its own
+ * intermediate image (the renormalization the paper's scheme is modelled
+ * on), nlevels times before the final solve.  Level 1 is hh_hierarchical's
+ * first step on the label image with blocks n_sub[0] and padding pad[0].
+ * Level l > 1 cuts the current intermediate image (21-component
+ * symmetrized stiffnesses) into n_sub[l-1]^3 blocks, solves each in the box
+ * extended by pad[l-1] voxels (periodic wrap) with anisotropic voxels,
+ * averages over the block, and assembles the symmetrized results into the
+ * next intermediate image.  The last image is solved whole (or, when it is a
+ * single voxel, is C*).  nlevels = 1 gives hh_hierarchical's C*.  Every
+ * n_sub[l] must divide its image, 2 pad[l] < that image's edges, and every
+ * box edge and the last image's edges must be compiled lengths.
+ * report.items counts level-1 subimages; report.voxel_iters sums all levels.
+ */
+int hh_hierarchical_levels(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, int labels_on_device,
+                           const hh_phase *phases, int nphase, const int *n_sub, const int *pad, int nlevels,
+                           const hh_opts *opts, double C_out[36], hh_report *report);
+
+/*
  * Partition + padding of the two-level scheme (Sec. 3; Sec. 4, Fig. 4) on
  * its own: copies every n_sub^3 block of the [nz][ny][nx] image, extended by
  * `pad` voxels of surrounding material (periodic wrap at the image edge),

@@ -959,6 +959,121 @@ int hh_hierarchical(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, 
   });
 }
 
+int hh_hierarchical_levels(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, int labels_on_device,
+                           const hh_phase* phases, int nphase, const int* n_sub, const int* pad, int nlevels,
+                           const hh_opts* opts, double C_out[36], hh_report* report) {
+  return guarded(ctx, [&]() -> int {
+    hh_opts o;
+    hh_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(ctx, o);
+    if (!labels || !C_out || !n_sub || !pad) fail(ctx, HH_EINVAL, "labels, n_sub, pad and C_out are required");
+    if (nlevels < 1 || nlevels > 8) fail(ctx, HH_EINVAL, "nlevels must be in 1..8");
+    if (nx < 1 || ny < 1 || nz < 1) fail(ctx, HH_EINVAL, "sizes must be positive");
+    // the chain of images: level l cuts (dx, dy, dz) into n_sub[l]^3 blocks
+    int d[3] = {nx, ny, nz};
+    for (int l = 0; l < nlevels; ++l) {
+      const int n = n_sub[l], p = pad[l];
+      if (n < 1) fail(ctx, HH_EINVAL, "block sizes must be positive");
+      if (d[0] % n || d[1] % n || d[2] % n)
+        fail(ctx, HH_EINVAL, "block size " + std::to_string(n) + " of level " + std::to_string(l + 1) +
+                                 " does not divide its image");
+      if (p < 0 || 2 * p >= std::min(d[0], std::min(d[1], d[2])))
+        fail(ctx, HH_EINVAL, "padding must satisfy 0 <= 2 pad < image size at every level");
+      check_shape(ctx, n + 2 * p, n + 2 * p, n + 2 * p, o.precision);
+      for (int& e : d) e /= n;
+    }
+    const bool single = d[0] == 1 && d[1] == 1 && d[2] == 1;
+    if (!single) check_shape(ctx, d[0], d[1], d[2], o.precision);
+    check_phases(ctx, phases, nphase);
+    const size_t tb = o.precision == 0 ? 4 : 8;
+    begin_report(ctx, report);
+    Profile prof{ctx, o.profile != 0, {}, 0, report};
+    double L[6][6];
+    unit_loads(L);
+    // level 1: the label image
+    const int n1 = n_sub[0], p1 = pad[0], b1 = n1 + 2 * p1;
+    int mx = nx / n1, my = ny / n1, mz = nz / n1;
+    const int items1 = mx * my * mz;
+    const long long nvox = (long long)nx * ny * nz;
+    const unsigned char* d_img =
+        device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "image");
+    const long long box1 = (long long)b1 * b1 * b1;
+    auto* d_pack = static_cast<unsigned char*>(ws(ctx, "pack", size_t(box1 * items1)));
+    prof.run(HH_K_SETUP, [&] { launch_gather_pad(d_img, nx, ny, nz, n1, p1, d_pack, ctx->stream); });
+    HIPCHK(hipGetLastError());
+    std::vector<Item> items(items1);
+    for (int i = 0; i < items1; ++i) {
+      Item& it = items[i];
+      it.nx = it.ny = it.nz = b1;
+      it.lab_off = box1 * i;
+      it.cf_off = -1;
+      const int r[6] = {p1, p1, p1, p1 + n1, p1 + n1, p1 + n1};
+      std::memcpy(it.region, r, sizeof(r));
+      it.phases.assign(phases, phases + nphase);
+    }
+    const char* names[2] = {"levels_cf0", "levels_cf1"};
+    void* cf = ws(ctx, names[0], size_t(items1) * 21 * tb);
+    GroupResult last = solve_group(ctx, items, d_pack, nullptr, false, o, L, prof, cf);
+    int rc = HH_OK;
+    for (int st : last.status) rc = worse(rc, st);
+    double vi = last.voxel_iters;
+    // further levels: blocks of the intermediate image with anisotropic voxels
+    for (int l = 1; l < nlevels; ++l) {
+      const int n = n_sub[l], p = pad[l], b = n + 2 * p;
+      const int nit = (mx / n) * (my / n) * (mz / n);
+      const long long box = (long long)b * b * b;
+      void* pack = ws(ctx, "levels_pack", size_t(nit) * size_t(box) * 21 * tb);
+      prof.run(HH_K_SETUP, [&] { launch_gather_field(o.precision, cf, mx, my, mz, n, p, pack, ctx->stream); });
+      HIPCHK(hipGetLastError());
+      std::vector<Item> lv(nit);
+      for (int i = 0; i < nit; ++i) {
+        Item& it = lv[i];
+        it.nx = it.ny = it.nz = b;
+        it.lab_off = 0;
+        it.cf_off = box * 21 * i;
+        const int r[6] = {p, p, p, p + n, p + n, p + n};
+        std::memcpy(it.region, r, sizeof(r));
+        it.phases.assign(1, hh_phase{1.0, 1.0});
+      }
+      void* next = ws(ctx, names[l % 2], size_t(nit) * 21 * tb);
+      last = solve_group(ctx, lv, nullptr, pack, true, o, L, prof, next);
+      for (int st : last.status) rc = worse(rc, st);
+      vi += last.voxel_iters;
+      cf = next;
+      mx /= n;
+      my /= n;
+      mz /= n;
+    }
+    if (single) {
+      end_report(ctx, report);
+      write_C(last, 0, C_out, nullptr);
+    } else {
+      Item fin;
+      fin.nx = mx;
+      fin.ny = my;
+      fin.nz = mz;
+      fin.lab_off = 0;
+      fin.cf_off = 0;
+      const int whole[6] = {0, 0, 0, mx, my, mz};
+      std::memcpy(fin.region, whole, sizeof(fin.region));
+      fin.phases.assign(1, hh_phase{1.0, 1.0});
+      last = solve_group(ctx, {fin}, nullptr, cf, true, o, L, prof, nullptr);
+      end_report(ctx, report);
+      write_C(last, 0, C_out, nullptr);
+      rc = worse(rc, last.status[0]);
+      vi += last.voxel_iters;
+    }
+    if (report) {
+      fill_item_report(report, last, 0);
+      report->voxel_iters = vi;
+      report->items = items1;
+      report->status = rc;
+    }
+    return rc;
+  });
+}
+
 int hh_gather_subimages(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, int labels_on_device, int n_sub,
                         int pad, uint8_t* pack_device) {
   return guarded(ctx, [&]() -> int {

@@ -56,6 +56,29 @@ __global__ void __launch_bounds__(256) k_gather_pad(const unsigned char* __restr
   }
 }
 
+// Boxes of an intermediate image of 21-component stiffnesses (the next
+// level of repeated coarse-graining): grid (box voxel blocks of 256, items);
+// one thread copies the 21 values of one box voxel from its wrapped source.
+template <class T>
+__global__ void __launch_bounds__(256) k_gather_field(const T* __restrict__ src, int mx, int my, int mz, int n,
+                                                      int p, int item0, T* __restrict__ out) {
+  const int b = n + 2 * p, nb3 = b * b * b;
+  const int item = item0 + blockIdx.y;
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= nb3) return;
+  const int bx = mx / n, by = my / n;  // blocks per axis
+  const int ix = item % bx, iy = (item / bx) % by, iz = item / (bx * by);
+  const int zz = v / (b * b), yy = (v / b) % b, xx = v % b;
+  int z = iz * n - p + zz, y = iy * n - p + yy, x = ix * n - p + xx;
+  z = z < 0 ? z + mz : (z >= mz ? z - mz : z);
+  y = y < 0 ? y + my : (y >= my ? y - my : y);
+  x = x < 0 ? x + mx : (x >= mx ? x - mx : x);
+  const T* s = src + (((long long)z * my + y) * mx + x) * 21;
+  T* d = out + ((long long)item * nb3 + v) * 21;
+#pragma unroll
+  for (int c = 0; c < 21; ++c) d[c] = s[c];
+}
+
 // Largest label of each item: blockIdx.y = item, blocks along x split it.
 __global__ void k_label_max(const unsigned char* __restrict__ labels, const long long* __restrict__ off,
                             const long long* __restrict__ count, int* __restrict__ out) {
@@ -119,6 +142,23 @@ void launch_gather_pad(const unsigned char* img, int nx, int ny, int nz, int n, 
       k_gather_pad<4><<<grid, 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, i0, cw, inv_cw, inv_b, out);
     else
       k_gather_pad<1><<<grid, 256, 0, st>>>(img, nx, ny, nz, n, p, mx, my, i0, cw, inv_cw, inv_b, out);
+  }
+}
+
+void launch_gather_field(int precision, const void* src, int mx, int my, int mz, int n, int p, void* out,
+                         hipStream_t st) {
+  const int nitems = (mx / n) * (my / n) * (mz / n);
+  const int b = n + 2 * p;
+  const unsigned gx = unsigned((b * b * b + 255) / 256);
+  for (int i0 = 0; i0 < nitems; i0 += 65535) {
+    const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
+    const dim3 grid(gx, unsigned(ni));
+    if (precision == 0)
+      k_gather_field<float><<<grid, 256, 0, st>>>(static_cast<const float*>(src), mx, my, mz, n, p, i0,
+                                                  static_cast<float*>(out));
+    else
+      k_gather_field<double><<<grid, 256, 0, st>>>(static_cast<const double*>(src), mx, my, mz, n, p, i0,
+                                                   static_cast<double*>(out));
   }
 }
 

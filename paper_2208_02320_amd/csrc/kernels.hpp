@@ -61,6 +61,10 @@ void launch_stiffness(int precision, const SysState* state, int nitems, double* 
 
 void launch_gather_pad(const unsigned char* img, int nx, int ny, int nz, int n, int p, unsigned char* out,
                        hipStream_t st);
+// Boxes (n + 2p)^3 of the (mz, my, mx) image of 21-component stiffnesses
+// (FP32 or FP64) around each n^3 block, wrapped: out[item][box voxel][21].
+void launch_gather_field(int precision, const void* src, int mx, int my, int mz, int n, int p, void* out,
+                         hipStream_t st);
 void launch_label_max(const unsigned char* labels, const long long* off, const long long* count, int nitems,
                       long long max_count, int* out, hipStream_t st);
 void launch_count_running(const SysState* st, int n, int* count, hipStream_t s);

@@ -28,7 +28,8 @@ NKERNEL = len(KERNEL_CLASSES)
 # Exported symbols (checked by the CPU test suite against include/hh.h).
 SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_last_error",
            "hh_workspace_bytes", "hh_release_workspace", "hh_size_supported", "hh_homogenize",
-           "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_gather_subimages",
+           "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_hierarchical_levels",
+           "hh_gather_subimages",
            "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_get_params",
            "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling",
            "hh_net_get_fraction_scaling", "hh_net_forward",
@@ -102,6 +103,8 @@ def load_library(path=LIB_PATH):
                                         DP, DP, ct.POINTER(I), ct.POINTER(I), ct.POINTER(Report)]
     lib.hh_hierarchical.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, I, I, I, ct.POINTER(Opts),
                                     DP, DP, ct.POINTER(Report)]
+    lib.hh_hierarchical_levels.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, ct.POINTER(I), ct.POINTER(I), I,
+                                           ct.POINTER(Opts), DP, ct.POINTER(Report)]
     lib.hh_gather_subimages.argtypes = [P, P, I, I, I, I, I, I, P]
     FP = ct.POINTER(ct.c_float)
     lib.hh_net_create.argtypes = [P, I, I, ct.c_ulonglong, ct.POINTER(P)]
@@ -341,6 +344,24 @@ class Context:
             self._check(rc)
         del keep
         return C.reshape(6, 6), Cs[:21 * m].reshape(m, 21), rep.as_dict()
+
+    def hierarchical_levels(self, labels, phases, levels, check=True, **opts):
+        """Repeated coarse-graining: levels = [(n_1, pad_1), (n_2, pad_2), ...];
+        returns (C*, report)."""
+        nz, ny, nx = tuple(labels.shape)
+        ptr, dev, keep = _buffer(labels, np.uint8)
+        o = default_opts(**opts)
+        ph = _phases(phases)
+        ns = (ct.c_int * len(levels))(*[int(n) for n, _ in levels])
+        ps = (ct.c_int * len(levels))(*[int(p) for _, p in levels])
+        C = np.zeros(36)
+        rep = Report()
+        rc = self._lib.hh_hierarchical_levels(self._h, ptr, nx, ny, nz, dev, ph, len(phases), ns, ps, len(levels),
+                                              ct.byref(o), _dptr(C), ct.byref(rep))
+        if check:
+            self._check(rc)
+        del keep
+        return C.reshape(6, 6), rep.as_dict()
 
     def gather_subimages(self, labels, n_sub, pad=0, out=None):
         """Padded subimage boxes of an image [z][y][x] as a device uint8 tensor

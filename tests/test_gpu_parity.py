@@ -201,6 +201,40 @@ def test_hierarchical_single_subimage(ctx):
         ctx.hierarchical(np.zeros((48, 24, 24), np.uint8), QP, 24, 0)
 
 
+def test_hierarchical_levels_fp64(ctx):
+    """Three levels: 4^3 subimages with 1 voxel of surround, then 2^3 blocks of
+    the 4^3 intermediate image with 1 voxel of surround, then the 2^3 image."""
+    lab = synth.four_phase(16, sigma=1.0, seed=6)
+    levels = [(4, 1), (2, 1)]
+    C, rep = ctx.hierarchical_levels(lab, FOUR, levels, tol=1e-11, precision=1)
+    ref, _ = hier.hierarchical_levels(lab, FOUR, levels, tol=1e-12, form="sym6")
+    assert g.rel_error(C, ref) < TOL64
+    assert rep["items"] == 64
+    C32, _ = ctx.hierarchical_levels(lab, FOUR, levels, tol=1e-6)
+    assert g.rel_error(C32, ref) < TOL32
+
+
+def test_hierarchical_levels_reduce_to_two_levels(ctx):
+    lab = synth.four_phase(16, sigma=1.0, seed=7)
+    C2, _, _ = ctx.hierarchical(lab, FOUR, 4, 1, tol=1e-6)
+    C1, _ = ctx.hierarchical_levels(lab, FOUR, [(4, 1)], tol=1e-6)
+    assert np.array_equal(C1, C2)
+    # a single block at level two is the two-level solve
+    Cb, _ = ctx.hierarchical_levels(lab, FOUR, [(4, 1), (4, 0)], tol=1e-6)
+    assert g.rel_error(Cb, C2) < 1e-12
+
+
+def test_hierarchical_levels_errors(ctx):
+    from paper_2208_02320_amd import hh
+    lab = np.zeros((16, 16, 16), np.uint8)
+    with pytest.raises(hh.HHError) as e:
+        ctx.hierarchical_levels(lab, FOUR, [(4, 1), (3, 0)])  # 3 does not divide 4
+    assert e.value.code == -1
+    with pytest.raises(hh.HHError) as e:
+        ctx.hierarchical_levels(lab, FOUR, [(4, 1), (2, 1)] * 5)  # more than 8 levels
+    assert e.value.code == -1
+
+
 def test_batch_mixed_sizes(ctx):
     recipe = synth.uneven_batch(6, sizes=(8, 12, 16), seed=77)
     imgs = [synth.item_image(it) for it in recipe]
