@@ -123,6 +123,16 @@ def bench_hier(args):
     ns = [32, 64, 128]
     Cinf, slope = hh.richardson(ns, [out[n]["C"] for n in ns])
     K, G = hh.moduli(Cinf)
+    # three levels: the 16^3 intermediate image of n = 32 cut again into 2^3
+    # blocks with 1 voxel of surround, then the 8^3 image
+    t = time.perf_counter()
+    C3, rep3 = ctx.hierarchical_levels(dev, phases, [(32, 8), (2, 1)], tol=1e-6)
+    torch.cuda.synchronize()
+    dt3 = time.perf_counter() - t
+    K3, G3 = hh.moduli(C3)
+    K2, G2 = hh.moduli(out[32]["C"])
+    print("bench: three levels (32 pad 8, 2 pad 1): K %.4f G %.4f (two levels: K %.4f G %.4f) in %.3f s" %
+          (K3, G3, K2, G2, dt3), file=sys.stderr, flush=True)
     r = out[64]
     line = {
         "metric": "subimages/s of the batched FFT solve in the two-level scheme",
@@ -136,6 +146,8 @@ def bench_hier(args):
                       "voxel_iters_per_s": out[n]["voxel_iters"] / out[n]["seconds"],
                       "K_G": hh.moduli(out[n]["C"])} for n in ns},
         "richardson": {"K_inf": K, "G_inf": G},
+        "three_levels": {"levels": [[32, 8], [2, 1]], "K_G": [K3, G3], "seconds": dt3,
+                         "two_level_K_G": [K2, G2]},
     }
     print(json.dumps(line), flush=True)
     ctx.close()
