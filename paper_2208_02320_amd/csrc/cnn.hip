@@ -128,8 +128,15 @@ template <int CI, int CO, bool LAB, int RB>
 void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16* W, const float* b, __bf16* Y, int D,
               int batch) {
   const int Do = D / 2, nvo = Do * Do * Do;
-  k_conv_fwd<CI, CO, LAB, RB><<<dim3(unsigned((nvo + 64 * RB - 1) / (64 * RB)), unsigned(batch)), 256, 0, ctx->stream>>>(
-      X, lw, W, b, Y, D, make_grid3(Do));
+  const dim3 grid(unsigned((nvo + 64 * RB - 1) / (64 * RB)), unsigned(batch));
+  if constexpr (CI == 32 && !LAB) {
+    // output rows that tile the 16 lanes of a row block: the x-shift path
+    if (Do <= 16 && 16 % Do == 0) {
+      k_conv_fwd<CI, CO, LAB, RB, true><<<grid, 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
+      return;
+    }
+  }
+  k_conv_fwd<CI, CO, LAB, RB><<<grid, 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
 }
 
 template <int CI, int CO>

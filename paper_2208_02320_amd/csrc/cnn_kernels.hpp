@@ -174,12 +174,30 @@ __global__ void k_zero_int(int* __restrict__ p, int n) {
 // B fragment (weights) it loads serves RB MFMAs.  X: [b][D^3][CIN] (or, with
 // LAB, the label window, CIN = 8), Y: [b][Do^3][COUT].
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, bool LAB, int RB>
+// v of lane l - 1 within each row of 16 lanes (DPP row shift right by one);
+// the first lane of a row gets zero
+__device__ __forceinline__ bf16x8 from_left_lane(bf16x8 v) {
+  typedef int i32x4 __attribute__((ext_vector_type(4)));
+  const i32x4 u = __builtin_bit_cast(i32x4, v);
+  i32x4 o;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) o[j] = __builtin_amdgcn_update_dpp(0, u[j], 0x111, 0xF, 0xF, false);
+  return __builtin_bit_cast(bf16x8, o);
+}
+
+// XS (x shift; CIN = 32, output rows of at most 16 voxels that tile the 16
+// lanes of a row block): the taps come in (tz, ty) groups of three.  A lane
+// loads its voxel's inputs at x = 2 ox (tx = 1) and 2 ox + 1 (tx = 2); the
+// input at x = 2 ox - 1 (tx = 0) is the tx = 2 input of the lane on its left,
+// taken across the row with a DPP shift (zero padding at ox = 0).  Two loads
+// per three taps instead of three.
+template <int CIN, int COUT, bool LAB, int RB, bool XS = false>
 __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
                                                   const __bf16* __restrict__ W, const float* __restrict__ bias,
                                                   __bf16* __restrict__ Y, int D, Grid3 go) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
   static_assert(!LAB || CIN == 8, "label input has 8 channels");
+  static_assert(!XS || (CIN == 32 && !LAB), "the x-shift path takes one tap per K step");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
   constexpr int VW = 16 * RB;  // output voxels of one wave
   // one-hot codes of labels 0..7 and a zero row (index 8) for padding and labels >= 8
@@ -242,6 +260,46 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   for (int r = 0; r < RB; ++r)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (XS) {
+    const int c0 = (lane >> 4) * 8;
+    bool xlo[RB];  // ox = 0: the tx = 0 input is padding
+#pragma unroll
+    for (int r = 0; r < RB; ++r) xlo[r] = (lowm[r] & 4u) != 0u;
+    // inputs at tx = 1, 2 of group g = 3 tz + ty, from a safe address where padded
+    auto load_pair = [&](int g, int r, bf16x8& a1, bf16x8& a2) {
+      const int tz = g / 3, ty = g % 3;
+      const unsigned m = (tz == 0 ? 1u : 0u) | (ty == 0 ? 2u : 0u) | 8u;
+      const bool ok = (lowm[r] & m) == 0u;
+      const int off = ok ? base[r] + (tz * rs + ty) * rs + 1 : 0;
+      const bf16x8 u1 = ld8(Xb + off * CIN + c0), u2 = ld8(Xb + (off + 1) * CIN + c0);
+      a1 = ok ? u1 : zero8();
+      a2 = ok ? u2 : zero8();
+    };
+#pragma unroll
+    for (int gz = 0; gz < 9; ++gz) {
+      bf16x8 c1[RB], c2[RB], a0[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) load_pair(gz, r, c1[r], c2[r]);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const bf16x8 sh = from_left_lane(c2[r]);
+        a0[r] = xlo[r] ? zero8() : sh;
+      }
+#pragma unroll
+      for (int tx = 0; tx < 3; ++tx) {
+        const int tap = gz * 3 + tx;
+        bf16x8 bw[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bw[t] = ld8(W + (tap * COUT + t * 16 + (lane & 15)) * CIN + c0);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const bf16x8 a = tx == 0 ? a0[r] : (tx == 1 ? c1[r] : c2[r]);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a, bw[t], acc[r][t]);
+        }
+      }
+    }
+  } else {
   // software pipeline: the loads of k-step ks + 1 are in flight during the MFMAs of ks
   Raw ra[RB];
   bool rok[RB];
@@ -273,6 +331,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a[r], bw[t], acc[r][t]);
+  }
   }
   if constexpr (STAGE) {
     // bias + ReLU into the wave's LDS tile (row = voxel, col = channel) ...

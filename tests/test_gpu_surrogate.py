@@ -54,9 +54,11 @@ def net_with(ctx, nphase, n, params, fstats=FSTATS):
     return net
 
 
-# pad 2: byte-wise label counts; pad 4 and 8: 4- and 8-byte chunks
+# pad 2: byte-wise label counts; pad 4 and 8: 4- and 8-byte chunks.  Inner
+# layers on outputs of 16, 8, 4, 2 voxels per row: the x-shift path of every
+# row width (n = 64 has the network's own sizes)
 @pytest.mark.parametrize("n,batch,nphase,pad", [(16, 3, 3, 2), (32, 2, 4, 2), (16, 5, 8, 2), (16, 3, 4, 4),
-                                                (16, 2, 5, 8)])
+                                                (16, 2, 5, 8), (64, 1, 4, 8)])
 def test_forward_matches_oracle(ctx, n, batch, nphase, pad):
     lab = boxes(batch, n + 2 * pad, nphase, seed=n + batch)
     p = ref.init_params(nphase, seed=7).astype(np.float32)
