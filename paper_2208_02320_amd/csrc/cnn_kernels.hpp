@@ -202,9 +202,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   constexpr int VW = 16 * RB;  // output voxels of one wave
   // one-hot codes of labels 0..7 and a zero row (index 8) for padding and labels >= 8
   __shared__ bf16x8 sOne[9];
-  // first layer (large output): each wave's output tile, [voxel][channel],
-  // goes out as whole 16-byte chunks; deeper layers store straight from the
-  // MFMA result layout
+  // first layer (large output): each wave's output tile goes out through LDS
+  // as whole 16-byte chunks; deeper layers store 8-byte words directly
   constexpr bool STAGE = LAB;
   __shared__ __align__(16) __bf16 sOut[STAGE ? 4 : 1][STAGE ? VW * COUT : 8];
   const int nvo = go.D2 * go.D;  // output voxels per item
@@ -295,7 +294,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
         for (int r = 0; r < RB; ++r) {
           const bf16x8 a = tx == 0 ? a0[r] : (tx == 1 ? c1[r] : c2[r]);
 #pragma unroll
-          for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a, bw[t], acc[r][t]);
+          for (int t = 0; t < NT; ++t) acc[r][t] = mfma(bw[t], a, acc[r][t]);
         }
       }
     }
@@ -330,24 +329,35 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(a[r], bw[t], acc[r][t]);
+      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(bw[t], a[r], acc[r][t]);
   }
   }
+  // D = W x X^T: lane l holds, for row block r and tile t, output channels
+  // t 16 + 4 (l / 16) + i (i = 0..3) of voxel v0 + 16 r + l % 16: bias, ReLU,
+  // and the four channels as one 8-byte word
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  const int q = lane >> 4;
+  auto out4 = [&](int r, int t, const float4& bb) {
+    bf16x4 o;
+    o[0] = (__bf16)fmaxf(acc[r][t][0] + bb.x, 0.0f);
+    o[1] = (__bf16)fmaxf(acc[r][t][1] + bb.y, 0.0f);
+    o[2] = (__bf16)fmaxf(acc[r][t][2] + bb.z, 0.0f);
+    o[3] = (__bf16)fmaxf(acc[r][t][3] + bb.w, 0.0f);
+    return o;
+  };
   if constexpr (STAGE) {
-    // bias + ReLU into the wave's LDS tile (row = voxel, col = channel) ...
+    // the wave's tile [voxel][channel] in LDS, then out as whole 16-byte
+    // chunks (the wave's voxels are consecutive)
     __bf16* so = sOut[wave];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + (lane & 15);
-      const float bb = bias[co];
+      const int co = t * 16 + 4 * q;
+      const float4 bb = *reinterpret_cast<const float4*>(bias + co);
 #pragma unroll
       for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          so[(r * 16 + (lane >> 4) * 4 + i) * COUT + co] = (__bf16)fmaxf(acc[r][t][i] + bb, 0.0f);
+        *reinterpret_cast<bf16x4*>(so + (r * 16 + (lane & 15)) * COUT + co) = out4(r, t, bb);
     }
     __syncthreads();
-    // ... then out as contiguous 16-byte chunks (the wave's voxels are consecutive)
     constexpr int CH = VW * COUT * 2 / 16;  // chunks per wave
     const int nv = min(VW, nvo - v0);       // valid voxels of this wave (may be <= 0)
     uint4* dst = reinterpret_cast<uint4*>(Y + ((long long)b * nvo + v0) * COUT);
@@ -359,15 +369,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
     __bf16* Yb = Y + (long long)b * nvo * COUT;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + (lane & 15);
-      const float bb = bias[co];
+      const int co = t * 16 + 4 * q;
+      const float4 bb = *reinterpret_cast<const float4*>(bias + co);
 #pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int v = v0 + r * 16 + (lane >> 4) * 4 + i;
-          if (v < nvo) Yb[v * COUT + co] = (__bf16)fmaxf(acc[r][t][i] + bb, 0.0f);
-        }
+      for (int r = 0; r < RB; ++r) {
+        const int v = v0 + r * 16 + (lane & 15);
+        if (v < nvo) *reinterpret_cast<bf16x4*>(Yb + (long long)v * COUT + co) = out4(r, t, bb);
+      }
     }
   }
 }
