@@ -131,6 +131,13 @@ void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16*
   const dim3 grid(unsigned((nvo + 64 * RB - 1) / (64 * RB)), unsigned(batch));
   if constexpr (CI == 32 && !LAB) {
     // output rows that tile the 16 lanes of a row block: the x-shift path
+    if constexpr (RB == 4) {
+      // rows of 16: a wave's row blocks are consecutive rows of one slice
+      if (Do == 16) {
+        k_conv_fwd<CI, CO, LAB, RB, true, true><<<grid, 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
+        return;
+      }
+    }
     if (Do <= 16 && 16 % Do == 0) {
       k_conv_fwd<CI, CO, LAB, RB, true><<<grid, 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
       return;

@@ -191,13 +191,18 @@ __device__ __forceinline__ bf16x8 from_left_lane(bf16x8 v) {
 // input at x = 2 ox - 1 (tx = 0) is the tx = 2 input of the lane on its left,
 // taken across the row with a DPP shift (zero padding at ox = 0).  Two loads
 // per three taps instead of three.
-template <int CIN, int COUT, bool LAB, int RB, bool XS = false>
+// YR (with XS; output rows of 16 voxels, RB = 4): a wave's four row blocks
+// are four consecutive output rows of one slice, so the ty = 0 inputs of row
+// block r are the ty = 2 inputs of row block r - 1, already in registers: 18
+// loads per tz instead of 24.
+template <int CIN, int COUT, bool LAB, int RB, bool XS = false, bool YR = false>
 __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
                                                   const __bf16* __restrict__ W, const float* __restrict__ bias,
                                                   __bf16* __restrict__ Y, int D, Grid3 go) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
   static_assert(!LAB || CIN == 8, "label input has 8 channels");
   static_assert(!XS || (CIN == 32 && !LAB), "the x-shift path takes one tap per K step");
+  static_assert(!YR || (XS && RB == 4), "row reuse: x-shift path, four row blocks");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
   constexpr int VW = 16 * RB;  // output voxels of one wave
   // one-hot codes of labels 0..7 and a zero row (index 8) for padding and labels >= 8
@@ -274,11 +279,9 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
       a1 = ok ? u1 : zero8();
       a2 = ok ? u2 : zero8();
     };
-#pragma unroll
-    for (int gz = 0; gz < 9; ++gz) {
-      bf16x8 c1[RB], c2[RB], a0[RB];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) load_pair(gz, r, c1[r], c2[r]);
+    // the three taps of group gz from the tx = 1, 2 inputs of every row block
+    auto group = [&](int gz, const bf16x8 (&c1)[RB], const bf16x8 (&c2)[RB]) {
+      bf16x8 a0[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const bf16x8 sh = from_left_lane(c2[r]);
@@ -296,6 +299,39 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
 #pragma unroll
           for (int t = 0; t < NT; ++t) acc[r][t] = mfma(bw[t], a, acc[r][t]);
         }
+      }
+    };
+    if constexpr (YR) {
+      // the row blocks are consecutive output rows of one slice: row block r's
+      // ty = 0 inputs (row 2 oy - 1) are row block r - 1's ty = 2 inputs
+#pragma unroll
+      for (int tz = 0; tz < 3; ++tz) {
+        bf16x8 p1[RB], p2[RB];
+        {
+          bf16x8 c1[RB], c2[RB];
+#pragma unroll
+          for (int r = 0; r < RB; ++r) load_pair(3 * tz + 1, r, c1[r], c2[r]);
+          group(3 * tz + 1, c1, c2);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) load_pair(3 * tz + 2, r, p1[r], p2[r]);
+        group(3 * tz + 2, p1, p2);
+        bf16x8 e1[RB], e2[RB];
+        load_pair(3 * tz, 0, e1[0], e2[0]);
+#pragma unroll
+        for (int r = 1; r < RB; ++r) {
+          e1[r] = p1[r - 1];
+          e2[r] = p2[r - 1];
+        }
+        group(3 * tz, e1, e2);
+      }
+    } else {
+#pragma unroll
+      for (int gz = 0; gz < 9; ++gz) {
+        bf16x8 c1[RB], c2[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) load_pair(gz, r, c1[r], c2[r]);
+        group(gz, c1, c2);
       }
     }
   } else {
