@@ -90,6 +90,11 @@ struct XCfg {
   static constexpr int P = lds_pad(N1, N2, L, CB);
   static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), variant_min_threads(V), 512);
   static constexpr int LDS = (N * L + N2 * P + N) * CB;
+  // waves per SIMD that the LDS budget admits (160 KB per CU); in FP32 with
+  // register DFTs of at most 16 points the compiler is asked to fit them (at
+  // most 4, 128 registers), so that registers do not cut that occupancy
+  static constexpr int OCC = clampi((163840 / LDS * (THREADS / 64) + 3) / 4, 1, 8);
+  static constexpr int WAVES_HINT = (CB == 8 && N1 <= 16 && N2 <= 16) ? (OCC < 4 ? OCC : 4) : 1;
 };
 
 // ---------------------------------------------------------------------------
@@ -441,7 +446,8 @@ __global__ void __launch_bounds__((AxisCfg<N, T, V>::THREADS)) k_ypass(GroupArgs
 // x pass: C2R, constitutive law, reductions, R2C
 // ---------------------------------------------------------------------------
 template <int N, class T, int MODE, int V>
-__global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g) {
+__global__ void __launch_bounds__((XCfg<N, T, V>::THREADS))
+__attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArgs g) {
   using Cf = XCfg<N, T, V>;
   constexpr int N1 = Cf::N1, N2 = Cf::N2, TH = Cf::THREADS;
   constexpr int R = Cf::R, L = 3 * R, P = Cf::P;
@@ -465,14 +471,29 @@ __global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g)
   cx<T>* tmp = cptr<T>(g.tmp, s * g.tmp_stride) + (long long)r0 * HXP * 6;
   cpair<T>* tmpp = reinterpret_cast<cpair<T>*>(tmp);  // 3 pairs per frequency
 
+  // Units (row, kx, pair) of the spectrum tile.  LM (line mapping; the
+  // workgroup has N1 threads per LDS line): thread j of line l = 3 row + pair
+  // takes kx = j + N1 k, so the LDS positions of kx and N - kx step by a
+  // compile-time stride and no index is divided; the 3 N1 threads of a row
+  // still read 3 N1 consecutive pairs.  Otherwise unit f = thread + k TH.
+  constexpr bool LM = TH == N1 * L && N % 2 == 0;
+  constexpr int KXL = (HX + N1 - 1) / N1;  // kx per thread with LM
+  constexpr int KU = LM ? KXL : KX;
+  const int lj = threadIdx.x % N1, lln = threadIdx.x / N1;  // LM: kx offset, line
+  const int lrl = lln / 3, lpr = lln - 3 * (lln / 3);       // LM: row, pair
   // issue this tile's global loads first: nothing they need waits on memory
-  cpair<T> v[KX];
+  cpair<T> v[KU];
   if constexpr (MODE != kXRhs) {
 #pragma unroll
-    for (int k = 0; k < KX; ++k) {
-      const int f = threadIdx.x + k * TH;
-      const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
-      if ((NU % TH == 0 || f < NU) && rl < nr) v[k] = tmpp[(rl * HXP + kx) * 3 + pr];
+    for (int k = 0; k < KU; ++k) {
+      if constexpr (LM) {
+        const int kx = lj + N1 * k;
+        if ((KXL * N1 == HX || kx < HX) && lrl < nr) v[k] = tmpp[(lrl * HXP + kx) * 3 + lpr];
+      } else {
+        const int f = threadIdx.x + k * TH;
+        const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
+        if ((NU % TH == 0 || f < NU) && rl < nr) v[k] = tmpp[(rl * HXP + kx) * 3 + pr];
+      }
     }
   }
   fill_twiddles<N, T>(tw);
@@ -497,13 +518,25 @@ __global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g)
   if constexpr (MODE != kXRhs) {
     // unpack: complex line (pair) = A + i B with A, B the spectra of two real lines
 #pragma unroll
-    for (int k = 0; k < KX; ++k) {
-      const int f = threadIdx.x + k * TH;
-      const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
-      if (NU % TH == 0 || f < NU) {
+    for (int k = 0; k < KU; ++k) {
+      int kx, rl, l;
+      bool in;
+      if constexpr (LM) {
+        kx = lj + N1 * k;
+        rl = lrl;
+        l = lln;
+        in = KXL * N1 == HX || kx < HX;
+      } else {
+        const int f = threadIdx.x + k * TH;
+        const int pr = f % 3, q = f / 3;
+        kx = q % HX;
+        rl = q / HX;
+        l = rl * 3 + pr;
+        in = NU % TH == 0 || f < NU;
+      }
+      if (in) {
         cx<T> A = v[k].a, B = v[k].b;
         if (rl >= nr) A = B = cx<T>{T(0), T(0)};
-        const int l = rl * 3 + pr;
         if (kx == 0 || 2 * kx == N) {
           buf[lds_at<N1, P>(kx, L) + l] = cx<T>{A.re, B.re};
         } else {
@@ -624,9 +657,7 @@ __global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g)
       sig_sum += double((threadIdx.x & 1) ? z0v.im : z0v.re);
     }
   }
-  for (int f = threadIdx.x; f < NU; f += TH) {
-    const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
-    if (rl >= nr) continue;
+  auto pack = [&](int kx, int rl, int pr) {
     const int l = rl * 3 + pr;
     const cx<T> zk = buf[lds_at<N1, P>(kx, L) + l];
     const cx<T> zm = buf[lds_at<N1, P>((N - kx) % N, L) + l];
@@ -634,6 +665,18 @@ __global__ void __launch_bounds__((XCfg<N, T, V>::THREADS)) k_xpass(GroupArgs g)
     o.a = cx<T>{T(0.5) * (zk.re + zm.re), T(0.5) * (zk.im - zm.im)};
     o.b = cx<T>{T(0.5) * (zk.im + zm.im), T(0.5) * (zm.re - zk.re)};
     tmpp[(rl * HXP + kx) * 3 + pr] = o;
+  };
+  if constexpr (LM) {
+#pragma unroll
+    for (int k = 0; k < KXL; ++k) {
+      const int kx = lj + N1 * k;
+      if ((KXL * N1 == HX || kx < HX) && lrl < nr) pack(kx, lrl, lpr);
+    }
+  } else {
+    for (int f = threadIdx.x; f < NU; f += TH) {
+      const int pr = f % 3, q = f / 3, kx = q % HX, rl = q / HX;
+      if (rl < nr) pack(kx, rl, pr);
+    }
   }
   __syncthreads();
   if (whole) {
