@@ -472,11 +472,11 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
   cpair<T>* tmpp = reinterpret_cast<cpair<T>*>(tmp);  // 3 pairs per frequency
 
   // Units (row, kx, pair) of the spectrum tile.  LM (line mapping; the
-  // workgroup has N1 threads per LDS line): thread j of line l = 3 row + pair
+  // workgroup has at least N1 threads per LDS line): thread j of line l = 3 row + pair
   // takes kx = j + N1 k, so the LDS positions of kx and N - kx step by a
   // compile-time stride and no index is divided; the 3 N1 threads of a row
   // still read 3 N1 consecutive pairs.  Otherwise unit f = thread + k TH.
-  constexpr bool LM = TH == N1 * L && N % 2 == 0;
+  constexpr bool LM = TH >= N1 * L && N % 2 == 0;  // threads past N1 L idle in the unit loops
   constexpr int KXL = (HX + N1 - 1) / N1;  // kx per thread with LM
   constexpr int KU = LM ? KXL : KX;
   const int lj = threadIdx.x % N1, lln = threadIdx.x / N1;  // LM: kx offset, line
@@ -525,7 +525,7 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
         kx = lj + N1 * k;
         rl = lrl;
         l = lln;
-        in = KXL * N1 == HX || kx < HX;
+        in = (KXL * N1 == HX || kx < HX) && (TH == N1 * L || lln < L);
       } else {
         const int f = threadIdx.x + k * TH;
         const int pr = f % 3, q = f / 3;
