@@ -85,10 +85,12 @@ T* dalloc(hh_ctx* ctx, size_t count) {
 
 // Voxels per weight-gradient chunk: at most kMaxChunks chunks for any total
 // (chunk >= total / kMaxChunks), each a multiple of the 32-voxel MFMA step.
-constexpr int kMaxChunks = 128;
+// The first layer's kernel takes all taps per block and so runs more,
+// smaller chunks (its partials are 16 times smaller than the last layer's).
+constexpr int kMaxChunks = 128, kMaxChunksLab = 1024;
 
-int wgrad_chunk(long long total) {
-  long long c = (total + kMaxChunks - 1) / kMaxChunks;
+int wgrad_chunk(long long total, int max_chunks) {
+  long long c = (total + max_chunks - 1) / max_chunks;
   c = (c + 31) / 32 * 32;
   return int(std::max<long long>(c, 32));
 }
@@ -104,8 +106,9 @@ void ensure_acts(hh_ctx* ctx, hh_net* net, int batch) {
     net->a[l] = dalloc<__bf16>(ctx, size_t(batch) * nv * kCout[l]);
     net->ga[l] = dalloc<float>(ctx, size_t(batch) * nv * kCout[l]);
     // any batch up to the capacity needs at most kMaxChunks partials
-    pmax = std::max<size_t>(pmax, size_t(kMaxChunks) * 27 * kCout[l] * kCin[l]);
-    bmax = std::max<size_t>(bmax, size_t(kMaxChunks) * kCout[l]);
+    const size_t nc = l == 0 ? kMaxChunksLab : kMaxChunks;
+    pmax = std::max<size_t>(pmax, nc * 27 * kCout[l] * kCin[l]);
+    bmax = std::max<size_t>(bmax, nc * kCout[l]);
   }
   net->out = dalloc<float>(ctx, size_t(batch) * kOut);
   net->tgt = dalloc<float>(ctx, size_t(batch) * kOut);
@@ -185,15 +188,20 @@ template <int CI, int CO, bool LAB>
 void conv_bwd(hh_ctx* ctx, hh_net* net, int l, const __bf16* X, int batch, float* dX) {
   const int D = edge(net, l), Do = D / 2;
   const long long total = (long long)Do * Do * Do * batch;
-  const int chunk = wgrad_chunk(total);
+  const int chunk = wgrad_chunk(total, LAB ? kMaxChunksLab : kMaxChunks);
   const int nch = int((total + chunk - 1) / chunk);
-  if (nch > kMaxChunks) fail(ctx, HH_EINVAL, "internal: weight-gradient chunk count");
-  k_conv_wgrad<CI, CO, LAB><<<dim3(nch, 27), 256, 0, ctx->stream>>>(net->ga[l], net->a[l], X, net->lw, net->part,
-                                                                    net->pbias, D, make_grid3(D / 2), batch, chunk);
+  if (nch > (LAB ? kMaxChunksLab : kMaxChunks)) fail(ctx, HH_EINVAL, "internal: weight-gradient chunk count");
+  if constexpr (LAB)
+    k_conv_wgrad_lab<CO><<<nch, 256, 0, ctx->stream>>>(net->ga[l], net->a[l], net->lw, net->part, net->pbias,
+                                                       make_grid3(D / 2), batch, chunk);
+  else
+    k_conv_wgrad<CI, CO><<<dim3(nch, 27), 256, 0, ctx->stream>>>(net->ga[l], net->a[l], X, net->part, net->pbias, D,
+                                                                 make_grid3(D / 2), batch, chunk);
   const long long nw = 27LL * CO * CI;
-  k_reduce_parts<<<unsigned(std::min<long long>((nw + 255) / 256, 4096)), 256, 0, ctx->stream>>>(
-      net->part, nch, nw, net->g + net->woff[l]);
-  k_reduce_parts<<<1, 256, 0, ctx->stream>>>(net->pbias, nch, CO, net->g + net->boff[l]);
+  k_reduce_parts_wide<<<unsigned((nw + 63) / 64), 1024, 0, ctx->stream>>>(net->part, nch, nw,
+                                                                          net->g + net->woff[l]);
+  k_reduce_parts_wide<<<unsigned((CO + 63) / 64), 1024, 0, ctx->stream>>>(net->pbias, nch, CO,
+                                                                          net->g + net->boff[l]);
   if constexpr (CI >= 16) {
     if (dX) {
       const int h = D / 2, ncls = h * h * h;  // voxels of one parity class per item

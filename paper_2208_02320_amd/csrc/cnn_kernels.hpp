@@ -200,7 +200,6 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
                                                   const __bf16* __restrict__ W, const float* __restrict__ bias,
                                                   __bf16* __restrict__ Y, int D, Grid3 go) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
-  static_assert(!LAB || CIN == 8, "label input has 8 channels");
   static_assert(!XS || (CIN == 32 && !LAB), "the x-shift path takes one tap per K step");
   static_assert(!YR || (XS && RB == 4), "row reuse: x-shift path, four row blocks");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
@@ -545,19 +544,18 @@ __global__ void __launch_bounds__(256) k_conv_dgrad(const float* __restrict__ dY
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient, one tap per block: partial dW[tap][cout][cin] over a chunk
-// of output voxels, dZ = dY * (Y > 0).  The chunk of dZ and of the gathered
-// input is staged in LDS transposed (channel-major) so that MFMA fragments
-// (K = voxels) are 16-byte LDS reads.  The bias gradient rides on tap 13.
+// weight gradient of a layer with bf16 input activations, one tap per block:
+// partial dW[tap][cout][cin] over a chunk of output voxels, dZ = dY * (Y > 0).
+// The chunk of dZ and of the gathered input is staged in LDS transposed
+// (channel-major) so that MFMA fragments (K = voxels) are 16-byte LDS reads.
+// The bias gradient rides on tap 13.
 // Partials: part[chunk][tap][COUT][CIN], bias partials pb[chunk][COUT].
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, bool LAB>
+template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY, const __bf16* __restrict__ Y,
-                                                    const __bf16* __restrict__ X, LabelWindow lw,
-                                                    float* __restrict__ part, float* __restrict__ pb, int D, Grid3 go,
-                                                    int batch, int chunk) {
+                                                    const __bf16* __restrict__ X, float* __restrict__ part,
+                                                    float* __restrict__ pb, int D, Grid3 go, int batch, int chunk) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0 && 256 % COUT == 0, "channel counts");
-  static_assert(!LAB || CIN == 8, "label input has 8 channels");
   constexpr int MT = COUT / 16, NTN = (CIN + 15) / 16;  // output tiles (cout x cin)
   constexpr int VS = 32;                                 // voxels per staged step (= MFMA K)
   __shared__ __bf16 sZ[COUT][VS + 8];
@@ -615,12 +613,8 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY
       const int bi = sPos[vl][0];
       if (bi >= 0 && ci < CIN) {
         const int iz = sPos[vl][1] + tz, iy = sPos[vl][2] + ty, ix = sPos[vl][3] + tx;
-        if (iz >= 0 && iy >= 0 && ix >= 0) {  // 2 o + t - 1 < D always
-          if constexpr (LAB)
-            xv = window_base(lw, bi)[(iz * lw.box + iy) * lw.box + ix] == ci ? 1.0f : 0.0f;
-          else
-            xv = (float)X[((long long)bi * D * D * D + (iz * D + iy) * D + ix) * CIN + ci];
-        }
+        if (iz >= 0 && iy >= 0 && ix >= 0)  // 2 o + t - 1 < D always
+          xv = (float)X[((long long)bi * D * D * D + (iz * D + iy) * D + ix) * CIN + ci];
       }
       sX[ci][vl] = (__bf16)xv;
     }
@@ -668,6 +662,153 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const float* __restrict__ dY
       for (int r = threadIdx.x; r < 256; r += COUT) t += sB[r];
       pb[(long long)blockIdx.x * COUT + threadIdx.x] = t;
     }
+  }
+}
+
+// Weight gradient of the first layer (8 one-hot input channels): each block
+// takes one chunk of voxels for all 27 taps.  Per 32-voxel step, dZ^T is
+// staged once, and so are the 27 tap labels of every staged voxel (8 where
+// the tap falls in the padding); the one-hot B fragments are formed in
+// registers from those labels.  Wave w owns taps w, w + 4, ...  Output and
+// bias partials are laid out as k_conv_wgrad's.
+template <int COUT>
+__global__ void __launch_bounds__(256) k_conv_wgrad_lab(const float* __restrict__ dY, const __bf16* __restrict__ Y,
+                                                        LabelWindow lw, float* __restrict__ part,
+                                                        float* __restrict__ pb, Grid3 go, int batch, int chunk) {
+  static_assert(COUT % 16 == 0 && 256 % COUT == 0, "channel counts");
+  constexpr int CIN = 8, MT = COUT / 16, VS = 32, TPW = 7;  // taps per wave: ceil(27 / 4)
+  __shared__ __bf16 sZ[COUT][VS + 8];
+  __shared__ unsigned char sL[VS][28];
+  __shared__ int sPos[VS][4];  // item, iz0, iy0, ix0 (input corner 2 o - 1) of each staged voxel; item -1 if none
+  __shared__ float sB[256];
+  const int nvo = go.D2 * go.D;
+  const float inv_nvo = 1.0f / float(nvo);
+  const long long total = (long long)nvo * batch;
+  const long long vbeg = (long long)blockIdx.x * chunk;
+  const long long vend = vbeg + chunk < total ? vbeg + chunk : total;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  f32x4 acc[TPW][MT];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q)
+#pragma unroll
+    for (int m = 0; m < MT; ++m) acc[q][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.0f;  // bias partial for cout = threadIdx.x % COUT
+  int b0 = int(vbeg / nvo), r0 = int(vbeg - (long long)b0 * nvo);
+  for (long long vs = vbeg; vs < vend; vs += VS) {
+    __syncthreads();
+    if (threadIdx.x < VS) {
+      const int vl = threadIdx.x;
+      int bi = -1, z = 0, y = 0, x = 0;
+      if (vs + vl < vend) {
+        const int q = fdiv(r0 + vl, nvo, inv_nvo);
+        bi = b0 + q;
+        split3(go, r0 + vl - q * nvo, z, y, x);
+      }
+      sPos[vl][0] = bi;
+      sPos[vl][1] = 2 * z - 1;
+      sPos[vl][2] = 2 * y - 1;
+      sPos[vl][3] = 2 * x - 1;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < COUT * VS; e += 256) {
+      const int co = e % COUT, vl = e / COUT;
+      float zv = 0.0f;
+      if (vs + vl < vend) {
+        const long long v = vs + vl;
+        const float gv = dY[v * COUT + co];
+        zv = (float)Y[v * COUT + co] > 0.0f ? gv : 0.0f;
+      }
+      sZ[co][vl] = (__bf16)zv;
+      bsum += zv;  // co == threadIdx.x % COUT since 256 % COUT == 0
+    }
+    for (int e = threadIdx.x; e < VS * 27; e += 256) {
+      const int vl = e / 27, t = e - vl * 27;
+      unsigned lab = 8u;
+      const int bi = sPos[vl][0];
+      if (bi >= 0) {
+        const int iz = sPos[vl][1] + t / 9, iy = sPos[vl][2] + (t / 3) % 3, ix = sPos[vl][3] + t % 3;
+        if (iz >= 0 && iy >= 0 && ix >= 0)  // 2 o + t - 1 < D always
+          lab = min(unsigned(window_base(lw, bi)[(iz * lw.box + iy) * lw.box + ix]), 8u);
+      }
+      sL[vl][t] = (unsigned char)lab;
+    }
+    __syncthreads();
+    bf16x8 a[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[m][j] = sZ[m * 16 + (lane & 15)][(lane >> 4) * 8 + j];
+    const unsigned ci = unsigned(lane & 15);  // B column: input channel (8..15 stay zero)
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wave + 4 * q;
+      if (t < 27) {
+        bf16x8 bw;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bw[j] = (__bf16)(ci < 8u && sL[(lane >> 4) * 8 + j][t] == ci ? 1.0f : 0.0f);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[q][m] = mfma(a[m], bw, acc[q][m]);
+      }
+    }
+    r0 += VS;
+    const int q = fdiv(r0, nvo, inv_nvo);
+    b0 += q;
+    r0 -= q * nvo;
+  }
+  // D tile rows = cout (A rows), cols = cin (B cols)
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wave + 4 * q;
+    if (t < 27) {
+      float* out = part + ((long long)blockIdx.x * 27 + t) * COUT * CIN;
+      const int cin = lane & 15;
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int co = m * 16 + (lane >> 4) * 4 + i;
+          if (cin < CIN) out[co * CIN + cin] = acc[q][m][i];
+        }
+    }
+  }
+  sB[threadIdx.x] = bsum;
+  __syncthreads();
+  if (threadIdx.x < COUT) {
+    float t = 0.0f;
+    for (int r = threadIdx.x; r < 256; r += COUT) t += sB[r];
+    pb[(long long)blockIdx.x * COUT + threadIdx.x] = t;
+  }
+}
+
+// Sum of weight-gradient partials over chunks, out[i] = sum_c part[c * n + i],
+// for many chunks: a block of 16 waves takes 64 consecutive outputs (one per
+// lane); wave w sums chunks w, w + 16, ... and the 16 wave sums are added in
+// wave order.  The order is fixed, so results do not depend on timing.
+__global__ void __launch_bounds__(1024) k_reduce_parts_wide(const float* __restrict__ part, int nchunk, long long n,
+                                                            float* __restrict__ out) {
+  __shared__ float sS[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long i = (long long)blockIdx.x * 64 + lane;
+  float s = 0.0f;
+  if (i < n) {
+    int c = wave;
+    for (; c + 48 < nchunk; c += 64) {
+      const float a0 = part[(long long)c * n + i], a1 = part[(long long)(c + 16) * n + i];
+      const float a2 = part[(long long)(c + 32) * n + i], a3 = part[(long long)(c + 48) * n + i];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; c < nchunk; c += 16) s += part[(long long)c * n + i];
+  }
+  sS[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && i < n) {
+    float t = 0.0f;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += sS[w][lane];
+    out[i] = t;
   }
 }
 
