@@ -219,6 +219,70 @@ def bench_study(args):
     ctx.close()
 
 
+def bench_timing(args):
+    """Computation time against size (the timing discussion of Sec. 4 and its
+    log-log figure): (a) the plain solve of one n^3 four-phase image (sigma 8,
+    seed 5) for n from 64 to 512, timed on a second call (the first tunes and
+    captures graphs), with a power-law fit t ~ n^a over n >= 128, where the
+    six systems fill the GPU; (b) the two-level scheme on a 900^3 image of the
+    same recipe, pad 0, for every subimage size dividing 900 with at least
+    three subimages per axis (75 to 300, the paper's partition grid), total
+    solve time against n with its fit.  One-time tuning and graph setup are
+    reported apart and left out of the fitted times."""
+    import numpy as np
+    import torch
+    from paper_2208_02320_amd import hh, synth
+    phases = synth.FOUR_PHASE["phases"]
+    sigma, seed = 8.0, 5
+    ctx = hh.Context(0)
+    single = []
+    for n in (64, 96, 128, 160, 192, 256, 320, 512):
+        lab = synth.four_phase_device(n, sigma=sigma, seed=seed)
+        torch.cuda.synchronize()
+        first = ctx.homogenize(lab, phases, tol=1e-6).report
+        t = time.perf_counter()
+        rep = ctx.homogenize(lab, phases, tol=1e-6).report
+        dt = time.perf_counter() - t
+        single.append({"n": n, "seconds": dt, "device_seconds": rep["seconds"], "iters": rep["iters"],
+                       "voxel_iters_per_s": rep["voxel_iters"] / dt, "setup_ms_first_call": first["setup_ms"]})
+        print("bench: timing single n=%d: %.3f s, iters %s, %.3g voxel-iter/s" %
+              (n, dt, rep["iters"], rep["voxel_iters"] / dt), file=sys.stderr, flush=True)
+        del lab
+    big = [r for r in single if r["n"] >= 128]
+    a_single = float(np.polyfit(np.log([r["n"] for r in big]), np.log([r["seconds"] for r in big]), 1)[0])
+    N = args.timing_size
+    lab = synth.four_phase_device(N, sigma=sigma, seed=seed)
+    torch.cuda.synchronize()
+    hier = []
+    for n in [n for n in range(75, N // 3 + 1) if N % n == 0]:
+        t = time.perf_counter()
+        C, _, rep = ctx.hierarchical(lab, phases, n, 0, tol=1e-6)
+        dt = time.perf_counter() - t
+        solve = dt - rep["setup_ms"] * 1e-3
+        K, G = hh.moduli(C)
+        hier.append({"n": n, "seconds": dt, "setup_ms": rep["setup_ms"], "solve_seconds": solve,
+                     "subimages": (N // n) ** 3, "voxel_iters_per_s": rep["voxel_iters"] / solve, "K": K, "G": G})
+        print("bench: timing hierarchy N=%d n=%d: %.2f s (setup %.0f ms), %.3g voxel-iter/s, K %.4f G %.4f" %
+              (N, n, dt, rep["setup_ms"], rep["voxel_iters"] / solve, K, G), file=sys.stderr, flush=True)
+    a_hier = float(np.polyfit(np.log([r["n"] for r in hier]), np.log([r["solve_seconds"] for r in hier]), 1)[0])
+    # M(n) = M_inf + c / n over the partition grid (Sec. 5's fit; no plain 900^3 reference here)
+    A = np.stack([np.ones(len(hier)), 1.0 / np.array([r["n"] for r in hier], float)], axis=1)
+    fit = {}
+    for m in ("K", "G"):
+        y = np.array([r[m] for r in hier])
+        coef = np.linalg.lstsq(A, y, rcond=None)[0]
+        fit[m] = {"M_inf": float(coef[0]), "c": float(coef[1]), "max_residual": float(np.abs(A @ coef - y).max())}
+    line = {
+        "metric": "time exponent of the plain solve (t ~ n^a, n = 128..512)", "value": a_single, "unit": "exponent",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "timing: four-phase images (sigma %g, seed %d), tol 1e-6; plain solves n = 64..512, "
+                               "two-level scheme on %d^3, pad 0" % (sigma, seed, N)},
+        "single": single, "hierarchy": hier, "hierarchy_time_exponent": a_hier, "hierarchy_n_inverse_fit": fit,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def bench_contrast(args):
     """Iterations and accuracy against phase contrast (Sec. 2 gives pores of
     1e-5 GPa, chosen there for stability): a 64^3 two-phase quartz / pore
@@ -439,7 +503,8 @@ def bench_cnn(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "cnn", "study", "contrast"),
+    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "cnn", "study", "contrast",
+                                               "timing"),
                     default="solve256")
     ap.add_argument("--sur-size", type=int, default=1024)
     ap.add_argument("--weights-dir", default=None)
@@ -447,6 +512,7 @@ def main():
     ap.add_argument("--bound-tol", type=float, default=0.0)
     ap.add_argument("--hier-size", type=int, default=512)
     ap.add_argument("--study-size", type=int, default=300)
+    ap.add_argument("--timing-size", type=int, default=900)
     ap.add_argument("--uneven-count", type=int, default=2048)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -471,6 +537,8 @@ def main():
         return bench_study(args)
     if args.workload == "contrast":
         return bench_contrast(args)
+    if args.workload == "timing":
+        return bench_timing(args)
 
     import torch
     from paper_2208_02320_amd import hh, synth
