@@ -189,19 +189,31 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
 
 // Sum NV doubles over a block of TH threads through LDS (no cross-lane
 // shuffles); result valid in thread 0.  scratch holds TH * NV doubles.
+// Each value is summed by G threads over strided shares, then thread 0 adds
+// the G partials in order; with fewer than NV * G threads, a thread takes
+// several (value, share) tasks.
 template <int NV, int TH>
 __device__ __forceinline__ void block_sum_lds(double (&v)[NV], double* scratch) {
-  constexpr int G = 8;
+  constexpr int G = 8, NT = NV * G, KT = (NT + TH - 1) / TH;
 #pragma unroll
   for (int i = 0; i < NV; ++i) scratch[i * TH + threadIdx.x] = v[i];
   __syncthreads();
-  double part = 0.0;
-  if (threadIdx.x < NV * G) {
-    const int i = threadIdx.x / G, gi = threadIdx.x % G;
-    for (int j = gi; j < TH; j += G) part += scratch[i * TH + j];
+  double part[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int t = threadIdx.x + k * TH;
+    part[k] = 0.0;
+    if (t < NT) {
+      const int i = t / G, gi = t % G;
+      for (int j = gi; j < TH; j += G) part[k] += scratch[i * TH + j];
+    }
   }
   __syncthreads();
-  if (threadIdx.x < NV * G) scratch[threadIdx.x] = part;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int t = threadIdx.x + k * TH;
+    if (t < NT) scratch[t] = part[k];
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -209,6 +221,28 @@ __device__ __forceinline__ void block_sum_lds(double (&v)[NV], double* scratch) 
       double t = 0.0;
       for (int gi = 0; gi < G; ++gi) t += scratch[i * G + gi];
       v[i] = t;
+    }
+  }
+}
+
+// block_sum_lds for a scratch that holds only CH values per thread
+// (TH * CH doubles): the values pass through it CH at a time, each summed as
+// block_sum_lds sums it.  Result valid in thread 0.
+template <int NV, int TH, int CH>
+__device__ __forceinline__ void block_sum_lds_chunked(double (&v)[NV], double* scratch) {
+  static_assert(CH >= 1 && CH < NV, "chunk size");
+#pragma unroll
+  for (int c0 = 0; c0 < NV; c0 += CH) {
+    constexpr int NC = CH;
+    double w[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) w[i] = c0 + i < NV ? v[c0 + i] : 0.0;
+    if (c0 > 0) __syncthreads();  // thread 0 has read the previous chunk
+    block_sum_lds<NC, TH>(w, scratch);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NC; ++i)
+        if (c0 + i < NV) v[c0 + i] = w[i];
     }
   }
 }
@@ -692,10 +726,17 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
         acc[7 + c] = s_sig[c];
       }
     }
-  } else if constexpr (TH * kPartX * 8 <= (N * L + N2 * P) * int(sizeof(cx<T>))) {
-    block_sum_lds<kPartX, TH>(acc, reinterpret_cast<double*>(buf));
   } else {
-    block_sum<kPartX>(acc, reinterpret_cast<double*>(buf));
+    // the tile buffer serves as scratch: all 13 values per thread at once,
+    // or as many as fit per pass
+    constexpr int kScratch = (N * L + N2 * P) * int(sizeof(cx<T>)) / (TH * 8);  // doubles per thread
+    if constexpr (kScratch >= kPartX) {
+      block_sum_lds<kPartX, TH>(acc, reinterpret_cast<double*>(buf));
+    } else if constexpr (kScratch >= 1) {
+      block_sum_lds_chunked<kPartX, TH, kScratch>(acc, reinterpret_cast<double*>(buf));
+    } else {
+      block_sum<kPartX>(acc, reinterpret_cast<double*>(buf));
+    }
   }
   if (threadIdx.x == 0) {
     double* out = g.part_x + ((long long)s * g.nwg_x + blockIdx.x) * kPartX;
