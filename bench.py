@@ -80,6 +80,23 @@ def profiled_traffic(kernel, n):
     return val if sha == kernel_source_hash() else None
 
 
+def error_vs_stored_oracle(n, C):
+    """Relative Frobenius error of the timed result's stiffness, Mandel-scaled
+    (shear rows and columns times sqrt 2), against the FP64 oracle's result
+    for the same seeded image at tol 1e-9, stored under tests/golden by a
+    script that runs only the oracle.  None for sizes without a stored result."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "four_phase_%d_seed1.json" % n)
+    if not os.path.exists(path):
+        return None
+    ref = json.load(open(path))
+    s = np.array([1.0, 1.0, 1.0, 2.0 ** 0.5, 2.0 ** 0.5, 2.0 ** 0.5])
+    M = np.outer(s, s)
+    Cr = np.array(ref["C_sym"])
+    e = float(np.linalg.norm((np.asarray(C) - Cr) * M) / np.linalg.norm(Cr * M))
+    return {"rel_error": e, "bound": 1e-5, "oracle": "FP64 oracle at tol %g (%s)" % (ref["tol"], ref["image"])}
+
+
 def cpu_baseline(lab, phases, iters=2):
     """FP64 oracle on a bounded sample: load 1 of the same image, the right-hand
     side plus the first ``iters`` CG iterations."""
@@ -556,8 +573,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     timed = []
+    last = None
     for _ in range(args.steps):
-        timed.append(ctx.homogenize(dev, phases, **opts).report)
+        last = ctx.homogenize(dev, phases, **opts)
+        timed.append(last.report)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     if not setup:  # no warm-up: the one-time setup fell inside the timed steps
@@ -584,6 +603,7 @@ def main():
     print("bench: per-class %s" % json.dumps(per_class), file=sys.stderr, flush=True)
 
     cpu = None if args.no_cpu else cpu_baseline(lab, phases, args.cpu_iters)
+    err = error_vs_stored_oracle(n, last.C) if last is not None else None
     out = {
         "metric": "voxel-iters/s of FFT elasticity solve",
         "value": vi / dt,
@@ -609,6 +629,7 @@ def main():
                      "algorithmic_bytes_per_system_iter": ab[dom],
                      "mean_launch_ms": round(ms[dom] / max(launches[dom], 1), 4)},
         "cpu_baseline": cpu,
+        "error_vs_oracle": err,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
