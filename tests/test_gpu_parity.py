@@ -270,6 +270,14 @@ def test_errors(ctx):
     with pytest.raises(hh.HHError) as e:
         ctx.homogenize(np.zeros((8, 8, 8), np.uint8), [(1.0, -1.0)])
     assert e.value.code == -1
+    with pytest.raises(hh.HHError) as e:
+        ctx.homogenize(np.zeros((8, 8, 8), np.uint8), [(float("nan"), 1.0)])
+    assert e.value.code == -1
+    loads = np.eye(6)
+    loads[:, 5] = loads[:, 4]  # two equal columns: the loads are not independent
+    with pytest.raises(hh.HHError) as e:
+        ctx.homogenize(np.zeros((8, 8, 8), np.uint8), QP[:1], loads=loads)
+    assert e.value.code == -1
 
 
 def test_fp32_tolerance_floor_reports_status(ctx):

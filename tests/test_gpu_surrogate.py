@@ -193,6 +193,22 @@ def constant_net(ctx, nphase, n, c21):
     return net
 
 
+def test_total_fallback_equals_plain_hierarchy(ctx):
+    """A prediction outside every item's Voigt-Reuss bracket (twice the
+    stiffest phase's Voigt bound) sends all items to the FFT solver; the
+    result is then the plain two-level scheme's."""
+    lab = synth.four_phase(48, seed=9)
+    n, pad = 16, 2
+    CV, _ = sg.core_bounds(lab, 0, 48, FOUR)
+    net = constant_net(ctx, 4, n, hier.to21(2.0 * CV))
+    C, Cs, fb, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=0.0, tol=1e-6)
+    Cp, Csp, _ = ctx.hierarchical(lab, FOUR, n, pad, tol=1e-6)
+    assert fb.all()
+    assert g.rel_error(C, Cp) < 1e-6
+    for i in range(len(fb)):
+        assert g.rel_error(hier.from21(Cs[i]), hier.from21(Csp[i])) < 1e-6, i
+
+
 def test_gate_and_fallback_match_oracle(ctx):
     lab = synth.four_phase(64, seed=4)
     n, pad = 16, 4
