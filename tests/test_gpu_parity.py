@@ -108,6 +108,30 @@ def test_long_and_prime_axes_fp32(ctx, n, axis):
     assert err < TOL32
 
 
+def compiled_lengths(precision):
+    from paper_2208_02320_amd import hh
+    return [n for n in range(2, 513) if hh.size_supported(n, precision)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_compiled_length(ctx, precision):
+    """Each compiled axis length has its own register-DFT plan (factors and
+    prime kernels); every one runs on a thin image with the long axis taking
+    x, y and z in turn, against the oracle."""
+    tol, rtol = (1e-6, TOL32) if precision == 0 else (1e-11, TOL64)
+    ph = [synth.QUARTZ, synth.FELDSPAR, synth.PORE]
+    worst = 0.0
+    for n in compiled_lengths(precision):
+        axis = n % 3
+        lab = thin(n, axis, seed=3 * n + precision)
+        r = ctx.homogenize(lab, ph, tol=tol, precision=precision, tune=0)
+        ref = oracle(lab, ph, tol=1e-12 if precision else 1e-10)
+        err = g.rel_error(r.C, ref.C_sym)
+        worst = max(worst, err)
+        assert err < rtol, (n, axis, err)
+    print("precision %d: %d lengths, worst error %.2e" % (precision, len(compiled_lengths(precision)), worst))
+
+
 @pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("n", [85, 95, 110])
 def test_prime_axes_fp64(ctx, n, axis):
