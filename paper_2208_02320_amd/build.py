@@ -3,7 +3,8 @@
 Every ``csrc/*.hip`` translation unit is compiled by ``hipcc`` for gfx950 in
 parallel, then linked into one shared library that exports the C ABI of
 ``include/hh.h``.  Also builds ``calib/copy``, the plain copy kernel used to
-calibrate profiler byte counters.  Run as ``python -m paper_2208_02320_amd.build``.
+calibrate profiler byte counters, and ``examples/hh_client``, a plain C client
+of the ABI.  Run as ``python -m paper_2208_02320_amd.build``.
 """
 from __future__ import annotations
 
@@ -64,9 +65,25 @@ def build(jobs=None, verbose=True):
     if p.returncode != 0:
         raise RuntimeError("calibration kernel build failed: %s\n%s" % (" ".join(cmd), p.stderr))
     os.replace(exe + ".tmp", exe)
+    if LIB == os.path.join(HERE, "libhh.so"):
+        build_client()
     if verbose:
         print("built %s in %.1fs" % (LIB, time.time() - t0), flush=True)
     return LIB
+
+
+def build_client():
+    """The plain C client of the ABI (examples/hh_client.c), linked against
+    libhh.so with gcc; it finds the library next to itself at run time."""
+    src = os.path.join(HERE, "examples", "hh_client.c")
+    exe = os.path.join(HERE, "examples", "hh_client")
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), src,
+           "-L", HERE, "-lhh", "-Wl,-rpath,$ORIGIN/..", "-o", exe + ".tmp"]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("C client build failed: %s\n%s" % (" ".join(cmd), p.stderr))
+    os.replace(exe + ".tmp", exe)
+    return exe
 
 
 if __name__ == "__main__":

@@ -4,6 +4,7 @@ oracle.  No GPU compute is called."""
 import ctypes as ct
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -83,3 +84,28 @@ def test_context_needs_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         hh.Context(0)
+
+
+def run_client(*args):
+    exe = os.path.join(ROOT, "paper_2208_02320_amd", "examples", "hh_client")
+    if not os.path.exists(exe):
+        pytest.skip("C client not built")
+    p = subprocess.run([exe] + [str(a) for a in args], capture_output=True, text=True, timeout=120)
+    out = {}
+    for line in p.stdout.splitlines():
+        key, *vals = line.split()
+        out[key] = [float(v) for v in vals]
+    return p.returncode, out, p.stderr
+
+
+def test_plain_c_client_host_entry_points():
+    """A C program linked against libhh.so, without Python: the Voigt moduli
+    of an isotropic matrix (lambda 2, mu 3) are K = lambda + 2 mu / 3 and
+    G = mu; the n^-1 fit recovers M(n) = 5 + 40 / n exactly; a context needs
+    a gfx950 device (HH_EDEVICE where there is none)."""
+    rc, out, err = run_client("host")
+    assert rc == 0, err
+    assert out["supported_f32"] == [256, 1, 7, 0]
+    assert np.allclose(out["moduli"], [4.0, 3.0], rtol=0, atol=1e-14)
+    assert np.allclose(out["richardson"], [5.0, 40.0], rtol=1e-12)
+    assert out["create"][0] in (0, -4)
