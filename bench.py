@@ -561,9 +561,14 @@ def main():
     from paper_2208_02320_amd import hh, synth
 
     n = args.size
-    lab = synth.four_phase(n, sigma=2.0, seed=1)
     phases = synth.FOUR_PHASE["phases"]
-    dev = torch.from_numpy(lab).to("cuda:0")
+    if n <= 512:
+        lab = synth.four_phase(n, sigma=2.0, seed=1)
+        dev = torch.from_numpy(lab).to("cuda:0")
+    else:  # the same recipe on the device (a host filter of 1024^3 voxels takes minutes)
+        dev = synth.four_phase_device(n, sigma=2.0, seed=1)
+        lab = None
+        args.no_cpu = True
     ctx = hh.Context(0)
     opts = dict(tol=1e-6, precision=0)
     print("bench: %d^3 four-phase, warmup %d" % (n, args.warmup), file=sys.stderr, flush=True)

@@ -83,6 +83,10 @@ typedef struct {
                         replayed (not with profile); 0 = plain launches; default 1 */
   int plan[3];       /* tile variant forced for the z, y and x passes (0..HH_NVARIANT-1,
                         FP64: 0 only); -1 = tuned or default; default -1 */
+  int loads_per_wave; /* 1..6: the load cases of an image are solved at most this many at
+                        a time (the others wait for device memory), and images then run
+                        one at a time; 0 = all six together unless the six systems of one
+                        image do not fit in device memory, then as many as fit; default 0 */
 } hh_opts;
 
 /* Per-call report. */
@@ -121,7 +125,7 @@ void hh_release_workspace(hh_ctx *ctx);
 /* 1 if axis length n has compiled FFT passes at `precision`, else 0.  The
  * list is fixed at build time.  FP32 (precision 0): 2 3 4 5 6 8 9 10 12 15 16
  * 18 20 24 25 27 30 32 36 40 45 48 50 60 64 70 72 75 80 85 90 95 96 100 110 120
- * 128 144 150 160 170 180 190 192 200 225 235 240 245 256 300 310 320 512
+ * 128 144 150 160 170 180 190 192 200 225 235 240 245 256 300 310 320 512 1024
  * (among them the boxes of the paper's subimage sizes of Sec. 5 with 5 or 10
  * voxels of padding).  FP64 (precision 1): 2 3 4 5 6 8 9 10 12 15 16 18 20
  * 24 25 27 30 32 36 40 45 48 60 64 80 85 95 96 110 128. */

@@ -154,6 +154,7 @@ void check_opts(hh_ctx* ctx, const hh_opts& o) {
   if (o.graph != 0 && o.graph != 1) fail(ctx, HH_EINVAL, "graph must be 0 or 1");
   for (int i = 0; i < 3; ++i)
     if (o.plan[i] < -1 || o.plan[i] >= kNVariant) fail(ctx, HH_EINVAL, "plan entries must be -1 or a variant index");
+  if (o.loads_per_wave < 0 || o.loads_per_wave > 6) fail(ctx, HH_EINVAL, "loads_per_wave must be in 0..6");
 }
 
 void check_shape(hh_ctx* ctx, int nx, int ny, int nz, int precision) {
@@ -251,6 +252,16 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
   int wave = int(std::max<size_t>(1, budget / (6 * per_sys)));
   wave = std::min<int>(wave, int(items.size()));
   wave = std::min(wave, 65535 / 6);
+  // Loads per wave: all six, unless the six systems of one image do not fit
+  // in the device memory (what is free plus this context's workspace).  Then
+  // each image runs alone, a few of its loads at a time, and its stiffness is
+  // formed once the final states of all six loads are in.
+  size_t held = 0;
+  for (const auto& b : ctx->bufs) held += b.second.second;
+  const size_t avail = size_t(0.85 * double(freeb + held));
+  const int fit = 6 * per_sys <= avail ? 6 : int(std::max<size_t>(1, avail / per_sys));
+  const int loads_per_wave = std::min(fit, o.loads_per_wave > 0 ? o.loads_per_wave : 6);
+  if (loads_per_wave < 6) wave = 1;
 
   // tile variants: forced, cached for this context, or tuned on the first wave
   std::array<int, 3> plan{{0, 0, 0}};
@@ -265,7 +276,7 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
   while ((6 << bucket) < wave * 6 && bucket < 20) ++bucket;
   const std::array<int, 6> key{{nx, ny, nz, P, aniso ? 1 : 0, bucket}};
   bool need_tune = false;
-  if (!forced_all && o.tune && P == 0) {
+  if (!forced_all && o.tune && P == 0 && loads_per_wave == 6) {
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
       for (int i = 0; i < 3; ++i)
@@ -300,9 +311,12 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
     if (ref_lam + 2.0 * ref_mu / 3.0 <= 0.0) ref_lam = 0.0;
   }
 
+  std::vector<SysState> split_state(6);  // final states of an image solved a few loads at a time
   for (int w0 = 0; w0 < nitems; w0 += wave) {
-    const int nw = std::min(wave, nitems - w0);
-    const int nsys = nw * 6;
+   const int nw = std::min(wave, nitems - w0);
+   for (int a0 = 0; a0 < 6; a0 += loads_per_wave) {
+    const int la = std::min(loads_per_wave, 6 - a0);  // loads of this wave
+    const int nsys = nw * la;
     std::vector<ItemDesc> idesc(nw);
     std::vector<SysDesc> sdesc(nsys);
     for (int i = 0; i < nw; ++i) {
@@ -320,11 +334,11 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
         d.lam[k] = it.phases[k].K - 2.0 * it.phases[k].G / 3.0;
         d.mu[k] = it.phases[k].G;
       }
-      for (int a = 0; a < 6; ++a) sdesc[i * 6 + a] = SysDesc{i, a};
+      for (int a = 0; a < la; ++a) sdesc[i * la + a] = SysDesc{i, a0 + a};
     }
     auto* d_items = static_cast<ItemDesc*>(ws(ctx, "items", sizeof(ItemDesc) * nw));
     auto* d_sys = static_cast<SysDesc*>(ws(ctx, "sys", sizeof(SysDesc) * nsys));
-    auto* d_state = static_cast<SysState*>(ws(ctx, "state", sizeof(SysState) * nsys));
+    auto* d_state = static_cast<SysState*>(ws(ctx, "state", sizeof(SysState) * nw * 6));
     auto* d_px = static_cast<double*>(ws(ctx, "part_x", sizeof(double) * kPartX * size_t(nwgx_max) * nsys));
     auto* d_pz = static_cast<double*>(ws(ctx, "part_z", sizeof(double) * size_t(nwgz_max) * nsys));
     void* d_tmp = ws(ctx, "tmp", size_t(nfreq) * 6 * cb * nsys);
@@ -512,15 +526,23 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
       prof.flush();
       if (running == 0) break;
     }
+    if (la < 6) {
+      // keep this wave's final states; after the last load, all six go back
+      // to the state array, in load order, for the stiffness of the image
+      HIPCHK(hipMemcpyAsync(split_state.data() + a0, d_state, sizeof(SysState) * la, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (a0 + la < 6) continue;
+      HIPCHK(hipMemcpyAsync(d_state, split_state.data(), sizeof(SysState) * 6, hipMemcpyHostToDevice, st));
+    }
     void* cf_out = nullptr;
     if (cfield_out) cf_out = static_cast<char*>(cfield_out) + size_t(w0) * 21 * (P == 0 ? 4 : 8);
     prof.run(HH_K_OTHER, [&] { launch_stiffness(P, d_state, nw, d_out, cf_out, d_ist, st); });
     HIPCHK(hipGetLastError());
-    std::vector<SysState> hst(nsys);
+    std::vector<SysState> hst(size_t(nw) * 6);
     std::vector<int> ist(nw);
     HIPCHK(hipMemcpyAsync(res.C72.data() + size_t(w0) * 72, d_out, sizeof(double) * 72 * nw, hipMemcpyDeviceToHost,
                           st));
-    HIPCHK(hipMemcpyAsync(hst.data(), d_state, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hst.data(), d_state, sizeof(SysState) * nw * 6, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(ist.data(), d_ist, sizeof(int) * nw, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     prof.flush();
@@ -536,6 +558,7 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
       }
       res.status[w0 + i] = code;
     }
+   }
   }
   return res;
 }
@@ -633,6 +656,7 @@ void hh_default_opts(hh_opts* o) {
   o->tune = 1;
   o->graph = 1;
   o->plan[0] = o->plan[1] = o->plan[2] = -1;
+  o->loads_per_wave = 0;
 }
 
 int hh_create(hh_ctx** out, int device, void* hip_stream) {

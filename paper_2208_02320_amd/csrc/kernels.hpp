@@ -50,6 +50,7 @@ SizeOpsFn size_ops_f32_19(int n, int v);
 SizeOpsFn size_ops_f32_20(int n, int v);
 SizeOpsFn size_ops_f32_21(int n, int v);
 SizeOpsFn size_ops_f32_22(int n, int v);
+SizeOpsFn size_ops_f32_23(int n, int v);
 SizeOpsFn size_ops_f64_0(int n, int v);
 SizeOpsFn size_ops_f64_1(int n, int v);
 SizeOpsFn size_ops_f64_2(int n, int v);

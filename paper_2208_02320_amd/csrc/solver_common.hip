@@ -218,7 +218,7 @@ __global__ void k_stiffness(const SysState* state, int nitems, double* out, T* c
 SizeOpsFn size_ops(int n, int precision, int variant) {
   using Part = SizeOpsFn (*)(int, int);
   if (variant < 0 || variant >= kNVariant) return nullptr;
-  static const Part f32[] = {size_ops_f32_0, size_ops_f32_1, size_ops_f32_2, size_ops_f32_3, size_ops_f32_4, size_ops_f32_5, size_ops_f32_6, size_ops_f32_7, size_ops_f32_8, size_ops_f32_9, size_ops_f32_10, size_ops_f32_11, size_ops_f32_12, size_ops_f32_13, size_ops_f32_14, size_ops_f32_15, size_ops_f32_16, size_ops_f32_17, size_ops_f32_18, size_ops_f32_19, size_ops_f32_20, size_ops_f32_21, size_ops_f32_22};
+  static const Part f32[] = {size_ops_f32_0, size_ops_f32_1, size_ops_f32_2, size_ops_f32_3, size_ops_f32_4, size_ops_f32_5, size_ops_f32_6, size_ops_f32_7, size_ops_f32_8, size_ops_f32_9, size_ops_f32_10, size_ops_f32_11, size_ops_f32_12, size_ops_f32_13, size_ops_f32_14, size_ops_f32_15, size_ops_f32_16, size_ops_f32_17, size_ops_f32_18, size_ops_f32_19, size_ops_f32_20, size_ops_f32_21, size_ops_f32_22, size_ops_f32_23};
   static const Part f64[] = {size_ops_f64_0, size_ops_f64_1, size_ops_f64_2, size_ops_f64_3};
   if (precision == 0) {
     for (Part p : f32)

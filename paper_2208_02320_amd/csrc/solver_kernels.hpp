@@ -37,7 +37,8 @@ namespace hh {
 
 // LDS budget of one tile.  y/z passes: at least 4 kx columns per tile so
 // that every tile row is a whole number of 64-byte sectors (no partial
-// writes); x pass: full spectrum rows.
+// writes), except in FP32 above 512 points, where 4 columns would not fit in
+// LDS and tiles take 2; x pass: full spectrum rows.
 #ifndef HH_LDS_TILE_X
 #define HH_LDS_TILE_X (24 * 1024)
 #endif
@@ -74,7 +75,7 @@ template <int N, class T, int V = 0>
 struct AxisCfg {
   static constexpr int N1 = split_n1(N), N2 = N / N1;
   static constexpr int CB = int(sizeof(cx<T>));
-  static constexpr int M = clampi(variant_budget(kLdsTileYZ, V) / (N * 6 * CB), CB == 8 ? 4 : 2, 16);
+  static constexpr int M = clampi(variant_budget(kLdsTileYZ, V) / (N * 6 * CB), CB == 8 && N <= 512 ? 4 : 2, 16);
   static constexpr int L = 6 * M;
   static constexpr int P = lds_pad(N1, N2, L, CB);
   static constexpr int THREADS = clampi(round64(L * maxi(N1, N2)), 64, 512);

@@ -52,7 +52,7 @@ class Opts(ct.Structure):
                 ("precision", ct.c_int), ("nyquist", ct.c_int), ("profile", ct.c_int),
                 ("stall_limit", ct.c_int), ("chunk", ct.c_int),
                 ("ref_lambda", ct.c_double), ("ref_mu", ct.c_double),
-                ("tune", ct.c_int), ("graph", ct.c_int), ("plan", ct.c_int * 3)]
+                ("tune", ct.c_int), ("graph", ct.c_int), ("plan", ct.c_int * 3), ("loads_per_wave", ct.c_int)]
 
 
 class Report(ct.Structure):

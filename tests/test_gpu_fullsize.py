@@ -99,3 +99,20 @@ def test_surrogate_1024_within_budget_of_plain_hierarchy(ctx):
     assert rs["seconds"] * 10 < rp["seconds"]
     na.close()
     nb.close()
+
+
+def test_1024cube_plain_solve_of_a_periodic_tiling(ctx):
+    """The largest compiled length at full size: a 1024^3 image that tiles
+    one 64^3 block 16 times per axis has the block's stiffness exactly.  Six
+    1024^3 systems need about 312 GB, so the solve runs its loads a few at a
+    time (the memory-split path)."""
+    import torch
+    block = synth.four_phase(64, sigma=2.0, seed=12)
+    Cb = ctx.homogenize(block, FOUR, tol=1e-6).C
+    tiled = torch.from_numpy(block).cuda().repeat(16, 16, 16).contiguous()
+    r = ctx.homogenize(tiled, FOUR, tol=1e-6)
+    del tiled
+    torch.cuda.empty_cache()
+    err = g.rel_error(r.C, Cb)
+    print("1024^3 tiling vs 64^3 block: %.2e, iters %s, %.1f s" % (err, r.report["iters"], r.report["seconds"]))
+    assert err < 1e-5

@@ -86,8 +86,9 @@ def test_sizes_fp32(ctx, n):
 
 # Lengths with prime factors above 5 (padded boxes of the paper's subimage
 # sizes 75, 90, 150, 180, 225, 300 with 5 or 10 voxels of padding) and the
-# longest FP32 axis, each on every axis in turn of a thin image.
-LONG32 = [85, 95, 110, 170, 190, 225, 235, 245, 300, 310, 320, 512]
+# longest FP32 axes (1024 runs 2-column y/z tiles), each on every axis in
+# turn of a thin image.
+LONG32 = [85, 95, 110, 170, 190, 225, 235, 245, 300, 310, 320, 512, 1024]
 
 
 def thin(n, axis, seed):
@@ -110,7 +111,7 @@ def test_long_and_prime_axes_fp32(ctx, n, axis):
 
 def compiled_lengths(precision):
     from paper_2208_02320_amd import hh
-    return [n for n in range(2, 513) if hh.size_supported(n, precision)]
+    return [n for n in range(2, 1025) if hh.size_supported(n, precision)]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -259,6 +260,28 @@ def test_hierarchical_levels_errors(ctx):
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("lpw", [1, 2, 4, 5])
+def test_loads_split_over_waves_give_the_same_result(ctx, lpw):
+    """An image's six load cases solved a few at a time (the path taken when
+    six systems do not fit in device memory) give bit-identical stiffness:
+    every system's arithmetic is the same, only the launches group them
+    differently.  Single image, a batch of three, and the two-level scheme."""
+    lab = synth.rocklike((24, 20, 16), [0.6, 0.25, 0.15], sigma=1.5, seed=41, low_to_high=[2, 1, 0])
+    ph = [synth.QUARTZ, synth.FELDSPAR, synth.PORE]
+    r6 = ctx.homogenize(lab, ph, tol=1e-6, tune=0)
+    r = ctx.homogenize(lab, ph, tol=1e-6, tune=0, loads_per_wave=lpw)
+    assert np.array_equal(r.C_raw, r6.C_raw)
+    assert r.report["iters"] == r6.report["iters"]
+    imgs = [lab, lab[::-1].copy(), np.ascontiguousarray(np.roll(lab, 5, axis=2))]
+    C6 = ctx.homogenize_batch(imgs, [ph] * 3, tol=1e-6, tune=0)[1]
+    C = ctx.homogenize_batch(imgs, [ph] * 3, tol=1e-6, tune=0, loads_per_wave=lpw)[1]
+    assert np.array_equal(C, C6)
+    big = synth.rocklike(32, [0.6, 0.25, 0.15], sigma=1.5, seed=42, low_to_high=[2, 1, 0])
+    H6 = ctx.hierarchical(big, ph, 16, 2, tol=1e-6, tune=0)[0]
+    H = ctx.hierarchical(big, ph, 16, 2, tol=1e-6, tune=0, loads_per_wave=lpw)[0]
+    assert np.array_equal(H, H6)
+
+
 def test_batch_mixed_sizes(ctx):
     recipe = synth.uneven_batch(6, sizes=(8, 12, 16), seed=77)
     imgs = [synth.item_image(it) for it in recipe]
@@ -296,6 +319,9 @@ def test_errors(ctx):
     assert e.value.code == -1
     with pytest.raises(hh.HHError) as e:
         ctx.homogenize(np.zeros((8, 8, 8), np.uint8), [(float("nan"), 1.0)])
+    assert e.value.code == -1
+    with pytest.raises(hh.HHError) as e:
+        ctx.homogenize(np.zeros((8, 8, 8), np.uint8), QP[:1], loads_per_wave=7)
     assert e.value.code == -1
     loads = np.eye(6)
     loads[:, 5] = loads[:, 4]  # two equal columns: the loads are not independent
