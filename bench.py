@@ -239,9 +239,9 @@ def bench_study(args):
 def bench_timing(args):
     """Computation time against size (the timing discussion of Sec. 4 and its
     log-log figure): (a) the plain solve of one n^3 four-phase image (sigma 8,
-    seed 5) for n from 64 to 512, timed on a second call (the first tunes and
+    seed 5) for n from 64 to 1024, timed on a second call (the first tunes and
     captures graphs), with a power-law fit t ~ n^a over n >= 128, where the
-    six systems fill the GPU; (b) the two-level scheme on a 900^3 image of the
+    six systems fill the GPU (1024^3 runs its loads in two memory waves); (b) the two-level scheme on a 900^3 image of the
     same recipe, pad 0, for every subimage size dividing 900 with at least
     three subimages per axis (75 to 300, the paper's partition grid), total
     solve time against n with its fit.  One-time tuning and graph setup are
@@ -253,9 +253,10 @@ def bench_timing(args):
     sigma, seed = 8.0, 5
     ctx = hh.Context(0)
     single = []
-    for n in (64, 96, 128, 160, 192, 256, 320, 512):
+    for n in (64, 96, 128, 160, 192, 256, 320, 512, 1024):
         lab = synth.four_phase_device(n, sigma=sigma, seed=seed)
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()  # the generator's temporaries
         first = ctx.homogenize(lab, phases, tol=1e-6).report
         t = time.perf_counter()
         rep = ctx.homogenize(lab, phases, tol=1e-6).report
@@ -268,8 +269,10 @@ def bench_timing(args):
     big = [r for r in single if r["n"] >= 128]
     a_single = float(np.polyfit(np.log([r["n"] for r in big]), np.log([r["seconds"] for r in big]), 1)[0])
     N = args.timing_size
+    ctx.release_workspace()
     lab = synth.four_phase_device(N, sigma=sigma, seed=seed)
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     hier = []
     for n in [n for n in range(75, N // 3 + 1) if N % n == 0]:
         t = time.perf_counter()
@@ -290,9 +293,9 @@ def bench_timing(args):
         coef = np.linalg.lstsq(A, y, rcond=None)[0]
         fit[m] = {"M_inf": float(coef[0]), "c": float(coef[1]), "max_residual": float(np.abs(A @ coef - y).max())}
     line = {
-        "metric": "time exponent of the plain solve (t ~ n^a, n = 128..512)", "value": a_single, "unit": "exponent",
+        "metric": "time exponent of the plain solve (t ~ n^a, n = 128..1024)", "value": a_single, "unit": "exponent",
         "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "timing: four-phase images (sigma %g, seed %d), tol 1e-6; plain solves n = 64..512, "
+        "config": {"workload": "timing: four-phase images (sigma %g, seed %d), tol 1e-6; plain solves n = 64..1024, "
                                "two-level scheme on %d^3, pad 0" % (sigma, seed, N)},
         "single": single, "hierarchy": hier, "hierarchy_time_exponent": a_hier, "hierarchy_n_inverse_fit": fit,
     }
@@ -443,6 +446,26 @@ def bench_surrogate(args):
     dtp = time.perf_counter() - t1
     err = float(surrogate.rel_error21(hh.upper21(C), hh.upper21(Cp))[0])
     sub_err = surrogate.rel_error21(Cs, Csp)
+    # the plain solve of the whole image (the paper's brute-force reference),
+    # where the axis length is compiled; its loads run a few at a time at 1024^3
+    brute = None
+    if hh.size_supported(N, 0):
+        torch.cuda.empty_cache()
+        ctx.release_workspace()
+        t2 = time.perf_counter()
+        rb = ctx.homogenize(img, phases, tol=1e-6)
+        torch.cuda.synchronize()
+        Kb, Gb = hh.moduli(rb.C)
+        Kh, Gh = hh.moduli(Cp)
+        Ks, Gs = hh.moduli(C)
+        brute = {"seconds": time.perf_counter() - t2, "K": Kb, "G": Gb,
+                 "plain_hierarchy_rel_error": float(surrogate.rel_error21(hh.upper21(Cp), hh.upper21(rb.C))[0]),
+                 "surrogate_rel_error": float(surrogate.rel_error21(hh.upper21(C), hh.upper21(rb.C))[0]),
+                 "K_G_err_pct": {"plain_hierarchy": [100 * (Kh / Kb - 1), 100 * (Gh / Gb - 1)],
+                                 "surrogate": [100 * (Ks / Kb - 1), 100 * (Gs / Gb - 1)]}}
+        print("bench: brute-force %d^3 in %.1f s: K %.4f G %.4f; hierarchy error %.2e, surrogate error %.2e" %
+              (N, brute["seconds"], Kb, Gb, brute["plain_hierarchy_rel_error"], brute["surrogate_rel_error"]),
+              file=sys.stderr, flush=True)
     line = {
         "metric": "subimages/s of the two-level scheme with surrogate and FFT fallback",
         "value": items / dt, "unit": "subimages/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -456,6 +479,7 @@ def bench_surrogate(args):
         "subimage_rel_error": {"mean": float(sub_err.mean()), "p95": float(np.quantile(sub_err, 0.95)),
                                "max": float(sub_err.max())},
         "plain_subimages_per_s": items / dtp, "speedup_vs_plain": dtp / dt,
+        "brute_force": brute,
         "roofline": {"bound": "mfma", "kernel": "network forward (4 BF16 convolutions + head)",
                      "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": round(tflops / 2500.0, 5), "traffic": None,

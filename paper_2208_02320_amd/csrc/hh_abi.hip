@@ -253,11 +253,15 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
   wave = std::min<int>(wave, int(items.size()));
   wave = std::min(wave, 65535 / 6);
   // Loads per wave: all six, unless the six systems of one image do not fit
-  // in the device memory (what is free plus this context's workspace).  Then
-  // each image runs alone, a few of its loads at a time, and its stiffness is
-  // formed once the final states of all six loads are in.
+  // in the device memory (what is free plus the field buffers this call
+  // re-allocates).  Then each image runs alone, a few of its loads at a
+  // time, and its stiffness is formed once the final states of all six loads
+  // are in.
   size_t held = 0;
-  for (const auto& b : ctx->bufs) held += b.second.second;
+  for (const char* name : {"tmp", "ar", "ap"}) {
+    auto it = ctx->bufs.find(name);
+    if (it != ctx->bufs.end()) held += it->second.second;
+  }
   const size_t avail = size_t(0.85 * double(freeb + held));
   const int fit = 6 * per_sys <= avail ? 6 : int(std::max<size_t>(1, avail / per_sys));
   const int loads_per_wave = std::min(fit, o.loads_per_wave > 0 ? o.loads_per_wave : 6);
