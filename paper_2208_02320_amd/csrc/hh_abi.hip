@@ -317,252 +317,253 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
 
   std::vector<SysState> split_state(6);  // final states of an image solved a few loads at a time
   for (int w0 = 0; w0 < nitems; w0 += wave) {
-   const int nw = std::min(wave, nitems - w0);
-   for (int a0 = 0; a0 < 6; a0 += loads_per_wave) {
-    const int la = std::min(loads_per_wave, 6 - a0);  // loads of this wave
-    const int nsys = nw * la;
-    std::vector<ItemDesc> idesc(nw);
-    std::vector<SysDesc> sdesc(nsys);
-    for (int i = 0; i < nw; ++i) {
-      const Item& it = items[w0 + i];
-      ItemDesc& d = idesc[i];
-      std::memset(&d, 0, sizeof(d));
-      d.lab_off = it.lab_off;
-      d.cf_off = it.cf_off;
-      for (int k = 0; k < 6; ++k) d.region[k] = it.region[k];
-      d.nphase = int(it.phases.size());
-      const double vol = double(it.region[3] - it.region[0]) * (it.region[4] - it.region[1]) *
-                         (it.region[5] - it.region[2]);
-      d.inv_region = 1.0 / vol;
-      for (int k = 0; k < d.nphase; ++k) {
-        d.lam[k] = it.phases[k].K - 2.0 * it.phases[k].G / 3.0;
-        d.mu[k] = it.phases[k].G;
+    const int nw = std::min(wave, nitems - w0);
+    for (int a0 = 0; a0 < 6; a0 += loads_per_wave) {
+      const int la = std::min(loads_per_wave, 6 - a0);  // loads of this wave
+      const int nsys = nw * la;
+      std::vector<ItemDesc> idesc(nw);
+      std::vector<SysDesc> sdesc(nsys);
+      for (int i = 0; i < nw; ++i) {
+        const Item& it = items[w0 + i];
+        ItemDesc& d = idesc[i];
+        std::memset(&d, 0, sizeof(d));
+        d.lab_off = it.lab_off;
+        d.cf_off = it.cf_off;
+        for (int k = 0; k < 6; ++k) d.region[k] = it.region[k];
+        d.nphase = int(it.phases.size());
+        const double vol = double(it.region[3] - it.region[0]) * (it.region[4] - it.region[1]) *
+                           (it.region[5] - it.region[2]);
+        d.inv_region = 1.0 / vol;
+        for (int k = 0; k < d.nphase; ++k) {
+          d.lam[k] = it.phases[k].K - 2.0 * it.phases[k].G / 3.0;
+          d.mu[k] = it.phases[k].G;
+        }
+        for (int a = 0; a < la; ++a) sdesc[i * la + a] = SysDesc{i, a0 + a};
       }
-      for (int a = 0; a < la; ++a) sdesc[i * la + a] = SysDesc{i, a0 + a};
-    }
-    auto* d_items = static_cast<ItemDesc*>(ws(ctx, "items", sizeof(ItemDesc) * nw));
-    auto* d_sys = static_cast<SysDesc*>(ws(ctx, "sys", sizeof(SysDesc) * nsys));
-    auto* d_state = static_cast<SysState*>(ws(ctx, "state", sizeof(SysState) * nw * 6));
-    auto* d_px = static_cast<double*>(ws(ctx, "part_x", sizeof(double) * kPartX * size_t(nwgx_max) * nsys));
-    auto* d_pz = static_cast<double*>(ws(ctx, "part_z", sizeof(double) * size_t(nwgz_max) * nsys));
-    void* d_tmp = ws(ctx, "tmp", size_t(nfreq) * 6 * cb * nsys);
-    void* d_ar = ws(ctx, "ar", size_t(nafreq_max) * 3 * cb * nsys);
-    void* d_ap = ws(ctx, "ap", size_t(nafreq_max) * 3 * cb * nsys);
-    auto* d_out = static_cast<double*>(ws(ctx, "cout", sizeof(double) * 72 * nw));
-    auto* d_ist = static_cast<int*>(ws(ctx, "istatus", sizeof(int) * nw));
-    auto* d_cnt = static_cast<int*>(ws(ctx, "count", sizeof(int)));
-    HIPCHK(hipMemcpyAsync(d_items, idesc.data(), sizeof(ItemDesc) * nw, hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(d_sys, sdesc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, ctx->stream));
+      auto* d_items = static_cast<ItemDesc*>(ws(ctx, "items", sizeof(ItemDesc) * nw));
+      auto* d_sys = static_cast<SysDesc*>(ws(ctx, "sys", sizeof(SysDesc) * nsys));
+      auto* d_state = static_cast<SysState*>(ws(ctx, "state", sizeof(SysState) * nw * 6));
+      auto* d_px = static_cast<double*>(ws(ctx, "part_x", sizeof(double) * kPartX * size_t(nwgx_max) * nsys));
+      auto* d_pz = static_cast<double*>(ws(ctx, "part_z", sizeof(double) * size_t(nwgz_max) * nsys));
+      void* d_tmp = ws(ctx, "tmp", size_t(nfreq) * 6 * cb * nsys);
+      void* d_ar = ws(ctx, "ar", size_t(nafreq_max) * 3 * cb * nsys);
+      void* d_ap = ws(ctx, "ap", size_t(nafreq_max) * 3 * cb * nsys);
+      auto* d_out = static_cast<double*>(ws(ctx, "cout", sizeof(double) * 72 * nw));
+      auto* d_ist = static_cast<int*>(ws(ctx, "istatus", sizeof(int) * nw));
+      auto* d_cnt = static_cast<int*>(ws(ctx, "count", sizeof(int)));
+      HIPCHK(hipMemcpyAsync(d_items, idesc.data(), sizeof(ItemDesc) * nw, hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(d_sys, sdesc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, ctx->stream));
 
-    // launch arguments for a choice of z and x variants over the first ns systems
-    auto make_args = [&](int ns, int zv, int xv) {
-      GroupArgs g;
-      std::memset(&g, 0, sizeof(g));
-      g.nx = nx;
-      g.ny = ny;
-      g.nz = nz;
-      g.hx = hx;
-      g.hxp = hxp;
-      g.nsys = ns;
-      g.nyq_zero = o.nyquist;
-      g.max_iter = o.max_iter;
-      g.scheme = o.scheme;
-      g.aniso = aniso ? 1 : 0;
-      g.stall_limit = o.stall_limit;
-      g.tol2 = o.tol * o.tol;
-      const double u = P == 0 ? 5.96e-8 : 1.11e-16;
-      g.zero_rhs2 = (64.0 * u) * (64.0 * u);
-      g.ref_lam = o.scheme == 1 ? ref_lam : 0.0;
-      g.ref_mu = o.scheme == 1 ? ref_mu : 0.5;
-      for (int a = 0; a < 6; ++a)
-        for (int c = 0; c < 6; ++c) g.loads[a][c] = loads[a][c];
-      g.sys = d_sys;
-      g.items = d_items;
-      g.labels = labels;
-      g.cfield = cfield;
-      g.tmp = d_tmp;
-      g.ar = d_ar;
-      g.ap = d_ap;
-      g.tmp_stride = nfreq * 6;
-      g.a_stride = nafreq_of(vz.geom[zv]) * 3;
-      g.state = d_state;
-      g.part_x = d_px;
-      g.part_z = d_pz;
-      g.nwg_x = nwgx_of(vx.geom[xv]);
-      g.nwg_z = nwgz_of(vz.geom[zv]);
-      return g;
-    };
-    const hipStream_t st = ctx->stream;
-
-    if (need_tune && w0 == 0) {
-      // Time each distinct variant of each pass on this group's buffers, over
-      // enough systems to cover ~2^24 voxels, before the right-hand side
-      // overwrites them.  Fields are cleared first; states read as running.
-      const auto t_start = std::chrono::steady_clock::now();
-      const double vox = double(nx) * ny * nz;
-      const int items_t = int(std::min<double>(nw, std::max(1.0, std::ceil(16777216.0 / (6.0 * vox)))));
-      const int ns = items_t * 6;
-      HIPCHK(hipMemsetAsync(d_state, 0, sizeof(SysState) * ns, st));
-      HIPCHK(hipMemsetAsync(d_tmp, 0, size_t(nfreq) * 6 * cb * ns, st));
-      HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nafreq_max) * 3 * cb * ns, st));
-      HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nafreq_max) * 3 * cb * ns, st));
-      auto timeit = [&](auto&& launch) {
-        launch();
-        HIPCHK(hipEventRecord(ctx->e0, st));
-        for (int r = 0; r < 3; ++r) launch();
-        HIPCHK(hipEventRecord(ctx->e1, st));
-        HIPCHK(hipEventSynchronize(ctx->e1));
-        HIPCHK(hipGetLastError());
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, ctx->e0, ctx->e1));
-        return ms;
+      // launch arguments for a choice of z and x variants over the first ns systems
+      auto make_args = [&](int ns, int zv, int xv) {
+        GroupArgs g;
+        std::memset(&g, 0, sizeof(g));
+        g.nx = nx;
+        g.ny = ny;
+        g.nz = nz;
+        g.hx = hx;
+        g.hxp = hxp;
+        g.nsys = ns;
+        g.nyq_zero = o.nyquist;
+        g.max_iter = o.max_iter;
+        g.scheme = o.scheme;
+        g.aniso = aniso ? 1 : 0;
+        g.stall_limit = o.stall_limit;
+        g.tol2 = o.tol * o.tol;
+        const double u = P == 0 ? 5.96e-8 : 1.11e-16;
+        g.zero_rhs2 = (64.0 * u) * (64.0 * u);
+        g.ref_lam = o.scheme == 1 ? ref_lam : 0.0;
+        g.ref_mu = o.scheme == 1 ? ref_mu : 0.5;
+        for (int a = 0; a < 6; ++a)
+          for (int c = 0; c < 6; ++c) g.loads[a][c] = loads[a][c];
+        g.sys = d_sys;
+        g.items = d_items;
+        g.labels = labels;
+        g.cfield = cfield;
+        g.tmp = d_tmp;
+        g.ar = d_ar;
+        g.ap = d_ap;
+        g.tmp_stride = nfreq * 6;
+        g.a_stride = nafreq_of(vz.geom[zv]) * 3;
+        g.state = d_state;
+        g.part_x = d_px;
+        g.part_z = d_pz;
+        g.nwg_x = nwgx_of(vx.geom[xv]);
+        g.nwg_z = nwgz_of(vz.geom[zv]);
+        return g;
       };
-      float best[3] = {1e30f, 1e30f, 1e30f};
-      std::array<int, 3> pick = plan;
-      for (int v = 0; v < kNVariant; ++v) {
-        if (o.plan[0] < 0 && vz.distinct(v)) {
-          const GroupArgs gt = make_args(ns, v, 0);
-          const float t = timeit([&] {
-            vz.f[v](kOpZ, kZInvCg, &gt, st, nullptr);
-            vz.f[v](kOpZ, kZFwdCg, &gt, st, nullptr);
-          });
-          if (t < best[0]) best[0] = t, pick[0] = v;
-        }
-        if (o.plan[1] < 0 && vy.distinct(v)) {
-          const GroupArgs gt = make_args(ns, 0, 0);
-          const float t = timeit([&] {
-            vy.f[v](kOpY, +1, &gt, st, nullptr);
-            vy.f[v](kOpY, -1, &gt, st, nullptr);
-          });
-          if (t < best[1]) best[1] = t, pick[1] = v;
-        }
-        if (o.plan[2] < 0 && vx.distinct(v)) {
-          const GroupArgs gt = make_args(ns, 0, v);
-          const float t = timeit([&] { vx.f[v](kOpX, kXCg, &gt, st, nullptr); });
-          if (t < best[2]) best[2] = t, pick[2] = v;
-        }
-      }
-      plan = pick;
-      if (o.plan[0] < 0 && o.plan[1] < 0 && o.plan[2] < 0) ctx->plans[key] = plan;
-      need_tune = false;
-      ctx->setup_ms += ms_since(t_start);
-    }
-    ctx->last_plan = plan;
-    const SizeOpsFn oz = vz.f[plan[0]], oy = vy.f[plan[1]], ox = vx.f[plan[2]];
+      const hipStream_t st = ctx->stream;
 
-    HIPCHK(hipMemsetAsync(d_state, 0, sizeof(SysState) * nsys, ctx->stream));
-    HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nafreq_max) * 3 * cb * nsys, ctx->stream));
-    if (o.scheme == 1) HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nafreq_max) * 3 * cb * nsys, ctx->stream));
-    const GroupArgs g = make_args(nsys, plan[0], plan[2]);
-
-    // right-hand side b = -G * (C : E)
-    prof.run(HH_K_SETUP, [&] { ox(kOpX, kXRhs, &g, st, nullptr); });
-    prof.run(HH_K_FIN, [&] { launch_fin_x(kXRhs, g, st); });
-    if (o.scheme == 0) {
-      prof.run(HH_K_SETUP, [&] { oy(kOpY, -1, &g, st, nullptr); });
-      prof.run(HH_K_SETUP, [&] { oz(kOpZ, kZFwdRhs, &g, st, nullptr); });
-      prof.run(HH_K_FIN, [&] { launch_fin_z(kZFwdRhs, g, st); });
-    }
-    const bool cg = o.scheme == 0;
-    // one CG (or fixed-point) iteration: five passes and two finalize kernels
-    auto iteration = [&](hipStream_t s) {
-      oz(kOpZ, cg ? kZInvCg : kZInvFp, &g, s, nullptr);
-      oy(kOpY, +1, &g, s, nullptr);
-      ox(kOpX, cg ? kXCg : kXFp, &g, s, nullptr);
-      launch_fin_x(cg ? kXCg : kXFp, g, s);
-      oy(kOpY, -1, &g, s, nullptr);
-      oz(kOpZ, cg ? kZFwdCg : kZFwdFp, &g, s, nullptr);
-      launch_fin_z(cg ? kZFwdCg : kZFwdFp, g, s);
-    };
-    const bool use_graph = o.graph && !o.profile && ctx->cap;
-    int launched = 0;
-    const int limit = o.max_iter + 1;
-    while (launched < limit) {
-      const int chunk = std::min(o.chunk, limit - launched);
-      if (use_graph) {
-        // the chunk's launches depend only on their arguments: capture once, replay
-        std::string gk(reinterpret_cast<const char*>(&g), sizeof(g));
-        const std::uintptr_t tag[5] = {std::uintptr_t(chunk), std::uintptr_t(cg ? 1 : 0),
-                                       reinterpret_cast<std::uintptr_t>(oz), reinterpret_cast<std::uintptr_t>(oy),
-                                       reinterpret_cast<std::uintptr_t>(ox)};
-        gk.append(reinterpret_cast<const char*>(tag), sizeof(tag));
-        auto it = ctx->graphs.find(gk);
-        hipGraphExec_t ex = nullptr;
-        if (it != ctx->graphs.end()) {
-          ex = it->second;
-        } else {
-          const auto t_start = std::chrono::steady_clock::now();
-          hipGraph_t graph = nullptr;
-          HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-          for (int k = 0; k < chunk; ++k) iteration(ctx->cap);
-          const hipError_t ec = hipStreamEndCapture(ctx->cap, &graph);
-          const hipError_t el = hipGetLastError();
-          if (ec != hipSuccess || el != hipSuccess || !graph) {
-            if (graph) (void)hipGraphDestroy(graph);
-            fail(ctx, HH_EDEVICE, std::string("graph capture failed: ") +
-                                      hipGetErrorString(ec != hipSuccess ? ec : el));
+      if (need_tune && w0 == 0) {
+        // Time each distinct variant of each pass on this group's buffers, over
+        // enough systems to cover ~2^24 voxels, before the right-hand side
+        // overwrites them.  Fields are cleared first; states read as running.
+        const auto t_start = std::chrono::steady_clock::now();
+        const double vox = double(nx) * ny * nz;
+        const int items_t = int(std::min<double>(nw, std::max(1.0, std::ceil(16777216.0 / (6.0 * vox)))));
+        const int ns = items_t * 6;
+        HIPCHK(hipMemsetAsync(d_state, 0, sizeof(SysState) * ns, st));
+        HIPCHK(hipMemsetAsync(d_tmp, 0, size_t(nfreq) * 6 * cb * ns, st));
+        HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nafreq_max) * 3 * cb * ns, st));
+        HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nafreq_max) * 3 * cb * ns, st));
+        auto timeit = [&](auto&& launch) {
+          launch();
+          HIPCHK(hipEventRecord(ctx->e0, st));
+          for (int r = 0; r < 3; ++r) launch();
+          HIPCHK(hipEventRecord(ctx->e1, st));
+          HIPCHK(hipEventSynchronize(ctx->e1));
+          HIPCHK(hipGetLastError());
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, ctx->e0, ctx->e1));
+          return ms;
+        };
+        float best[3] = {1e30f, 1e30f, 1e30f};
+        std::array<int, 3> pick = plan;
+        for (int v = 0; v < kNVariant; ++v) {
+          if (o.plan[0] < 0 && vz.distinct(v)) {
+            const GroupArgs gt = make_args(ns, v, 0);
+            const float t = timeit([&] {
+              vz.f[v](kOpZ, kZInvCg, &gt, st, nullptr);
+              vz.f[v](kOpZ, kZFwdCg, &gt, st, nullptr);
+            });
+            if (t < best[0]) best[0] = t, pick[0] = v;
           }
-          const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-          (void)hipGraphDestroy(graph);
-          if (ei != hipSuccess) fail(ctx, HH_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
-          if (ctx->graphs.size() >= 64) clear_graphs(ctx);
-          ctx->graphs[gk] = ex;
-          ctx->setup_ms += ms_since(t_start);
+          if (o.plan[1] < 0 && vy.distinct(v)) {
+            const GroupArgs gt = make_args(ns, 0, 0);
+            const float t = timeit([&] {
+              vy.f[v](kOpY, +1, &gt, st, nullptr);
+              vy.f[v](kOpY, -1, &gt, st, nullptr);
+            });
+            if (t < best[1]) best[1] = t, pick[1] = v;
+          }
+          if (o.plan[2] < 0 && vx.distinct(v)) {
+            const GroupArgs gt = make_args(ns, 0, v);
+            const float t = timeit([&] { vx.f[v](kOpX, kXCg, &gt, st, nullptr); });
+            if (t < best[2]) best[2] = t, pick[2] = v;
+          }
         }
-        HIPCHK(hipGraphLaunch(ex, st));
-      } else {
-        for (int k = 0; k < chunk; ++k) {
-          prof.run(HH_K_ZINV, [&] { oz(kOpZ, cg ? kZInvCg : kZInvFp, &g, st, nullptr); });
-          prof.run(HH_K_YINV, [&] { oy(kOpY, +1, &g, st, nullptr); });
-          prof.run(HH_K_X, [&] { ox(kOpX, cg ? kXCg : kXFp, &g, st, nullptr); });
-          prof.run(HH_K_FIN, [&] { launch_fin_x(cg ? kXCg : kXFp, g, st); });
-          prof.run(HH_K_YFWD, [&] { oy(kOpY, -1, &g, st, nullptr); });
-          prof.run(HH_K_ZFWD, [&] { oz(kOpZ, cg ? kZFwdCg : kZFwdFp, &g, st, nullptr); });
-          prof.run(HH_K_FIN, [&] { launch_fin_z(cg ? kZFwdCg : kZFwdFp, g, st); });
-        }
+        plan = pick;
+        if (o.plan[0] < 0 && o.plan[1] < 0 && o.plan[2] < 0) ctx->plans[key] = plan;
+        need_tune = false;
+        ctx->setup_ms += ms_since(t_start);
       }
-      launched += chunk;
+      ctx->last_plan = plan;
+      const SizeOpsFn oz = vz.f[plan[0]], oy = vy.f[plan[1]], ox = vx.f[plan[2]];
+
+      HIPCHK(hipMemsetAsync(d_state, 0, sizeof(SysState) * nsys, ctx->stream));
+      HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nafreq_max) * 3 * cb * nsys, ctx->stream));
+      if (o.scheme == 1) HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nafreq_max) * 3 * cb * nsys, ctx->stream));
+      const GroupArgs g = make_args(nsys, plan[0], plan[2]);
+
+      // right-hand side b = -G * (C : E)
+      prof.run(HH_K_SETUP, [&] { ox(kOpX, kXRhs, &g, st, nullptr); });
+      prof.run(HH_K_FIN, [&] { launch_fin_x(kXRhs, g, st); });
+      if (o.scheme == 0) {
+        prof.run(HH_K_SETUP, [&] { oy(kOpY, -1, &g, st, nullptr); });
+        prof.run(HH_K_SETUP, [&] { oz(kOpZ, kZFwdRhs, &g, st, nullptr); });
+        prof.run(HH_K_FIN, [&] { launch_fin_z(kZFwdRhs, g, st); });
+      }
+      const bool cg = o.scheme == 0;
+      // one CG (or fixed-point) iteration: five passes and two finalize kernels
+      auto iteration = [&](hipStream_t s) {
+        oz(kOpZ, cg ? kZInvCg : kZInvFp, &g, s, nullptr);
+        oy(kOpY, +1, &g, s, nullptr);
+        ox(kOpX, cg ? kXCg : kXFp, &g, s, nullptr);
+        launch_fin_x(cg ? kXCg : kXFp, g, s);
+        oy(kOpY, -1, &g, s, nullptr);
+        oz(kOpZ, cg ? kZFwdCg : kZFwdFp, &g, s, nullptr);
+        launch_fin_z(cg ? kZFwdCg : kZFwdFp, g, s);
+      };
+      const bool use_graph = o.graph && !o.profile && ctx->cap;
+      int launched = 0;
+      const int limit = o.max_iter + 1;
+      while (launched < limit) {
+        const int chunk = std::min(o.chunk, limit - launched);
+        if (use_graph) {
+          // the chunk's launches depend only on their arguments: capture once, replay
+          std::string gk(reinterpret_cast<const char*>(&g), sizeof(g));
+          const std::uintptr_t tag[5] = {std::uintptr_t(chunk), std::uintptr_t(cg ? 1 : 0),
+                                         reinterpret_cast<std::uintptr_t>(oz), reinterpret_cast<std::uintptr_t>(oy),
+                                         reinterpret_cast<std::uintptr_t>(ox)};
+          gk.append(reinterpret_cast<const char*>(tag), sizeof(tag));
+          auto it = ctx->graphs.find(gk);
+          hipGraphExec_t ex = nullptr;
+          if (it != ctx->graphs.end()) {
+            ex = it->second;
+          } else {
+            const auto t_start = std::chrono::steady_clock::now();
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < chunk; ++k) iteration(ctx->cap);
+            const hipError_t ec = hipStreamEndCapture(ctx->cap, &graph);
+            const hipError_t el = hipGetLastError();
+            if (ec != hipSuccess || el != hipSuccess || !graph) {
+              if (graph) (void)hipGraphDestroy(graph);
+              fail(ctx, HH_EDEVICE, std::string("graph capture failed: ") +
+                                        hipGetErrorString(ec != hipSuccess ? ec : el));
+            }
+            const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess)
+              fail(ctx, HH_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
+            if (ctx->graphs.size() >= 64) clear_graphs(ctx);
+            ctx->graphs[gk] = ex;
+            ctx->setup_ms += ms_since(t_start);
+          }
+          HIPCHK(hipGraphLaunch(ex, st));
+        } else {
+          for (int k = 0; k < chunk; ++k) {
+            prof.run(HH_K_ZINV, [&] { oz(kOpZ, cg ? kZInvCg : kZInvFp, &g, st, nullptr); });
+            prof.run(HH_K_YINV, [&] { oy(kOpY, +1, &g, st, nullptr); });
+            prof.run(HH_K_X, [&] { ox(kOpX, cg ? kXCg : kXFp, &g, st, nullptr); });
+            prof.run(HH_K_FIN, [&] { launch_fin_x(cg ? kXCg : kXFp, g, st); });
+            prof.run(HH_K_YFWD, [&] { oy(kOpY, -1, &g, st, nullptr); });
+            prof.run(HH_K_ZFWD, [&] { oz(kOpZ, cg ? kZFwdCg : kZFwdFp, &g, st, nullptr); });
+            prof.run(HH_K_FIN, [&] { launch_fin_z(cg ? kZFwdCg : kZFwdFp, g, st); });
+          }
+        }
+        launched += chunk;
+        HIPCHK(hipGetLastError());
+        launch_count_running(d_state, nsys, d_cnt, st);
+        int running = 0;
+        HIPCHK(hipMemcpyAsync(&running, d_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        prof.flush();
+        if (running == 0) break;
+      }
+      if (la < 6) {
+        // keep this wave's final states; after the last load, all six go back
+        // to the state array, in load order, for the stiffness of the image
+        HIPCHK(hipMemcpyAsync(split_state.data() + a0, d_state, sizeof(SysState) * la, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (a0 + la < 6) continue;
+        HIPCHK(hipMemcpyAsync(d_state, split_state.data(), sizeof(SysState) * 6, hipMemcpyHostToDevice, st));
+      }
+      void* cf_out = nullptr;
+      if (cfield_out) cf_out = static_cast<char*>(cfield_out) + size_t(w0) * 21 * (P == 0 ? 4 : 8);
+      prof.run(HH_K_OTHER, [&] { launch_stiffness(P, d_state, nw, d_out, cf_out, d_ist, st); });
       HIPCHK(hipGetLastError());
-      launch_count_running(d_state, nsys, d_cnt, st);
-      int running = 0;
-      HIPCHK(hipMemcpyAsync(&running, d_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+      std::vector<SysState> hst(size_t(nw) * 6);
+      std::vector<int> ist(nw);
+      HIPCHK(hipMemcpyAsync(res.C72.data() + size_t(w0) * 72, d_out, sizeof(double) * 72 * nw, hipMemcpyDeviceToHost,
+                            st));
+      HIPCHK(hipMemcpyAsync(hst.data(), d_state, sizeof(SysState) * nw * 6, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(ist.data(), d_ist, sizeof(int) * nw, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       prof.flush();
-      if (running == 0) break;
-    }
-    if (la < 6) {
-      // keep this wave's final states; after the last load, all six go back
-      // to the state array, in load order, for the stiffness of the image
-      HIPCHK(hipMemcpyAsync(split_state.data() + a0, d_state, sizeof(SysState) * la, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (a0 + la < 6) continue;
-      HIPCHK(hipMemcpyAsync(d_state, split_state.data(), sizeof(SysState) * 6, hipMemcpyHostToDevice, st));
-    }
-    void* cf_out = nullptr;
-    if (cfield_out) cf_out = static_cast<char*>(cfield_out) + size_t(w0) * 21 * (P == 0 ? 4 : 8);
-    prof.run(HH_K_OTHER, [&] { launch_stiffness(P, d_state, nw, d_out, cf_out, d_ist, st); });
-    HIPCHK(hipGetLastError());
-    std::vector<SysState> hst(size_t(nw) * 6);
-    std::vector<int> ist(nw);
-    HIPCHK(hipMemcpyAsync(res.C72.data() + size_t(w0) * 72, d_out, sizeof(double) * 72 * nw, hipMemcpyDeviceToHost,
-                          st));
-    HIPCHK(hipMemcpyAsync(hst.data(), d_state, sizeof(SysState) * nw * 6, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ist.data(), d_ist, sizeof(int) * nw, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    prof.flush();
-    const double vox = double(nx) * ny * nz;
-    for (int i = 0; i < nw; ++i) {
-      int code = status_code(ist[i]);
-      for (int a = 0; a < 6; ++a) {
-        const SysState& s = hst[i * 6 + a];
-        res.iters[size_t(w0 + i) * 6 + a] = s.iter;
-        res.rel[size_t(w0 + i) * 6 + a] = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
-        res.voxel_iters += vox * s.iter;
-        code = worse(code, status_code(s.status == kRunning ? kNoConv : s.status));
+      const double vox = double(nx) * ny * nz;
+      for (int i = 0; i < nw; ++i) {
+        int code = status_code(ist[i]);
+        for (int a = 0; a < 6; ++a) {
+          const SysState& s = hst[i * 6 + a];
+          res.iters[size_t(w0 + i) * 6 + a] = s.iter;
+          res.rel[size_t(w0 + i) * 6 + a] = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
+          res.voxel_iters += vox * s.iter;
+          code = worse(code, status_code(s.status == kRunning ? kNoConv : s.status));
+        }
+        res.status[w0 + i] = code;
       }
-      res.status[w0 + i] = code;
     }
-   }
   }
   return res;
 }
