@@ -141,6 +141,9 @@ int hh_size_supported(int n, int precision);
  *   Omega_R inside the periodic box; NULL = the whole box.
  * C_out: symmetrized (C + C^T)/2 of C_R = Sigma_R E_R^-1, 36 doubles.
  * C_raw: the raw C_R (may be NULL).  report: may be NULL.
+ * The six load cases run together; when their six systems (about 52 GB
+ * each at 1024^3 in FP32) do not fit in device memory they run a few at a
+ * time (hh_opts.loads_per_wave), with the same result.
  */
 int hh_homogenize(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, int labels_on_device,
                   const hh_phase *phases, int nphase, const double *loads, const int *region,
