@@ -80,21 +80,40 @@ def profiled_traffic(kernel, n):
     return val if sha == kernel_source_hash() else None
 
 
-def error_vs_stored_oracle(n, C):
-    """Relative Frobenius error of the timed result's stiffness, Mandel-scaled
-    (shear rows and columns times sqrt 2), against the FP64 oracle's result
-    for the same seeded image at tol 1e-9, stored under tests/golden by a
-    script that runs only the oracle.  None for sizes without a stored result."""
-    import numpy as np
-    path = os.path.join(ROOT, "tests", "golden", "four_phase_%d_seed1.json" % n)
-    if not os.path.exists(path):
-        return None
-    ref = json.load(open(path))
+def _mandel_rel_error(C, Cref):
+    """||C - Cref||_F / ||Cref||_F with shear rows and columns times sqrt 2."""
     s = np.array([1.0, 1.0, 1.0, 2.0 ** 0.5, 2.0 ** 0.5, 2.0 ** 0.5])
     M = np.outer(s, s)
-    Cr = np.array(ref["C_sym"])
-    e = float(np.linalg.norm((np.asarray(C) - Cr) * M) / np.linalg.norm(Cr * M))
-    return {"rel_error": e, "bound": 1e-5, "oracle": "FP64 oracle at tol %g (%s)" % (ref["tol"], ref["image"])}
+    Cref = np.asarray(Cref)
+    return float(np.linalg.norm((np.asarray(C) - Cref) * M) / np.linalg.norm(Cref * M))
+
+
+def _stored_oracle(name):
+    """FP64 oracle results stored under tests/golden by a script that runs only
+    the oracle and the seeded generator (tol 1e-9); None where absent."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def error_vs_stored_oracle(n, C):
+    """Relative error of the timed result's stiffness against the stored FP64
+    oracle result for the same seeded image.  None for sizes without one."""
+    ref = _stored_oracle("four_phase_%d_seed1.json" % n)
+    if ref is None:
+        return None
+    return {"rel_error": _mandel_rel_error(C, ref["C_sym"]), "bound": 1e-5,
+            "oracle": "FP64 oracle at tol %g (%s)" % (ref["tol"], ref["image"])}
+
+
+def sampled_error_vs_stored_oracle(name, C_of_item):
+    """Largest relative error over the sampled items of a stored FP64 oracle
+    result; C_of_item(index) gives the GPU stiffness of an item."""
+    ref = _stored_oracle(name)
+    if ref is None:
+        return None
+    errs = [_mandel_rel_error(C_of_item(it["index"]), it["C_sym"]) for it in ref["items"]]
+    return {"max_rel_error": max(errs), "items": len(errs), "bound": 1e-5,
+            "oracle": "FP64 oracle at tol %g, %s" % (ref["tol"], name)}
 
 
 def cpu_baseline(lab, phases, iters=2):
@@ -133,7 +152,7 @@ def bench_hier(args):
         C, Cs, rep = ctx.hierarchical(dev, phases, n, 8, tol=1e-6)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        out[n] = dict(C=C, seconds=dt, items=rep["items"], voxel_iters=rep["voxel_iters"],
+        out[n] = dict(C=C, Cs=Cs, seconds=dt, items=rep["items"], voxel_iters=rep["voxel_iters"],
                       level2_iters=rep["iters"])
         print("bench: hier n=%d pad 8: %d subimages in %.3f s, %.3e voxel-iter/s" %
               (n, rep["items"], dt, rep["voxel_iters"] / dt), file=sys.stderr, flush=True)
@@ -163,6 +182,9 @@ def bench_hier(args):
                       "voxel_iters_per_s": out[n]["voxel_iters"] / out[n]["seconds"],
                       "K_G": hh.moduli(out[n]["C"])} for n in ns},
         "richardson": {"K_inf": K, "G_inf": G},
+        "error_vs_oracle": (sampled_error_vs_stored_oracle("four_phase_512_n64_p8_items.json",
+                                                           lambda i: _full36(out[64]["Cs"][i]))
+                            if N == 512 else None),
         "three_levels": {"levels": [[32, 8], [2, 1]], "K_G": [K3, G3], "seconds": dt3,
                          "two_level_K_G": [K2, G2]},
     }
@@ -377,6 +399,8 @@ def bench_uneven(args):
                                % (len(imgs), sizes)},
         "subimages_per_s": len(imgs) / dt, "seconds": dt, "status_ok": int((st == 0).sum()),
         "mean_iters": float(iters.mean()),
+        "error_vs_oracle": (sampled_error_vs_stored_oracle("uneven_2048_items.json", lambda i: C[i])
+                            if len(imgs) == 2048 else None),
     }
     print(json.dumps(line), flush=True)
     ctx.close()
