@@ -207,7 +207,8 @@ def bench_study(args):
     image with a correlation length near the paper's rocks (smoothing sigma 8,
     seed 5), homogenized directly (the reference) and by the two-level scheme
     for subimage sizes 50, 60, 75, 100 with 0, 5 and 10 voxels of padding per
-    side; the arithmetic mean of the subimage stiffnesses beside each, and the
+    side (with --study-size 1024: 64, 128, 256 and 0, 8, 16 voxels, boxes of
+    compiled lengths only); the arithmetic mean of the subimage stiffnesses beside each, and the
     n^-1 extrapolation per padding.  Only sizes with at least three subimages
     per axis: with two, the intermediate image has only the mean and Nyquist
     frequencies, and its solve returns the arithmetic mean."""
@@ -224,10 +225,19 @@ def bench_study(args):
     Kr, Gr = hh.moduli(ref.C)
     print("bench: study %d^3 reference K %.4f G %.4f in %.2f s (iters %s)" % (N, Kr, Gr, t_ref, ref.report["iters"]),
           file=sys.stderr, flush=True)
-    ns = [n for n in (50, 60, 75, 100) if N % n == 0 and N // n >= 3]
+    # subimage sizes and paddings: the 300^3 stand-in uses sizes near the paper's
+    # (3 to 6 per axis); a power-of-two image (1024^3, whose plain solve is the
+    # paper's brute-force scale) uses 64, 128, 256 with 0, 8, 16 voxels
+    if N % 256 == 0:
+        cand, pads = (64, 128, 256), (0, 8, 16)
+    else:
+        cand, pads = (50, 60, 75, 100), (0, 5, 10)
+    ns = [n for n in cand if N % n == 0 and N // n >= 3]
     runs = {}
-    for pad in (0, 5, 10):
+    for pad in pads:
         for n in ns:
+            if not hh.size_supported(n + 2 * pad, 0):
+                continue  # box length without compiled passes
             t = time.perf_counter()
             C, Cs, rep = ctx.hierarchical(lab, phases, n, pad, tol=1e-6)
             dt = time.perf_counter() - t
@@ -238,16 +248,20 @@ def bench_study(args):
                   "G %+.3f %%; %.2f s" % (n, pad, K, 100 * (K / Kr - 1), G, 100 * (G / Gr - 1),
                                          100 * (Ka / Kr - 1), 100 * (Ga / Gr - 1), dt), file=sys.stderr, flush=True)
     fits = {}
-    for pad in (0, 5, 10):
-        Cinf, _ = hh.richardson(ns, [runs[(n, pad)]["C"] for n in ns])
+    for pad in pads:
+        nsp = [n for n in ns if (n, pad) in runs]
+        if len(nsp) < 2:
+            continue
+        Cinf, _ = hh.richardson(nsp, [runs[(n, pad)]["C"] for n in nsp])
         Ki, Gi = hh.moduli(Cinf)
-        fits[pad] = {"K_inf": Ki, "G_inf": Gi, "K_err_pct": 100 * (Ki / Kr - 1), "G_err_pct": 100 * (Gi / Gr - 1)}
+        fits[pad] = {"n": nsp, "K_inf": Ki, "G_inf": Gi, "K_err_pct": 100 * (Ki / Kr - 1),
+                     "G_err_pct": 100 * (Gi / Gr - 1)}
     total = time.perf_counter() - t0
     line = {
-        "metric": "seconds for the two-level error study (reference solve + 12 hierarchies)",
+        "metric": "seconds for the two-level error study (reference solve + %d hierarchies)" % len(runs),
         "value": total, "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "error study, %d^3 four-phase (sigma %g, seed %d), n in %s, pad 0/5/10, tol 1e-6"
-                               % (N, sigma, seed, ns)},
+        "config": {"workload": "error study, %d^3 four-phase (sigma %g, seed %d), n in %s, pad %s, tol 1e-6"
+                               % (N, sigma, seed, ns, "/".join(str(p) for p in pads))},
         "reference": {"K": Kr, "G": Gr, "seconds": t_ref, "iters": ref.report["iters"]},
         "runs": [{"n": n, "pad": pad, "K_err_pct": 100 * (r["K"] / Kr - 1), "G_err_pct": 100 * (r["G"] / Gr - 1),
                   "K_mean_err_pct": 100 * (r["K_am"] / Kr - 1), "G_mean_err_pct": 100 * (r["G_am"] / Gr - 1),
