@@ -242,7 +242,7 @@ def bench_study(args):
             C, Cs, rep = ctx.hierarchical(lab, phases, n, pad, tol=1e-6)
             dt = time.perf_counter() - t
             K, G = hh.moduli(C)
-            Ka, Ga = hh.moduli(_full36(Cs.reshape(-1, 21).mean(axis=0)))
+            Ka, Ga = hh.mean_moduli(Cs)
             runs[(n, pad)] = dict(C=C, K=K, G=G, K_am=Ka, G_am=Ga, seconds=dt)
             print("bench: study n=%d pad %d: K %.4f (%+.3f %%) G %.4f (%+.3f %%); mean of subimages K %+.3f %% "
                   "G %+.3f %%; %.2f s" % (n, pad, K, 100 * (K / Kr - 1), G, 100 * (G / Gr - 1),

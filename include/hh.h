@@ -302,6 +302,12 @@ int hh_richardson(const int *n, const double *C, int m, double C_inf[36], double
  * G = (C11+C22+C33 - (C12+C13+C23) + 3(C44+C55+C66))/15.  Host only. */
 int hh_moduli(const double C[36], double *K, double *G);
 
+/* The arithmetic-mean comparator of Sec. 5 (AM): the mean over m subimages
+ * of the Voigt bulk and shear moduli (as hh_moduli) of their stiffnesses.
+ * C_sub: m x 21 upper-triangle components, as hh_hierarchical writes them.
+ * Host only; HH_EINVAL for m < 1 or NULL pointers. */
+int hh_mean_moduli(const double *C_sub, long long m, double *K, double *G);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,12 @@ matrices from the DFT matrix and the wave numbers (with the same Nyquist
 reading as the oracle: the Nyquist wavenumber component is zero).  The normal
 equations B^T C B u = -B^T C E are solved by least squares (their null space
 holds rigid translations and the Nyquist modes).  Tiny grids only.
+
+Under the other even-grid reading (``nyquist='zero'``: the operator vanishes
+at every frequency with a Nyquist component) the trial displacements are
+restricted instead: u = Phi v, with Phi the real filter that removes every
+Fourier mode having a Nyquist index on some axis, so the strains range over
+exactly the compatible fields without support on those frequencies.
 """
 from __future__ import annotations
 
@@ -33,8 +39,27 @@ def derivative_matrix(n, nyquist="component"):
     return D.real
 
 
+def nyquist_filter(n):
+    """Real n x n projector onto the trigonometric modes of an n-point periodic
+    grid other than the Nyquist mode (the identity for odd n)."""
+    j = np.arange(n)
+    F = np.exp(-2j * np.pi * np.outer(j, j) / n)
+    m = np.rint(np.fft.fftfreq(n) * n)
+    keep = ~((n % 2 == 0) & (np.abs(m) == n // 2))
+    Phi = (F.conj().T / n) @ np.diag(keep.astype(float)) @ F
+    if np.abs(Phi.imag).max() > 1e-10:
+        raise ValueError("filter not real")
+    return Phi.real
+
+
 def gradient_matrices(shape, nyquist="component"):
-    """(Dx, Dy, Dz) acting on fields flattened in C order [z][y][x]."""
+    """(Dx, Dy, Dz) acting on fields flattened in C order [z][y][x].  With
+    nyquist='zero' each derivative acts on the Nyquist-filtered field."""
+    if nyquist == "zero":
+        nz, ny, nx = shape
+        Fz, Fy, Fx = (nyquist_filter(n) for n in (nz, ny, nx))
+        dz, dy, dx = (derivative_matrix(n) @ f for n, f in ((nz, Fz), (ny, Fy), (nx, Fx)))
+        return (np.kron(Fz, np.kron(Fy, dx)), np.kron(Fz, np.kron(dy, Fx)), np.kron(dz, np.kron(Fy, Fx)))
     nz, ny, nx = shape
     Iz, Iy, Ix = np.eye(nz), np.eye(ny), np.eye(nx)
     Dx = np.kron(Iz, np.kron(Iy, derivative_matrix(nx, nyquist)))

@@ -1334,4 +1334,22 @@ int hh_moduli(const double C[36], double* K, double* G) {
   return HH_OK;
 }
 
+int hh_mean_moduli(const double* C_sub, long long m, double* K, double* G) {
+  if (!C_sub || !K || !G || m < 1) return HH_EINVAL;
+  // upper-triangle index of (i, j), i <= j, row-major
+  auto at = [](int i, int j) { return i * 6 - i * (i - 1) / 2 + (j - i); };
+  double sk = 0.0, sg = 0.0;
+  for (long long q = 0; q < m; ++q) {
+    const double* c = C_sub + q * 21;
+    const double d = c[at(0, 0)] + c[at(1, 1)] + c[at(2, 2)];
+    const double o = c[at(0, 1)] + c[at(0, 2)] + c[at(1, 2)];
+    const double s = c[at(3, 3)] + c[at(4, 4)] + c[at(5, 5)];
+    sk += (d + 2.0 * o) / 9.0;
+    sg += (d - o + 3.0 * s) / 15.0;
+  }
+  *K = sk / double(m);
+  *G = sg / double(m);
+  return HH_OK;
+}
+
 }  // extern "C"

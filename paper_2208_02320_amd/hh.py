@@ -34,7 +34,7 @@ SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_la
            "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling",
            "hh_net_get_fraction_scaling", "hh_net_forward",
            "hh_net_gradient", "hh_net_train_step", "hh_net_predict", "hh_hierarchical_surrogate",
-           "hh_richardson", "hh_moduli")
+           "hh_richardson", "hh_moduli", "hh_mean_moduli")
 
 
 class HHError(RuntimeError):
@@ -126,6 +126,7 @@ def load_library(path=LIB_PATH):
                                               ct.POINTER(Opts), DP, DP, ct.POINTER(I), ct.POINTER(Report)]
     lib.hh_richardson.argtypes = [ct.POINTER(I), DP, I, DP, DP]
     lib.hh_moduli.argtypes = [DP, DP, DP]
+    lib.hh_mean_moduli.argtypes = [DP, LL, DP, DP]
     for name in SYMBOLS:
         getattr(lib, name)
     _lib = lib
@@ -541,6 +542,18 @@ def moduli(C):
     rc = lib.hh_moduli(_dptr(C), ct.byref(K), ct.byref(G))
     if rc != HH_OK:
         raise HHError(rc, "hh_moduli")
+    return K.value, G.value
+
+
+def mean_moduli(C_sub21):
+    """Arithmetic mean of the subimages' Voigt (K, G) (the AM comparator of
+    Sec. 5), from the m x 21 upper-triangle stiffnesses of hh_hierarchical."""
+    lib = load_library()
+    c = np.ascontiguousarray(np.asarray(C_sub21, dtype=np.float64).reshape(-1, 21))
+    K, G = ct.c_double(), ct.c_double()
+    rc = lib.hh_mean_moduli(_dptr(c), c.shape[0], ct.byref(K), ct.byref(G))
+    if rc != HH_OK:
+        raise HHError(rc, "hh_mean_moduli")
     return K.value, G.value
 
 

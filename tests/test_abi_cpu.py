@@ -77,6 +77,19 @@ def test_richardson_host_entry_point():
         hh.richardson([32, 32], Cs[:2])
 
 
+def test_mean_moduli_host_entry_point():
+    """The AM comparator of Sec. 5 equals the oracle's arithmetic mean of the
+    subimage moduli."""
+    from paper_2208_02320_amd import hh
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((27, 6, 6))
+    C = np.einsum("nij,nkj->nik", A, A) + 6 * np.eye(6)
+    K, G = hh.mean_moduli(np.stack([hier.to21(c) for c in C]))
+    assert np.allclose([K, G], hier.arithmetic_mean_moduli(C), rtol=1e-14)
+    with pytest.raises(hh.HHError):
+        hh.mean_moduli(np.zeros((0, 21)))
+
+
 def test_context_needs_gpu():
     import torch
     from paper_2208_02320_amd import hh
