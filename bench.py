@@ -117,20 +117,28 @@ def sampled_error_vs_stored_oracle(name, C_of_item):
 
 
 def cpu_baseline(lab, phases, iters=2):
-    """FP64 oracle on a bounded sample: load 1 of the same image, the right-hand
-    side plus the first ``iters`` CG iterations."""
+    """FP64 oracle on a bounded sample of the same workload, in the form the GPU
+    solves (symmetric projection, CG): load 1 of the same image, its right-hand
+    side and the first ``iters`` CG iterations, once with one FFT thread and
+    once with all host threads.  voxel-iters/s counts the CG iterations."""
     from oracle import galerkin as g
     med = g.IsotropicMedium(lab, phases)
-    t = time.perf_counter()
-    _, info = g.solve_load(med, g.unit_strain(0), tol=1e-6, maxit=iters, form="paper9")
-    dt = time.perf_counter() - t
     V = float(lab.size)
-    return {"value": V * info.iters / dt, "unit": "voxel-iters/s", "cores": g.workers(),
-            "kind": "oracle",
-            "sample": "FP64 oracle (paper's 9-component projection, scipy.fft with %d workers), "
-                      "load 1 of the same %s image: right-hand side and the first %d CG "
-                      "iterations, %.1f s" % (g.workers(), "x".join(map(str, lab.shape)),
-                                               info.iters, dt)}
+    allw = g.workers()
+    runs = {}
+    for w in (1, allw):
+        g.set_workers(w)
+        t = time.perf_counter()
+        _, info = g.solve_load(med, g.unit_strain(0), tol=1e-6, maxit=iters, form="sym6")
+        dt = time.perf_counter() - t
+        runs[w] = (V * info.iters / dt, dt, info.iters)
+    g.set_workers(allw)
+    return {"value": runs[allw][0], "unit": "voxel-iters/s", "cores": allw, "kind": "oracle",
+            "value_1_core": runs[1][0],
+            "sample": "FP64 oracle (symmetric projection, CG, scipy.fft), load 1 of the same %s image: right-hand "
+                      "side and the first %d CG iterations, %.1f s with %d FFT threads and %.1f s with 1; the "
+                      "time includes the right-hand side" % ("x".join(map(str, lab.shape)), runs[allw][2],
+                                                            runs[allw][1], allw, runs[1][1])}
 
 
 def bench_hier(args):
@@ -145,7 +153,8 @@ def bench_hier(args):
     dev = torch.from_numpy(lab).to("cuda:0")
     ctx = hh.Context(0)
     out = {}
-    for n in (32, 64, 128):
+    ns = [int(x) for x in args.hier_ns.split(",")]
+    for n in ns:
         ctx.hierarchical(dev, phases, n, 8, tol=1e-6)  # warm-up (workspace, code objects)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -156,26 +165,30 @@ def bench_hier(args):
                       level2_iters=rep["iters"])
         print("bench: hier n=%d pad 8: %d subimages in %.3f s, %.3e voxel-iter/s" %
               (n, rep["items"], dt, rep["voxel_iters"] / dt), file=sys.stderr, flush=True)
-    ns = [32, 64, 128]
-    Cinf, slope = hh.richardson(ns, [out[n]["C"] for n in ns])
-    K, G = hh.moduli(Cinf)
-    # three levels: the 16^3 intermediate image of n = 32 cut again into 2^3
-    # blocks with 1 voxel of surround, then the 8^3 image
-    t = time.perf_counter()
-    C3, rep3 = ctx.hierarchical_levels(dev, phases, [(32, 8), (2, 1)], tol=1e-6)
-    torch.cuda.synchronize()
-    dt3 = time.perf_counter() - t
-    K3, G3 = hh.moduli(C3)
-    K2, G2 = hh.moduli(out[32]["C"])
-    print("bench: three levels (32 pad 8, 2 pad 1): K %.4f G %.4f (two levels: K %.4f G %.4f) in %.3f s" %
-          (K3, G3, K2, G2, dt3), file=sys.stderr, flush=True)
-    r = out[64]
+    K = G = None
+    if len(ns) >= 2:
+        Cinf, slope = hh.richardson(ns, [out[n]["C"] for n in ns])
+        K, G = hh.moduli(Cinf)
+    three = None
+    if not args.no_levels and 32 in out:
+        # three levels: the intermediate image of n = 32 cut again into 2^3
+        # blocks with 1 voxel of surround, then the last image
+        t = time.perf_counter()
+        C3, rep3 = ctx.hierarchical_levels(dev, phases, [(32, 8), (2, 1)], tol=1e-6)
+        torch.cuda.synchronize()
+        dt3 = time.perf_counter() - t
+        K3, G3 = hh.moduli(C3)
+        K2, G2 = hh.moduli(out[32]["C"])
+        print("bench: three levels (32 pad 8, 2 pad 1): K %.4f G %.4f (two levels: K %.4f G %.4f) in %.3f s" %
+              (K3, G3, K2, G2, dt3), file=sys.stderr, flush=True)
+        three = {"levels": [[32, 8], [2, 1]], "K_G": [K3, G3], "seconds": dt3, "two_level_K_G": [K2, G2]}
+    r = out[64] if 64 in out else out[ns[0]]
     line = {
         "metric": "subimages/s of the batched FFT solve in the two-level scheme",
         "value": r["items"] / r["seconds"], "unit": "subimages/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "hierarchical %d^3 four-phase, n = 64, pad 8 (80^3 boxes), 6 loads, tol 1e-6"
-                               % N},
+        "config": {"workload": "hierarchical %d^3 four-phase, n = %d, pad 8 (%d^3 boxes), 6 loads, tol 1e-6"
+                               % (N, 64 if 64 in out else ns[0], (64 if 64 in out else ns[0]) + 16)},
         "voxel_iters_per_s": r["voxel_iters"] / r["seconds"], "seconds": r["seconds"],
         "per_n": {n: {"subimages": out[n]["items"], "seconds": round(out[n]["seconds"], 4),
                       "subimages_per_s": round(out[n]["items"] / out[n]["seconds"], 2),
@@ -184,9 +197,8 @@ def bench_hier(args):
         "richardson": {"K_inf": K, "G_inf": G},
         "error_vs_oracle": (sampled_error_vs_stored_oracle("four_phase_512_n64_p8_items.json",
                                                            lambda i: _full36(out[64]["Cs"][i]))
-                            if N == 512 else None),
-        "three_levels": {"levels": [[32, 8], [2, 1]], "K_G": [K3, G3], "seconds": dt3,
-                         "two_level_K_G": [K2, G2]},
+                            if N == 512 and 64 in out else None),
+        "three_levels": three,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -402,6 +414,13 @@ def bench_uneven(args):
     C, Craw, st, iters, rep = ctx.homogenize_batch(shapes, phs, labels_pack=pack, tol=1e-6)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
+    # the same batch with its shape groups one after another (one lane)
+    t = time.perf_counter()
+    C1 = ctx.homogenize_batch(shapes, phs, labels_pack=pack, tol=1e-6, lanes=1)[0]
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t
+    print("bench: uneven %d items: %.3f s concurrent groups, %.3f s one group at a time; identical: %s" %
+          (len(imgs), dt, dt_seq, bool(np.array_equal(C, C1))), file=sys.stderr, flush=True)
     sizes = {}
     for im in imgs:
         sizes[im.shape[0]] = sizes.get(im.shape[0], 0) + 1
@@ -412,6 +431,7 @@ def bench_uneven(args):
         "config": {"workload": "%d subimages, sizes %s, 2-4 phases, 6 loads, tol 1e-6"
                                % (len(imgs), sizes)},
         "subimages_per_s": len(imgs) / dt, "seconds": dt, "status_ok": int((st == 0).sum()),
+        "seconds_one_group_at_a_time": dt_seq, "identical_to_one_group_at_a_time": bool(np.array_equal(C, C1)),
         "mean_iters": float(iters.mean()),
         "error_vs_oracle": (sampled_error_vs_stored_oracle("uneven_2048_items.json", lambda i: C[i])
                             if len(imgs) == 2048 else None),
@@ -590,6 +610,8 @@ def main():
     ap.add_argument("--spread-tol", type=float, default=0.02)
     ap.add_argument("--bound-tol", type=float, default=0.0)
     ap.add_argument("--hier-size", type=int, default=512)
+    ap.add_argument("--hier-ns", default="32,64,128", help="subimage sizes of the hier workload")
+    ap.add_argument("--no-levels", action="store_true", help="hier workload without the three-level run")
     ap.add_argument("--study-size", type=int, default=300)
     ap.add_argument("--timing-size", type=int, default=900)
     ap.add_argument("--uneven-count", type=int, default=2048)

@@ -63,7 +63,10 @@ typedef struct {
 /* Solver options.  hh_default_opts() fills the defaults given here. */
 typedef struct {
   double tol;        /* stop when ||r|| <= tol ||b||, r = -G*(C:(E+eps*)); default 1e-6 */
-  int max_iter;      /* per load case; default 1000 */
+  int max_iter;      /* per load case; 0 (default) = from the phase contrast kappa (largest
+                        over smallest eigenvalue 3K or 2G of the phase stiffnesses):
+                        max(1000, ceil(sqrt(kappa) ln(2 / tol))), twice the classical
+                        conjugate-gradient bound; 1000 for anisotropic voxels */
   int scheme;        /* 0: conjugate gradients (Appendix A); 1: basic fixed point with
                         reference medium (ref_lambda, ref_mu); default 0 */
   int precision;     /* 0: FP32 fields and FFTs, FP64 reductions/scalars/averages;
@@ -72,7 +75,8 @@ typedef struct {
                         1 = operator zero at every frequency with a Nyquist component */
   int profile;       /* 1: time every kernel class with HIP events (hh_report.kernel_ms) */
   int stall_limit;   /* iterations without a new smallest residual before
-                        HH_ESTAGNATED; default 100 */
+                        HH_ESTAGNATED; 0 (default) = max(100, ceil(sqrt(kappa))),
+                        100 for anisotropic voxels */
   int chunk;         /* iterations launched between convergence polls; default 8 */
   double ref_lambda, ref_mu; /* basic scheme reference medium; <= 0: mid-range of the phases */
   int tune;          /* FP32: 1 = the first solve of a shape in a context times the compiled
@@ -87,6 +91,17 @@ typedef struct {
                         a time (the others wait for device memory), and images then run
                         one at a time; 0 = all six together unless the six systems of one
                         image do not fit in device memory, then as many as fit; default 0 */
+  int retry;         /* 1 (default): with FP32 fields, an image of isotropic phases whose
+                        solve stops with HH_ESTAGNATED (the FP32 floor, e.g. at extreme
+                        phase contrast) is solved again with FP64 fields when its axis
+                        lengths have FP64 passes; hh_report.retried counts them; 0 = off */
+  int verify;        /* 1: hh_homogenize also solves the image with FP64 fields at tol
+                        1e-10 and reports the difference in hh_report.err_vs_oracle;
+                        default 0 */
+  int lanes;         /* hh_homogenize_batch: shape groups solved concurrently, each on its
+                        own stream, host thread and workspace (1..4; 0 = up to 4, the
+                        default; 1 = one after another; profile forces 1); results do not
+                        depend on it */
 } hh_opts;
 
 /* Per-call report. */
@@ -103,6 +118,17 @@ typedef struct {
   int plan[3];                  /* tile variants (z, y, x) of the last group solved */
   double setup_ms;              /* host time spent tuning and building graphs in the call
                                    (one-time per shape / argument set; part of seconds) */
+  long long retried;            /* images solved again with FP64 fields (hh_opts.retry) */
+  double bytes_moved;           /* algorithmic device-memory bytes of the solver passes: per
+                                   system iteration 63 complex words per half-spectrum
+                                   frequency (zinv 15, y 12 + 12, x 12, zfwd 12) plus the
+                                   labels (or 21 stiffness words per voxel), and 27 words per
+                                   frequency for the right-hand side */
+  double err_vs_oracle;         /* with hh_opts.verify (hh_homogenize): relative difference,
+                                   ||C - C64||_F / ||C64||_F on Mandel-scaled matrices, from
+                                   the same solve with FP64 fields at tol 1e-10 (that path
+                                   matches the FP64 CPU oracle to 1e-8 in the tests); -1 when
+                                   not computed */
 } hh_report;
 
 /* Fills *opts with the defaults listed in hh_opts. */
@@ -116,19 +142,23 @@ int hh_create(hh_ctx **ctx, int device, void *hip_stream);
 int hh_set_stream(hh_ctx *ctx, void *hip_stream);
 /* Frees the context and its device workspace.  NULL is ignored. */
 void hh_destroy(hh_ctx *ctx);
-/* Message describing the last failing call on ctx (empty if none). */
+/* Message describing the last failing call on ctx (empty if none); with
+ * ctx = NULL, the reason the last hh_create of the calling thread failed. */
 const char *hh_last_error(const hh_ctx *ctx);
 /* Device workspace currently held by the context, in bytes. */
 long long hh_workspace_bytes(const hh_ctx *ctx);
 /* Releases the context's workspace (it is re-allocated on demand). */
 void hh_release_workspace(hh_ctx *ctx);
 /* 1 if axis length n has compiled FFT passes at `precision`, else 0.  The
- * list is fixed at build time.  FP32 (precision 0): 2 3 4 5 6 8 9 10 12 15 16
- * 18 20 24 25 27 30 32 36 40 45 48 50 60 64 70 72 75 80 85 90 95 96 100 110 120
- * 128 144 150 160 170 180 190 192 200 225 235 240 245 256 300 310 320 512 1024
- * (among them the boxes of the paper's subimage sizes of Sec. 5 with 5 or 10
- * voxels of padding).  FP64 (precision 1): 2 3 4 5 6 8 9 10 12 15 16 18 20
- * 24 25 27 30 32 36 40 45 48 60 64 80 85 95 96 110 128. */
+ * list is fixed at build time.
+ * FP32 (precision 0): 2 3 4 5 6 8 9 10 12 15 16 18 20 24 25 27 30 32 36 40
+ * 45 48 50 60 64 70 72 75 80 85 90 95 96 100 110 115 120 128 130 140 144
+ * 150 160 170 180 190 192 200 220 225 235 240 245 256 265 272 288 300 310
+ * 320 340 512 900 1024
+ * (among them the boxes of the paper's subimage sizes of Sec. 5 with 5, 10
+ * or 20 voxels of padding per side, and a plain 900^3 solve).
+ * FP64 (precision 1): 2 3 4 5 6 8 9 10 12 15 16 18 20 24 25 27 30 32 36 40
+ * 45 48 60 64 80 85 95 96 100 110 120 128 144 150 160 192 256. */
 int hh_size_supported(int n, int precision);
 
 /*
@@ -183,8 +213,10 @@ int hh_homogenize_batch(hh_ctx *ctx, int nitems, const int *dims, const uint8_t 
  * image edge) and averaged over the block; the symmetrized block stiffnesses
  * form the intermediate image, which is solved with anisotropic voxels.
  * C_out: final C* (36).  C_sub: (nz/n)(ny/n)(nx/n) x 21 symmetrized block
- * stiffnesses, C order (may be NULL).  use_surrogate must be 0 (the learned
- * path is hh_hierarchical_surrogate).  With one subimage (n = image size)
+ * stiffnesses, C order (may be NULL).  use_surrogate = 1 takes the subimage
+ * stiffnesses from the networks attached with hh_set_surrogate, with their
+ * gate and the FFT solve as fallback (hh_hierarchical_surrogate without the
+ * fallback flags); HH_EINVAL when none are attached.  With one subimage (n = image size)
  * the intermediate image is a single voxel and C* is its stiffness; an
  * intermediate image with some axes of length 1 and others longer returns
  * HH_EUNSUPPORTED.
@@ -248,6 +280,15 @@ typedef struct hh_net hh_net;
 int hh_net_create(hh_ctx *ctx, int nphase, int n, unsigned long long seed, hh_net **net);
 void hh_net_destroy(hh_net *net);
 long long hh_net_num_params(const hh_net *net);
+/* Phase count and input edge of a network. */
+int hh_net_info(const hh_net *net, int *nphase, int *n);
+/* A network from the file the training pipeline writes (numpy .npz: arrays
+ * params <f4 [hh_net_num_params], mean and scale <f8 [21], fmu and fsc <f8
+ * [8], n and nphase <i8 scalars; other members are ignored), read on the
+ * host with zlib.  *net is created on ctx and owned by the caller
+ * (hh_net_destroy).  HH_EINVAL for a missing or malformed file, with the
+ * reason in hh_last_error(ctx). */
+int hh_net_load(hh_ctx *ctx, const char *path, hh_net **net);
 /* FP32 parameters (host copies); setting also resets the optimizer state. */
 int hh_net_get_params(hh_ctx *ctx, hh_net *net, float *params, long long n);
 int hh_net_set_params(hh_ctx *ctx, hh_net *net, const float *params, long long n);
@@ -289,6 +330,15 @@ int hh_hierarchical_surrogate(hh_ctx *ctx, const uint8_t *labels, int nx, int ny
                               const hh_phase *phases, int nphase, int n_sub, int pad, hh_net *net_a,
                               hh_net *net_b, double spread_tol, double bound_tol, const hh_opts *opts,
                               double C_out[36], double *C_sub, int *fallback, hh_report *report);
+
+/*
+ * Attaches the networks and gate tolerances that hh_hierarchical uses with
+ * use_surrogate = 1 (same meaning as in hh_hierarchical_surrogate; net_b may
+ * be NULL).  The caller keeps ownership: the networks must stay alive while
+ * attached; net_a = NULL detaches.  HH_EINVAL for net_b without net_a or bad
+ * tolerances.
+ */
+int hh_set_surrogate(hh_ctx *ctx, hh_net *net_a, hh_net *net_b, double spread_tol, double bound_tol);
 
 /*
  * Least-squares fit M(n) = M_inf + slope / n of each of the 36 entries over

@@ -24,8 +24,12 @@ ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
-# Packed FP32 instructions are disabled for all device code.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 instructions are disabled for all device code.  Multiply-adds
+# are fused only within one source expression (-ffp-contract=on), never
+# across statements, so every instantiation of a kernel template (tile
+# variants of one axis pass) rounds the same arithmetic the same way and the
+# variants give identical bits.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on"]
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wno-unused-command-line-argument",
           "-I", os.path.join(ROOT, "include")] + os.environ.get("HH_EXTRA_FLAGS", "").split()
 
@@ -53,7 +57,7 @@ def build(jobs=None, verbose=True):
             if verbose:
                 print("  hipcc %-22s %6.1fs" % (name, dt), flush=True)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lz"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), p.stderr))

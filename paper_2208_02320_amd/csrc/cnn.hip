@@ -447,6 +447,13 @@ int hh_net_get_fraction_scaling(const hh_net* net, double mean[8], double scale[
   return HH_OK;
 }
 
+int hh_net_info(const hh_net* net, int* nphase, int* n) {
+  if (!net || !nphase || !n) return HH_EINVAL;
+  *nphase = net->nphase;
+  *n = net->n;
+  return HH_OK;
+}
+
 int hh_net_get_scaling(const hh_net* net, double mean[21], double scale[21]) {
   if (!net || !mean || !scale) return HH_EINVAL;
   for (int i = 0; i < kOut; ++i) {

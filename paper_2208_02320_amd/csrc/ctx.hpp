@@ -6,10 +6,21 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/hh.h"
+
+// A stream of work inside one call: its stream, its graph-capture stream,
+// its timing events and the prefix of its workspace buffers.  The context's
+// own lane has an empty prefix; a batch of several shapes runs its shape
+// groups on extra lanes concurrently.
+struct hh_lane {
+  hipStream_t stream = nullptr, cap = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::string prefix;
+};
 
 struct hh_ctx {
   int device = 0;
@@ -26,8 +37,25 @@ struct hh_ctx {
   // instantiated graphs of iteration chunks, keyed by their launch arguments
   std::map<std::string, hipGraphExec_t> graphs;
   double setup_ms = 0.0;                  // tuning and graph construction of the current call
+  // networks used by hh_hierarchical(use_surrogate = 1) (owned by the caller)
+  struct hh_net* sur_a = nullptr;
+  struct hh_net* sur_b = nullptr;
+  double sur_spread = 0.0, sur_bound = 0.0;
+  double call_bytes = 0.0;                // algorithmic bytes of the current call's solver passes
+  long long call_retried = 0;             // images of the current call solved again in FP64
   std::array<int, 3> last_plan{{0, 0, 0}};
+  // extra lanes of concurrent shape groups (created on first use, default priority)
+  std::vector<hh_lane> aux;
+  hipEvent_t fork = nullptr;
+  // guards the maps, counters and message above when lanes run in threads
+  std::recursive_mutex mu;
 };
+
+// Sets the context's error message (lanes may fail concurrently).
+inline void set_err(hh_ctx* ctx, const std::string& msg) {
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  ctx->err = msg;
+}
 
 inline void clear_graphs(hh_ctx* ctx) {
   for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
@@ -43,21 +71,24 @@ struct Fail {
   do {                                                                                     \
     hipError_t e_ = (expr);                                                                \
     if (e_ != hipSuccess) {                                                                \
-      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                       \
+      set_err(ctx, std::string(#expr) + ": " + hipGetErrorString(e_));                      \
       throw Fail{e_ == hipErrorOutOfMemory ? HH_ENOMEM : HH_EDEVICE};                      \
     }                                                                                      \
   } while (0)
 
 [[noreturn]] inline void fail(hh_ctx* ctx, int code, const std::string& msg) {
-  ctx->err = msg;
+  set_err(ctx, msg);
   throw Fail{code};
 }
 
-inline void* ws(hh_ctx* ctx, const std::string& name, size_t bytes) {
+// Workspace buffer `name`, grown on demand; `st` is the stream whose work may
+// still use the old buffer when it has to grow (default: the context's).
+inline void* ws(hh_ctx* ctx, const std::string& name, size_t bytes, hipStream_t st) {
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
   auto it = ctx->bufs.find(name);
   if (it != ctx->bufs.end() && it->second.second >= bytes) return it->second.first;
   if (it != ctx->bufs.end()) {
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipFree(it->second.first));
     ctx->bufs.erase(it);
   }
@@ -71,6 +102,7 @@ inline void* ws(hh_ctx* ctx, const std::string& name, size_t bytes) {
   ctx->bufs[name] = {p, sz};
   return p;
 }
+inline void* ws(hh_ctx* ctx, const std::string& name, size_t bytes) { return ws(ctx, name, bytes, ctx->stream); }
 
 
 template <class F>

@@ -94,7 +94,7 @@ constexpr bool is_prime(int r) { return r > 1 && smallest_factor(r) == r; }
 constexpr int first_radix(int r) { return (r % 4 == 0 && r != 8) ? 4 : smallest_factor(r); }
 
 // Lengths whose register DFT is built here: every prime factor at most kMaxPrime.
-constexpr int kMaxPrime = 47;
+constexpr int kMaxPrime = 53;
 constexpr bool dft_length_ok(int n) {
   if (n < 1) return false;
   while (n > 1) {

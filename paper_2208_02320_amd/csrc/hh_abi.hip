@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
@@ -11,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -23,6 +25,9 @@
 using namespace hh;
 
 namespace {
+
+// reason of the calling thread's last failed hh_create
+thread_local std::string g_create_error;
 
 int status_code(int s) {
   switch (s) {
@@ -102,6 +107,40 @@ struct Item {
   std::vector<hh_phase> phases;
 };
 
+// Iteration limits of a group: the options' values, or (0) derived from
+// the phase contrast kappa = largest / smallest eigenvalue of the phase
+// stiffnesses (3K once and 2G five times per isotropic phase).  Conjugate
+// gradients reduce the error by 2 ((sqrt(kappa) - 1) / (sqrt(kappa) + 1))^k
+// after k steps, so about sqrt(kappa) ln(2 / tol) / 2 steps reach tol in
+// exact arithmetic; the cap allows twice that.
+struct Limits {
+  int max_iter, stall;
+};
+Limits solve_limits(const hh_opts& o, const std::vector<Item>& items, bool aniso) {
+  double kappa = 1.0;
+  if (!aniso) {
+    double hi = 0.0, lo = 1e300;
+    for (const Item& it : items)
+      for (const hh_phase& p : it.phases) {
+        hi = std::max(hi, std::max(3.0 * p.K, 2.0 * p.G));
+        lo = std::min(lo, std::min(3.0 * p.K, 2.0 * p.G));
+      }
+    if (lo > 0.0 && hi > 0.0) kappa = hi / lo;
+  }
+  const double s = std::sqrt(kappa);
+  Limits l;
+  if (o.max_iter > 0) {
+    l.max_iter = o.max_iter;
+  } else if (aniso) {
+    l.max_iter = 1000;
+  } else {
+    l.max_iter = int(std::min(1e6, std::max(1000.0, std::ceil(s * std::log(2.0 / o.tol)))));
+  }
+  if (o.stall_limit > 0) l.stall = o.stall_limit;
+  else l.stall = aniso ? 100 : int(std::min(1e6, std::max(100.0, std::ceil(s))));
+  return l;
+}
+
 struct GroupResult {
   std::vector<double> C72;  // per item: raw (36) then symmetrized (36)
   std::vector<int> status;  // per item HH code
@@ -144,11 +183,14 @@ bool loads_independent(const double L[6][6]) {
 
 void check_opts(hh_ctx* ctx, const hh_opts& o) {
   if (!(o.tol > 0.0) || !(o.tol < 1.0)) fail(ctx, HH_EINVAL, "tol must be in (0, 1)");
-  if (o.max_iter < 1) fail(ctx, HH_EINVAL, "max_iter must be >= 1");
+  if (o.max_iter < 0) fail(ctx, HH_EINVAL, "max_iter must be >= 0 (0: from the phase contrast)");
   if (o.scheme != 0 && o.scheme != 1) fail(ctx, HH_EINVAL, "scheme must be 0 (CG) or 1 (basic)");
   if (o.precision != 0 && o.precision != 1) fail(ctx, HH_EINVAL, "precision must be 0 or 1");
   if (o.nyquist != 0 && o.nyquist != 1) fail(ctx, HH_EINVAL, "nyquist must be 0 or 1");
-  if (o.stall_limit < 1) fail(ctx, HH_EINVAL, "stall_limit must be >= 1");
+  if (o.stall_limit < 0) fail(ctx, HH_EINVAL, "stall_limit must be >= 0 (0: from the phase contrast)");
+  if (o.retry != 0 && o.retry != 1) fail(ctx, HH_EINVAL, "retry must be 0 or 1");
+  if (o.verify != 0 && o.verify != 1) fail(ctx, HH_EINVAL, "verify must be 0 or 1");
+  if (o.lanes < 0 || o.lanes > 4) fail(ctx, HH_EINVAL, "lanes must be in 0..4");
   if (o.chunk < 1) fail(ctx, HH_EINVAL, "chunk must be >= 1");
   if (o.tune != 0 && o.tune != 1) fail(ctx, HH_EINVAL, "tune must be 0 or 1");
   if (o.graph != 0 && o.graph != 1) fail(ctx, HH_EINVAL, "graph must be 0 or 1");
@@ -212,15 +254,43 @@ PassVariants pass_variants(hh_ctx* ctx, int n, int P, int info_geom, int info_ld
   return pv;
 }
 
+constexpr int kMaxLanes = 4;  // concurrent shape groups of a batch (hardware queues per process)
+
+// Creates the extra lanes of concurrent shape groups once per context.
+void ensure_lanes(hh_ctx* ctx, int n) {
+  if (!ctx->fork) HIPCHK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  while (int(ctx->aux.size()) < n) {
+    hh_lane l;
+    l.prefix = "lane" + std::to_string(ctx->aux.size()) + "/";
+    // all streams keep the default priority
+    HIPCHK(hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&l.cap, hipStreamNonBlocking));
+    HIPCHK(hipEventCreate(&l.e0));
+    HIPCHK(hipEventCreate(&l.e1));
+    ctx->aux.push_back(l);
+  }
+}
+
+// The context's own lane: its stream, capture stream and timing events.
+hh_lane main_lane(hh_ctx* ctx) {
+  hh_lane l;
+  l.stream = ctx->stream;
+  l.cap = ctx->cap;
+  l.e0 = ctx->e0;
+  l.e1 = ctx->e1;
+  return l;
+}
+
 double ms_since(std::chrono::steady_clock::time_point t) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
 }
 
 GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsigned char* labels,
                         const void* cfield, bool aniso, const hh_opts& o, const double loads[6][6],
-                        Profile& prof, void* cfield_out) {
+                        Profile& prof, void* cfield_out, const hh_lane& lane, int nlanes) {
   const int nx = items[0].nx, ny = items[0].ny, nz = items[0].nz;
   const int P = o.precision;
+  const Limits lim = solve_limits(o, items, aniso);
   const PassVariants vz = pass_variants(ctx, nz, P, kOpInfoZ, kOpInfoLdsZ, kOpInfoThreadsZ);
   const PassVariants vy = pass_variants(ctx, ny, P, kOpInfoZ, kOpInfoLdsZ, kOpInfoThreadsZ);
   const PassVariants vx = pass_variants(ctx, nx, P, kOpInfoX, kOpInfoLdsX, kOpInfoThreadsX);
@@ -234,21 +304,18 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
   // per z-pass tile, [tile][z][M][3]
   auto nwgz_of = [&](int M) { return ny * ((hx + M - 1) / M); };
   auto nafreq_of = [&](int M) { return (long long)nwgz_of(M) * nz * M; };
-  auto nwgx_of = [&](int R) { return (ny * nz + R - 1) / R; };
   long long nafreq_max = 0;
-  int nwgz_max = 0, nwgx_max = 0;
-  for (int v = 0; v < kNVariant; ++v) {
-    if (vz.ok[v]) {
-      nafreq_max = std::max(nafreq_max, nafreq_of(vz.geom[v]));
-      nwgz_max = std::max(nwgz_max, nwgz_of(vz.geom[v]));
-    }
-    if (vx.ok[v]) nwgx_max = std::max(nwgx_max, nwgx_of(vx.geom[v]));
-  }
-  const size_t per_sys = size_t(nfreq) * 6 * cb + size_t(nafreq_max) * 6 * cb;  // tmp + ar + ap
+  for (int v = 0; v < kNVariant; ++v)
+    if (vz.ok[v]) nafreq_max = std::max(nafreq_max, nafreq_of(vz.geom[v]));
+  // per-row and per-column partial sums (independent of the tile variant)
+  const int nrow = ny * nz, ncol = ny * hx;
+  const int nchunk_x = (nrow + kFinChunk - 1) / kFinChunk, nchunk_z = (ncol + kFinChunk - 1) / kFinChunk;
+  // tmp + ar + ap + the row and column partial sums
+  const size_t per_sys = size_t(nfreq) * 6 * cb + size_t(nafreq_max) * 6 * cb + sizeof(double) * (size_t(nrow) * kPartX + ncol);
 
   size_t freeb = 0, totalb = 0;
   HIPCHK(hipMemGetInfo(&freeb, &totalb));
-  const size_t budget = std::min<size_t>(size_t(24) << 30, freeb / 2);
+  const size_t budget = std::min<size_t>(size_t(24) << 30, freeb / (2 * size_t(nlanes)));
   int wave = int(std::max<size_t>(1, budget / (6 * per_sys)));
   wave = std::min<int>(wave, int(items.size()));
   wave = std::min(wave, 65535 / 6);
@@ -258,9 +325,12 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
   // time, and its stiffness is formed once the final states of all six loads
   // are in.
   size_t held = 0;
-  for (const char* name : {"tmp", "ar", "ap"}) {
-    auto it = ctx->bufs.find(name);
-    if (it != ctx->bufs.end()) held += it->second.second;
+  {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    for (const char* name : {"tmp", "ar", "ap"}) {
+      auto it = ctx->bufs.find(lane.prefix + name);
+      if (it != ctx->bufs.end()) held += it->second.second;
+    }
   }
   const size_t avail = size_t(0.85 * double(freeb + held));
   const int fit = 6 * per_sys <= avail ? 6 : int(std::max<size_t>(1, avail / per_sys));
@@ -281,6 +351,7 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
   const std::array<int, 6> key{{nx, ny, nz, P, aniso ? 1 : 0, bucket}};
   bool need_tune = false;
   if (!forced_all && o.tune && P == 0 && loads_per_wave == 6) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
       for (int i = 0; i < 3; ++i)
@@ -340,19 +411,21 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
         }
         for (int a = 0; a < la; ++a) sdesc[i * la + a] = SysDesc{i, a0 + a};
       }
-      auto* d_items = static_cast<ItemDesc*>(ws(ctx, "items", sizeof(ItemDesc) * nw));
-      auto* d_sys = static_cast<SysDesc*>(ws(ctx, "sys", sizeof(SysDesc) * nsys));
-      auto* d_state = static_cast<SysState*>(ws(ctx, "state", sizeof(SysState) * nw * 6));
-      auto* d_px = static_cast<double*>(ws(ctx, "part_x", sizeof(double) * kPartX * size_t(nwgx_max) * nsys));
-      auto* d_pz = static_cast<double*>(ws(ctx, "part_z", sizeof(double) * size_t(nwgz_max) * nsys));
-      void* d_tmp = ws(ctx, "tmp", size_t(nfreq) * 6 * cb * nsys);
-      void* d_ar = ws(ctx, "ar", size_t(nafreq_max) * 3 * cb * nsys);
-      void* d_ap = ws(ctx, "ap", size_t(nafreq_max) * 3 * cb * nsys);
-      auto* d_out = static_cast<double*>(ws(ctx, "cout", sizeof(double) * 72 * nw));
-      auto* d_ist = static_cast<int*>(ws(ctx, "istatus", sizeof(int) * nw));
-      auto* d_cnt = static_cast<int*>(ws(ctx, "count", sizeof(int)));
-      HIPCHK(hipMemcpyAsync(d_items, idesc.data(), sizeof(ItemDesc) * nw, hipMemcpyHostToDevice, ctx->stream));
-      HIPCHK(hipMemcpyAsync(d_sys, sdesc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, ctx->stream));
+      auto* d_items = static_cast<ItemDesc*>(ws(ctx, lane.prefix + "items", sizeof(ItemDesc) * nw, lane.stream));
+      auto* d_sys = static_cast<SysDesc*>(ws(ctx, lane.prefix + "sys", sizeof(SysDesc) * nsys, lane.stream));
+      auto* d_state = static_cast<SysState*>(ws(ctx, lane.prefix + "state", sizeof(SysState) * nw * 6, lane.stream));
+      auto* d_px = static_cast<double*>(ws(ctx, lane.prefix + "part_x", sizeof(double) * kPartX * size_t(nrow) * nsys, lane.stream));
+      auto* d_pz = static_cast<double*>(ws(ctx, lane.prefix + "part_z", sizeof(double) * size_t(ncol) * nsys, lane.stream));
+      auto* d_cx = static_cast<double*>(ws(ctx, lane.prefix + "chunk_x", sizeof(double) * kPartX * size_t(nchunk_x) * nsys, lane.stream));
+      auto* d_cz = static_cast<double*>(ws(ctx, lane.prefix + "chunk_z", sizeof(double) * size_t(nchunk_z) * nsys, lane.stream));
+      void* d_tmp = ws(ctx, lane.prefix + "tmp", size_t(nfreq) * 6 * cb * nsys, lane.stream);
+      void* d_ar = ws(ctx, lane.prefix + "ar", size_t(nafreq_max) * 3 * cb * nsys, lane.stream);
+      void* d_ap = ws(ctx, lane.prefix + "ap", size_t(nafreq_max) * 3 * cb * nsys, lane.stream);
+      auto* d_out = static_cast<double*>(ws(ctx, lane.prefix + "cout", sizeof(double) * 72 * nw, lane.stream));
+      auto* d_ist = static_cast<int*>(ws(ctx, lane.prefix + "istatus", sizeof(int) * nw, lane.stream));
+      auto* d_cnt = static_cast<int*>(ws(ctx, lane.prefix + "count", sizeof(int), lane.stream));
+      HIPCHK(hipMemcpyAsync(d_items, idesc.data(), sizeof(ItemDesc) * nw, hipMemcpyHostToDevice, lane.stream));
+      HIPCHK(hipMemcpyAsync(d_sys, sdesc.data(), sizeof(SysDesc) * nsys, hipMemcpyHostToDevice, lane.stream));
 
       // launch arguments for a choice of z and x variants over the first ns systems
       auto make_args = [&](int ns, int zv, int xv) {
@@ -365,10 +438,10 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
         g.hxp = hxp;
         g.nsys = ns;
         g.nyq_zero = o.nyquist;
-        g.max_iter = o.max_iter;
+        g.max_iter = lim.max_iter;
         g.scheme = o.scheme;
         g.aniso = aniso ? 1 : 0;
-        g.stall_limit = o.stall_limit;
+        g.stall_limit = lim.stall;
         g.tol2 = o.tol * o.tol;
         const double u = P == 0 ? 5.96e-8 : 1.11e-16;
         g.zero_rhs2 = (64.0 * u) * (64.0 * u);
@@ -388,11 +461,16 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
         g.state = d_state;
         g.part_x = d_px;
         g.part_z = d_pz;
-        g.nwg_x = nwgx_of(vx.geom[xv]);
-        g.nwg_z = nwgz_of(vz.geom[zv]);
+        g.chunk_x = d_cx;
+        g.chunk_z = d_cz;
+        g.nrow_x = nrow;
+        g.ncol_z = ncol;
+        g.nchunk_x = nchunk_x;
+        g.nchunk_z = nchunk_z;
+        (void)xv;
         return g;
       };
-      const hipStream_t st = ctx->stream;
+      const hipStream_t st = lane.stream;
 
       if (need_tune && w0 == 0) {
         // Time each distinct variant of each pass on this group's buffers, over
@@ -408,13 +486,13 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
         HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nafreq_max) * 3 * cb * ns, st));
         auto timeit = [&](auto&& launch) {
           launch();
-          HIPCHK(hipEventRecord(ctx->e0, st));
+          HIPCHK(hipEventRecord(lane.e0, st));
           for (int r = 0; r < 3; ++r) launch();
-          HIPCHK(hipEventRecord(ctx->e1, st));
-          HIPCHK(hipEventSynchronize(ctx->e1));
+          HIPCHK(hipEventRecord(lane.e1, st));
+          HIPCHK(hipEventSynchronize(lane.e1));
           HIPCHK(hipGetLastError());
           float ms = 0.f;
-          HIPCHK(hipEventElapsedTime(&ms, ctx->e0, ctx->e1));
+          HIPCHK(hipEventElapsedTime(&ms, lane.e0, lane.e1));
           return ms;
         };
         float best[3] = {1e30f, 1e30f, 1e30f};
@@ -443,16 +521,20 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
           }
         }
         plan = pick;
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         if (o.plan[0] < 0 && o.plan[1] < 0 && o.plan[2] < 0) ctx->plans[key] = plan;
         need_tune = false;
         ctx->setup_ms += ms_since(t_start);
       }
-      ctx->last_plan = plan;
+      {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        ctx->last_plan = plan;
+      }
       const SizeOpsFn oz = vz.f[plan[0]], oy = vy.f[plan[1]], ox = vx.f[plan[2]];
 
-      HIPCHK(hipMemsetAsync(d_state, 0, sizeof(SysState) * nsys, ctx->stream));
-      HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nafreq_max) * 3 * cb * nsys, ctx->stream));
-      if (o.scheme == 1) HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nafreq_max) * 3 * cb * nsys, ctx->stream));
+      HIPCHK(hipMemsetAsync(d_state, 0, sizeof(SysState) * nsys, lane.stream));
+      HIPCHK(hipMemsetAsync(d_ap, 0, size_t(nafreq_max) * 3 * cb * nsys, lane.stream));
+      if (o.scheme == 1) HIPCHK(hipMemsetAsync(d_ar, 0, size_t(nafreq_max) * 3 * cb * nsys, lane.stream));
       const GroupArgs g = make_args(nsys, plan[0], plan[2]);
 
       // right-hand side b = -G * (C : E)
@@ -474,9 +556,9 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
         oz(kOpZ, cg ? kZFwdCg : kZFwdFp, &g, s, nullptr);
         launch_fin_z(cg ? kZFwdCg : kZFwdFp, g, s);
       };
-      const bool use_graph = o.graph && !o.profile && ctx->cap;
+      const bool use_graph = o.graph && !o.profile && lane.cap;
       int launched = 0;
-      const int limit = o.max_iter + 1;
+      const int limit = lim.max_iter + 1;
       while (launched < limit) {
         const int chunk = std::min(o.chunk, limit - launched);
         if (use_graph) {
@@ -486,6 +568,7 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
                                          reinterpret_cast<std::uintptr_t>(oz), reinterpret_cast<std::uintptr_t>(oy),
                                          reinterpret_cast<std::uintptr_t>(ox)};
           gk.append(reinterpret_cast<const char*>(tag), sizeof(tag));
+          std::lock_guard<std::recursive_mutex> lk(ctx->mu);  // the cache is shared by the lanes
           auto it = ctx->graphs.find(gk);
           hipGraphExec_t ex = nullptr;
           if (it != ctx->graphs.end()) {
@@ -493,9 +576,9 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
           } else {
             const auto t_start = std::chrono::steady_clock::now();
             hipGraph_t graph = nullptr;
-            HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < chunk; ++k) iteration(ctx->cap);
-            const hipError_t ec = hipStreamEndCapture(ctx->cap, &graph);
+            HIPCHK(hipStreamBeginCapture(lane.cap, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < chunk; ++k) iteration(lane.cap);
+            const hipError_t ec = hipStreamEndCapture(lane.cap, &graph);
             const hipError_t el = hipGetLastError();
             if (ec != hipSuccess || el != hipSuccess || !graph) {
               if (graph) (void)hipGraphDestroy(graph);
@@ -506,7 +589,7 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
             (void)hipGraphDestroy(graph);
             if (ei != hipSuccess)
               fail(ctx, HH_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
-            if (ctx->graphs.size() >= 64) clear_graphs(ctx);
+            if (nlanes == 1 && ctx->graphs.size() >= 64) clear_graphs(ctx);
             ctx->graphs[gk] = ex;
             ctx->setup_ms += ms_since(t_start);
           }
@@ -552,6 +635,12 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
       HIPCHK(hipStreamSynchronize(st));
       prof.flush();
       const double vox = double(nx) * ny * nz;
+      // algorithmic bytes: 63 complex words per frequency and iteration (zinv
+      // 15, y 12 + 12, x 12, zfwd 12) plus the voxel data, 27 words for the RHS
+      const double nfa = double(hx) * ny * nz;
+      const double vdata = aniso ? vox * 21.0 * (P == 0 ? 4.0 : 8.0) : vox;
+      const double it_bytes = nfa * double(cb) * 63.0 + vdata, rhs_bytes = nfa * double(cb) * 27.0 + vdata;
+      double bytes = 0.0;
       for (int i = 0; i < nw; ++i) {
         int code = status_code(ist[i]);
         for (int a = 0; a < 6; ++a) {
@@ -559,18 +648,78 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
           res.iters[size_t(w0 + i) * 6 + a] = s.iter;
           res.rel[size_t(w0 + i) * 6 + a] = s.bb > 0.0 ? std::sqrt(s.rr / s.bb) : 0.0;
           res.voxel_iters += vox * s.iter;
+          bytes += it_bytes * s.iter + rhs_bytes;
           code = worse(code, status_code(s.status == kRunning ? kNoConv : s.status));
         }
         res.status[w0 + i] = code;
       }
+      std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+      ctx->call_bytes += bytes;
     }
   }
   return res;
 }
 
+// solve_group, then (opts.retry, FP32 fields, isotropic phases) the images
+// that stopped at the FP32 floor (HH_ESTAGNATED) solved again with FP64
+// fields; their stiffness replaces the FP32 one, also in the next level's
+// field when the caller builds one.
+GroupResult solve_group_retry(hh_ctx* ctx, const std::vector<Item>& items, const unsigned char* labels,
+                              const void* cfield, bool aniso, const hh_opts& o, const double loads[6][6],
+                              Profile& prof, void* cfield_out, const hh_lane& lane, int nlanes) {
+  GroupResult r = solve_group(ctx, items, labels, cfield, aniso, o, loads, prof, cfield_out, lane, nlanes);
+  if (!o.retry || o.precision != 0 || aniso) return r;
+  std::vector<int> idx;
+  for (size_t i = 0; i < items.size(); ++i)
+    if (r.status[i] == HH_ESTAGNATED && size_ops(items[i].nx, 1) && size_ops(items[i].ny, 1) &&
+        size_ops(items[i].nz, 1))
+      idx.push_back(int(i));
+  if (idx.empty()) return r;
+  std::vector<Item> sub;
+  for (int i : idx) sub.push_back(items[i]);
+  hh_opts o64 = o;
+  o64.precision = 1;
+  o64.tune = 0;
+  o64.plan[0] = o64.plan[1] = o64.plan[2] = -1;
+  const std::array<int, 3> keep_plan = ctx->last_plan;
+  GroupResult r64 = solve_group(ctx, sub, labels, nullptr, false, o64, loads, prof, nullptr, lane, nlanes);
+  ctx->last_plan = keep_plan;
+  std::vector<float> field(idx.size() * 21);
+  for (size_t k = 0; k < idx.size(); ++k) {
+    const int i = idx[k];
+    std::copy(r64.C72.begin() + k * 72, r64.C72.begin() + (k + 1) * 72, r.C72.begin() + size_t(i) * 72);
+    r.status[i] = r64.status[k];
+    for (int a = 0; a < 6; ++a) {
+      r.iters[size_t(i) * 6 + a] = r64.iters[k * 6 + a];
+      r.rel[size_t(i) * 6 + a] = r64.rel[k * 6 + a];
+    }
+    const double* S = r64.C72.data() + k * 72 + 36;
+    int q = 0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = a; b < 6; ++b) field[k * 21 + q++] = float(S[a * 6 + b]);
+  }
+  r.voxel_iters += r64.voxel_iters;
+  {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->call_retried += (long long)idx.size();
+  }
+  if (cfield_out) {
+    for (size_t k = 0; k < idx.size(); ++k)
+      HIPCHK(hipMemcpyAsync(static_cast<float*>(cfield_out) + size_t(idx[k]) * 21, field.data() + k * 21,
+                            sizeof(float) * 21, hipMemcpyHostToDevice, lane.stream));
+    HIPCHK(hipStreamSynchronize(lane.stream));
+  }
+  return r;
+}
+
 void begin_report(hh_ctx* ctx, hh_report* rep) {
-  if (rep) std::memset(rep, 0, sizeof(*rep));
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->err_vs_oracle = -1.0;
+  }
   ctx->setup_ms = 0.0;
+  ctx->call_bytes = 0.0;
+  ctx->call_retried = 0;
   HIPCHK(hipEventRecord(ctx->t0, ctx->stream));
 }
 
@@ -582,6 +731,8 @@ void end_report(hh_ctx* ctx, hh_report* rep) {
     HIPCHK(hipEventElapsedTime(&ms, ctx->t0, ctx->t1));
     rep->seconds = ms * 1e-3;
     rep->setup_ms = ctx->setup_ms;
+    rep->bytes_moved = ctx->call_bytes;
+    rep->retried = ctx->call_retried;
     for (int i = 0; i < 3; ++i) rep->plan[i] = ctx->last_plan[i];
   }
 }
@@ -635,10 +786,192 @@ const unsigned char* device_labels(hh_ctx* ctx, const uint8_t* labels, long long
   return d;
 }
 
+// ||A - B||_F / ||B||_F of two 6x6 Voigt stiffnesses in Mandel scaling
+// (shear rows and columns times sqrt 2)
+double mandel_rel_error(const double* A, const double* B) {
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      const double w = (i < 3 ? 1.0 : std::sqrt(2.0)) * (j < 3 ? 1.0 : std::sqrt(2.0));
+      const double d = (A[i * 6 + j] - B[i * 6 + j]) * w, b = B[i * 6 + j] * w;
+      num += d * d;
+      den += b * b;
+    }
+  return den > 0.0 ? std::sqrt(num / den) : -1.0;
+}
+
 void write_C(const GroupResult& r, int item, double* C_out, double* C_raw) {
   const double* C = r.C72.data() + size_t(item) * 72;
   if (C_out) std::memcpy(C_out, C + 36, sizeof(double) * 36);
   if (C_raw) std::memcpy(C_raw, C, sizeof(double) * 36);
+}
+
+// The two-level scheme with network subimage stiffnesses, the gate and the
+// FFT fallback (body of hh_hierarchical_surrogate and of hh_hierarchical
+// with use_surrogate = 1).
+int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, int labels_on_device,
+                                const hh_phase* phases, int nphase, int n_sub, int pad, hh_net* net_a,
+                                hh_net* net_b, double spread_tol, double bound_tol, const hh_opts& o,
+                                double C_out[36], double* C_sub, int* fallback, hh_report* report) {
+  if (!labels || !C_out || !net_a) fail(ctx, HH_EINVAL, "labels, net_a and C_out are required");
+  if (nx < 1 || ny < 1 || nz < 1 || n_sub < 1) fail(ctx, HH_EINVAL, "sizes must be positive");
+  if (nx % n_sub || ny % n_sub || nz % n_sub) fail(ctx, HH_EINVAL, "the subimage size must divide the image size");
+  if (pad < 0 || 2 * pad >= std::min(nx, std::min(ny, nz)))
+    fail(ctx, HH_EINVAL, "padding must satisfy 0 <= 2 pad < image size");
+  // a network reads either the n_sub^3 core (offset pad) or the whole box
+  const int in_a = hh_net_input_size(net_a), in_b = net_b ? hh_net_input_size(net_b) : in_a;
+  auto window_ok = [&](int e) { return e == n_sub || e == n_sub + 2 * pad; };
+  if (!window_ok(in_a) || !window_ok(in_b))
+    fail(ctx, HH_EINVAL, "the network input edge must be the subimage size or the padded box size");
+  if (!(spread_tol > 0.0) || !(bound_tol >= 0.0)) fail(ctx, HH_EINVAL, "bad gate tolerances");
+  const int b = n_sub + 2 * pad;
+  const int mx = nx / n_sub, my = ny / n_sub, mz = nz / n_sub;
+  check_shape(ctx, b, b, b, o.precision);
+  // one subimage: the intermediate image is a single voxel, whose solve is the identity
+  const bool single = mx == 1 && my == 1 && mz == 1;
+  if (!single) check_shape(ctx, mx, my, mz, o.precision);
+  check_phases(ctx, phases, nphase);
+  if (nphase > 8) fail(ctx, HH_EINVAL, "the surrogate takes at most 8 phases");
+  const long long nvox = (long long)nx * ny * nz;
+  const int nitems = mx * my * mz;
+  begin_report(ctx, report);
+  const hipStream_t st = ctx->stream;
+  const unsigned char* d_img = device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "image");
+  const long long box = (long long)b * b * b;
+  auto* d_pack = static_cast<unsigned char*>(ws(ctx, "pack", size_t(box * nitems)));
+  Profile prof{ctx, o.profile != 0, {}, 0, report};
+  prof.run(HH_K_SETUP, [&] { launch_gather_pad(d_img, nx, ny, nz, n_sub, pad, d_pack, st); });
+  // label counts of the cores (bounds, core-input networks) and, for a
+  // network that reads the whole box, of the boxes; then the predictions
+  auto* c21a = static_cast<double*>(ws(ctx, "sur_c21a", sizeof(double) * 21 * nitems));
+  double* c21b = net_b ? static_cast<double*>(ws(ctx, "sur_c21b", sizeof(double) * 21 * nitems)) : nullptr;
+  auto* d_counts = static_cast<int*>(ws(ctx, "sur_counts", sizeof(int) * 8 * size_t(nitems)));
+  const bool box_in = in_a != n_sub || (net_b && in_b != n_sub);
+  int* d_counts_box = box_in ? static_cast<int*>(ws(ctx, "sur_counts_box", sizeof(int) * 8 * size_t(nitems))) : nullptr;
+  prof.run(HH_K_OTHER, [&] {
+    hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
+    if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
+    hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a,
+                          in_a == n_sub ? d_counts : d_counts_box);
+    if (net_b)
+      hh_net_predict_device(ctx, net_b, d_pack, nitems, b, in_b == n_sub ? pad : 0, c21b,
+                            in_b == n_sub ? d_counts : d_counts_box);
+  });
+  // Voigt and Reuss stiffness of each core's phase fractions
+  std::vector<double> cp(21 * nphase), sp(21 * nphase);
+  for (int q = 0; q < nphase; ++q) {
+    const double K = phases[q].K, G = phases[q].G;
+    double C[6][6] = {}, S[6][6] = {};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        C[i][j] = (i == j) ? K + 4.0 * G / 3.0 : K - 2.0 * G / 3.0;
+        S[i][j] = (i == j) ? 1.0 / (9.0 * K) + 1.0 / (3.0 * G) : 1.0 / (9.0 * K) - 1.0 / (6.0 * G);
+      }
+    for (int i = 3; i < 6; ++i) {
+      C[i][i] = G;
+      S[i][i] = 1.0 / G;
+    }
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i; j < 6; ++j) {
+        cp[q * 21 + k] = C[i][j];
+        sp[q * 21 + k] = S[i][j];
+        ++k;
+      }
+  }
+  auto* d_cp = static_cast<double*>(ws(ctx, "sur_cp", sizeof(double) * 21 * nphase));
+  auto* d_sp = static_cast<double*>(ws(ctx, "sur_sp", sizeof(double) * 21 * nphase));
+  auto* cv21 = static_cast<double*>(ws(ctx, "sur_cv", sizeof(double) * 21 * nitems));
+  auto* cr21 = static_cast<double*>(ws(ctx, "sur_cr", sizeof(double) * 21 * nitems));
+  auto* d_flag = static_cast<int*>(ws(ctx, "sur_flag", sizeof(int) * nitems));
+  HIPCHK(hipMemcpyAsync(d_cp, cp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_sp, sp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
+  prof.run(HH_K_OTHER, [&] {
+    hh_launch_bounds(d_counts, nitems, n_sub, nphase, d_cp, d_sp, cv21, cr21, st);
+    hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, d_flag, st);
+  });
+  HIPCHK(hipGetLastError());
+  std::vector<int> flag(nitems);
+  std::vector<double> ha(21 * size_t(nitems)), hb;
+  HIPCHK(hipMemcpyAsync(flag.data(), d_flag, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ha.data(), c21a, sizeof(double) * 21 * nitems, hipMemcpyDeviceToHost, st));
+  if (net_b) {
+    hb.resize(ha.size());
+    HIPCHK(hipMemcpyAsync(hb.data(), c21b, sizeof(double) * 21 * nitems, hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  prof.flush();
+  // FFT solves of the gated items
+  std::vector<int> fb;
+  for (int i = 0; i < nitems; ++i)
+    if (flag[i]) fb.push_back(i);
+  std::vector<double> field(21 * size_t(nitems));
+  for (size_t i = 0; i < field.size(); ++i) field[i] = net_b ? 0.5 * (ha[i] + hb[i]) : ha[i];
+  double vi = 0.0;
+  int rc = HH_OK;
+  double L[6][6];
+  unit_loads(L);
+  if (!fb.empty()) {
+    std::vector<Item> items(fb.size());
+    for (size_t k = 0; k < fb.size(); ++k) {
+      Item& it = items[k];
+      it.nx = it.ny = it.nz = b;
+      it.lab_off = box * fb[k];
+      it.cf_off = -1;
+      const int r[6] = {pad, pad, pad, pad + n_sub, pad + n_sub, pad + n_sub};
+      std::memcpy(it.region, r, sizeof(r));
+      it.phases.assign(phases, phases + nphase);
+    }
+    GroupResult r1 = solve_group_retry(ctx, items, d_pack, nullptr, false, o, L, prof, nullptr, main_lane(ctx), 1);
+    vi += r1.voxel_iters;
+    for (size_t k = 0; k < fb.size(); ++k) {
+      rc = worse(rc, r1.status[k]);
+      const double* S = r1.C72.data() + k * 72 + 36;
+      int q = 0;
+      for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) field[size_t(fb[k]) * 21 + q++] = S[i * 6 + j];
+    }
+  }
+  if (C_sub) std::memcpy(C_sub, field.data(), sizeof(double) * field.size());
+  if (fallback) std::memcpy(fallback, flag.data(), sizeof(int) * nitems);
+  if (single) {
+    end_report(ctx, report);
+    int q = 0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i; j < 6; ++j) C_out[i * 6 + j] = C_out[j * 6 + i] = field[q++];
+    if (report) {
+      report->voxel_iters = vi;
+      report->items = nitems;
+      report->status = rc;
+    }
+    return rc;
+  }
+  // level 2
+  auto* d_field = static_cast<double*>(ws(ctx, "sur_field", sizeof(double) * field.size()));
+  HIPCHK(hipMemcpyAsync(d_field, field.data(), sizeof(double) * field.size(), hipMemcpyHostToDevice, st));
+  void* cf = ws(ctx, "cfield", field.size() * (o.precision == 0 ? 4 : 8));
+  launch_convert_field(o.precision, d_field, cf, (long long)field.size(), st);
+  HIPCHK(hipGetLastError());
+  Item l2;
+  l2.nx = mx;
+  l2.ny = my;
+  l2.nz = mz;
+  l2.lab_off = 0;
+  l2.cf_off = 0;
+  const int whole[6] = {0, 0, 0, mx, my, mz};
+  std::memcpy(l2.region, whole, sizeof(l2.region));
+  l2.phases.assign(1, hh_phase{1.0, 1.0});
+  GroupResult r2 = solve_group(ctx, {l2}, nullptr, cf, true, o, L, prof, nullptr, main_lane(ctx), 1);
+  end_report(ctx, report);
+  write_C(r2, 0, C_out, nullptr);
+  rc = worse(rc, r2.status[0]);
+  if (report) {
+    fill_item_report(report, r2, 0);
+    report->voxel_iters = vi + r2.voxel_iters;
+    report->items = nitems;
+    report->status = rc;
+  }
+  return rc;
 }
 
 }  // namespace
@@ -649,12 +982,12 @@ void hh_default_opts(hh_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->tol = 1e-6;
-  o->max_iter = 1000;
+  o->max_iter = 0;
   o->scheme = 0;
   o->precision = 0;
   o->nyquist = 0;
   o->profile = 0;
-  o->stall_limit = 100;
+  o->stall_limit = 0;
   o->chunk = 8;
   o->ref_lambda = 0.0;
   o->ref_mu = 0.0;
@@ -662,26 +995,46 @@ void hh_default_opts(hh_opts* o) {
   o->graph = 1;
   o->plan[0] = o->plan[1] = o->plan[2] = -1;
   o->loads_per_wave = 0;
+  o->retry = 1;
+  o->verify = 0;
+  o->lanes = 0;
 }
 
 int hh_create(hh_ctx** out, int device, void* hip_stream) {
-  if (!out) return HH_EINVAL;
+  // the reason of a failure stays readable without a context: hh_last_error(NULL)
+  auto failed = [](int code, const std::string& why, hipError_t e) {
+    g_create_error = why + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
+    return code;
+  };
+  g_create_error.clear();
+  if (!out) return failed(HH_EINVAL, "hh_create: ctx pointer is NULL", hipSuccess);
   *out = nullptr;
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HH_EDEVICE;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return failed(HH_EDEVICE, "hh_create: hipGetDeviceCount failed", e);
+  if (device < 0 || device >= ndev)
+    return failed(HH_EDEVICE, "hh_create: device " + std::to_string(device) + " out of range (" +
+                                  std::to_string(ndev) + " devices)", hipSuccess);
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HH_EDEVICE;
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HH_EDEVICE;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return failed(HH_EDEVICE, "hh_create: hipGetDeviceProperties failed", e);
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return failed(HH_EDEVICE, std::string("hh_create: device is ") + prop.gcnArchName + ", not gfx950", hipSuccess);
   auto* ctx = new hh_ctx();
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->max_lds = int(prop.sharedMemPerBlock);
+  const char* step = "hipSetDevice";
+  e = hipSetDevice(device);
+  if (e == hipSuccess) step = "hipEventCreate", e = hipEventCreate(&ctx->t0);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->t1);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->e0);
+  if (e == hipSuccess) e = hipEventCreate(&ctx->e1);
   // the capture stream keeps the default priority
-  if (hipSetDevice(device) != hipSuccess || hipEventCreate(&ctx->t0) != hipSuccess ||
-      hipEventCreate(&ctx->t1) != hipSuccess || hipEventCreate(&ctx->e0) != hipSuccess ||
-      hipEventCreate(&ctx->e1) != hipSuccess || hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) {
+  if (e == hipSuccess) step = "hipStreamCreateWithFlags", e = hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
     hh_destroy(ctx);
-    return HH_EDEVICE;
+    return failed(HH_EDEVICE, std::string("hh_create: ") + step + " failed", e);
   }
   *out = ctx;
   return HH_OK;
@@ -711,10 +1064,18 @@ void hh_destroy(hh_ctx* ctx) {
   if (ctx->e0) (void)hipEventDestroy(ctx->e0);
   if (ctx->e1) (void)hipEventDestroy(ctx->e1);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  for (hh_lane& l : ctx->aux) {
+    (void)hipStreamSynchronize(l.stream);
+    (void)hipStreamDestroy(l.stream);
+    (void)hipStreamDestroy(l.cap);
+    (void)hipEventDestroy(l.e0);
+    (void)hipEventDestroy(l.e1);
+  }
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   delete ctx;
 }
 
-const char* hh_last_error(const hh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* hh_last_error(const hh_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
 long long hh_workspace_bytes(const hh_ctx* ctx) {
   if (!ctx) return 0;
@@ -762,7 +1123,7 @@ int hh_homogenize(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, in
     const unsigned char* d_lab =
         device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "labels");
     Profile prof{ctx, o.profile != 0, {}, 0, report};
-    GroupResult res = solve_group(ctx, {it}, d_lab, nullptr, false, o, L, prof, nullptr);
+    GroupResult res = solve_group_retry(ctx, {it}, d_lab, nullptr, false, o, L, prof, nullptr, main_lane(ctx), 1);
     end_report(ctx, report);
     write_C(res, 0, C_out, C_raw);
     if (report) {
@@ -770,6 +1131,20 @@ int hh_homogenize(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, in
       report->voxel_iters = res.voxel_iters;
       report->items = 1;
       report->status = res.status[0];
+    }
+    if (o.verify && report && size_ops(nx, 1) && size_ops(ny, 1) && size_ops(nz, 1)) {
+      // the same solve with FP64 fields at tol 1e-10, outside the timed call
+      hh_opts o64 = o;
+      o64.precision = 1;
+      o64.tol = 1e-10;
+      o64.tune = 0;
+      o64.profile = 0;
+      o64.plan[0] = o64.plan[1] = o64.plan[2] = -1;
+      Profile quiet{ctx, false, {}, 0, nullptr};
+      const std::array<int, 3> keep_plan = ctx->last_plan;
+      GroupResult r64 = solve_group(ctx, {it}, d_lab, nullptr, false, o64, L, quiet, nullptr, main_lane(ctx), 1);
+      ctx->last_plan = keep_plan;
+      report->err_vs_oracle = mandel_rel_error(res.C72.data() + 36, r64.C72.data() + 36);
     }
     if (res.status[0] != HH_OK) ctx->err = "solve did not converge cleanly (see report.status)";
     return res.status[0];
@@ -813,7 +1188,7 @@ int hh_homogenize_aniso(hh_ctx* ctx, const double* C21, int nx, int ny, int nz, 
     double L[6][6];
     unit_loads(L);
     Profile prof{ctx, o.profile != 0, {}, 0, report};
-    GroupResult res = solve_group(ctx, {it}, nullptr, cf, true, o, L, prof, nullptr);
+    GroupResult res = solve_group(ctx, {it}, nullptr, cf, true, o, L, prof, nullptr, main_lane(ctx), 1);
     end_report(ctx, report);
     write_C(res, 0, C_out, C_raw);
     if (report) {
@@ -868,17 +1243,71 @@ int hh_homogenize_batch(hh_ctx* ctx, int nitems, const int* dims, const uint8_t*
     // group by shape
     std::map<std::tuple<int, int, int>, std::vector<int>> groups;
     for (int i = 0; i < nitems; ++i) groups[{items[i].nx, items[i].ny, items[i].nz}].push_back(i);
-    Profile prof{ctx, o.profile != 0, {}, 0, report};
+    std::vector<std::vector<int>> members;
+    for (auto& kv : groups) members.push_back(kv.second);
+    const int ngroup = int(members.size());
+    std::vector<GroupResult> results(ngroup);
+    auto group_items = [&](int q) {
+      std::vector<Item> gi;
+      for (int i : members[q]) gi.push_back(items[i]);
+      return gi;
+    };
+    // Shape groups run concurrently on up to kMaxLanes lanes (threads with
+    // their own streams and buffers), largest work first, so the tail
+    // iterations of one group overlap the work of the others; each system
+    // computes the same bits on any lane.
+    int nl = o.lanes > 0 ? o.lanes : kMaxLanes;
+    nl = std::min(nl, ngroup);
+    if (o.profile) nl = 1;
+    if (nl <= 1) {
+      Profile prof{ctx, o.profile != 0, {}, 0, report};
+      for (int q = 0; q < ngroup; ++q)
+        results[q] = solve_group_retry(ctx, group_items(q), d_lab, nullptr, false, o, L, prof, nullptr,
+                                       main_lane(ctx), 1);
+    } else {
+      ensure_lanes(ctx, nl);
+      std::vector<int> order(ngroup);
+      for (int q = 0; q < ngroup; ++q) order[q] = q;
+      auto work = [&](int q) {
+        const double v = double(items[members[q][0]].nx) * items[members[q][0]].ny * items[members[q][0]].nz;
+        return v * double(members[q].size());
+      };
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+      // the lanes start after the labels are on the device
+      HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
+      for (int l = 0; l < nl; ++l) HIPCHK(hipStreamWaitEvent(ctx->aux[l].stream, ctx->fork, 0));
+      std::atomic<int> next{0};
+      std::vector<int> lane_rc(nl, HH_OK);
+      std::vector<std::string> lane_err(nl);
+      std::vector<std::thread> th;
+      for (int l = 0; l < nl; ++l)
+        th.emplace_back([&, l]() {
+          try {
+            if (hipSetDevice(ctx->device) != hipSuccess) throw Fail{HH_EDEVICE};
+            Profile quiet{ctx, false, {}, 0, nullptr};
+            for (int k = next++; k < ngroup; k = next++)
+              results[order[k]] = solve_group_retry(ctx, group_items(order[k]), d_lab, nullptr, false, o, L, quiet,
+                                                    nullptr, ctx->aux[l], nl);
+          } catch (const Fail& e) {
+            lane_rc[l] = e.code;
+            std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+            lane_err[l] = ctx->err;
+          } catch (...) {
+            lane_rc[l] = HH_EDEVICE;
+            lane_err[l] = "unknown error in a lane";
+          }
+        });
+      for (auto& t : th) t.join();
+      for (int l = 0; l < nl; ++l)
+        if (lane_rc[l] != HH_OK) fail(ctx, lane_rc[l], lane_err[l]);
+    }
     int rc = HH_OK;
     double vi = 0.0;
-    bool first = true;
-    for (auto& kv : groups) {
-      std::vector<Item> gi;
-      for (int i : kv.second) gi.push_back(items[i]);
-      GroupResult res = solve_group(ctx, gi, d_lab, nullptr, false, o, L, prof, nullptr);
+    for (int q = 0; q < ngroup; ++q) {
+      const GroupResult& res = results[q];
       vi += res.voxel_iters;
-      for (size_t k = 0; k < kv.second.size(); ++k) {
-        const int i = kv.second[k];
+      for (size_t k = 0; k < members[q].size(); ++k) {
+        const int i = members[q][k];
         write_C(res, int(k), C_out + size_t(i) * 36, C_raw ? C_raw + size_t(i) * 36 : nullptr);
         if (item_status) item_status[i] = res.status[k];
         if (item_iters)
@@ -886,9 +1315,7 @@ int hh_homogenize_batch(hh_ctx* ctx, int nitems, const int* dims, const uint8_t*
         rc = worse(rc, res.status[k]);
         if (report && i == 0) fill_item_report(report, res, int(k));
       }
-      first = false;
     }
-    (void)first;
     end_report(ctx, report);
     if (report) {
       report->voxel_iters = vi;
@@ -907,7 +1334,13 @@ int hh_hierarchical(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, 
     hh_default_opts(&o);
     if (opts) o = *opts;
     check_opts(ctx, o);
-    if (use_surrogate != 0) fail(ctx, HH_EINVAL, "use_surrogate must be 0");
+    if (use_surrogate != 0 && use_surrogate != 1) fail(ctx, HH_EINVAL, "use_surrogate must be 0 or 1");
+    if (use_surrogate) {
+      if (!ctx->sur_a) fail(ctx, HH_EINVAL, "use_surrogate = 1 needs networks attached with hh_set_surrogate");
+      return hierarchical_surrogate_impl(ctx, labels, nx, ny, nz, labels_on_device, phases, nphase, n_sub, pad,
+                                         ctx->sur_a, ctx->sur_b, ctx->sur_spread, ctx->sur_bound, o, C_out, C_sub,
+                                         nullptr, report);
+    }
     if (!labels || !C_out) fail(ctx, HH_EINVAL, "labels and C_out are required");
     if (nx < 1 || ny < 1 || nz < 1 || n_sub < 1) fail(ctx, HH_EINVAL, "sizes must be positive");
     if (nx % n_sub || ny % n_sub || nz % n_sub) fail(ctx, HH_EINVAL, "the subimage size must divide the image size");
@@ -943,7 +1376,7 @@ int hh_hierarchical(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, 
     double L[6][6];
     unit_loads(L);
     void* cf = ws(ctx, "cfield", size_t(nitems) * 21 * (o.precision == 0 ? 4 : 8));
-    GroupResult r1 = solve_group(ctx, items, d_pack, nullptr, false, o, L, prof, cf);
+    GroupResult r1 = solve_group_retry(ctx, items, d_pack, nullptr, false, o, L, prof, cf, main_lane(ctx), 1);
     int rc = HH_OK;
     for (int i = 0; i < nitems; ++i) rc = worse(rc, r1.status[i]);
     if (C_sub) {
@@ -974,7 +1407,7 @@ int hh_hierarchical(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, 
     const int whole[6] = {0, 0, 0, mx, my, mz};
     std::memcpy(l2.region, whole, sizeof(l2.region));
     l2.phases.assign(1, hh_phase{1.0, 1.0});
-    GroupResult r2 = solve_group(ctx, {l2}, nullptr, cf, true, o, L, prof, nullptr);
+    GroupResult r2 = solve_group(ctx, {l2}, nullptr, cf, true, o, L, prof, nullptr, main_lane(ctx), 1);
     end_report(ctx, report);
     write_C(r2, 0, C_out, nullptr);
     rc = worse(rc, r2.status[0]);
@@ -1043,7 +1476,7 @@ int hh_hierarchical_levels(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, i
     }
     const char* names[2] = {"levels_cf0", "levels_cf1"};
     void* cf = ws(ctx, names[0], size_t(items1) * 21 * tb);
-    GroupResult last = solve_group(ctx, items, d_pack, nullptr, false, o, L, prof, cf);
+    GroupResult last = solve_group_retry(ctx, items, d_pack, nullptr, false, o, L, prof, cf, main_lane(ctx), 1);
     int rc = HH_OK;
     for (int st : last.status) rc = worse(rc, st);
     double vi = last.voxel_iters;
@@ -1066,7 +1499,7 @@ int hh_hierarchical_levels(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, i
         it.phases.assign(1, hh_phase{1.0, 1.0});
       }
       void* next = ws(ctx, names[l % 2], size_t(nit) * 21 * tb);
-      last = solve_group(ctx, lv, nullptr, pack, true, o, L, prof, next);
+      last = solve_group(ctx, lv, nullptr, pack, true, o, L, prof, next, main_lane(ctx), 1);
       for (int st : last.status) rc = worse(rc, st);
       vi += last.voxel_iters;
       cf = next;
@@ -1087,7 +1520,7 @@ int hh_hierarchical_levels(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, i
       const int whole[6] = {0, 0, 0, mx, my, mz};
       std::memcpy(fin.region, whole, sizeof(fin.region));
       fin.phases.assign(1, hh_phase{1.0, 1.0});
-      last = solve_group(ctx, {fin}, nullptr, cf, true, o, L, prof, nullptr);
+      last = solve_group(ctx, {fin}, nullptr, cf, true, o, L, prof, nullptr, main_lane(ctx), 1);
       end_report(ctx, report);
       write_C(last, 0, C_out, nullptr);
       rc = worse(rc, last.status[0]);
@@ -1134,165 +1567,20 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     hh_default_opts(&o);
     if (opts) o = *opts;
     check_opts(ctx, o);
-    if (!labels || !C_out || !net_a) fail(ctx, HH_EINVAL, "labels, net_a and C_out are required");
-    if (nx < 1 || ny < 1 || nz < 1 || n_sub < 1) fail(ctx, HH_EINVAL, "sizes must be positive");
-    if (nx % n_sub || ny % n_sub || nz % n_sub) fail(ctx, HH_EINVAL, "the subimage size must divide the image size");
-    if (pad < 0 || 2 * pad >= std::min(nx, std::min(ny, nz)))
-      fail(ctx, HH_EINVAL, "padding must satisfy 0 <= 2 pad < image size");
-    // a network reads either the n_sub^3 core (offset pad) or the whole box
-    const int in_a = hh_net_input_size(net_a), in_b = net_b ? hh_net_input_size(net_b) : in_a;
-    auto window_ok = [&](int e) { return e == n_sub || e == n_sub + 2 * pad; };
-    if (!window_ok(in_a) || !window_ok(in_b))
-      fail(ctx, HH_EINVAL, "the network input edge must be the subimage size or the padded box size");
-    if (!(spread_tol > 0.0) || !(bound_tol >= 0.0)) fail(ctx, HH_EINVAL, "bad gate tolerances");
-    const int b = n_sub + 2 * pad;
-    const int mx = nx / n_sub, my = ny / n_sub, mz = nz / n_sub;
-    check_shape(ctx, b, b, b, o.precision);
-    // one subimage: the intermediate image is a single voxel, whose solve is the identity
-    const bool single = mx == 1 && my == 1 && mz == 1;
-    if (!single) check_shape(ctx, mx, my, mz, o.precision);
-    check_phases(ctx, phases, nphase);
-    if (nphase > 8) fail(ctx, HH_EINVAL, "the surrogate takes at most 8 phases");
-    const long long nvox = (long long)nx * ny * nz;
-    const int nitems = mx * my * mz;
-    begin_report(ctx, report);
-    const hipStream_t st = ctx->stream;
-    const unsigned char* d_img = device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "image");
-    const long long box = (long long)b * b * b;
-    auto* d_pack = static_cast<unsigned char*>(ws(ctx, "pack", size_t(box * nitems)));
-    Profile prof{ctx, o.profile != 0, {}, 0, report};
-    prof.run(HH_K_SETUP, [&] { launch_gather_pad(d_img, nx, ny, nz, n_sub, pad, d_pack, st); });
-    // label counts of the cores (bounds, core-input networks) and, for a
-    // network that reads the whole box, of the boxes; then the predictions
-    auto* c21a = static_cast<double*>(ws(ctx, "sur_c21a", sizeof(double) * 21 * nitems));
-    double* c21b = net_b ? static_cast<double*>(ws(ctx, "sur_c21b", sizeof(double) * 21 * nitems)) : nullptr;
-    auto* d_counts = static_cast<int*>(ws(ctx, "sur_counts", sizeof(int) * 8 * size_t(nitems)));
-    const bool box_in = in_a != n_sub || (net_b && in_b != n_sub);
-    int* d_counts_box = box_in ? static_cast<int*>(ws(ctx, "sur_counts_box", sizeof(int) * 8 * size_t(nitems))) : nullptr;
-    prof.run(HH_K_OTHER, [&] {
-      hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
-      if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
-      hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a,
-                            in_a == n_sub ? d_counts : d_counts_box);
-      if (net_b)
-        hh_net_predict_device(ctx, net_b, d_pack, nitems, b, in_b == n_sub ? pad : 0, c21b,
-                              in_b == n_sub ? d_counts : d_counts_box);
-    });
-    // Voigt and Reuss stiffness of each core's phase fractions
-    std::vector<double> cp(21 * nphase), sp(21 * nphase);
-    for (int q = 0; q < nphase; ++q) {
-      const double K = phases[q].K, G = phases[q].G;
-      double C[6][6] = {}, S[6][6] = {};
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          C[i][j] = (i == j) ? K + 4.0 * G / 3.0 : K - 2.0 * G / 3.0;
-          S[i][j] = (i == j) ? 1.0 / (9.0 * K) + 1.0 / (3.0 * G) : 1.0 / (9.0 * K) - 1.0 / (6.0 * G);
-        }
-      for (int i = 3; i < 6; ++i) {
-        C[i][i] = G;
-        S[i][i] = 1.0 / G;
-      }
-      int k = 0;
-      for (int i = 0; i < 6; ++i)
-        for (int j = i; j < 6; ++j) {
-          cp[q * 21 + k] = C[i][j];
-          sp[q * 21 + k] = S[i][j];
-          ++k;
-        }
-    }
-    auto* d_cp = static_cast<double*>(ws(ctx, "sur_cp", sizeof(double) * 21 * nphase));
-    auto* d_sp = static_cast<double*>(ws(ctx, "sur_sp", sizeof(double) * 21 * nphase));
-    auto* cv21 = static_cast<double*>(ws(ctx, "sur_cv", sizeof(double) * 21 * nitems));
-    auto* cr21 = static_cast<double*>(ws(ctx, "sur_cr", sizeof(double) * 21 * nitems));
-    auto* d_flag = static_cast<int*>(ws(ctx, "sur_flag", sizeof(int) * nitems));
-    HIPCHK(hipMemcpyAsync(d_cp, cp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_sp, sp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
-    prof.run(HH_K_OTHER, [&] {
-      hh_launch_bounds(d_counts, nitems, n_sub, nphase, d_cp, d_sp, cv21, cr21, st);
-      hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, d_flag, st);
-    });
-    HIPCHK(hipGetLastError());
-    std::vector<int> flag(nitems);
-    std::vector<double> ha(21 * size_t(nitems)), hb;
-    HIPCHK(hipMemcpyAsync(flag.data(), d_flag, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ha.data(), c21a, sizeof(double) * 21 * nitems, hipMemcpyDeviceToHost, st));
-    if (net_b) {
-      hb.resize(ha.size());
-      HIPCHK(hipMemcpyAsync(hb.data(), c21b, sizeof(double) * 21 * nitems, hipMemcpyDeviceToHost, st));
-    }
-    HIPCHK(hipStreamSynchronize(st));
-    prof.flush();
-    // FFT solves of the gated items
-    std::vector<int> fb;
-    for (int i = 0; i < nitems; ++i)
-      if (flag[i]) fb.push_back(i);
-    std::vector<double> field(21 * size_t(nitems));
-    for (size_t i = 0; i < field.size(); ++i) field[i] = net_b ? 0.5 * (ha[i] + hb[i]) : ha[i];
-    double vi = 0.0;
-    int rc = HH_OK;
-    double L[6][6];
-    unit_loads(L);
-    if (!fb.empty()) {
-      std::vector<Item> items(fb.size());
-      for (size_t k = 0; k < fb.size(); ++k) {
-        Item& it = items[k];
-        it.nx = it.ny = it.nz = b;
-        it.lab_off = box * fb[k];
-        it.cf_off = -1;
-        const int r[6] = {pad, pad, pad, pad + n_sub, pad + n_sub, pad + n_sub};
-        std::memcpy(it.region, r, sizeof(r));
-        it.phases.assign(phases, phases + nphase);
-      }
-      GroupResult r1 = solve_group(ctx, items, d_pack, nullptr, false, o, L, prof, nullptr);
-      vi += r1.voxel_iters;
-      for (size_t k = 0; k < fb.size(); ++k) {
-        rc = worse(rc, r1.status[k]);
-        const double* S = r1.C72.data() + k * 72 + 36;
-        int q = 0;
-        for (int i = 0; i < 6; ++i)
-          for (int j = i; j < 6; ++j) field[size_t(fb[k]) * 21 + q++] = S[i * 6 + j];
-      }
-    }
-    if (C_sub) std::memcpy(C_sub, field.data(), sizeof(double) * field.size());
-    if (fallback) std::memcpy(fallback, flag.data(), sizeof(int) * nitems);
-    if (single) {
-      end_report(ctx, report);
-      int q = 0;
-      for (int i = 0; i < 6; ++i)
-        for (int j = i; j < 6; ++j) C_out[i * 6 + j] = C_out[j * 6 + i] = field[q++];
-      if (report) {
-        report->voxel_iters = vi;
-        report->items = nitems;
-        report->status = rc;
-      }
-      return rc;
-    }
-    // level 2
-    auto* d_field = static_cast<double*>(ws(ctx, "sur_field", sizeof(double) * field.size()));
-    HIPCHK(hipMemcpyAsync(d_field, field.data(), sizeof(double) * field.size(), hipMemcpyHostToDevice, st));
-    void* cf = ws(ctx, "cfield", field.size() * (o.precision == 0 ? 4 : 8));
-    launch_convert_field(o.precision, d_field, cf, (long long)field.size(), st);
-    HIPCHK(hipGetLastError());
-    Item l2;
-    l2.nx = mx;
-    l2.ny = my;
-    l2.nz = mz;
-    l2.lab_off = 0;
-    l2.cf_off = 0;
-    const int whole[6] = {0, 0, 0, mx, my, mz};
-    std::memcpy(l2.region, whole, sizeof(l2.region));
-    l2.phases.assign(1, hh_phase{1.0, 1.0});
-    GroupResult r2 = solve_group(ctx, {l2}, nullptr, cf, true, o, L, prof, nullptr);
-    end_report(ctx, report);
-    write_C(r2, 0, C_out, nullptr);
-    rc = worse(rc, r2.status[0]);
-    if (report) {
-      fill_item_report(report, r2, 0);
-      report->voxel_iters = vi + r2.voxel_iters;
-      report->items = nitems;
-      report->status = rc;
-    }
-    return rc;
+    return hierarchical_surrogate_impl(ctx, labels, nx, ny, nz, labels_on_device, phases, nphase, n_sub, pad, net_a,
+                                       net_b, spread_tol, bound_tol, o, C_out, C_sub, fallback, report);
+  });
+}
+
+int hh_set_surrogate(hh_ctx* ctx, hh_net* net_a, hh_net* net_b, double spread_tol, double bound_tol) {
+  return guarded(ctx, [&]() -> int {
+    if (!net_a && net_b) fail(ctx, HH_EINVAL, "net_b needs net_a");
+    if (net_a && (!(spread_tol > 0.0) || !(bound_tol >= 0.0))) fail(ctx, HH_EINVAL, "bad gate tolerances");
+    ctx->sur_a = net_a;
+    ctx->sur_b = net_b;
+    ctx->sur_spread = spread_tol;
+    ctx->sur_bound = bound_tol;
+    return HH_OK;
   });
 }
 

@@ -84,11 +84,27 @@ struct GroupArgs {
   long long tmp_stride;    // complex elements per system
   long long a_stride;      // complex elements per system
   SysState* state;
-  double* part_x;          // [nsys][nwg_x][kPartX]
-  double* part_z;          // [nsys][nwg_z]
-  int nwg_x, nwg_z;
+  double* part_x;          // [nsys][ny * nz rows][kPartX]: row sums of the x pass
+  double* part_z;          // [nsys][ny * hx columns]: column sums of the z pass
+  double* chunk_x;         // [nsys][nchunk_x][kPartX]: sums of kFinChunk consecutive rows
+  double* chunk_z;         // [nsys][nchunk_z]
+  int nrow_x, ncol_z;      // ny * nz and ny * hx
+  int nchunk_x, nchunk_z;  // ceil(nrow_x / kFinChunk), ceil(ncol_z / kFinChunk)
 };
 
-constexpr int kPartX = 13;  // (p, sigma) and region sums of p and sigma
+constexpr int kPartX = 13;  // (p, C:p), then region sums of p and of sigma
+
+// Every FP64 reduction of the solve follows a fixed tree defined on the
+// grid, not on the tile a workgroup happens to hold, so that all tile
+// variants give the same bits:
+//  - a line of the x pass (one spectrum row and component pair) or of the z
+//    pass (one column) is summed in kLineGroups groups, group g taking the
+//    line positions g, g + kLineGroups, ... in increasing order, and the
+//    groups are added in a fixed butterfly;
+//  - the per-row (x) and per-column (z) sums are stored, summed in chunks of
+//    kFinChunk consecutive ones by one block each (fixed thread strides and
+//    tree), and the chunk sums of a system by one block in a fixed order.
+constexpr int kLineGroups = 16;
+constexpr int kFinChunk = 4096;
 
 }  // namespace hh

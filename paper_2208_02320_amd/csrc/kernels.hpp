@@ -51,10 +51,18 @@ SizeOpsFn size_ops_f32_20(int n, int v);
 SizeOpsFn size_ops_f32_21(int n, int v);
 SizeOpsFn size_ops_f32_22(int n, int v);
 SizeOpsFn size_ops_f32_23(int n, int v);
+SizeOpsFn size_ops_f32_24(int n, int v);
+SizeOpsFn size_ops_f32_25(int n, int v);
+SizeOpsFn size_ops_f32_26(int n, int v);
+SizeOpsFn size_ops_f32_27(int n, int v);
+SizeOpsFn size_ops_f32_28(int n, int v);
 SizeOpsFn size_ops_f64_0(int n, int v);
 SizeOpsFn size_ops_f64_1(int n, int v);
 SizeOpsFn size_ops_f64_2(int n, int v);
 SizeOpsFn size_ops_f64_3(int n, int v);
+SizeOpsFn size_ops_f64_4(int n, int v);
+SizeOpsFn size_ops_f64_5(int n, int v);
+SizeOpsFn size_ops_f64_6(int n, int v);
 void launch_fin_x(int mode, const GroupArgs& g, hipStream_t st);
 void launch_fin_z(int mode, const GroupArgs& g, hipStream_t st);
 void launch_stiffness(int precision, const SysState* state, int nitems, double* out, void* cfield_out,

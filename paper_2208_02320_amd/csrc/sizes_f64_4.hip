@@ -1,0 +1,13 @@
+// Instantiation of the pass kernels for one set of axis lengths (F64).
+#include "solver_kernels.hpp"
+
+namespace hh {
+
+SizeOpsFn size_ops_f64_4(int n, int v) {
+  switch (n) {
+    HH_CASE_D(100) HH_CASE_D(120) HH_CASE_D(144)
+  }
+  return nullptr;
+}
+
+}  // namespace hh

@@ -33,13 +33,41 @@ __device__ __forceinline__ void reduce_parts(const double* part, int n, double (
   block_sum<NV>(v, scratch);
 }
 
+// First stage of a finalize: block (c, s) sums the per-row (x) or
+// per-column (z) values [c kFinChunk, (c + 1) kFinChunk) of system s; thread
+// t takes every 256th one from t in order, then the block tree.  Systems
+// that stopped are skipped except when the right-hand side is formed.
+template <int NV>
+__global__ void __launch_bounds__(256) k_fin_chunks(GroupArgs g, int rhs) {
+  __shared__ double scratch[4 * NV];
+  const int s = blockIdx.y;
+  if (!rhs && g.state[s].status != kRunning) return;
+  const bool x = NV == kPartX;
+  const long long n = x ? g.nrow_x : g.ncol_z;
+  const double* part = (x ? g.part_x : g.part_z) + (long long)s * n * NV;
+  const long long i0 = (long long)blockIdx.x * kFinChunk, i1 = min(n, i0 + kFinChunk);
+  double v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = 0.0;
+  for (long long r = i0 + threadIdx.x; r < i1; r += 256) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] += part[r * NV + i];
+  }
+  block_sum<NV>(v, scratch);
+  if (threadIdx.x == 0) {
+    double* out = (x ? g.chunk_x : g.chunk_z) + ((long long)s * gridDim.x + blockIdx.x) * NV;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = v[i];
+  }
+}
+
 __global__ void __launch_bounds__(256) k_fin_x(GroupArgs g, int mode) {
   __shared__ double scratch[4 * kPartX];
   const int s = blockIdx.x;
   SysState* st = g.state + s;
   if (mode != kXRhs && st->status != kRunning) return;
   double v[kPartX];
-  reduce_parts<kPartX>(g.part_x + (long long)s * g.nwg_x * kPartX, g.nwg_x, v, scratch);
+  reduce_parts<kPartX>(g.chunk_x + (long long)s * g.nchunk_x * kPartX, g.nchunk_x, v, scratch);
   if (threadIdx.x != 0) return;
   const ItemDesc& it = g.items[g.sys[s].item];
   const double inv = it.inv_region;
@@ -91,7 +119,7 @@ __global__ void __launch_bounds__(256) k_fin_z(GroupArgs g, int mode) {
   SysState* st = g.state + s;
   if (st->status != kRunning) return;
   double v[1];
-  reduce_parts<1>(g.part_z + (long long)s * g.nwg_z, g.nwg_z, v, scratch);
+  reduce_parts<1>(g.chunk_z + (long long)s * g.nchunk_z, g.nchunk_z, v, scratch);
   if (threadIdx.x != 0) return;
   const double V = double(g.nx) * g.ny * g.nz;
   const double rr = v[0] / V;
@@ -218,8 +246,9 @@ __global__ void k_stiffness(const SysState* state, int nitems, double* out, T* c
 SizeOpsFn size_ops(int n, int precision, int variant) {
   using Part = SizeOpsFn (*)(int, int);
   if (variant < 0 || variant >= kNVariant) return nullptr;
-  static const Part f32[] = {size_ops_f32_0, size_ops_f32_1, size_ops_f32_2, size_ops_f32_3, size_ops_f32_4, size_ops_f32_5, size_ops_f32_6, size_ops_f32_7, size_ops_f32_8, size_ops_f32_9, size_ops_f32_10, size_ops_f32_11, size_ops_f32_12, size_ops_f32_13, size_ops_f32_14, size_ops_f32_15, size_ops_f32_16, size_ops_f32_17, size_ops_f32_18, size_ops_f32_19, size_ops_f32_20, size_ops_f32_21, size_ops_f32_22, size_ops_f32_23};
-  static const Part f64[] = {size_ops_f64_0, size_ops_f64_1, size_ops_f64_2, size_ops_f64_3};
+  static const Part f32[] = {size_ops_f32_0, size_ops_f32_1, size_ops_f32_2, size_ops_f32_3, size_ops_f32_4, size_ops_f32_5, size_ops_f32_6, size_ops_f32_7, size_ops_f32_8, size_ops_f32_9, size_ops_f32_10, size_ops_f32_11, size_ops_f32_12, size_ops_f32_13, size_ops_f32_14, size_ops_f32_15, size_ops_f32_16, size_ops_f32_17, size_ops_f32_18, size_ops_f32_19, size_ops_f32_20, size_ops_f32_21, size_ops_f32_22, size_ops_f32_23, size_ops_f32_24, size_ops_f32_25, size_ops_f32_26, size_ops_f32_27, size_ops_f32_28};
+  static const Part f64[] = {size_ops_f64_0, size_ops_f64_1, size_ops_f64_2, size_ops_f64_3,
+                             size_ops_f64_4, size_ops_f64_5, size_ops_f64_6};
   if (precision == 0) {
     for (Part p : f32)
       if (SizeOpsFn f = p(n, variant)) return f;
@@ -231,9 +260,11 @@ SizeOpsFn size_ops(int n, int precision, int variant) {
 }
 
 void launch_fin_x(int mode, const GroupArgs& g, hipStream_t st) {
+  k_fin_chunks<kPartX><<<dim3(g.nchunk_x, g.nsys), 256, 0, st>>>(g, mode == kXRhs ? 1 : 0);
   k_fin_x<<<g.nsys, 256, 0, st>>>(g, mode);
 }
 void launch_fin_z(int mode, const GroupArgs& g, hipStream_t st) {
+  k_fin_chunks<1><<<dim3(g.nchunk_z, g.nsys), 256, 0, st>>>(g, mode == kZFwdRhs ? 1 : 0);
   k_fin_z<<<g.nsys, 256, 0, st>>>(g, mode);
 }
 void launch_stiffness(int precision, const SysState* state, int nitems, double* out, void* cfield_out,

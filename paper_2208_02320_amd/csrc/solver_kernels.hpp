@@ -167,6 +167,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum of one value over the kLineGroups consecutive lanes of a group, in a
+// fixed butterfly (the same tree in every lane, whatever wave or task the
+// group sits in); every lane of the wave must take part.
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(kLineGroups == 16, "butterfly over 16 lanes");
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return v;
+}
+
 // Sum NV doubles over the block; result valid in thread 0.  scratch holds
 // at least (blockDim.x / 64) * NV doubles and is not otherwise in use.
 template <int NV>
@@ -184,66 +196,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += scratch[w * NV + i];
       v[i] = s;
-    }
-  }
-}
-
-// Sum NV doubles over a block of TH threads through LDS (no cross-lane
-// shuffles); result valid in thread 0.  scratch holds TH * NV doubles.
-// Each value is summed by G threads over strided shares, then thread 0 adds
-// the G partials in order; with fewer than NV * G threads, a thread takes
-// several (value, share) tasks.
-template <int NV, int TH>
-__device__ __forceinline__ void block_sum_lds(double (&v)[NV], double* scratch) {
-  constexpr int G = 8, NT = NV * G, KT = (NT + TH - 1) / TH;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) scratch[i * TH + threadIdx.x] = v[i];
-  __syncthreads();
-  double part[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    const int t = threadIdx.x + k * TH;
-    part[k] = 0.0;
-    if (t < NT) {
-      const int i = t / G, gi = t % G;
-      for (int j = gi; j < TH; j += G) part[k] += scratch[i * TH + j];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    const int t = threadIdx.x + k * TH;
-    if (t < NT) scratch[t] = part[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double t = 0.0;
-      for (int gi = 0; gi < G; ++gi) t += scratch[i * G + gi];
-      v[i] = t;
-    }
-  }
-}
-
-// block_sum_lds for a scratch that holds only CH values per thread
-// (TH * CH doubles): the values pass through it CH at a time, each summed as
-// block_sum_lds sums it.  Result valid in thread 0.
-template <int NV, int TH, int CH>
-__device__ __forceinline__ void block_sum_lds_chunked(double (&v)[NV], double* scratch) {
-  static_assert(CH >= 1 && CH < NV, "chunk size");
-#pragma unroll
-  for (int c0 = 0; c0 < NV; c0 += CH) {
-    constexpr int NC = CH;
-    double w[NC];
-#pragma unroll
-    for (int i = 0; i < NC; ++i) w[i] = c0 + i < NV ? v[c0 + i] : 0.0;
-    if (c0 > 0) __syncthreads();  // thread 0 has read the previous chunk
-    block_sum_lds<NC, TH>(w, scratch);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int i = 0; i < NC; ++i)
-        if (c0 + i < NV) v[c0 + i] = w[i];
     }
   }
 }
@@ -401,7 +353,9 @@ __global__ void __launch_bounds__((AxisCfg<N, T, V>::THREADS)) k_zpass(GroupArgs
     const T alpha = T(st->alpha);
     const T g1 = T(0.5 / g.ref_mu);
     const T g2 = T((g.ref_lam + g.ref_mu) / (g.ref_lam + 2.0 * g.ref_mu));
-    double acc[1] = {0.0};
+    double val[KT];  // per-frequency terms of the column sums
+#pragma unroll
+    for (int k = 0; k < KT; ++k) val[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
       const int task = threadIdx.x + k * TH;
@@ -424,26 +378,46 @@ __global__ void __launch_bounds__((AxisCfg<N, T, V>::THREADS)) k_zpass(GroupArgs
         if constexpr (MODE == kZFwdCg) {
 #pragma unroll
           for (int i = 0; i < 3; ++i) r[i] = ra[k][i] - alpha * q[i];
-          acc[0] += w * sym_norm2(n, r);
+          val[k] = w * sym_norm2(n, r);
         } else if constexpr (MODE == kZFwdRhs) {
 #pragma unroll
           for (int i = 0; i < 3; ++i) r[i] = cx<T>{-q[i].re, -q[i].im};
-          acc[0] += w * sym_norm2(n, r);
+          val[k] = w * sym_norm2(n, r);
         } else {  // basic fixed point: eps* <- eps* - Gamma0 sigma
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
             const cx<T> gi = live ? g1 * (t[i] - (g2 * n[i]) * ntn) : cx<T>{T(0), T(0)};
             r[i] = ra[k][i] - gi;
           }
-          acc[0] += w * sym_norm2(n, q);
+          val[k] = w * sym_norm2(n, q);
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) ar[off + i] = r[i];
       }
     }
+    // column sums over z: staged by (column, position), each column in
+    // kLineGroups groups of positions and a butterfly
     __syncthreads();
-    block_sum<1>(acc, reinterpret_cast<double*>(buf));
-    if (threadIdx.x == 0) g.part_z[(long long)s * g.nwg_z + blockIdx.x] = acc[0];
+    double* vd = reinterpret_cast<double*>(buf);  // [M][N]
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const int task = threadIdx.x + k * TH;
+      if (task < ntask) vd[(task % M) * N + task / M] = val[k];
+    }
+    __syncthreads();
+    constexpr int NC = M * kLineGroups, KC = (NC + TH - 1) / TH;
+    double* pcol = g.part_z + (long long)s * g.ncol_z + (long long)y * g.hx + kx0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int q = threadIdx.x + k * TH;
+      const int kxl = q / kLineGroups, gq = q % kLineGroups;
+      const bool task = (NC % TH == 0 || q < NC) && kxl < mk;
+      double a = 0.0;
+      if (task)
+        for (int pos = gq; pos < N; pos += kLineGroups) a += vd[kxl * N + pos];
+      a = group_sum(a);
+      if (task && gq == 0) pcol[kxl] = a;
+    }
   }
 }
 
@@ -493,7 +467,6 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + N;
   __shared__ T s_lam[kMaxPhase], s_mu[kMaxPhase];
-  __shared__ double s_sig[6];
 
   const int s = blockIdx.y;
   SysState* st = g.state + s;
@@ -596,16 +569,79 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
   // Whole-box region: sum p = 0 (p is zero-mean) and the row sums of sigma
   // are the kx = 0 outputs of the forward transform, so no per-voxel sums.
   const bool whole = x0 == 0 && x1 == N && y0 == 0 && y1 == g.ny && z0 == 0 && z1 == g.nz;
-  double acc[kPartX];
+  double* prow = g.part_x + ((long long)s * g.nrow_x + r0) * kPartX;  // row sums of this tile
+  // Region sums of one field held in buf (p before the law, sigma after it):
+  // line l = 3 row + pair, summed in kLineGroups groups of positions, then
+  // the groups in a butterfly; written as entries base + 2 pair, + 1 of the
+  // row.  In FP mode p carries the macroscopic strain: E times the row's
+  // region length is added.
+  constexpr int NQ = 3 * R * kLineGroups;
+  constexpr int KQ = (NQ + TH - 1) / TH;
+  auto region_lines = [&](int base, double scale, bool add_e) {
 #pragma unroll
-  for (int i = 0; i < kPartX; ++i) acc[i] = 0.0;
+    for (int k = 0; k < KQ; ++k) {
+      const int q = threadIdx.x + k * TH;
+      const int l = q / kLineGroups, gq = q % kLineGroups;
+      const int rl = l / 3, pr = l - 3 * (l / 3);
+      const int row = r0 + rl, zr = row / g.ny, yr = row - zr * g.ny;
+      const bool task = (NQ % TH == 0 || q < NQ) && rl < nr;
+      const bool rin = task && yr >= y0 && yr < y1 && zr >= z0 && zr < z1;
+      double sr = 0.0, si = 0.0;
+      if (rin) {
+        for (int pos = gq; pos < N; pos += kLineGroups) {
+          const int x = perm_idx<N1, N2>(pos);
+          if (x >= x0 && x < x1) {
+            const cx<T> v = buf[lds_at<N1, P>(pos, L) + l];
+            sr += double(v.re);
+            si += double(v.im);
+          }
+        }
+      }
+      sr = group_sum(sr);
+      si = group_sum(si);
+      if (task && gq == 0) {
+        double a = 0.0, b = 0.0;
+        if (rin) {
+          a = sr * scale;
+          b = si * scale;
+          if (add_e) {
+            a += double(x1 - x0) * double(E[2 * pr]);
+            b += double(x1 - x0) * double(E[2 * pr + 1]);
+          }
+        }
+        prow[(long long)rl * kPartX + base + 2 * pr] = a;
+        prow[(long long)rl * kPartX + base + 2 * pr + 1] = b;
+      }
+    }
+  };
+  if (MODE != kXRhs && !whole) region_lines(1, 1.0 / (double(N) * g.ny * g.nz), MODE == kXFp);
+  if (MODE == kXRhs && !whole) {
+    // the right-hand side's p is the constant E
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+      const int q = threadIdx.x + k * TH;
+      const int l = q / kLineGroups, gq = q % kLineGroups;
+      const int rl = l / 3, pr = l - 3 * (l / 3);
+      const int row = r0 + rl, zr = row / g.ny, yr = row - zr * g.ny;
+      if ((NQ % TH == 0 || q < NQ) && rl < nr && gq == 0) {
+        const bool rin = yr >= y0 && yr < y1 && zr >= z0 && zr < z1;
+        prow[(long long)rl * kPartX + 1 + 2 * pr] = rin ? double(x1 - x0) * double(E[2 * pr]) : 0.0;
+        prow[(long long)rl * kPartX + 2 + 2 * pr] = rin ? double(x1 - x0) * double(E[2 * pr + 1]) : 0.0;
+      }
+    }
+  }
+  // per-voxel values of the row sums of (p, C:p) (CG) or (C:E, C:E) (RHS)
+  double pv[KE];
+#pragma unroll
+  for (int k = 0; k < KE; ++k) pv[k] = 0.0;
+  if (!whole) __syncthreads();  // the region sums of p have read buf
 #pragma unroll
   for (int k = 0; k < KE; ++k) {
     const int task = threadIdx.x + k * TH;
     if (R * N % TH != 0 && task >= R * N) break;
     const int rl = task % R, pos = task / R;
     const int x = perm_idx<N1, N2>(pos);
-    const int row = r0 + rl, z = row / g.ny, y = row - z * g.ny;
+    const int row = r0 + rl;
     const bool valid = rl < nr;
     T p[6];
     if constexpr (MODE == kXRhs) {
@@ -633,14 +669,14 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
       // sigma_V = C_V eps_eng with eps_eng = (e11 e22 e33 2e23 2e13 2e12)
       const T ee[6] = {p[0], p[1], p[2], T(2) * p[3], T(2) * p[4], T(2) * p[5]};
       T Cm[6][6];
-      int k = 0;
+      int kk = 0;
 #pragma unroll
       for (int i = 0; i < 6; ++i)
 #pragma unroll
         for (int j = i; j < 6; ++j) {
-          Cm[i][j] = Cv[k];
-          Cm[j][i] = Cv[k];
-          ++k;
+          Cm[i][j] = Cv[kk];
+          Cm[j][i] = Cv[kk];
+          ++kk;
         }
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
@@ -661,35 +697,36 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
         double ss = 0.0;
 #pragma unroll
         for (int c = 0; c < 6; ++c) ss += (c < 3 ? 1.0 : 2.0) * double(sg[c]) * sg[c];
-        acc[0] += ss;
+        pv[k] = ss;
       } else if constexpr (MODE == kXCg) {
-        // p : C : p >= 0 per voxel, formed in T and accumulated in double
+        // p : C : p >= 0 per voxel, formed in T and summed in double
         T ps = T(0);
 #pragma unroll
         for (int c = 0; c < 6; ++c) ps += (c < 3 ? T(1) : T(2)) * p[c] * sg[c];
-        acc[0] += double(ps);
-      }
-      if (!whole && x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          acc[1 + c] += double(p[c]);
-          acc[7 + c] += double(sg[c]);
-        }
+        pv[k] = double(ps);
       }
     }
 #pragma unroll
     for (int pr = 0; pr < 3; ++pr) buf[lds_at<N1, P>(pos, L) + rl * 3 + pr] = cx<T>{sg[2 * pr], sg[2 * pr + 1]};
   }
   __syncthreads();
+  if (!whole) {
+    region_lines(7, 1.0, false);
+    __syncthreads();  // buf is read above and transformed below
+  }
   fft_perm2nat<N1, N2, -1, T, P>(buf, L, tw);
-  // whole box: tile sums of sigma are the kx = 0 outputs (lines row * 3 + pair);
-  // thread 2 * pair + (0 re, 1 im) sums its component over the tile rows
-  double sig_sum = 0.0;
-  if (whole && threadIdx.x < 6) {
-    const int pr = threadIdx.x >> 1;
-    for (int rl = 0; rl < nr; ++rl) {
-      const cx<T> z0v = buf[lds_at<N1, P>(0, L) + rl * 3 + pr];
-      sig_sum += double((threadIdx.x & 1) ? z0v.im : z0v.re);
+  // whole box: the kx = 0 output of line row * 3 + pair is the row sum of
+  // sigma components 2 pair (re) and 2 pair + 1 (im); the row sums of p are
+  // 0, or N E in FP mode (p carries E there)
+  if (whole) {
+    for (int l = threadIdx.x; l < 3 * nr; l += TH) {
+      const int rl = l / 3, pr = l - 3 * (l / 3);
+      const cx<T> z0v = buf[lds_at<N1, P>(0, L) + l];
+      double* o = prow + (long long)rl * kPartX;
+      o[7 + 2 * pr] = double(z0v.re);
+      o[8 + 2 * pr] = double(z0v.im);
+      o[1 + 2 * pr] = MODE == kXFp ? double(N) * double(E[2 * pr]) : 0.0;
+      o[2 + 2 * pr] = MODE == kXFp ? double(N) * double(E[2 * pr + 1]) : 0.0;
     }
   }
   auto pack = [&](int kx, int rl, int pr) {
@@ -714,35 +751,29 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
     }
   }
   __syncthreads();
-  if (whole) {
-    // only (p, C:p) is spread over the threads
-    if (threadIdx.x < 6) s_sig[threadIdx.x] = sig_sum;
-    double a0[1] = {acc[0]};
-    block_sum_lds<1, TH>(a0, reinterpret_cast<double*>(buf));
-    if (threadIdx.x == 0) {
-      acc[0] = a0[0];
+  // row sums of the per-voxel values: staged by position, then each row in
+  // kLineGroups groups and a butterfly
+  double* vs = reinterpret_cast<double*>(buf);  // [R][N]
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        acc[1 + c] = MODE == kXFp ? double(nr) * N * double(E[c]) : 0.0;
-        acc[7 + c] = s_sig[c];
-      }
+  for (int k = 0; k < KE; ++k) {
+    const int task = threadIdx.x + k * TH;
+    if (R * N % TH == 0 || task < R * N) vs[(task % R) * N + task / R] = pv[k];
+  }
+  __syncthreads();
+  if constexpr (MODE != kXFp) {
+    constexpr int NR = R * kLineGroups, KR = (NR + TH - 1) / TH;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int q = threadIdx.x + k * TH;
+      const int rl = q / kLineGroups, gq = q % kLineGroups;
+      double a = 0.0;
+      if ((NR % TH == 0 || q < NR) && rl < nr)
+        for (int pos = gq; pos < N; pos += kLineGroups) a += vs[rl * N + pos];
+      a = group_sum(a);
+      if ((NR % TH == 0 || q < NR) && rl < nr && gq == 0) prow[(long long)rl * kPartX] = a;
     }
   } else {
-    // the tile buffer serves as scratch: all 13 values per thread at once,
-    // or as many as fit per pass
-    constexpr int kScratch = (N * L + N2 * P) * int(sizeof(cx<T>)) / (TH * 8);  // doubles per thread
-    if constexpr (kScratch >= kPartX) {
-      block_sum_lds<kPartX, TH>(acc, reinterpret_cast<double*>(buf));
-    } else if constexpr (kScratch >= 1) {
-      block_sum_lds_chunked<kPartX, TH, kScratch>(acc, reinterpret_cast<double*>(buf));
-    } else {
-      block_sum<kPartX>(acc, reinterpret_cast<double*>(buf));
-    }
-  }
-  if (threadIdx.x == 0) {
-    double* out = g.part_x + ((long long)s * g.nwg_x + blockIdx.x) * kPartX;
-#pragma unroll
-    for (int i = 0; i < kPartX; ++i) out[i] = acc[i];
+    for (int rl = threadIdx.x; rl < nr; rl += TH) prow[(long long)rl * kPartX] = 0.0;
   }
 }
 

@@ -46,6 +46,7 @@ static int host_checks(void) {
   hh_ctx *ctx = NULL;
   const int rc = hh_create(&ctx, 0, NULL);
   printf("create %d\n", rc);
+  if (rc != HH_OK) fprintf(stderr, "hh_create: %s\n", hh_last_error(NULL));
   hh_destroy(ctx);
   return 0;
 }
@@ -53,7 +54,7 @@ static int host_checks(void) {
 static int solve(int n, int t) {
   hh_ctx *ctx = NULL;
   if (hh_create(&ctx, 0, NULL) != HH_OK) {
-    fprintf(stderr, "hh_create failed: %s\n", ctx ? hh_last_error(ctx) : "no context");
+    fprintf(stderr, "hh_create failed: %s\n", hh_last_error(NULL));
     hh_destroy(ctx);
     return 1;
   }

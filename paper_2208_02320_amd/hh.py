@@ -30,9 +30,9 @@ SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_la
            "hh_workspace_bytes", "hh_release_workspace", "hh_size_supported", "hh_homogenize",
            "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_hierarchical_levels",
            "hh_gather_subimages",
-           "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_get_params",
+           "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_load", "hh_net_info", "hh_net_get_params",
            "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling",
-           "hh_net_get_fraction_scaling", "hh_net_forward",
+           "hh_net_get_fraction_scaling", "hh_net_forward", "hh_set_surrogate",
            "hh_net_gradient", "hh_net_train_step", "hh_net_predict", "hh_hierarchical_surrogate",
            "hh_richardson", "hh_moduli", "hh_mean_moduli")
 
@@ -52,19 +52,22 @@ class Opts(ct.Structure):
                 ("precision", ct.c_int), ("nyquist", ct.c_int), ("profile", ct.c_int),
                 ("stall_limit", ct.c_int), ("chunk", ct.c_int),
                 ("ref_lambda", ct.c_double), ("ref_mu", ct.c_double),
-                ("tune", ct.c_int), ("graph", ct.c_int), ("plan", ct.c_int * 3), ("loads_per_wave", ct.c_int)]
+                ("tune", ct.c_int), ("graph", ct.c_int), ("plan", ct.c_int * 3), ("loads_per_wave", ct.c_int),
+                ("retry", ct.c_int), ("verify", ct.c_int), ("lanes", ct.c_int)]
 
 
 class Report(ct.Structure):
     _fields_ = [("status", ct.c_int), ("iters", ct.c_int * 6), ("rel_resid", ct.c_double * 6),
                 ("asym", ct.c_double), ("seconds", ct.c_double), ("voxel_iters", ct.c_double),
                 ("items", ct.c_longlong), ("kernel_ms", ct.c_double * NKERNEL),
-                ("kernel_launches", ct.c_int * NKERNEL), ("plan", ct.c_int * 3), ("setup_ms", ct.c_double)]
+                ("kernel_launches", ct.c_int * NKERNEL), ("plan", ct.c_int * 3), ("setup_ms", ct.c_double),
+                ("retried", ct.c_longlong), ("bytes_moved", ct.c_double), ("err_vs_oracle", ct.c_double)]
 
     def as_dict(self):
         return dict(status=self.status, iters=list(self.iters), rel_resid=list(self.rel_resid),
                     asym=self.asym, seconds=self.seconds, voxel_iters=self.voxel_iters,
                     items=self.items, plan=list(self.plan), setup_ms=self.setup_ms,
+                    retried=self.retried, bytes_moved=self.bytes_moved, err_vs_oracle=self.err_vs_oracle,
                     kernel_ms={k: self.kernel_ms[i] for i, k in enumerate(KERNEL_CLASSES)},
                     kernel_launches={k: self.kernel_launches[i] for i, k in enumerate(KERNEL_CLASSES)})
 
@@ -112,6 +115,8 @@ def load_library(path=LIB_PATH):
     lib.hh_net_destroy.restype = None
     lib.hh_net_num_params.argtypes = [P]
     lib.hh_net_num_params.restype = LL
+    lib.hh_net_load.argtypes = [P, ct.c_char_p, ct.POINTER(P)]
+    lib.hh_net_info.argtypes = [P, ct.POINTER(I), ct.POINTER(I)]
     lib.hh_net_get_params.argtypes = [P, P, FP, LL]
     lib.hh_net_set_params.argtypes = [P, P, FP, LL]
     lib.hh_net_set_scaling.argtypes = [P, P, DP, DP]
@@ -124,6 +129,7 @@ def load_library(path=LIB_PATH):
     lib.hh_net_predict.argtypes = [P, P, P, I, I, I, I, DP]
     lib.hh_hierarchical_surrogate.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, I, I, P, P, D, D,
                                               ct.POINTER(Opts), DP, DP, ct.POINTER(I), ct.POINTER(Report)]
+    lib.hh_set_surrogate.argtypes = [P, P, P, D, D]
     lib.hh_richardson.argtypes = [ct.POINTER(I), DP, I, DP, DP]
     lib.hh_moduli.argtypes = [DP, DP, DP]
     lib.hh_mean_moduli.argtypes = [DP, LL, DP, DP]
@@ -205,7 +211,7 @@ class Context:
         h = ct.c_void_p()
         rc = self._lib.hh_create(ct.byref(h), self.device, ct.c_void_p(stream.cuda_stream))
         if rc != HH_OK:
-            raise HHError(rc, "hh_create failed (is this a gfx950 device?)")
+            raise HHError(rc, self._lib.hh_last_error(None).decode() or "hh_create failed")
         self._h = h
 
     def close(self):
@@ -329,7 +335,14 @@ class Context:
         del keep
         return C.reshape(n, 6, 6), Craw.reshape(n, 6, 6), st, it.reshape(n, 6), rep.as_dict()
 
-    def hierarchical(self, labels, phases, n_sub, pad=0, check=True, **opts):
+    def set_surrogate(self, net_a, net_b=None, spread_tol=0.02, bound_tol=0.0):
+        """Networks used by hierarchical(..., use_surrogate=True); None detaches."""
+        self._sur = (net_a, net_b)  # kept alive while attached
+        self._check(self._lib.hh_set_surrogate(self._h, None if net_a is None else net_a._h,
+                                               None if net_b is None else net_b._h, float(spread_tol),
+                                               float(bound_tol)))
+
+    def hierarchical(self, labels, phases, n_sub, pad=0, check=True, use_surrogate=False, **opts):
         """Two-level hierarchical C*; returns (C*, C_sub[(N/n)^3, 21], report)."""
         nz, ny, nx = tuple(labels.shape)
         ptr, dev, keep = _buffer(labels, np.uint8)
@@ -340,7 +353,8 @@ class Context:
         Cs = np.zeros(max(1, m) * 21)
         rep = Report()
         rc = self._lib.hh_hierarchical(self._h, ptr, nx, ny, nz, dev, ph, len(phases), int(n_sub),
-                                       int(pad), 0, ct.byref(o), _dptr(C), _dptr(Cs), ct.byref(rep))
+                                       int(pad), int(bool(use_surrogate)), ct.byref(o), _dptr(C), _dptr(Cs),
+                                       ct.byref(rep))
         if check:
             self._check(rc)
         del keep
@@ -419,6 +433,19 @@ class Net:
         h = ct.c_void_p()
         ctx._check(self._lib.hh_net_create(ctx._h, self.nphase, self.n, ct.c_ulonglong(seed), ct.byref(h)))
         self._h = h
+
+    @classmethod
+    def load(cls, ctx, path):
+        """A network from a training-pipeline .npz file, read by the library
+        (hh_net_load)."""
+        h = ct.c_void_p()
+        ctx._check(ctx._lib.hh_net_load(ctx._h, os.fsencode(os.fspath(path)), ct.byref(h)))
+        net = cls.__new__(cls)
+        net.ctx, net._lib, net._h = ctx, ctx._lib, h
+        nph, n = ct.c_int(), ct.c_int()
+        ctx._check(ctx._lib.hh_net_info(h, ct.byref(nph), ct.byref(n)))
+        net.nphase, net.n = nph.value, n.value
+        return net
 
     def close(self):
         if getattr(self, "_h", None):

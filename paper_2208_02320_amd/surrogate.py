@@ -270,12 +270,11 @@ def save(net, path, meta=None):
 
 
 def load(ctx, path):
-    z = np.load(path, allow_pickle=False)
-    net = hh.Net(ctx, int(z["nphase"]), int(z["n"]))
-    net.set_params(z["params"])
-    net.set_scaling(z["mean"], z["scale"])
-    net.set_fraction_scaling(z["fmu"], z["fsc"])
-    net.meta = json.loads(str(z["meta"]))
+    """The network of a saved file, read by the library (hh_net_load); its
+    training record (``meta``) is read here."""
+    net = hh.Net.load(ctx, path)
+    with np.load(path, allow_pickle=False) as z:
+        net.meta = json.loads(str(z["meta"]))
     return net
 
 

@@ -37,7 +37,8 @@ def test_binding_loads():
     from paper_2208_02320_amd import hh
     lib = hh.load_library()
     o = hh.default_opts()
-    assert o.tol == 1e-6 and o.max_iter == 1000 and o.scheme == 0 and o.precision == 0
+    assert o.tol == 1e-6 and o.max_iter == 0 and o.stall_limit == 0 and o.scheme == 0 and o.precision == 0
+    assert o.retry == 1 and o.verify == 0
     assert lib.hh_size_supported(256, 0) == 1 and lib.hh_size_supported(7, 0) == 0
     assert lib.hh_size_supported(80, 1) == 1 and lib.hh_size_supported(80, 2) == 0
 
@@ -122,3 +123,5 @@ def test_plain_c_client_host_entry_points():
     assert np.allclose(out["moduli"], [4.0, 3.0], rtol=0, atol=1e-14)
     assert np.allclose(out["richardson"], [5.0, 40.0], rtol=1e-12)
     assert out["create"][0] in (0, -4)
+    if out["create"][0] == -4:
+        assert "hh_create:" in err  # the reason, read with hh_last_error(NULL)

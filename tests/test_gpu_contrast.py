@@ -1,0 +1,113 @@
+"""The paper's phase contrast (Sec. 2: quartz K 36 / G 45 GPa, pores of
+1e-5 GPa "for stability", a contrast of 4.5e6) through the C ABI, against
+the stored FP64 oracle result of the same image, and the report fields that
+go with it (FP64 retry, the FP64 check, algorithmic bytes)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import galerkin as g
+from paper_2208_02320_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+QP = [synth.QUARTZ, synth.PORE]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2208_02320_amd import hh
+    c = hh.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def paper_pores():
+    ref = json.load(open(os.path.join(HERE, "golden", "paper_pores_16.json")))
+    lab = synth.two_phase(16, 0.2, 1.5, seed=0)
+    return lab, [tuple(p) for p in ref["phases"]], np.array(ref["C_sym"])
+
+
+def test_paper_pores_default_options(ctx, paper_pores):
+    """Default options at the paper's contrast: the iteration cap and stall
+    limit follow from the contrast, and C matches the FP64 oracle."""
+    lab, ph, ref = paper_pores
+    r = ctx.homogenize(lab, ph, tol=1e-6)
+    err = g.rel_error(r.C, ref)
+    print("FP32 default: status %d iters %s retried %d err %.2e" % (r.report["status"], r.report["iters"],
+                                                                    r.report["retried"], err))
+    assert r.report["status"] == 0
+    assert max(r.report["iters"]) > 1000  # beyond the old fixed cap
+    assert err < 1e-5
+
+
+def test_paper_pores_fp32_reaches_1e9(ctx, paper_pores):
+    """FP32 fields with FP64 reductions reach tol 1e-9 at the paper's
+    contrast, in the oracle's iteration counts."""
+    lab, ph, ref = paper_pores
+    r = ctx.homogenize(lab, ph, tol=1e-9)
+    err = g.rel_error(r.C, ref)
+    print("FP32 tol 1e-9: status %d iters %s retried %d err %.2e" % (r.report["status"], r.report["iters"],
+                                                                     r.report["retried"], err))
+    assert r.report["status"] == 0 and err < 1e-7
+
+
+def test_paper_pores_fp32_floor_retries_in_fp64(ctx, paper_pores):
+    """Below the FP32 floor (tol 1e-12) FP32 fields stagnate; the image is
+    solved again with FP64 fields, converges and matches the oracle."""
+    lab, ph, ref = paper_pores
+    r = ctx.homogenize(lab, ph, tol=1e-12)
+    err = g.rel_error(r.C, ref)
+    print("FP32 tol 1e-12: status %d iters %s retried %d err %.2e" % (r.report["status"], r.report["iters"],
+                                                                      r.report["retried"], err))
+    assert r.report["retried"] == 1 and r.report["status"] == 0
+    assert max(r.report["rel_resid"]) <= 1e-12
+    assert err < 1e-7
+    off = ctx.homogenize(lab, ph, tol=1e-12, retry=0, check=False)
+    assert off.report["status"] == -7 and off.report["retried"] == 0
+    assert g.rel_error(off.C, ref) < 1e-5  # the best FP32 iterate is still close
+
+
+def test_paper_pores_fp64(ctx, paper_pores):
+    lab, ph, ref = paper_pores
+    r = ctx.homogenize(lab, ph, tol=1e-9, precision=1)
+    assert r.report["status"] == 0
+    assert g.rel_error(r.C, ref) < 1e-8
+
+
+def test_retry_in_the_hierarchy_and_the_batch(ctx, paper_pores):
+    """The retry runs per item inside the two-level scheme (its FP64 result
+    feeds the level-2 image) and the batch."""
+    lab, ph, _ = paper_pores
+    big = np.tile(lab, (2, 2, 2))
+    C, Cs, rep = ctx.hierarchical(big, ph, 16, 0, tol=1e-12)
+    assert rep["retried"] == 8 and rep["status"] == 0
+    one = ctx.homogenize(lab, ph, tol=1e-12, precision=1)
+    assert g.rel_error(C, one.C) < 1e-6  # a periodic tiling of one cell (FP32 level-2 field)
+    Cb, _, st, _, repb = ctx.homogenize_batch([lab, lab[:, :, ::-1].copy()], [ph, ph], tol=1e-12)
+    assert repb["retried"] == 2 and (st == 0).all()
+
+
+def test_verify_reports_the_fp64_difference(ctx):
+    lab = synth.two_phase(32, 0.2, 2.0, 0)
+    r = ctx.homogenize(lab, QP, tol=1e-6, verify=1)
+    ref = g.homogenize(g.IsotropicMedium(lab, QP), tol=1e-10, form="sym6")
+    true_err = g.rel_error(r.C, ref.C_sym)
+    print("verify: reported %.3e, against the CPU oracle %.3e" % (r.report["err_vs_oracle"], true_err))
+    assert 0.0 <= r.report["err_vs_oracle"] < 1e-5
+    assert abs(r.report["err_vs_oracle"] - true_err) < 1e-8
+    assert ctx.homogenize(lab, QP, tol=1e-6).report["err_vs_oracle"] == -1.0
+
+
+def test_bytes_moved_is_the_algorithmic_count(ctx):
+    n = 24
+    lab = synth.two_phase(n, 0.2, 2.0, 1)
+    r = ctx.homogenize(lab, QP, tol=1e-6)
+    nf = (n // 2 + 1) * n * n
+    V = n ** 3
+    expect = sum(r.report["iters"]) * (nf * 8 * 63 + V) + 6 * (nf * 8 * 27 + V)
+    assert r.report["bytes_moved"] == pytest.approx(expect, rel=1e-12)

@@ -50,10 +50,10 @@ def test_every_tile_variant_matches_oracle(ctx, shape, plan):
 @pytest.mark.parametrize("n", [300, 320])
 def test_region_sums_agree_across_x_variants(ctx, n):
     """Sub-box averages through the x-pass tile variants: at these lengths
-    variant 1 runs 64-thread workgroups, fewer than the 104 summing tasks of
-    the 13-value block reduction, variant 0 holds all of them, and variant 2
-    fits its values in the tile buffer.  Four iterations of each; the
-    iterates differ only in the grouping of FP64 sums."""
+    variant 1 runs 64-thread workgroups, fewer than the 3 R x 16 line-group
+    tasks of the region sums, and variants 0 and 2 hold more rows.  Four
+    iterations of each; the sums follow the same fixed tree in every
+    variant, so the results are identical."""
     from paper_2208_02320_amd import synth as sy
     lab = sy.four_phase_device(n, sigma=2.0, seed=7)
     region = (10, 12, 14, n - 10, n - 12, n - 14)
@@ -63,9 +63,7 @@ def test_region_sums_agree_across_x_variants(ctx, n):
         assert r.report["plan"] == [0, 0, xv]
         out[xv] = r.C_raw
     for xv in (1, 2):
-        err = g.rel_error(out[xv], out[0])
-        print("n %d x variant %d against 0: %.2e" % (n, xv, err))
-        assert err < 1e-6
+        assert np.array_equal(out[xv], out[0]), xv
 
 
 def test_graph_replay_equals_plain_launches(ctx):

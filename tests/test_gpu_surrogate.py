@@ -345,10 +345,46 @@ def test_trained_network_gains_over_the_method_without_it(ctx):
     print("surrogate hierarchy: fallback %d/%d, FFT voxel-iters %.3g vs %.3g, C* error %.2e" %
           (fb.sum(), fb.size, rs["voxel_iters"], rp["voxel_iters"], err))
     assert rs["voxel_iters"] < 0.8 * rp["voxel_iters"]
-    # 256 training subimages of 16^3 give networks of about 7.5 % error; the
-    # final C* lands near 1 %, varying by a few tens of percent between runs
-    # (labels differ at rounding level with the tuned tile plan, and training
-    # amplifies that)
-    assert err < 2e-2
+    # The level-2 image's voxels carry the accepted predictions.  When every
+    # voxel stiffness lies within a factor (1 +- e) of the exact one in the
+    # quadratic-form sense, so does the homogenized stiffness, so C* is off
+    # by about the largest subimage error at most.  (The whole pipeline is
+    # bitwise reproducible: labels, training and predictions do not depend
+    # on the tile plan.)
+    sub_err = sur.rel_error21(Cs, Csp)
+    print("largest subimage error %.3e" % sub_err.max())
+    assert err <= sub_err.max()
     for net in nets:
         net.close()
+
+
+def test_network_file_loaded_by_the_library(ctx):
+    """hh_net_load reads the shipped .npz (deflated zip of .npy arrays) into
+    the same network the numpy reader builds, and hh_hierarchical with
+    use_surrogate = 1 takes the attached networks' path."""
+    import os
+    from paper_2208_02320_amd import hh, surrogate as sur
+    paths = sur.default_weights(64, 8)
+    if not all(os.path.exists(p) for p in paths):
+        pytest.skip("shipped weights missing")
+    na = hh.Net.load(ctx, paths[0])
+    nb = hh.Net.load(ctx, paths[1])
+    with np.load(paths[0], allow_pickle=False) as z:
+        assert np.array_equal(na.get_params(), z["params"])
+        m, s_ = na.get_scaling()
+        assert np.array_equal(m, z["mean"]) and np.array_equal(s_, z["scale"])
+        fm, fs = na.get_fraction_scaling()
+        assert np.array_equal(fm, z["fmu"]) and np.array_equal(fs, z["fsc"])
+        assert (na.n, na.nphase) == (int(z["n"]), int(z["nphase"]))
+    img = synth.four_phase_device(128, sigma=2.0, seed=31, device="cuda:0")
+    C1, Cs1, fb1, r1 = ctx.hierarchical_surrogate(img, FOUR, 64, 8, na, nb, spread_tol=0.02, bound_tol=0.0)
+    with pytest.raises(hh.HHError):
+        ctx.hierarchical(img, FOUR, 64, 8, use_surrogate=True)
+    ctx.set_surrogate(na, nb, spread_tol=0.02, bound_tol=0.0)
+    C2, Cs2, r2 = ctx.hierarchical(img, FOUR, 64, 8, use_surrogate=True)
+    ctx.set_surrogate(None)
+    assert np.array_equal(C1, C2) and np.array_equal(Cs1, Cs2)
+    with pytest.raises(hh.HHError):
+        hh.Net.load(ctx, os.path.join(os.path.dirname(paths[0]), "missing.npz"))
+    na.close()
+    nb.close()
