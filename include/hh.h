@@ -92,16 +92,16 @@ typedef struct {
                         one at a time; 0 = all six together unless the six systems of one
                         image do not fit in device memory, then as many as fit; default 0 */
   int retry;         /* 1 (default): with FP32 fields, an image of isotropic phases whose
-                        solve stops with HH_ESTAGNATED (the FP32 floor, e.g. at extreme
-                        phase contrast) is solved again with FP64 fields when its axis
-                        lengths have FP64 passes; hh_report.retried counts them; 0 = off */
+                        solve stops with HH_ESTAGNATED or HH_EBREAKDOWN (the FP32 floor, e.g.
+                        at extreme phase contrast) is solved again with FP64 fields when its axis
+                        lengths have FP64 passes, with at least the contrast-derived stall
+                        limit; hh_report.retried counts them; 0 = off */
   int verify;        /* 1: hh_homogenize also solves the image with FP64 fields at tol
                         1e-10 and reports the difference in hh_report.err_vs_oracle;
                         default 0 */
   int lanes;         /* hh_homogenize_batch: shape groups solved concurrently, each on its
-                        own stream, host thread and workspace (1..4; 0 = up to 4, the
-                        default; 1 = one after another; profile forces 1); results do not
-                        depend on it */
+                        own stream, host thread and workspace (1..4; 0 = default = 1, one
+                        group after another; profile forces 1); results do not depend on it */
 } hh_opts;
 
 /* Per-call report. */

@@ -661,9 +661,11 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
 }
 
 // solve_group, then (opts.retry, FP32 fields, isotropic phases) the images
-// that stopped at the FP32 floor (HH_ESTAGNATED) solved again with FP64
-// fields; their stiffness replaces the FP32 one, also in the next level's
-// field when the caller builds one.
+// that stopped at the FP32 floor solved again with FP64 fields: a residual
+// that stopped decreasing (HH_ESTAGNATED), or (p, Ap) rounded to <= 0 or a
+// non-finite value (HH_EBREAKDOWN; in exact arithmetic (p, Ap) > 0).  Their
+// stiffness replaces the FP32 one, also in the next level's field when the
+// caller builds one.
 GroupResult solve_group_retry(hh_ctx* ctx, const std::vector<Item>& items, const unsigned char* labels,
                               const void* cfield, bool aniso, const hh_opts& o, const double loads[6][6],
                               Profile& prof, void* cfield_out, const hh_lane& lane, int nlanes) {
@@ -671,7 +673,8 @@ GroupResult solve_group_retry(hh_ctx* ctx, const std::vector<Item>& items, const
   if (!o.retry || o.precision != 0 || aniso) return r;
   std::vector<int> idx;
   for (size_t i = 0; i < items.size(); ++i)
-    if (r.status[i] == HH_ESTAGNATED && size_ops(items[i].nx, 1) && size_ops(items[i].ny, 1) &&
+    if ((r.status[i] == HH_ESTAGNATED || r.status[i] == HH_EBREAKDOWN) && size_ops(items[i].nx, 1) &&
+        size_ops(items[i].ny, 1) &&
         size_ops(items[i].nz, 1))
       idx.push_back(int(i));
   if (idx.empty()) return r;
@@ -681,6 +684,10 @@ GroupResult solve_group_retry(hh_ctx* ctx, const std::vector<Item>& items, const
   o64.precision = 1;
   o64.tune = 0;
   o64.plan[0] = o64.plan[1] = o64.plan[2] = -1;
+  // FP64 fields have no FP32 floor: at least the contrast-derived stall limit
+  hh_opts oa = o;
+  oa.stall_limit = 0;
+  o64.stall_limit = std::max(o.stall_limit, solve_limits(oa, sub, false).stall);
   const std::array<int, 3> keep_plan = ctx->last_plan;
   GroupResult r64 = solve_group(ctx, sub, labels, nullptr, false, o64, loads, prof, nullptr, lane, nlanes);
   ctx->last_plan = keep_plan;
@@ -1256,7 +1263,7 @@ int hh_homogenize_batch(hh_ctx* ctx, int nitems, const int* dims, const uint8_t*
     // their own streams and buffers), largest work first, so the tail
     // iterations of one group overlap the work of the others; each system
     // computes the same bits on any lane.
-    int nl = o.lanes > 0 ? o.lanes : kMaxLanes;
+    int nl = o.lanes > 0 ? o.lanes : 1;
     nl = std::min(nl, ngroup);
     if (o.profile) nl = 1;
     if (nl <= 1) {

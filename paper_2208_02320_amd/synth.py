@@ -31,6 +31,12 @@ PHASE_TABLE = (QUARTZ, FELDSPAR, CLAY, PORE)
 FOUR_PHASE = dict(phases=[QUARTZ, FELDSPAR, CLAY, PORE],
                   fracs=[0.55, 0.15, 0.10, 0.20], low_to_high=[3, 2, 1, 0])
 TWO_PHASE = dict(phases=[QUARTZ, PORE], fracs=[0.80, 0.20], low_to_high=[1, 0])
+# The paper's own two-phase moduli: quartz K 36 / G 45 GPa and pores of 1e-5
+# GPa (Sec. 2), and the second set of Appendix B, a phase ten times stiffer
+# than the other (its soft bulk modulus is printed garbled; read as 9.80,
+# a tenth of 98.04).
+PAPER_TWO_PHASE = [(36.0, 45.0), (1e-5, 1e-5)]
+APPENDIX_B_TWO_PHASE = [(98.04, 37.59), (9.80, 3.76)]
 
 
 def smoothed_noise(shape, sigma, seed, dtype=np.float32):

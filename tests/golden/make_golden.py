@@ -5,6 +5,7 @@ Usage:  python tests/golden/make_golden.py four_phase_256
         python tests/golden/make_golden.py hier_512_items [jobs]
         python tests/golden/make_golden.py uneven_2048_items [jobs]
         python tests/golden/make_golden.py paper_pores_16
+        python tests/golden/make_golden.py study_48 [jobs]
 The sampled workloads solve their items in ``jobs`` processes (one FFT
 thread each).
 """
@@ -109,9 +110,35 @@ def paper_pores_16():
     json.dump(out, open(os.path.join(HERE, "paper_pores_16.json"), "w"), indent=1)
 
 
+def _study_run(np_):
+    g.set_workers(1)
+    n, p = np_
+    lab = synth.four_phase(48, sigma=2.0, seed=21)
+    t = time.time()
+    h = hier.hierarchical(lab, synth.FOUR_PHASE["phases"], n, p, tol=1e-9, form="sym6")
+    K_am, G_am = hier.arithmetic_mean_moduli(h.C_sub)
+    print("study n", n, "pad", p, time.time() - t, flush=True)
+    return dict(n=n, pad=p, C=h.C.tolist(), K_am=float(K_am), G_am=float(G_am), seconds=time.time() - t)
+
+
+def study_48(jobs=1):
+    """The error study of Sec. 5 in miniature: a 48^3 four-phase image (sigma
+    2, seed 21), its plain stiffness, and the two-level scheme for subimage
+    sizes 8, 12, 16 with 0 and 2 voxels of padding, with the arithmetic mean
+    of the subimage moduli; CG to 1e-9."""
+    lab = synth.four_phase(48, sigma=2.0, seed=21)
+    t = time.time()
+    ref = g.homogenize(g.IsotropicMedium(lab, synth.FOUR_PHASE["phases"]), tol=1e-9, form="sym6")
+    runs = _pool_map(_study_run, [(n, p) for p in (0, 2) for n in (8, 12, 16)], jobs)
+    out = dict(image="synth.four_phase(48, sigma=2.0, seed=21)", tol=1e-9, form="sym6", C_ref=ref.C_sym.tolist(),
+               ref_seconds=time.time() - t, runs=runs)
+    json.dump(out, open(os.path.join(HERE, "study_48.json"), "w"), indent=1)
+
+
 if __name__ == "__main__":
     fn = {"four_phase_256": four_phase_256, "hier_512_items": hier_512_items,
-          "uneven_2048_items": uneven_2048_items, "paper_pores_16": paper_pores_16}[sys.argv[1]]
+          "uneven_2048_items": uneven_2048_items, "paper_pores_16": paper_pores_16,
+          "study_48": study_48}[sys.argv[1]]
     if len(sys.argv) > 2:
         fn(jobs=int(sys.argv[2]))
     else:

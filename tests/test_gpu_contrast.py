@@ -45,31 +45,36 @@ def test_paper_pores_default_options(ctx, paper_pores):
     assert err < 1e-5
 
 
-def test_paper_pores_fp32_reaches_1e9(ctx, paper_pores):
-    """FP32 fields with FP64 reductions reach tol 1e-9 at the paper's
-    contrast, in the oracle's iteration counts."""
+def test_paper_pores_fp32_reaches_1e12(ctx, paper_pores):
+    """FP32 fields with FP64 reductions follow the FP64 oracle's iteration
+    counts at the paper's contrast and keep reducing the recurrence residual
+    far below the FP32 unit roundoff; C stays within 1e-7 of the oracle."""
     lab, ph, ref = paper_pores
-    r = ctx.homogenize(lab, ph, tol=1e-9)
-    err = g.rel_error(r.C, ref)
-    print("FP32 tol 1e-9: status %d iters %s retried %d err %.2e" % (r.report["status"], r.report["iters"],
-                                                                     r.report["retried"], err))
-    assert r.report["status"] == 0 and err < 1e-7
+    for tol in (1e-9, 1e-12):
+        r = ctx.homogenize(lab, ph, tol=tol)
+        err = g.rel_error(r.C, ref)
+        print("FP32 tol %g: status %d iters %s retried %d err %.2e" % (tol, r.report["status"], r.report["iters"],
+                                                                       r.report["retried"], err))
+        assert r.report["status"] == 0 and err < 1e-7
 
 
-def test_paper_pores_fp32_floor_retries_in_fp64(ctx, paper_pores):
-    """Below the FP32 floor (tol 1e-12) FP32 fields stagnate; the image is
-    solved again with FP64 fields, converges and matches the oracle."""
+def test_stagnation_retries_in_fp64(ctx, paper_pores):
+    """A stall limit of 3 makes the FP32 solve stop with HH_ESTAGNATED within
+    a few iterations at this contrast (the residual is not monotone); the
+    image is then solved with FP64 fields, under the contrast-derived stall
+    limit, and matches the oracle."""
     lab, ph, ref = paper_pores
-    r = ctx.homogenize(lab, ph, tol=1e-12)
-    err = g.rel_error(r.C, ref)
-    print("FP32 tol 1e-12: status %d iters %s retried %d err %.2e" % (r.report["status"], r.report["iters"],
-                                                                      r.report["retried"], err))
-    assert r.report["retried"] == 1 and r.report["status"] == 0
-    assert max(r.report["rel_resid"]) <= 1e-12
-    assert err < 1e-7
-    off = ctx.homogenize(lab, ph, tol=1e-12, retry=0, check=False)
+    off = ctx.homogenize(lab, ph, tol=1e-9, stall_limit=3, retry=0, check=False)
     assert off.report["status"] == -7 and off.report["retried"] == 0
-    assert g.rel_error(off.C, ref) < 1e-5  # the best FP32 iterate is still close
+    r = ctx.homogenize(lab, ph, tol=1e-9, stall_limit=3)
+    err = g.rel_error(r.C, ref)
+    print("stall_limit 3: FP32 alone stops after %s; with the retry status %d iters %s err %.2e" % (
+        off.report["iters"], r.report["status"], r.report["iters"], err))
+    assert r.report["retried"] == 1 and r.report["status"] == 0
+    assert max(r.report["rel_resid"]) <= 1e-9
+    assert err < 1e-7
+    direct = ctx.homogenize(lab, ph, tol=1e-9, precision=1)
+    assert np.array_equal(r.C, direct.C)  # the retry is the FP64 solve
 
 
 def test_paper_pores_fp64(ctx, paper_pores):
@@ -84,11 +89,11 @@ def test_retry_in_the_hierarchy_and_the_batch(ctx, paper_pores):
     feeds the level-2 image) and the batch."""
     lab, ph, _ = paper_pores
     big = np.tile(lab, (2, 2, 2))
-    C, Cs, rep = ctx.hierarchical(big, ph, 16, 0, tol=1e-12)
+    C, Cs, rep = ctx.hierarchical(big, ph, 16, 0, tol=1e-9, stall_limit=3)
     assert rep["retried"] == 8 and rep["status"] == 0
-    one = ctx.homogenize(lab, ph, tol=1e-12, precision=1)
+    one = ctx.homogenize(lab, ph, tol=1e-9, precision=1)
     assert g.rel_error(C, one.C) < 1e-6  # a periodic tiling of one cell (FP32 level-2 field)
-    Cb, _, st, _, repb = ctx.homogenize_batch([lab, lab[:, :, ::-1].copy()], [ph, ph], tol=1e-12)
+    Cb, _, st, _, repb = ctx.homogenize_batch([lab, lab[:, :, ::-1].copy()], [ph, ph], tol=1e-9, stall_limit=3)
     assert repb["retried"] == 2 and (st == 0).all()
 
 

@@ -88,7 +88,7 @@ def test_sizes_fp32(ctx, n):
 # sizes 75, 90, 150, 180, 225, 300 with 5 or 10 voxels of padding) and the
 # longest FP32 axes (1024 runs 2-column y/z tiles), each on every axis in
 # turn of a thin image.
-LONG32 = [85, 95, 110, 170, 190, 225, 235, 245, 300, 310, 320, 512, 1024]
+LONG32 = [85, 95, 110, 115, 130, 140, 170, 190, 220, 225, 235, 245, 265, 272, 288, 300, 310, 320, 340, 512, 900, 1024]
 
 
 def thin(n, axis, seed):
