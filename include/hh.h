@@ -180,6 +180,24 @@ int hh_homogenize(hh_ctx *ctx, const uint8_t *labels, int nx, int ny, int nz, in
                   const hh_opts *opts, double C_out[36], double C_raw[36], hh_report *report);
 
 /*
+ * hh_homogenize for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one label image already on the device, the six unit loads,
+ * the whole box as region.  Its buffers come from a static device array of
+ * 128 MiB that the library holds on every GPU it runs on until the process
+ * ends (enough for FP32 images up to about 64^3; larger images return
+ * HH_EINVAL before any device work).  It calls no hipMalloc or hipFree and
+ * no allocating library routine, and launches plainly (opts.graph, profile,
+ * retry, verify and lanes are ignored).  All calls on one GPU share that
+ * array: calls that overlap on one GPU, from any context or thread, race.
+ * The array keeps the last call's contents; every call clears what must
+ * start at zero.  Arguments and results as in hh_homogenize.
+ */
+int hh_homogenize_noalloc(hh_ctx *ctx, const uint8_t *labels_device, int nx, int ny, int nz,
+                          const hh_phase *phases, int nphase, const hh_opts *opts, double C_out[36],
+                          hh_report *report);
+
+/*
  * Effective stiffness of an image of anisotropic voxels (the intermediate
  * image of Sec. 3, solved as stated at the end of Sec. 4).
  * C21: per voxel 21 upper-triangle components, [nz][ny][nx][21] doubles

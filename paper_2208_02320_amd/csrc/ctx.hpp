@@ -41,6 +41,12 @@ struct hh_ctx {
   struct hh_net* sur_a = nullptr;
   struct hh_net* sur_b = nullptr;
   double sur_spread = 0.0, sur_bound = 0.0;
+  // While arena_base is set (the allocation-free entry point), ws() carves
+  // its buffers from that preallocated region with a bump pointer reset per
+  // call, and never allocates or frees device memory.
+  char* arena_base = nullptr;
+  size_t arena_size = 0, arena_used = 0;
+  std::map<std::string, std::pair<void*, size_t>> arena_bufs;
   double call_bytes = 0.0;                // algorithmic bytes of the current call's solver passes
   long long call_retried = 0;             // images of the current call solved again in FP64
   std::array<int, 3> last_plan{{0, 0, 0}};
@@ -85,6 +91,18 @@ struct Fail {
 // still use the old buffer when it has to grow (default: the context's).
 inline void* ws(hh_ctx* ctx, const std::string& name, size_t bytes, hipStream_t st) {
   std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  if (ctx->arena_base) {
+    auto a = ctx->arena_bufs.find(name);
+    if (a != ctx->arena_bufs.end() && a->second.second >= bytes) return a->second.first;
+    const size_t sz = (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
+    if (ctx->arena_used + sz > ctx->arena_size)
+      fail(ctx, HH_ENOMEM, "the call needs more than the " + std::to_string(ctx->arena_size) +
+                               " bytes of the library's static scratch (at buffer " + name + ")");
+    void* p = ctx->arena_base + ctx->arena_used;
+    ctx->arena_used += sz;
+    ctx->arena_bufs[name] = {p, sz};
+    return p;
+  }
   auto it = ctx->bufs.find(name);
   if (it != ctx->bufs.end() && it->second.second >= bytes) return it->second.first;
   if (it != ctx->bufs.end()) {

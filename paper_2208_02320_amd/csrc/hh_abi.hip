@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -28,6 +29,34 @@ namespace {
 
 // reason of the calling thread's last failed hh_create
 thread_local std::string g_create_error;
+
+// Device scratch of the allocation-free entry point: one static array per
+// GPU the library runs on, held until the process ends.  Host code uses it
+// only through the address hipGetSymbolAddress returns for each device
+// (taken once per device by hh_create, with that device current).
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The address of this device's scratch (the device is current); HH_OK or HH_EDEVICE.
+int init_scratch(int device, std::string& why) {
+  if (device < 0 || device >= kMaxDevices) {
+    why = "hh_create: device index beyond the scratch table";
+    return HH_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return HH_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    why = std::string("hh_create: hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(e);
+    return HH_EDEVICE;
+  }
+  g_scratch_ptr[device] = ptr;
+  return HH_OK;
+}
 
 int status_code(int s) {
   switch (s) {
@@ -813,6 +842,24 @@ void write_C(const GroupResult& r, int item, double* C_out, double* C_raw) {
   if (C_raw) std::memcpy(C_raw, C, sizeof(double) * 36);
 }
 
+// Device bytes one image's solve with all six loads together takes from the
+// workspace: spectrum and both 3-vector fields of the six systems (the
+// largest z-tile layout), the row and column sums and their chunk sums, and
+// 64 KiB for the descriptors, states and label checks.
+size_t noalloc_bytes(hh_ctx* ctx, int nx, int ny, int nz, int precision) {
+  const PassVariants vz = pass_variants(ctx, nz, precision, kOpInfoZ, kOpInfoLdsZ, kOpInfoThreadsZ);
+  const int hx = nx / 2 + 1;
+  const size_t cb = precision == 0 ? 8 : 16;
+  const size_t nfreq = size_t(spectrum_pitch(hx)) * ny * nz;
+  size_t nafreq = 0;
+  for (int v = 0; v < kNVariant; ++v)
+    if (vz.ok[v]) nafreq = std::max(nafreq, size_t(ny) * ((hx + vz.geom[v] - 1) / vz.geom[v]) * nz * vz.geom[v]);
+  const size_t nrow = size_t(ny) * nz, ncol = size_t(ny) * hx;
+  const size_t nchunk = (nrow + kFinChunk - 1) / kFinChunk + (ncol + kFinChunk - 1) / kFinChunk;
+  const size_t per_sys = nfreq * 6 * cb + nafreq * 6 * cb + 8 * (nrow * kPartX + ncol + nchunk * kPartX);
+  return 6 * per_sys + (size_t(64) << 10);
+}
+
 // The two-level scheme with network subimage stiffnesses, the gate and the
 // FFT fallback (body of hh_hierarchical_surrogate and of hh_hierarchical
 // with use_surrogate = 1).
@@ -1043,6 +1090,11 @@ int hh_create(hh_ctx** out, int device, void* hip_stream) {
     hh_destroy(ctx);
     return failed(HH_EDEVICE, std::string("hh_create: ") + step + " failed", e);
   }
+  std::string why;
+  if (init_scratch(device, why) != HH_OK) {
+    hh_destroy(ctx);
+    return failed(HH_EDEVICE, why, hipSuccess);
+  }
   *out = ctx;
   return HH_OK;
 }
@@ -1156,6 +1208,50 @@ int hh_homogenize(hh_ctx* ctx, const uint8_t* labels, int nx, int ny, int nz, in
     if (res.status[0] != HH_OK) ctx->err = "solve did not converge cleanly (see report.status)";
     return res.status[0];
   });
+}
+
+int hh_homogenize_noalloc(hh_ctx* ctx, const uint8_t* labels_device, int nx, int ny, int nz, const hh_phase* phases,
+                          int nphase, const hh_opts* opts, double C_out[36], hh_report* report) {
+  if (!ctx) return HH_EINVAL;
+  hh_opts o;
+  hh_default_opts(&o);
+  if (opts) o = *opts;
+  // plain launches only (no graph instantiation), no profiling events, no
+  // FP64 retry or check (they would need more scratch)
+  o.graph = 0;
+  o.profile = 0;
+  o.retry = 0;
+  o.verify = 0;
+  o.lanes = 1;
+  int rc = guarded(ctx, [&]() -> int {
+    if (!labels_device || !C_out) fail(ctx, HH_EINVAL, "labels_device and C_out are required");
+    check_opts(ctx, o);
+    check_shape(ctx, nx, ny, nz, o.precision);
+    const size_t need = noalloc_bytes(ctx, nx, ny, nz, o.precision);
+    if (need > kScratchBytes)
+      fail(ctx, HH_EINVAL, "a " + std::to_string(nx) + "x" + std::to_string(ny) + "x" + std::to_string(nz) +
+                               " image needs about " + std::to_string(need) + " bytes of scratch; the allocation-free "
+                               "entry point holds " + std::to_string(kScratchBytes) + " (FP32 images up to about 64^3)");
+    void* base = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      base = g_scratch_ptr[ctx->device];
+    }
+    if (!base) fail(ctx, HH_EDEVICE, "the static scratch of this device was not set up");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->arena_base = static_cast<char*>(base);
+    ctx->arena_size = kScratchBytes;
+    ctx->arena_used = 0;
+    ctx->arena_bufs.clear();
+    return HH_OK;
+  });
+  if (rc != HH_OK) return rc;
+  rc = hh_homogenize(ctx, labels_device, nx, ny, nz, 1, phases, nphase, nullptr, nullptr, &o, C_out, nullptr, report);
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->arena_base = nullptr;
+  ctx->arena_size = ctx->arena_used = 0;
+  ctx->arena_bufs.clear();
+  return rc;
 }
 
 int hh_homogenize_aniso(hh_ctx* ctx, const double* C21, int nx, int ny, int nz, int c21_on_device,

@@ -28,7 +28,7 @@ NKERNEL = len(KERNEL_CLASSES)
 # Exported symbols (checked by the CPU test suite against include/hh.h).
 SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_last_error",
            "hh_workspace_bytes", "hh_release_workspace", "hh_size_supported", "hh_homogenize",
-           "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_hierarchical_levels",
+           "hh_homogenize_noalloc", "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_hierarchical_levels",
            "hh_gather_subimages",
            "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_load", "hh_net_info", "hh_net_get_params",
            "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling",
@@ -100,6 +100,8 @@ def load_library(path=LIB_PATH):
     lib.hh_size_supported.argtypes = [I, I]
     lib.hh_homogenize.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, DP, ct.POINTER(I),
                                   ct.POINTER(Opts), DP, DP, ct.POINTER(Report)]
+    lib.hh_homogenize_noalloc.argtypes = [P, P, I, I, I, ct.POINTER(Phase), I, ct.POINTER(Opts), DP,
+                                          ct.POINTER(Report)]
     lib.hh_homogenize_aniso.argtypes = [P, P, I, I, I, I, ct.POINTER(Opts), DP, DP, ct.POINTER(Report)]
     lib.hh_homogenize_batch.argtypes = [P, I, ct.POINTER(I), P, LL, I, ct.POINTER(LL), ct.POINTER(Phase),
                                         ct.POINTER(I), ct.POINTER(I), ct.POINTER(I), ct.POINTER(Opts),
@@ -264,6 +266,24 @@ class Context:
             self._check(rc)
         del keep
         return Result(C.reshape(6, 6), Craw.reshape(6, 6), rep.as_dict())
+
+    def homogenize_noalloc(self, labels, phases, check=True, **opts):
+        """hh_homogenize_noalloc: C (6x6, symmetrized) and report of one label
+        image already on the device (a contiguous uint8 tensor [z][y][x])."""
+        if not (_is_torch(labels) and labels.is_cuda):
+            raise ValueError("labels must be a device tensor")
+        nz, ny, nx = tuple(labels.shape)
+        ptr, dev, keep = _buffer(labels, np.uint8)
+        o = default_opts(**opts)
+        ph = _phases(phases)
+        C = np.zeros(36)
+        rep = Report()
+        rc = self._lib.hh_homogenize_noalloc(self._h, ptr, nx, ny, nz, ph, len(phases), ct.byref(o), _dptr(C),
+                                             ct.byref(rep))
+        if check:
+            self._check(rc)
+        del keep
+        return Result(C.reshape(6, 6), None, rep.as_dict())
 
     def homogenize_aniso(self, C21, check=True, **opts):
         """Stiffness of an image of anisotropic voxels; C21 has shape (nz, ny, nx, 21)."""
