@@ -257,14 +257,19 @@ def bench_study(args):
             if not hh.size_supported(n + 2 * pad, 0):
                 continue  # box length without compiled passes
             t = time.perf_counter()
-            C, Cs, rep = ctx.hierarchical(lab, phases, n, pad, tol=1e-6)
+            C, Cs, rep = ctx.hierarchical(lab, phases, n, pad, tol=1e-6, check=False)
             dt = time.perf_counter() - t
             K, G = hh.moduli(C)
             Ka, Ga = hh.mean_moduli(Cs)
+            if rep["status"] != 0:
+                print("bench: study n=%d pad %d: status %d (level-2 iterations %s)" % (n, pad, rep["status"],
+                                                                                    rep["iters"]),
+                      file=sys.stderr, flush=True)
             if rep["retried"]:
                 print("bench: study n=%d pad %d: %d subimages solved again with FP64 fields" % (n, pad, rep["retried"]),
                       file=sys.stderr, flush=True)
-            runs[(n, pad)] = dict(C=C, K=K, G=G, K_am=Ka, G_am=Ga, seconds=dt, retried=rep["retried"])
+            runs[(n, pad)] = dict(C=C, K=K, G=G, K_am=Ka, G_am=Ga, seconds=dt, retried=rep["retried"],
+                                  status=rep["status"])
             print("bench: study n=%d pad %d: K %.4f (%+.3f %%) G %.4f (%+.3f %%); mean of subimages K %+.3f %% "
                   "G %+.3f %%; %.2f s" % (n, pad, K, 100 * (K / Kr - 1), G, 100 * (G / Gr - 1),
                                          100 * (Ka / Kr - 1), 100 * (Ga / Gr - 1), dt), file=sys.stderr, flush=True)
@@ -288,7 +293,7 @@ def bench_study(args):
         "reference": {"K": Kr, "G": Gr, "seconds": t_ref, "iters": ref.report["iters"]},
         "runs": [{"n": n, "pad": pad, "K_err_pct": 100 * (r["K"] / Kr - 1), "G_err_pct": 100 * (r["G"] / Gr - 1),
                   "K_mean_err_pct": 100 * (r["K_am"] / Kr - 1), "G_mean_err_pct": 100 * (r["G_am"] / Gr - 1),
-                  "seconds": r["seconds"], "fp64_retries": r["retried"]}
+                  "seconds": r["seconds"], "fp64_retries": r["retried"], "status": r["status"]}
                  for (n, pad), r in sorted(runs.items(), key=lambda kv: (kv[0][1], kv[0][0]))],
         "richardson": fits,
     }
@@ -563,6 +568,81 @@ def bench_surrogate(args):
     ctx.close()
 
 
+def surrogate_leg(ctx, img, phases, nets, steps=3, warmup=1, spread_tol=0.02, bound_tol=0.0, n=64, pad=8):
+    """The two-level scheme with the network pair, gate and FFT fallback on one
+    device image, timed over ``steps`` calls after ``warmup``; the plain FFT
+    hierarchy of the same image, timed once, is the reference of its C* error
+    and of the speed-up."""
+    import torch
+    from paper_2208_02320_amd import hh, surrogate
+    na, nb = nets
+    kw = dict(spread_tol=spread_tol, bound_tol=bound_tol, tol=1e-6)
+    for _ in range(warmup):
+        ctx.hierarchical_surrogate(img, phases, n, pad, na, nb, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        C, Cs, fb, rep = ctx.hierarchical_surrogate(img, phases, n, pad, na, nb, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    t1 = time.perf_counter()
+    Cp, Csp, repp = ctx.hierarchical(img, phases, n, pad, tol=1e-6)
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - t1
+    sub = surrogate.rel_error21(Cs, Csp)
+    acc = ~fb
+    return {"subimages": int(rep["items"]), "subimages_per_s": rep["items"] / dt, "ms_per_step": dt * 1e3,
+            "fallback_fraction": float(fb.mean()),
+            "rel_error_vs_plain": float(surrogate.rel_error21(hh.upper21(C), hh.upper21(Cp))[0]),
+            "subimage_rel_error_accepted": {"mean": float(sub[acc].mean()) if acc.any() else None,
+                                            "max": float(sub[acc].max()) if acc.any() else None},
+            "plain_subimages_per_s": rep["items"] / dtp, "plain_seconds": dtp, "speedup_vs_plain": dtp / dt,
+            "K_G": hh.moduli(C), "plain_K_G": hh.moduli(Cp)}
+
+
+def bench_surrogate_ood(args):
+    """The shipped network pair (trained on sigma 2, fractions 0.55/0.15/0.10/
+    0.20) on images it has not seen: a coarser texture (sigma 8), a different
+    fraction mix (porosity 0.30) and a finer one (sigma 1.2).  Each line gives
+    the gate's fallback fraction and the final C* error against the plain FFT
+    hierarchy of the same image."""
+    import torch
+    from paper_2208_02320_amd import hh, surrogate, synth
+    N = args.sur_size
+    phases = synth.FOUR_PHASE["phases"]
+    ctx = hh.Context(0)
+    nets = [surrogate.load(ctx, pth) for pth in surrogate.default_weights(64, 8, args.weights_dir)]
+    low = synth.FOUR_PHASE["low_to_high"]
+    cases = [("training recipe (sigma 2, seed 3)", dict(fracs=synth.FOUR_PHASE["fracs"], sigma=2.0, seed=3)),
+             ("sigma 8 (seed 5)", dict(fracs=synth.FOUR_PHASE["fracs"], sigma=8.0, seed=5)),
+             ("porosity 0.30 (fractions 0.45/0.15/0.10/0.30, seed 6)", dict(fracs=[0.45, 0.15, 0.10, 0.30],
+                                                                             sigma=2.0, seed=6)),
+             ("sigma 1.2 (seed 7)", dict(fracs=synth.FOUR_PHASE["fracs"], sigma=1.2, seed=7))]
+    rows = []
+    for name, c in cases:
+        img = synth.rocklike_device(N, c["fracs"], sigma=c["sigma"], seed=c["seed"], low_to_high=low)
+        torch.cuda.synchronize()
+        leg = surrogate_leg(ctx, img, phases, nets, steps=1, warmup=1, spread_tol=args.spread_tol,
+                            bound_tol=args.bound_tol)
+        leg["image"] = name
+        rows.append(leg)
+        print("bench: surrogate on %s: fallback %.3f, C* error %.2e, %.0f subimages/s, %.0fx the plain hierarchy" %
+              (name, leg["fallback_fraction"], leg["rel_error_vs_plain"], leg["subimages_per_s"],
+               leg["speedup_vs_plain"]), file=sys.stderr, flush=True)
+        del img
+        torch.cuda.empty_cache()
+    line = {"metric": "C* error of the surrogate pipeline against the plain hierarchy, worst over the images",
+            "value": max(r["rel_error_vs_plain"] for r in rows), "unit": "relative", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "bf16 network / f32 solver", "data": "synthetic",
+            "config": {"workload": "surrogate pair on %d^3 four-phase images off its training recipe, n = 64, pad 8, "
+                                   "spread_tol %g, bound_tol %g" % (N, args.spread_tol, args.bound_tol)},
+            "images": rows}
+    print(json.dumps(line), flush=True)
+    for net in nets:
+        net.close()
+    ctx.close()
+
+
 def bench_cnn(args):
     """Network kernels alone: inference over the 4096 padded 64^3 subimages of
     the 1024^3 surrogate workload, and Adam training steps at batch 32."""
@@ -616,8 +696,8 @@ def bench_cnn(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "cnn", "study", "contrast",
-                                               "timing"),
+    ap.add_argument("--workload", choices=("solve256", "hier", "uneven", "surrogate", "surrogate_ood", "cnn", "study",
+                                               "contrast", "timing"),
                     default="solve256")
     ap.add_argument("--sur-size", type=int, default=1024)
     ap.add_argument("--weights-dir", default=None)
@@ -637,6 +717,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="default workload without its surrogate leg")
     ap.add_argument("--cpu-iters", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -651,6 +732,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "cnn":
         return bench_cnn(args)
+    if args.workload == "surrogate_ood":
+        return bench_surrogate_ood(args)
     if args.workload == "study":
         return bench_study(args)
     if args.workload == "contrast":
@@ -708,6 +791,27 @@ def main():
                  for k in KCLS}
     print("bench: per-class %s" % json.dumps(per_class), file=sys.stderr, flush=True)
 
+    # the surrogate pipeline on the 1024^3 workload (shipped networks, gate, FFT
+    # fallback, level 2) against the plain FFT hierarchy of the same image
+    sur = None
+    if not args.no_surrogate:
+        from paper_2208_02320_amd import surrogate
+        paths = surrogate.default_weights(64, 8, args.weights_dir)
+        if all(os.path.exists(pth) for pth in paths):
+            ctx.release_workspace()
+            nets = [surrogate.load(ctx, pth) for pth in paths]
+            img = synth.four_phase_device(args.sur_size, sigma=2.0, seed=3, device="cuda:0")
+            torch.cuda.synchronize()
+            sur = surrogate_leg(ctx, img, phases, nets, steps=args.steps, warmup=1, spread_tol=args.spread_tol,
+                                bound_tol=args.bound_tol)
+            sur["workload"] = ("hierarchical %d^3 four-phase (seed 3), n = 64, pad 8, shipped network pair, "
+                               "spread_tol %g, FFT fallback tol 1e-6" % (args.sur_size, args.spread_tol))
+            print("bench: surrogate %d^3: %.0f subimages/s, fallback %.3f, C* error %.2e, %.0fx the plain hierarchy" %
+                  (args.sur_size, sur["subimages_per_s"], sur["fallback_fraction"], sur["rel_error_vs_plain"],
+                   sur["speedup_vs_plain"]), file=sys.stderr, flush=True)
+            del img
+            for net in nets:
+                net.close()
     cpu = None if args.no_cpu else cpu_baseline(lab, phases, args.cpu_iters)
     err = error_vs_stored_oracle(n, last.C) if last is not None else None
     out = {
@@ -736,6 +840,7 @@ def main():
                      "mean_launch_ms": round(ms[dom] / max(launches[dom], 1), 4)},
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
+        "surrogate": sur,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -350,6 +350,17 @@ int hh_hierarchical_surrogate(hh_ctx *ctx, const uint8_t *labels, int nx, int ny
                               double C_out[36], double *C_sub, int *fallback, hh_report *report);
 
 /*
+ * Persistent autotuner cache: reads the tile plans stored in the text file
+ * `path` for this GPU architecture and build (lines "hh-plan <arch> <tag>
+ * nx ny nz precision aniso bucket z y x"; others are skipped), and appends
+ * every plan the context tunes from now on.  A missing file is created by
+ * the first tuned shape; an unwritable one only costs tuning time.  Plans
+ * change speed, never results (every tile variant gives the same bits).
+ * path = NULL stops the appending.
+ */
+int hh_plan_cache(hh_ctx *ctx, const char *path);
+
+/*
  * Attaches the networks and gate tolerances that hh_hierarchical uses with
  * use_surrogate = 1 (same meaning as in hh_hierarchical_surrogate; net_b may
  * be NULL).  The caller keeps ownership: the networks must stay alive while

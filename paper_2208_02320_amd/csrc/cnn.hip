@@ -33,6 +33,7 @@ struct hh_net {
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
   __bf16* W[kLayers] = {};
   __bf16* Wt[kLayers] = {};
+  __bf16* W4 = nullptr;  // first layer by tap pairs (networks of at most four phases)
   double mean[kOut], scale[kOut];
   double *d_mean = nullptr, *d_scale = nullptr;
   double fmu[kFrac], fsc[kFrac];  // standardization of the phase-fraction features
@@ -124,6 +125,7 @@ void ensure_acts(hh_ctx* ctx, hh_net* net, int batch) {
 void cast_all(hh_ctx* ctx, hh_net* net) {
   for (int l = 0; l < kLayers; ++l)
     k_cast_weights<<<256, 256, 0, ctx->stream>>>(net->p + net->woff[l], kCin[l], kCout[l], net->W[l], net->Wt[l]);
+  k_cast_pairs4<<<16, 256, 0, ctx->stream>>>(net->p + net->woff[0], kCout[0], net->W4);
   HIPCHK(hipGetLastError());
 }
 
@@ -169,7 +171,11 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
     launch_count_labels(labels, (long long)box * box * box, box, o, n, 0, batch, net->cnt, ctx->stream);
     net->cnt_in = net->cnt;
   }
-  conv_fwd<8, 32, true, 4>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
+  // labels of at most four phases: the four-channel path (half the k-steps)
+  if (net->nphase <= 4)
+    conv_fwd<4, 32, true, 4>(ctx, nullptr, net->lw, net->W4, net->p + net->boff[0], net->a[0], edge(net, 0), batch);
+  else
+    conv_fwd<8, 32, true, 4>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
   conv_fwd<32, 32, false, 4>(ctx, net->a[0], net->lw, net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
   conv_fwd<32, 64, false, 2>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
   conv_fwd_splitk<64, 64>(ctx, net->a[2], net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch);
@@ -322,6 +328,7 @@ int hh_net_create(hh_ctx* ctx, int nphase, int n, unsigned long long seed, hh_ne
         net->W[l] = dalloc<__bf16>(ctx, 27LL * kCout[l] * kCin[l]);
         net->Wt[l] = dalloc<__bf16>(ctx, 27LL * kCout[l] * kCin[l]);
       }
+      net->W4 = dalloc<__bf16>(ctx, 14LL * kCout[0] * 8);
       net->d_mean = dalloc<double>(ctx, kOut);
       net->d_scale = dalloc<double>(ctx, kOut);
       net->d_fmu = dalloc<float>(ctx, kFrac);
@@ -377,6 +384,7 @@ void hh_net_destroy(hh_net* net) {
   for (int l = 0; l < kLayers; ++l) {
     (void)hipFree(net->W[l]);
     (void)hipFree(net->Wt[l]);
+    if (l == 0) (void)hipFree(net->W4);
   }
   (void)hipFree(net->d_mean);
   (void)hipFree(net->d_scale);

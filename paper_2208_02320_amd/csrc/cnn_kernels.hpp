@@ -82,6 +82,15 @@ __device__ __forceinline__ const unsigned char* window_base(const LabelWindow& w
   return w.labels + (long long)b * w.stride + ((long long)w.o * w.box + w.o) * w.box + w.o;
 }
 
+typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
+// one-hot code of a label over 4 channels (the zero code for 4 and above)
+__device__ __forceinline__ bf16x4v onehot4(int lab) {
+  bf16x4v h;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) h[c] = (__bf16)(c == lab ? 1.0f : 0.0f);
+  return h;
+}
+
 __device__ __forceinline__ bf16x8 onehot8(int lab) {
   bf16x8 h;
 #pragma unroll
@@ -195,17 +204,22 @@ __device__ __forceinline__ bf16x8 from_left_lane(bf16x8 v) {
 // are four consecutive output rows of one slice, so the ty = 0 inputs of row
 // block r are the ty = 2 inputs of row block r - 1, already in registers: 18
 // loads per tz instead of 24.
+// LAB with CIN = 4 (networks of at most four phases): a lane's eight K values
+// are the four channels of two consecutive taps, so K = 27 x 4 takes 4 k-steps
+// instead of 7; W is then laid out [tap pair][COUT][8] (k_cast_pairs4).
 template <int CIN, int COUT, bool LAB, int RB, bool XS = false, bool YR = false>
 __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
                                                   const __bf16* __restrict__ W, const float* __restrict__ bias,
                                                   __bf16* __restrict__ Y, int D, Grid3 go) {
-  static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
+  static_assert((LAB ? (CIN == 8 || CIN == 4) : CIN % 8 == 0) && COUT % 16 == 0, "channel counts");
+  constexpr bool L4 = LAB && CIN == 4;
   static_assert(!XS || (CIN == 32 && !LAB), "the x-shift path takes one tap per K step");
   static_assert(!YR || (XS && RB == 4), "row reuse: x-shift path, four row blocks");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
   constexpr int VW = 16 * RB;  // output voxels of one wave
   // one-hot codes of labels 0..7 and a zero row (index 8) for padding and labels >= 8
   __shared__ bf16x8 sOne[9];
+  __shared__ bf16x4v sOne4[5];  // four-channel codes of labels 0..3 and a zero row (index 4)
   // first layer (large output): each wave's output tile goes out through LDS
   // as whole 16-byte chunks; deeper layers store 8-byte words directly
   constexpr bool STAGE = LAB;
@@ -216,6 +230,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   const int v0 = blockIdx.x * (64 * RB) + wave * VW;
   if constexpr (LAB) {
     if (threadIdx.x < 9) sOne[threadIdx.x] = threadIdx.x < 8 ? onehot8(threadIdx.x) : zero8();
+    if (threadIdx.x < 5) sOne4[threadIdx.x] = onehot4(threadIdx.x);
     __syncthreads();
   }
   const __bf16* Xb = LAB ? nullptr : X + (long long)b * D * D * D * CIN;
@@ -244,6 +259,15 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   using Raw = typename std::conditional<LAB, int, bf16x8>::type;
   auto load_a = [&](int ks, int r, bool& ok) -> Raw {
     const int tap = tap_of(ks);
+    if constexpr (L4) {
+      // taps tap and tap + 1: both labels, each mapped to row 4 (zero) where padded
+      const bool ok0 = tap < 27 && (lowm[r] & (tap_mask(tap) | 8u)) == 0u;
+      const bool ok1 = tap + 1 < 27 && (lowm[r] & (tap_mask(tap + 1) | 8u)) == 0u;
+      const int l0 = int(Lb[ok0 ? base[r] + tap_off(tap) : 0]);
+      const int l1 = int(Lb[ok1 ? base[r] + tap_off(tap + 1) : 0]);
+      ok = true;
+      return (ok0 ? min(l0, 4) : 4) | ((ok1 ? min(l1, 4) : 4) << 8);
+    }
     ok = tap < 27 && (lowm[r] & (tap_mask(tap) | 8u)) == 0u;
     const int off = ok ? base[r] + tap_off(tap) : 0;
     if constexpr (LAB) {
@@ -255,6 +279,10 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   };
   auto load_b = [&](int ks, int t) {
     const int k = ks * 32 + (lane >> 4) * 8;
+    if constexpr (L4) {
+      const int j = k / 8;  // tap pair
+      return ld8(W + ((j < 14 ? j : 0) * COUT + t * 16 + (lane & 15)) * 8);
+    }
     const int tap = k / CIN, c0 = k % CIN;
     return ld8(W + ((tap < 27 ? tap : 0) * COUT + t * 16 + (lane & 15)) * CIN + c0);
   };
@@ -350,10 +378,14 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
     for (int t = 0; t < NT; ++t) bw[t] = btap ? rb_[t] : zero8();
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      if constexpr (LAB)
+      if constexpr (L4) {
+        const bf16x4v lo = sOne4[ra[r] & 0xff], hi = sOne4[ra[r] >> 8];
+        a[r] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      } else if constexpr (LAB) {
         a[r] = sOne[rok[r] ? min(ra[r], 8) : 8];
-      else
+      } else {
         a[r] = rok[r] ? ra[r] : zero8();
+      }
     }
     if (ks + 1 < KS) {
 #pragma unroll
@@ -883,6 +915,17 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// First-layer weights for the four-channel path: W4[j][co][c] is tap 2 j
+// (c < 4) or tap 2 j + 1 (c >= 4), channel c % 4, zero past tap 26; j < 14.
+__global__ void k_cast_pairs4(const float* __restrict__ w, int cout, __bf16* __restrict__ W4) {
+  const int n = 14 * cout * 8;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int c = i % 8, co = (i / 8) % cout, j = i / (8 * cout);
+    const int tap = 2 * j + c / 4;
+    W4[i] = (__bf16)(tap < 27 ? w[((long long)tap * cout + co) * 8 + c % 4] : 0.0f);
   }
 }
 

@@ -34,6 +34,8 @@ struct hh_ctx {
   int max_lds = 65536;                    // LDS bytes a workgroup may use
   // tuned tile variants (z, y, x) per (nx, ny, nz, precision, aniso, systems bucket)
   std::map<std::array<int, 6>, std::array<int, 3>> plans;
+  std::string plan_file;  // tuned plans appended here and read by hh_plan_cache (empty: none)
+  std::string arch;       // gcnArchName up to its feature list
   // instantiated graphs of iteration chunks, keyed by their launch arguments
   std::map<std::string, hipGraphExec_t> graphs;
   double setup_ms = 0.0;                  // tuning and graph construction of the current call

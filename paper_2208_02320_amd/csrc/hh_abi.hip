@@ -300,6 +300,20 @@ void ensure_lanes(hh_ctx* ctx, int n) {
   }
 }
 
+// Tuned plans on disk (hh_plan_cache): one line per shape,
+//   hh-plan <arch> <variants> <nx> <ny> <nz> <precision> <aniso> <bucket> <z> <y> <x>
+// where <variants> names the compiled tile-variant set, so that a file
+// written by another build or GPU is ignored.
+const char* kPlanTag = "v5";
+void save_plan(hh_ctx* ctx, const std::array<int, 6>& key, const std::array<int, 3>& plan) {
+  if (ctx->plan_file.empty()) return;
+  FILE* f = std::fopen(ctx->plan_file.c_str(), "a");
+  if (!f) return;  // the cache is an optimisation: a read-only location only costs tuning time
+  std::fprintf(f, "hh-plan %s %s %d %d %d %d %d %d %d %d %d\n", ctx->arch.c_str(), kPlanTag, key[0], key[1], key[2],
+               key[3], key[4], key[5], plan[0], plan[1], plan[2]);
+  std::fclose(f);
+}
+
 // The context's own lane: its stream, capture stream and timing events.
 hh_lane main_lane(hh_ctx* ctx) {
   hh_lane l;
@@ -551,7 +565,10 @@ GroupResult solve_group(hh_ctx* ctx, const std::vector<Item>& items, const unsig
         }
         plan = pick;
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        if (o.plan[0] < 0 && o.plan[1] < 0 && o.plan[2] < 0) ctx->plans[key] = plan;
+        if (o.plan[0] < 0 && o.plan[1] < 0 && o.plan[2] < 0) {
+          ctx->plans[key] = plan;
+          save_plan(ctx, key, plan);
+        }
         need_tune = false;
         ctx->setup_ms += ms_since(t_start);
       }
@@ -1078,6 +1095,8 @@ int hh_create(hh_ctx** out, int device, void* hip_stream) {
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->max_lds = int(prop.sharedMemPerBlock);
+  ctx->arch = prop.gcnArchName;
+  ctx->arch = ctx->arch.substr(0, ctx->arch.find(':'));
   const char* step = "hipSetDevice";
   e = hipSetDevice(device);
   if (e == hipSuccess) step = "hipEventCreate", e = hipEventCreate(&ctx->t0);
@@ -1672,6 +1691,31 @@ int hh_hierarchical_surrogate(hh_ctx* ctx, const uint8_t* labels, int nx, int ny
     check_opts(ctx, o);
     return hierarchical_surrogate_impl(ctx, labels, nx, ny, nz, labels_on_device, phases, nphase, n_sub, pad, net_a,
                                        net_b, spread_tol, bound_tol, o, C_out, C_sub, fallback, report);
+  });
+}
+
+int hh_plan_cache(hh_ctx* ctx, const char* path) {
+  return guarded(ctx, [&]() -> int {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->plan_file = path ? path : "";
+    if (!path) return HH_OK;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return HH_OK;  // created by the first tuned shape
+    char tag[64], arch[64], ver[16];
+    int v[11];
+    int loaded = 0;
+    while (std::fscanf(f, "%63s %63s %15s %d %d %d %d %d %d %d %d %d", tag, arch, ver, &v[0], &v[1], &v[2], &v[3],
+                       &v[4], &v[5], &v[6], &v[7], &v[8]) == 12) {
+      if (std::strcmp(tag, "hh-plan") != 0 || ctx->arch != arch || std::strcmp(ver, kPlanTag) != 0) continue;
+      bool ok = true;
+      for (int i = 6; i < 9; ++i) ok = ok && v[i] >= 0 && v[i] < kNVariant;
+      if (!ok) continue;
+      ctx->plans[std::array<int, 6>{{v[0], v[1], v[2], v[3], v[4], v[5]}}] = {{v[6], v[7], v[8]}};
+      ++loaded;
+    }
+    std::fclose(f);
+    (void)loaded;
+    return HH_OK;
   });
 }
 

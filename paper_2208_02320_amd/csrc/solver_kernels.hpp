@@ -467,6 +467,7 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + N;
   __shared__ T s_lam[kMaxPhase], s_mu[kMaxPhase];
+  __shared__ unsigned char s_rin[R];  // tile row inside the averaging region (y and z)
 
   const int s = blockIdx.y;
   SysState* st = g.state + s;
@@ -509,6 +510,11 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
     const int i = threadIdx.x < it.nphase ? threadIdx.x : 0;
     s_lam[threadIdx.x] = T(it.lam[i]);
     s_mu[threadIdx.x] = T(it.mu[i]);
+  }
+  if (threadIdx.x < R) {
+    const int row = r0 + threadIdx.x, zr = row / g.ny, yr = row - zr * g.ny;
+    s_rin[threadIdx.x] = threadIdx.x < nr && yr >= it.region[1] && yr < it.region[4] && zr >= it.region[2] &&
+                         zr < it.region[5];
   }
 
   // labels of this thread's voxels, fetched before anything waits on memory
@@ -577,28 +583,46 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
   // region length is added.
   constexpr int NQ = 3 * R * kLineGroups;
   constexpr int KQ = (NQ + TH - 1) / TH;
+  // Every task of a thread has the same group (the thread count is a
+  // multiple of kLineGroups); its positions inside the region's x range,
+  // one bit per position, are found once.
+  constexpr int NJ = (N + kLineGroups - 1) / kLineGroups;
+  static_assert(NJ <= 64, "one 64-bit mask of positions per group");
+  const int gq = threadIdx.x % kLineGroups;
+  unsigned long long xin = 0ull;
+  if (!whole) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int pos = gq + kLineGroups * j;
+      if (pos < N) {
+        const int x = perm_idx<N1, N2>(pos);
+        if (x >= x0 && x < x1) xin |= 1ull << j;
+      }
+    }
+  }
   auto region_lines = [&](int base, double scale, bool add_e) {
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
       const int q = threadIdx.x + k * TH;
-      const int l = q / kLineGroups, gq = q % kLineGroups;
+      const int l = q / kLineGroups;
       const int rl = l / 3, pr = l - 3 * (l / 3);
-      const int row = r0 + rl, zr = row / g.ny, yr = row - zr * g.ny;
       const bool task = (NQ % TH == 0 || q < NQ) && rl < nr;
-      const bool rin = task && yr >= y0 && yr < y1 && zr >= z0 && zr < z1;
+      const bool rin = task && s_rin[rl];
       double sr = 0.0, si = 0.0;
       if (rin) {
-        for (int pos = gq; pos < N; pos += kLineGroups) {
-          const int x = perm_idx<N1, N2>(pos);
-          if (x >= x0 && x < x1) {
-            const cx<T> v = buf[lds_at<N1, P>(pos, L) + l];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          if ((xin >> j) & 1ull) {
+            const cx<T> v = buf[lds_at<N1, P>(gq + kLineGroups * j, L) + l];
             sr += double(v.re);
             si += double(v.im);
           }
         }
       }
-      sr = group_sum(sr);
-      si = group_sum(si);
+      if (__ballot(rin) != 0ull) {  // a wave without region rows has only zeros to add
+        sr = group_sum(sr);
+        si = group_sum(si);
+      }
       if (task && gq == 0) {
         double a = 0.0, b = 0.0;
         if (rin) {
@@ -620,11 +644,10 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
       const int q = threadIdx.x + k * TH;
-      const int l = q / kLineGroups, gq = q % kLineGroups;
+      const int l = q / kLineGroups;
       const int rl = l / 3, pr = l - 3 * (l / 3);
-      const int row = r0 + rl, zr = row / g.ny, yr = row - zr * g.ny;
       if ((NQ % TH == 0 || q < NQ) && rl < nr && gq == 0) {
-        const bool rin = yr >= y0 && yr < y1 && zr >= z0 && zr < z1;
+        const bool rin = s_rin[rl];
         prow[(long long)rl * kPartX + 1 + 2 * pr] = rin ? double(x1 - x0) * double(E[2 * pr]) : 0.0;
         prow[(long long)rl * kPartX + 2 + 2 * pr] = rin ? double(x1 - x0) * double(E[2 * pr + 1]) : 0.0;
       }

@@ -32,7 +32,7 @@ SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_la
            "hh_gather_subimages",
            "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_load", "hh_net_info", "hh_net_get_params",
            "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling",
-           "hh_net_get_fraction_scaling", "hh_net_forward", "hh_set_surrogate",
+           "hh_net_get_fraction_scaling", "hh_net_forward", "hh_set_surrogate", "hh_plan_cache",
            "hh_net_gradient", "hh_net_train_step", "hh_net_predict", "hh_hierarchical_surrogate",
            "hh_richardson", "hh_moduli", "hh_mean_moduli")
 
@@ -132,6 +132,7 @@ def load_library(path=LIB_PATH):
     lib.hh_hierarchical_surrogate.argtypes = [P, P, I, I, I, I, ct.POINTER(Phase), I, I, I, P, P, D, D,
                                               ct.POINTER(Opts), DP, DP, ct.POINTER(I), ct.POINTER(Report)]
     lib.hh_set_surrogate.argtypes = [P, P, P, D, D]
+    lib.hh_plan_cache.argtypes = [P, ct.c_char_p]
     lib.hh_richardson.argtypes = [ct.POINTER(I), DP, I, DP, DP]
     lib.hh_moduli.argtypes = [DP, DP, DP]
     lib.hh_mean_moduli.argtypes = [DP, LL, DP, DP]
@@ -354,6 +355,10 @@ class Context:
             self._check(rc)
         del keep
         return C.reshape(n, 6, 6), Craw.reshape(n, 6, 6), st, it.reshape(n, 6), rep.as_dict()
+
+    def plan_cache(self, path):
+        """Persistent autotuner plans in the text file ``path`` (None stops appending)."""
+        self._check(self._lib.hh_plan_cache(self._h, None if path is None else os.fsencode(os.fspath(path))))
 
     def set_surrogate(self, net_a, net_b=None, spread_tol=0.02, bound_tol=0.0):
         """Networks used by hierarchical(..., use_surrogate=True); None detaches."""

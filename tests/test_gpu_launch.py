@@ -116,3 +116,25 @@ def test_unavailable_variant_is_rejected(ctx):
         ctx.homogenize(lab, FOUR, precision=1, plan=(1, 0, 0))
     with pytest.raises(hh.HHError):
         ctx.homogenize(lab, FOUR, plan=(5, 0, 0))
+
+
+def test_plan_cache_file_is_written_and_reused(tmp_path):
+    """A context with a plan file appends the plans it tunes; a later context
+    reading the file uses them without tuning, with the same result."""
+    from paper_2208_02320_amd import hh
+    path = tmp_path / "plans.txt"
+    lab = synth.four_phase(40, seed=14)
+    with hh.Context(0) as a:
+        a.plan_cache(path)
+        r1 = a.homogenize(lab, FOUR, tol=1e-6)
+    lines = [l.split() for l in open(path)]
+    assert len(lines) == 1 and lines[0][0] == "hh-plan" and lines[0][1].startswith("gfx950")
+    assert [int(v) for v in lines[0][3:6]] == [40, 40, 40]
+    assert [int(v) for v in lines[0][9:12]] == r1.report["plan"]
+    with hh.Context(0) as b:
+        b.plan_cache(path)
+        r2 = b.homogenize(lab, FOUR, tol=1e-6)
+    assert r2.report["plan"] == r1.report["plan"]
+    assert r2.report["setup_ms"] < r1.report["setup_ms"]
+    assert np.array_equal(r2.C, r1.C)
+    assert len(open(path).readlines()) == 1  # nothing new was tuned
