@@ -167,15 +167,29 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of one value over the kLineGroups consecutive lanes of a group, in a
-// fixed butterfly (the same tree in every lane, whatever wave or task the
-// group sits in); every lane of the wave must take part.
+// v of another lane of the same row of 16 lanes, by a DPP move (no LDS
+// traffic): CTRL 0xB1 and 0x4E are the quad permutations [1 0 3 2] and
+// [2 3 0 1]; 0x141 mirrors each half row (lane i <-> 7 - i), 0x140 the row
+// (i <-> 15 - i).  Every lane reads a lane of its own row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_pair(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(u)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(u >> 32)), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (unsigned long long)unsigned(lo) | ((unsigned long long)unsigned(hi) << 32));
+}
+
+// Sum of one value over the kLineGroups consecutive lanes of a group (one row
+// of 16 lanes): pairs, quads, half rows, rows, each step adding a partner
+// lane's partial.  Addition commutes, so every lane of the group ends with
+// the same bits, and the tree is the same whatever wave or task the group
+// sits in; every lane of the wave must take part.
 __device__ __forceinline__ double group_sum(double v) {
-  static_assert(kLineGroups == 16, "butterfly over 16 lanes");
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
+  static_assert(kLineGroups == 16, "butterfly over one row of 16 lanes");
+  v += dpp_pair<0xB1>(v);
+  v += dpp_pair<0x4E>(v);
+  v += dpp_pair<0x141>(v);
+  v += dpp_pair<0x140>(v);
   return v;
 }
 
@@ -468,6 +482,7 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
   cx<T>* buf = tw + N;
   __shared__ T s_lam[kMaxPhase], s_mu[kMaxPhase];
   __shared__ unsigned char s_rin[R];  // tile row inside the averaging region (y and z)
+  __shared__ cx<T> s_dc[L];           // kx = 0 input of each line (its sum over x is N times this)
 
   const int s = blockIdx.y;
   SysState* st = g.state + s;
@@ -553,6 +568,7 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
         if (rl >= nr) A = B = cx<T>{T(0), T(0)};
         if (kx == 0 || 2 * kx == N) {
           buf[lds_at<N1, P>(kx, L) + l] = cx<T>{A.re, B.re};
+          if (kx == 0) s_dc[l] = cx<T>{A.re, B.re};
         } else {
           buf[lds_at<N1, P>(kx, L) + l] = cx<T>{A.re - B.im, A.im + B.re};
           buf[lds_at<N1, P>(N - kx, L) + l] = cx<T>{A.re + B.im, B.re - A.im};
@@ -576,61 +592,92 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
   // are the kx = 0 outputs of the forward transform, so no per-voxel sums.
   const bool whole = x0 == 0 && x1 == N && y0 == 0 && y1 == g.ny && z0 == 0 && z1 == g.nz;
   double* prow = g.part_x + ((long long)s * g.nrow_x + r0) * kPartX;  // row sums of this tile
-  // Region sums of one field held in buf (p before the law, sigma after it):
-  // line l = 3 row + pair, summed in kLineGroups groups of positions, then
-  // the groups in a butterfly; written as entries base + 2 pair, + 1 of the
-  // row.  In FP mode p carries the macroscopic strain: E times the row's
-  // region length is added.
+  // Region sums of one field held in buf (p before the law, sigma after it),
+  // per line l = 3 row + pair.  The region's x range [x0, x1) holds K
+  // points; the summed set S is that range when K <= N - K and its
+  // complement otherwise, the region's sum then being the line's total
+  // minus the complement's (the total comes from the transform: N times
+  // the kx = 0 input for p, the kx = 0 output for sigma).  The elements of
+  // S in increasing x are summed in kLineGroups groups, group g taking
+  // elements g, g + kLineGroups, ... in order, and the groups are added in
+  // a butterfly; the result sits in the group-0 lane of each line's task.
   constexpr int NQ = 3 * R * kLineGroups;
   constexpr int KQ = (NQ + TH - 1) / TH;
   // Every task of a thread has the same group (the thread count is a
-  // multiple of kLineGroups); its positions inside the region's x range,
-  // one bit per position, are found once.
-  constexpr int NJ = (N + kLineGroups - 1) / kLineGroups;
-  static_assert(NJ <= 64, "one 64-bit mask of positions per group");
+  // multiple of kLineGroups); the LDS offsets of its elements of S are
+  // found once (kept in registers for lines up to 256 points).
+  constexpr int NJS = (N / 2 + kLineGroups - 1) / kLineGroups;  // |S| <= N / 2
+  constexpr bool kOffRegs = NJS <= 8;
   const int gq = threadIdx.x % kLineGroups;
-  unsigned long long xin = 0ull;
-  if (!whole) {
+  const int K = x1 - x0;
+  const bool comp = N - K < K;
+  const int KS = comp ? N - K : K;
+  auto s_off = [&](int j) -> int {  // LDS offset of element gq + kLineGroups j of S, -1 past its end
+    const int i = gq + kLineGroups * j;
+    if (i >= KS) return -1;
+    const int x = comp ? (i < x0 ? i : x1 + (i - x0)) : x0 + i;
+    return lds_at<N1, P>((x % N2) * N1 + x / N2, L);  // position of x (inverse of perm_idx)
+  };
+  int soff[kOffRegs ? NJS : 1];
+  if constexpr (kOffRegs) {
+    if (!whole) {
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int pos = gq + kLineGroups * j;
-      if (pos < N) {
-        const int x = perm_idx<N1, N2>(pos);
-        if (x >= x0 && x < x1) xin |= 1ull << j;
-      }
+      for (int j = 0; j < NJS; ++j) soff[j] = s_off(j);
     }
   }
-  auto region_lines = [&](int base, double scale, bool add_e) {
+  auto region_sums = [&](double (&sr)[KQ], double (&si)[KQ]) {
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+      const int q = threadIdx.x + k * TH;
+      const int l = q / kLineGroups;
+      const int rl = l / 3;
+      const bool rin = (NQ % TH == 0 || q < NQ) && rl < nr && s_rin[rl];
+      double a = 0.0, b = 0.0;
+      if (rin) {
+#pragma unroll
+        for (int j = 0; j < NJS; ++j) {
+          int o;
+          if constexpr (kOffRegs) o = soff[j];
+          else o = s_off(j);
+          if (o >= 0) {
+            const cx<T> v = buf[o + l];
+            a += double(v.re);
+            b += double(v.im);
+          }
+        }
+      }
+      if (__ballot(rin) != 0ull) {  // a wave without region rows has only zeros to add
+        a = group_sum(a);
+        b = group_sum(b);
+      }
+      sr[k] = a;
+      si[k] = b;
+    }
+  };
+  // the sums' entries base + 2 pair, + 1 of each row, from S's sums and the
+  // lines' totals; zero outside the region
+  auto region_write = [&](int base, const double (&sr)[KQ], const double (&si)[KQ], const cx<T>* tot,
+                          double tscale, double scale, bool add_e) {
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
       const int q = threadIdx.x + k * TH;
       const int l = q / kLineGroups;
       const int rl = l / 3, pr = l - 3 * (l / 3);
-      const bool task = (NQ % TH == 0 || q < NQ) && rl < nr;
-      const bool rin = task && s_rin[rl];
-      double sr = 0.0, si = 0.0;
-      if (rin) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          if ((xin >> j) & 1ull) {
-            const cx<T> v = buf[lds_at<N1, P>(gq + kLineGroups * j, L) + l];
-            sr += double(v.re);
-            si += double(v.im);
-          }
-        }
-      }
-      if (__ballot(rin) != 0ull) {  // a wave without region rows has only zeros to add
-        sr = group_sum(sr);
-        si = group_sum(si);
-      }
-      if (task && gq == 0) {
+      if ((NQ % TH == 0 || q < NQ) && rl < nr && gq == 0) {
         double a = 0.0, b = 0.0;
-        if (rin) {
-          a = sr * scale;
-          b = si * scale;
+        if (s_rin[rl]) {
+          a = sr[k];
+          b = si[k];
+          if (comp) {
+            const cx<T> t = tot[l];
+            a = tscale * double(t.re) - a;
+            b = tscale * double(t.im) - b;
+          }
+          a *= scale;
+          b *= scale;
           if (add_e) {
-            a += double(x1 - x0) * double(E[2 * pr]);
-            b += double(x1 - x0) * double(E[2 * pr + 1]);
+            a += double(K) * double(E[2 * pr]);
+            b += double(K) * double(E[2 * pr + 1]);
           }
         }
         prow[(long long)rl * kPartX + base + 2 * pr] = a;
@@ -638,7 +685,11 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
       }
     }
   };
-  if (MODE != kXRhs && !whole) region_lines(1, 1.0 / (double(N) * g.ny * g.nz), MODE == kXFp);
+  if (MODE != kXRhs && !whole) {
+    double sr[KQ], si[KQ];
+    region_sums(sr, si);
+    region_write(1, sr, si, s_dc, double(N), 1.0 / (double(N) * g.ny * g.nz), MODE == kXFp);
+  }
   if (MODE == kXRhs && !whole) {
     // the right-hand side's p is the constant E
 #pragma unroll
@@ -648,8 +699,8 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
       const int rl = l / 3, pr = l - 3 * (l / 3);
       if ((NQ % TH == 0 || q < NQ) && rl < nr && gq == 0) {
         const bool rin = s_rin[rl];
-        prow[(long long)rl * kPartX + 1 + 2 * pr] = rin ? double(x1 - x0) * double(E[2 * pr]) : 0.0;
-        prow[(long long)rl * kPartX + 2 + 2 * pr] = rin ? double(x1 - x0) * double(E[2 * pr + 1]) : 0.0;
+        prow[(long long)rl * kPartX + 1 + 2 * pr] = rin ? double(K) * double(E[2 * pr]) : 0.0;
+        prow[(long long)rl * kPartX + 2 + 2 * pr] = rin ? double(K) * double(E[2 * pr + 1]) : 0.0;
       }
     }
   }
@@ -733,11 +784,17 @@ __attribute__((amdgpu_waves_per_eu(XCfg<N, T, V>::WAVES_HINT))) k_xpass(GroupArg
     for (int pr = 0; pr < 3; ++pr) buf[lds_at<N1, P>(pos, L) + rl * 3 + pr] = cx<T>{sg[2 * pr], sg[2 * pr + 1]};
   }
   __syncthreads();
+  double ssr[KQ], ssi[KQ];  // sigma's sums over S, completed after the transform
   if (!whole) {
-    region_lines(7, 1.0, false);
+    region_sums(ssr, ssi);
     __syncthreads();  // buf is read above and transformed below
   }
   fft_perm2nat<N1, N2, -1, T, P>(buf, L, tw);
+  if (!whole) {
+    // the kx = 0 output of line l is the line's total of sigma
+    const cx<T>* tot = buf + lds_at<N1, P>(0, L);
+    region_write(7, ssr, ssi, tot, 1.0, 1.0, false);
+  }
   // whole box: the kx = 0 output of line row * 3 + pair is the row sum of
   // sigma components 2 pair (re) and 2 pair + 1 (im); the row sums of p are
   // 0, or N E in FP mode (p carries E there)
