@@ -350,7 +350,20 @@ def bench_timing(args):
         print("bench: timing hierarchy N=%d n=%d: %.2f s (setup %.0f ms), %.3g voxel-iter/s, K %.4f G %.4f" %
               (N, n, dt, rep["setup_ms"], rep["voxel_iters"] / solve, K, G), file=sys.stderr, flush=True)
     a_hier = float(np.polyfit(np.log([r["n"] for r in hier]), np.log([r["solve_seconds"] for r in hier]), 1)[0])
-    # M(n) = M_inf + c / n over the partition grid (Sec. 5's fit; no plain 900^3 reference here)
+    # the plain solve of the same N^3 image, the reference of the scheme's error
+    plain = None
+    if hh.size_supported(N, 0):
+        ctx.release_workspace()
+        t = time.perf_counter()
+        rp = ctx.homogenize(lab, phases, tol=1e-6)
+        dtp = time.perf_counter() - t
+        Kp, Gp = hh.moduli(rp.C)
+        plain = {"seconds": dtp, "K": Kp, "G": Gp, "iters": rp.report["iters"]}
+        for r in hier:
+            r["K_err_pct"] = 100 * (r["K"] / Kp - 1)
+            r["G_err_pct"] = 100 * (r["G"] / Gp - 1)
+        print("bench: timing plain %d^3: %.2f s, K %.4f G %.4f" % (N, dtp, Kp, Gp), file=sys.stderr, flush=True)
+    # M(n) = M_inf + c / n over the partition grid (Sec. 5 fit)
     A = np.stack([np.ones(len(hier)), 1.0 / np.array([r["n"] for r in hier], float)], axis=1)
     fit = {}
     for m in ("K", "G"):
@@ -363,6 +376,7 @@ def bench_timing(args):
         "config": {"workload": "timing: four-phase images (sigma %g, seed %d), tol 1e-6; plain solves n = 64..1024, "
                                "two-level scheme on %d^3, pad 0" % (sigma, seed, N)},
         "single": single, "hierarchy": hier, "hierarchy_time_exponent": a_hier, "hierarchy_n_inverse_fit": fit,
+        "plain_reference": plain,
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -568,11 +582,12 @@ def bench_surrogate(args):
     ctx.close()
 
 
-def surrogate_leg(ctx, img, phases, nets, steps=3, warmup=1, spread_tol=0.02, bound_tol=0.0, n=64, pad=8):
+def surrogate_leg(ctx, img, phases, nets, steps=3, warmup=1, spread_tol=0.02, bound_tol=0.0, n=64, pad=8,
+                  keep_plain=False):
     """The two-level scheme with the network pair, gate and FFT fallback on one
     device image, timed over ``steps`` calls after ``warmup``; the plain FFT
     hierarchy of the same image, timed once, is the reference of its C* error
-    and of the speed-up."""
+    and of the speed-up (its C* under "_C_plain" with ``keep_plain``)."""
     import torch
     from paper_2208_02320_amd import hh, surrogate
     na, nb = nets
@@ -597,7 +612,7 @@ def surrogate_leg(ctx, img, phases, nets, steps=3, warmup=1, spread_tol=0.02, bo
             "subimage_rel_error_accepted": {"mean": float(sub[acc].mean()) if acc.any() else None,
                                             "max": float(sub[acc].max()) if acc.any() else None},
             "plain_subimages_per_s": rep["items"] / dtp, "plain_seconds": dtp, "speedup_vs_plain": dtp / dt,
-            "K_G": hh.moduli(C), "plain_K_G": hh.moduli(Cp)}
+            "K_G": hh.moduli(C), "plain_K_G": hh.moduli(Cp), **({"_C_plain": Cp} if keep_plain else {})}
 
 
 def bench_surrogate_ood(args):
@@ -622,20 +637,34 @@ def bench_surrogate_ood(args):
     for name, c in cases:
         img = synth.rocklike_device(N, c["fracs"], sigma=c["sigma"], seed=c["seed"], low_to_high=low)
         torch.cuda.synchronize()
+        for net in nets:
+            net.set_fraction_gate(args.frac_z)
         leg = surrogate_leg(ctx, img, phases, nets, steps=1, warmup=1, spread_tol=args.spread_tol,
-                            bound_tol=args.bound_tol)
+                            bound_tol=args.bound_tol, keep_plain=True)
+        Cp = leg.pop("_C_plain")
         leg["image"] = name
+        # the same gate without its phase-fraction test
+        for net in nets:
+            net.set_fraction_gate(0.0)
+        C0, _, fb0, _ = ctx.hierarchical_surrogate(img, phases, 64, 8, nets[0], nets[1], spread_tol=args.spread_tol,
+                                                   bound_tol=args.bound_tol, tol=1e-6)
+        leg["without_fraction_test"] = {
+            "fallback_fraction": float(fb0.mean()),
+            "rel_error_vs_plain": float(surrogate.rel_error21(hh.upper21(C0), hh.upper21(Cp))[0])}
         rows.append(leg)
-        print("bench: surrogate on %s: fallback %.3f, C* error %.2e, %.0f subimages/s, %.0fx the plain hierarchy" %
+        print("bench: surrogate on %s: fallback %.3f, C* error %.2e, %.0f subimages/s, %.0fx the plain hierarchy; "
+              "without the fraction test: fallback %.3f, C* error %.2e" %
               (name, leg["fallback_fraction"], leg["rel_error_vs_plain"], leg["subimages_per_s"],
-               leg["speedup_vs_plain"]), file=sys.stderr, flush=True)
+               leg["speedup_vs_plain"], leg["without_fraction_test"]["fallback_fraction"],
+               leg["without_fraction_test"]["rel_error_vs_plain"]), file=sys.stderr, flush=True)
         del img
         torch.cuda.empty_cache()
     line = {"metric": "C* error of the surrogate pipeline against the plain hierarchy, worst over the images",
             "value": max(r["rel_error_vs_plain"] for r in rows), "unit": "relative", "n_gpus": 1,
             "higher_is_better": False, "dtype": "bf16 network / f32 solver", "data": "synthetic",
             "config": {"workload": "surrogate pair on %d^3 four-phase images off its training recipe, n = 64, pad 8, "
-                                   "spread_tol %g, bound_tol %g" % (N, args.spread_tol, args.bound_tol)},
+                                   "spread_tol %g, bound_tol %g, fraction z_max %g" %
+                                   (N, args.spread_tol, args.bound_tol, args.frac_z)},
             "images": rows}
     print(json.dumps(line), flush=True)
     for net in nets:
@@ -703,6 +732,7 @@ def main():
     ap.add_argument("--weights-dir", default=None)
     ap.add_argument("--spread-tol", type=float, default=0.02)
     ap.add_argument("--bound-tol", type=float, default=0.0)
+    ap.add_argument("--frac-z", type=float, default=5.0, help="limit of the gate's phase-fraction test")
     ap.add_argument("--hier-size", type=int, default=512)
     ap.add_argument("--hier-ns", default="32,64,128", help="subimage sizes of the hier workload")
     ap.add_argument("--no-levels", action="store_true", help="hier workload without the three-level run")

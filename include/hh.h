@@ -317,6 +317,15 @@ int hh_net_get_scaling(const hh_net *net, double mean[21], double scale[21]);
  * fraction f_c of label c in the input window (c = 0..7; default 0 and 1). */
 int hh_net_set_fraction_scaling(hh_ctx *ctx, hh_net *net, const double mean[8], const double scale[8]);
 int hh_net_get_fraction_scaling(const hh_net *net, double mean[8], double scale[8]);
+/* Input-space test of the surrogate gate (hh_hierarchical_surrogate): an
+ * item goes to the FFT solver when a label's fraction f_c in this
+ * network's input window lies more than z_max feature scales from the
+ * mean, |f_c - mean_c| * scale_c > z_max (the fraction scaling above: the
+ * training windows' mean and inverse standard deviation), or, for a label
+ * whose scale is 0 (its fraction never varied in training), differs from
+ * mean_c by at least one voxel.  Default 5; z_max = 0 switches the test
+ * off.  HH_EINVAL for a negative or non-finite z_max. */
+int hh_net_set_fraction_gate(hh_ctx *ctx, hh_net *net, double z_max);
 /* Normalized outputs y (host, batch x 21). */
 int hh_net_forward(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_on_device, int batch, int box,
                    int offset, float *out);
@@ -338,9 +347,10 @@ int hh_net_predict(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_o
  * or the whole (n_sub + 2 pad)^3 box as its input edge says; a gate sends an
  * item to the FFT solver (the hh_hierarchical path) when the mean prediction
  * is not positive definite, leaves the Voigt-Reuss bracket of the core's
- * phase fractions by more than bound_tol (relative, Mandel norm), or - with
- * two networks - when the two predictions differ by more than spread_tol
- * (relative).  net_b may be NULL.  fallback: (N/n)^3 flags (may be NULL);
+ * phase fractions by more than bound_tol (relative, Mandel norm), when a
+ * network's input window has phase fractions outside the range the network
+ * was trained on (hh_net_set_fraction_gate), or - with two networks - when
+ * the two predictions differ by more than spread_tol (relative).  net_b may be NULL.  fallback: (N/n)^3 flags (may be NULL);
  * C_sub as in hh_hierarchical.  report.items counts subimages,
  * report.voxel_iters the fallback and level-2 solves.
  */

@@ -14,7 +14,12 @@ its definition, with eigenvalues (the kernel uses Cholesky pivots):
   M(C) - M(C_R) + t I must be positive definite, where C_V and C_R are the
   Voigt and Reuss stiffnesses of the subimage's phase fractions (the
   bracket of Sec. 1's classical bounds);
-* with two networks, ||M(C_a) - M(C_b)||_F <= spread_tol ||M(C_a)||_F.
+* with two networks, ||M(C_a) - M(C_b)||_F <= spread_tol ||M(C_a)||_F;
+* input-space test, per network: with f_c the fraction of label c in the
+  network's input window and (mu_c, s_c) the mean and inverse standard
+  deviation of that fraction over the training windows, |f_c - mu_c| s_c
+  <= z_max for every label with s_c > 0, and f_c = mu_c (to within half a
+  voxel) for a label with s_c = 0; z_max = 0 skips the test.
 
 Any failed condition flags the item for the FFT solver.
 """
@@ -52,6 +57,20 @@ def gate(c21a, c21b, CV, CR, spread_tol, bound_tol):
         return True
     if c21b is not None and np.linalg.norm(Ma - Mb) > spread_tol * nrm:
         return True
+    return False
+
+
+def fractions_outside(window_labels, mu, sc, z_max):
+    """True when the input-space test fails for one network's window."""
+    if not z_max > 0.0:
+        return False
+    w = np.asarray(window_labels)
+    nv = w.size
+    for c in range(8):
+        f = np.count_nonzero(w == c) / nv
+        d = abs(f - mu[c])
+        if (d * sc[c] > z_max) if sc[c] > 0.0 else (d > 0.5 / nv):
+            return True
     return False
 
 

@@ -37,6 +37,7 @@ struct hh_net {
   double mean[kOut], scale[kOut];
   double *d_mean = nullptr, *d_scale = nullptr;
   double fmu[kFrac], fsc[kFrac];  // standardization of the phase-fraction features
+  double fzmax = 5.0;              // the gate's limit on |feature| (0: no test)
   float *d_fmu = nullptr, *d_fsc = nullptr;
   long long step = 0;
   int cap = 0;  // batch capacity of the activation buffers
@@ -289,8 +290,22 @@ void hh_launch_bounds(const int* counts, int nitems, int n, int nphase, const do
 }
 
 void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,
-                    double spread_tol, double bound_tol, int* flag, hipStream_t st) {
-  k_gate<<<(nitems + 63) / 64, 64, 0, st>>>(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, flag);
+                    double spread_tol, double bound_tol, const FracGate& ga, const FracGate& gb, int* flag,
+                    hipStream_t st) {
+  k_gate<<<(nitems + 63) / 64, 64, 0, st>>>(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, ga, gb, flag);
+}
+
+FracGate hh_net_fraction_gate(const hh_net* net, const int* counts) {
+  FracGate q;
+  if (!net) return q;
+  q.counts = counts;
+  q.inv_nv = 1.0 / (double(net->n) * net->n * net->n);
+  for (int c = 0; c < kFrac; ++c) {
+    q.mu[c] = net->fmu[c];
+    q.sc[c] = net->fsc[c];
+  }
+  q.zmax = net->fzmax;
+  return q;
 }
 
 int hh_net_input_size(const hh_net* net) { return net ? net->n : 0; }
@@ -442,6 +457,15 @@ int hh_net_set_fraction_scaling(hh_ctx* ctx, hh_net* net, const double mean[8], 
       net->fsc[i] = scale[i];
     }
     upload_fraction_scaling(ctx, net);
+    return HH_OK;
+  });
+}
+
+int hh_net_set_fraction_gate(hh_ctx* ctx, hh_net* net, double z_max) {
+  return guarded(ctx, [&]() -> int {
+    if (!net) fail(ctx, HH_EINVAL, "null network");
+    if (!std::isfinite(z_max) || z_max < 0.0) fail(ctx, HH_EINVAL, "z_max must be finite and >= 0");
+    net->fzmax = z_max;
     return HH_OK;
   });
 }

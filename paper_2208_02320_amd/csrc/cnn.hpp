@@ -19,6 +19,17 @@ void hh_launch_counts(const unsigned char* labels, int nitems, int box, int o, i
 // components, device).
 void hh_launch_bounds(const int* counts, int nitems, int n, int nphase, const double* Cp21, const double* Sp21,
                       double* cv21, double* cr21, hipStream_t st);
+// Input-space test of the gate for one network: label counts of its input
+// windows ([nitems][8], device; null switches the test off), 1 / window
+// voxels, the fraction features' mean and scale, and the limit z_max.
+struct FracGate {
+  const int* counts = nullptr;
+  double inv_nv = 0.0;
+  double mu[8] = {}, sc[8] = {};
+  double zmax = 0.0;
+};
+FracGate hh_net_fraction_gate(const hh_net* net, const int* counts);
 void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,
-                    double spread_tol, double bound_tol, int* flag, hipStream_t st);
+                    double spread_tol, double bound_tol, const FracGate& ga, const FracGate& gb, int* flag,
+                    hipStream_t st);
 int hh_net_input_size(const hh_net* net);

@@ -24,6 +24,7 @@
 #include <string>
 #include <vector>
 
+#include "cnn.hpp"
 #include "intdiv.hpp"
 
 #pragma once
@@ -963,7 +964,7 @@ __device__ bool chol_pd(double A[6][6]) {
 
 __global__ void k_gate(const double* __restrict__ c21a, const double* __restrict__ c21b,
                        const double* __restrict__ cv21, const double* __restrict__ cr21, int nitems, double spread_tol,
-                       double bound_tol, int* __restrict__ flag) {
+                       double bound_tol, FracGate ga, FracGate gb, int* __restrict__ flag) {
   const int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= nitems) return;
   const double s[6] = {1.0, 1.0, 1.0, 1.4142135623730951, 1.4142135623730951, 1.4142135623730951};
@@ -994,6 +995,17 @@ __global__ void k_gate(const double* __restrict__ c21a, const double* __restrict
     for (int j = 0; j < 6; ++j) B[i][j] = C[i][j] - CR[i][j] + (i == j ? shift : 0.0);
   if (!chol_pd(B)) bad = 1;
   if (c21b && dif > spread_tol * spread_tol * nrm) bad = 1;
+  // phase fractions of each network's input window against its training range
+  auto outside = [&](const FracGate& q) {
+    if (!q.counts || !(q.zmax > 0.0)) return false;
+    bool out = false;
+    for (int c = 0; c < 8; ++c) {
+      const double d = fabs(double(q.counts[(long long)it * 8 + c]) * q.inv_nv - q.mu[c]);
+      out = out || (q.sc[c] > 0.0 ? d * q.sc[c] > q.zmax : d > 0.5 * q.inv_nv);
+    }
+    return out;
+  };
+  if (outside(ga) || outside(gb)) bad = 1;
   flag[it] = bad;
 }
 

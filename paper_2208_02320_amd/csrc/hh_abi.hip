@@ -959,7 +959,9 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   HIPCHK(hipMemcpyAsync(d_sp, sp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
   prof.run(HH_K_OTHER, [&] {
     hh_launch_bounds(d_counts, nitems, n_sub, nphase, d_cp, d_sp, cv21, cr21, st);
-    hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, d_flag, st);
+    const FracGate ga = hh_net_fraction_gate(net_a, in_a == n_sub ? d_counts : d_counts_box);
+    const FracGate gb = hh_net_fraction_gate(net_b, in_b == n_sub ? d_counts : d_counts_box);
+    hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, ga, gb, d_flag, st);
   });
   HIPCHK(hipGetLastError());
   std::vector<int> flag(nitems);

@@ -93,9 +93,9 @@ struct XCfg {
   static constexpr int LDS = (N * L + N2 * P + N) * CB;
   // waves per SIMD that the LDS budget admits (160 KB per CU); in FP32 with
   // register DFTs of at most 16 points the compiler is asked to fit them (at
-  // most 4, 128 registers), so that registers do not cut that occupancy
+  // most 6, 80 registers), so that registers do not cut that occupancy
   static constexpr int OCC = clampi((163840 / LDS * (THREADS / 64) + 3) / 4, 1, 8);
-  static constexpr int WAVES_HINT = (CB == 8 && N1 <= 16 && N2 <= 16) ? (OCC < 4 ? OCC : 4) : 1;
+  static constexpr int WAVES_HINT = (CB == 8 && N1 <= 16 && N2 <= 16) ? (OCC < 6 ? OCC : 6) : 1;
 };
 
 // ---------------------------------------------------------------------------

@@ -31,7 +31,7 @@ SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_la
            "hh_homogenize_noalloc", "hh_homogenize_aniso", "hh_homogenize_batch", "hh_hierarchical", "hh_hierarchical_levels",
            "hh_gather_subimages",
            "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_load", "hh_net_info", "hh_net_get_params",
-           "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling",
+           "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling", "hh_net_set_fraction_gate",
            "hh_net_get_fraction_scaling", "hh_net_forward", "hh_set_surrogate", "hh_plan_cache",
            "hh_net_gradient", "hh_net_train_step", "hh_net_predict", "hh_hierarchical_surrogate",
            "hh_richardson", "hh_moduli", "hh_mean_moduli")
@@ -82,6 +82,12 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("HIP library %s is not built; run python -m paper_2208_02320_amd.build" % path)
+    # torch first: its HIP runtime is then the one the library binds to (the
+    # contexts run on torch's streams), never a second copy next to it
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ct.CDLL(path)
     P, I, D, LL = ct.c_void_p, ct.c_int, ct.c_double, ct.c_longlong
     DP = ct.POINTER(ct.c_double)
@@ -124,6 +130,7 @@ def load_library(path=LIB_PATH):
     lib.hh_net_set_scaling.argtypes = [P, P, DP, DP]
     lib.hh_net_get_scaling.argtypes = [P, DP, DP]
     lib.hh_net_set_fraction_scaling.argtypes = [P, P, DP, DP]
+    lib.hh_net_set_fraction_gate.argtypes = [P, P, D]
     lib.hh_net_get_fraction_scaling.argtypes = [P, DP, DP]
     lib.hh_net_forward.argtypes = [P, P, P, I, I, I, I, FP]
     lib.hh_net_gradient.argtypes = [P, P, P, I, I, I, I, FP, FP, FP]
@@ -512,6 +519,10 @@ class Net:
         m = np.ascontiguousarray(np.asarray(mean, dtype=np.float64).reshape(8))
         s = np.ascontiguousarray(np.asarray(scale, dtype=np.float64).reshape(8))
         self.ctx._check(self._lib.hh_net_set_fraction_scaling(self.ctx._h, self._h, _dptr(m), _dptr(s)))
+
+    def set_fraction_gate(self, z_max):
+        """Limit of the gate's phase-fraction test (feature scales; 0: off)."""
+        self.ctx._check(self._lib.hh_net_set_fraction_gate(self.ctx._h, self._h, float(z_max)))
 
     def get_fraction_scaling(self):
         m, s = np.zeros(8), np.zeros(8)

@@ -243,6 +243,38 @@ def test_gate_and_fallback_match_oracle(ctx):
     net.close()
 
 
+def test_fraction_gate_matches_oracle(ctx):
+    """Input-space test: items whose core phase fractions lie more than
+    z_max feature scales from the network's training mean go to the FFT
+    solver, the same items as the oracle's test picks; z_max = 0 accepts
+    all (the prediction sits inside every item's bracket)."""
+    lab = synth.four_phase(64, seed=4)
+    n, pad = 16, 4
+    CV, CR = sg.core_bounds(lab, 0, 64, FOUR)
+    c = hier.to21(0.5 * (CV + CR))
+    net = constant_net(ctx, 4, n, c)
+    mu = np.array([0.55, 0.15, 0.10, 0.20, 0, 0, 0, 0])
+    sc = np.array([20.0, 60.0, 60.0, 30.0, 0, 0, 0, 0])
+    net.set_fraction_scaling(mu, sc)
+    origins = hier.partition(lab, n)
+    z = 1.5
+    want = np.array([sg.fractions_outside(hier.padded_box(lab, o, n, 0), mu, sc, z) for o in origins])
+    net.set_fraction_gate(z)
+    C, Cs, fb, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=1.0, tol=1e-6)
+    print("fraction gate: %d of %d items to the FFT solver (oracle %d)" % (fb.sum(), len(fb), want.sum()))
+    assert 0 < want.sum() < len(want)
+    assert np.array_equal(fb, want)
+    assert np.array_equal(Cs[~fb], np.broadcast_to(c, Cs[~fb].shape))
+    _, Cs_fft, _ = ctx.hierarchical(lab, FOUR, n, pad, tol=1e-6)
+    assert np.abs(Cs[fb] - Cs_fft[fb]).max() < 1e-5 * np.abs(Cs_fft).max()
+    net.set_fraction_gate(0.0)
+    _, _, fb0, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=1.0, tol=1e-6)
+    assert not fb0.any()
+    with pytest.raises(RuntimeError):
+        net.set_fraction_gate(-1.0)
+    net.close()
+
+
 def test_spread_between_networks_sends_all_to_fft(ctx):
     lab = synth.four_phase(32, seed=6)
     n, pad = 16, 2

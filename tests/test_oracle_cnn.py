@@ -112,3 +112,26 @@ def test_gate_spread_between_networks():
     b = a.copy()
     b[15] += 0.06 * np.linalg.norm(sg.mandel(0.5 * (CV + CR))) / 2.0
     assert sg.gate(a, b, CV, CR, 0.05, 0.0)
+
+
+def test_gate_fraction_range():
+    """The input-space test on a 4^3 window with 16 voxels of label 0 and
+    48 of label 1 (fractions 1/4 and 3/4), against means 0.2 and 0.8 with
+    scale 10: both features are 0.5 from the mean."""
+    from oracle import surrogate as sg
+    w = np.ones((4, 4, 4), np.uint8)
+    w[:1] = 0
+    mu = np.array([0.2, 0.8, 0, 0, 0, 0, 0, 0])
+    sc = np.array([10.0, 10.0, 0, 0, 0, 0, 0, 0])
+    assert sg.fractions_outside(w, mu, sc, 0.4)
+    assert not sg.fractions_outside(w, mu, sc, 0.6)
+    assert not sg.fractions_outside(w, mu, sc, 0.0)  # test off
+    # a label that never varied in training (scale 0) must keep its mean:
+    # one voxel of label 2 fails at any positive limit (it replaces a voxel
+    # of label 0, whose feature moves to 0.34)
+    w[0, 0, 0] = 2
+    assert sg.fractions_outside(w, mu, sc, 100.0)
+    assert not sg.fractions_outside(w, mu, sc, 0.0)
+    mu2 = mu.copy()
+    mu2[2] = 1.0 / 64
+    assert not sg.fractions_outside(w, mu2, sc, 0.6)
