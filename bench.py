@@ -182,6 +182,10 @@ def bench_hier(args):
         print("bench: three levels (32 pad 8, 2 pad 1): K %.4f G %.4f (two levels: K %.4f G %.4f) in %.3f s" %
               (K3, G3, K2, G2, dt3), file=sys.stderr, flush=True)
         three = {"levels": [[32, 8], [2, 1]], "K_G": [K3, G3], "seconds": dt3, "two_level_K_G": [K2, G2]}
+    rates = {n: box_pass_rates(ctx, dev, phases, n, 8) for n in ns}
+    for n in ns:
+        print("bench: hier n=%d pass rates with every launch full (TB/s): %s" %
+              (n, ", ".join("%s %.2f" % kv for kv in rates[n]["TBps"].items())), file=sys.stderr, flush=True)
     r = out[64] if 64 in out else out[ns[0]]
     line = {
         "metric": "subimages/s of the batched FFT solve in the two-level scheme",
@@ -195,6 +199,7 @@ def bench_hier(args):
                       "voxel_iters_per_s": out[n]["voxel_iters"] / out[n]["seconds"],
                       "K_G": hh.moduli(out[n]["C"])} for n in ns},
         "richardson": {"K_inf": K, "G_inf": G},
+        "pass_rates": rates,
         "error_vs_oracle": (sampled_error_vs_stored_oracle("four_phase_512_n64_p8_items.json",
                                                            lambda i: _full36(out[64]["Cs"][i]))
                             if N == 512 and 64 in out else None),
@@ -202,6 +207,33 @@ def bench_hier(args):
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+PASS_BYTES = {"zinv": 120, "yinv": 96, "x": 96, "yfwd": 96, "zfwd": 96}  # per frequency and system-iteration
+
+
+def box_pass_rates(ctx, img, phases, n, pad, iters=10):
+    """HBM rate of each pass on the padded boxes of the two-level scheme with
+    every launch full: the first boxes of the image (about 72 M voxels), their
+    core as the averaging region, a tolerance out of reach and a fixed number
+    of iterations, the second of two calls (the first tunes).  Algorithmic
+    bytes of the system-iterations run over the summed launch times of each
+    pass class (HIP events on the library's stream)."""
+    b = n + 2 * pad
+    pack = ctx.gather_subimages(img, n, pad)
+    cnt = min(pack.shape[0], max(1, int(72e6 // b ** 3)))
+    pack = pack[:cnt].contiguous().reshape(-1)
+    core = [(pad, pad, pad, pad + n, pad + n, pad + n)] * cnt
+    for _ in range(2):
+        _, _, _, it, rep = ctx.homogenize_batch([(b, b, b)] * cnt, [phases] * cnt, regions=core, labels_pack=pack,
+                                                tol=1e-14, profile=1, max_iter=iters, check=False)
+    nf = b * b * (b // 2 + 1)
+    sys_iters = float(np.sum(it))
+    tb = {}
+    for k, B in PASS_BYTES.items():
+        byt = sys_iters * (nf * B + (b ** 3 if k == "x" else 0))
+        tb[k] = round(byt / (rep["kernel_ms"][k] * 1e-3) / 1e12, 3)
+    return {"boxes": cnt, "box": b, "system_iterations": sys_iters, "TBps": tb}
 
 
 def _full36(c21):
