@@ -675,27 +675,27 @@ def bench_surrogate_ood(args):
                             bound_tol=args.bound_tol, keep_plain=True)
         Cp = leg.pop("_C_plain")
         leg["image"] = name
-        # the same gate without its phase-fraction test
+        # the same gate without its input-space tests (phase fractions, interface density)
         for net in nets:
             net.set_fraction_gate(0.0)
         C0, _, fb0, _ = ctx.hierarchical_surrogate(img, phases, 64, 8, nets[0], nets[1], spread_tol=args.spread_tol,
                                                    bound_tol=args.bound_tol, tol=1e-6)
-        leg["without_fraction_test"] = {
+        leg["without_input_tests"] = {
             "fallback_fraction": float(fb0.mean()),
             "rel_error_vs_plain": float(surrogate.rel_error21(hh.upper21(C0), hh.upper21(Cp))[0])}
         rows.append(leg)
         print("bench: surrogate on %s: fallback %.3f, C* error %.2e, %.0f subimages/s, %.0fx the plain hierarchy; "
-              "without the fraction test: fallback %.3f, C* error %.2e" %
+              "without the input-space tests: fallback %.3f, C* error %.2e" %
               (name, leg["fallback_fraction"], leg["rel_error_vs_plain"], leg["subimages_per_s"],
-               leg["speedup_vs_plain"], leg["without_fraction_test"]["fallback_fraction"],
-               leg["without_fraction_test"]["rel_error_vs_plain"]), file=sys.stderr, flush=True)
+               leg["speedup_vs_plain"], leg["without_input_tests"]["fallback_fraction"],
+               leg["without_input_tests"]["rel_error_vs_plain"]), file=sys.stderr, flush=True)
         del img
         torch.cuda.empty_cache()
     line = {"metric": "C* error of the surrogate pipeline against the plain hierarchy, worst over the images",
             "value": max(r["rel_error_vs_plain"] for r in rows), "unit": "relative", "n_gpus": 1,
             "higher_is_better": False, "dtype": "bf16 network / f32 solver", "data": "synthetic",
             "config": {"workload": "surrogate pair on %d^3 four-phase images off its training recipe, n = 64, pad 8, "
-                                   "spread_tol %g, bound_tol %g, fraction z_max %g" %
+                                   "spread_tol %g, bound_tol %g, input-test z_max %g" %
                                    (N, args.spread_tol, args.bound_tol, args.frac_z)},
             "images": rows}
     print(json.dumps(line), flush=True)
@@ -764,7 +764,8 @@ def main():
     ap.add_argument("--weights-dir", default=None)
     ap.add_argument("--spread-tol", type=float, default=0.02)
     ap.add_argument("--bound-tol", type=float, default=0.0)
-    ap.add_argument("--frac-z", type=float, default=5.0, help="limit of the gate's phase-fraction test")
+    ap.add_argument("--frac-z", type=float, default=5.0,
+                    help="limit of the gate's input-space tests (phase fractions, interface density)")
     ap.add_argument("--hier-size", type=int, default=512)
     ap.add_argument("--hier-ns", default="32,64,128", help="subimage sizes of the hier workload")
     ap.add_argument("--no-levels", action="store_true", help="hier workload without the three-level run")

@@ -303,7 +303,8 @@ int hh_net_info(const hh_net *net, int *nphase, int *n);
 /* A network from the file the training pipeline writes (numpy .npz: arrays
  * params <f4 [hh_net_num_params], mean and scale <f8 [21], fmu and fsc <f8
  * [8], n and nphase <i8 scalars; other members are ignored), read on the
- * host with zlib.  *net is created on ctx and owned by the caller
+ * host with zlib; optional <f8 scalars imu and isc set the interface
+ * statistics (hh_net_set_interface_stats).  *net is created on ctx and owned by the caller
  * (hh_net_destroy).  HH_EINVAL for a missing or malformed file, with the
  * reason in hh_last_error(ctx). */
 int hh_net_load(hh_ctx *ctx, const char *path, hh_net **net);
@@ -326,6 +327,16 @@ int hh_net_get_fraction_scaling(const hh_net *net, double mean[8], double scale[
  * mean_c by at least one voxel.  Default 5; z_max = 0 switches the test
  * off.  HH_EINVAL for a negative or non-finite z_max. */
 int hh_net_set_fraction_gate(hh_ctx *ctx, hh_net *net, double z_max);
+/* Texture test of the same gate: the interface density d of a window is
+ * the fraction of its face-adjacent voxel pairs (along x, y and z, inside
+ * the window: 3 n^2 (n - 1) pairs) whose labels differ.  An item goes to
+ * the FFT solver when |d - mean| * scale > z_max (the limit above) for this
+ * network's input window; mean and scale are the training windows' mean
+ * and inverse standard deviation of d.  scale = 0 (the default) switches
+ * the test off.  HH_EINVAL unless 0 <= mean <= 1 and scale is finite and
+ * >= 0. */
+int hh_net_set_interface_stats(hh_ctx *ctx, hh_net *net, double mean, double scale);
+int hh_net_get_interface_stats(const hh_net *net, double *mean, double *scale);
 /* Normalized outputs y (host, batch x 21). */
 int hh_net_forward(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_on_device, int batch, int box,
                    int offset, float *out);
@@ -348,9 +359,10 @@ int hh_net_predict(hh_ctx *ctx, hh_net *net, const uint8_t *labels, int labels_o
  * item to the FFT solver (the hh_hierarchical path) when the mean prediction
  * is not positive definite, leaves the Voigt-Reuss bracket of the core's
  * phase fractions by more than bound_tol (relative, Mandel norm), when a
- * network's input window has phase fractions outside the range the network
- * was trained on (hh_net_set_fraction_gate), or - with two networks - when
- * the two predictions differ by more than spread_tol (relative).  net_b may be NULL.  fallback: (N/n)^3 flags (may be NULL);
+ * network's input window has phase fractions or an interface density outside
+ * the range the network was trained on (hh_net_set_fraction_gate,
+ * hh_net_set_interface_stats), or - with two networks - when the two
+ * predictions differ by more than spread_tol (relative).  net_b may be NULL.  fallback: (N/n)^3 flags (may be NULL);
  * C_sub as in hh_hierarchical.  report.items counts subimages,
  * report.voxel_iters the fallback and level-2 solves.
  */

@@ -19,7 +19,11 @@ its definition, with eigenvalues (the kernel uses Cholesky pivots):
   network's input window and (mu_c, s_c) the mean and inverse standard
   deviation of that fraction over the training windows, |f_c - mu_c| s_c
   <= z_max for every label with s_c > 0, and f_c = mu_c (to within half a
-  voxel) for a label with s_c = 0; z_max = 0 skips the test.
+  voxel) for a label with s_c = 0; z_max = 0 skips the test;
+* texture test, per network with interface statistics (mean m, inverse
+  standard deviation s > 0 of the training windows' interface density):
+  |d - m| s <= z_max, where d is the fraction of the window's face-adjacent
+  voxel pairs (along each axis, inside the window) whose labels differ.
 
 Any failed condition flags the item for the FFT solver.
 """
@@ -72,6 +76,30 @@ def fractions_outside(window_labels, mu, sc, z_max):
         if (d * sc[c] > z_max) if sc[c] > 0.0 else (d > 0.5 / nv):
             return True
     return False
+
+
+def interface_density(window_labels):
+    """Fraction of the face-adjacent voxel pairs of a window whose labels
+    differ, counted pair by pair over the three axes."""
+    w = np.asarray(window_labels)
+    nz, ny, nx = w.shape
+    diff = pairs = 0
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                for dz, dy, dx in ((0, 0, 1), (0, 1, 0), (1, 0, 0)):
+                    z2, y2, x2 = z + dz, y + dy, x + dx
+                    if z2 < nz and y2 < ny and x2 < nx:
+                        pairs += 1
+                        diff += int(w[z, y, x] != w[z2, y2, x2])
+    return diff / pairs
+
+
+def interface_outside(window_labels, mean, scale, z_max):
+    """True when the texture test fails for one network's window."""
+    if not (z_max > 0.0 and scale > 0.0):
+        return False
+    return abs(interface_density(window_labels) - mean) * scale > z_max
 
 
 def gate_margin(c21a, c21b, CV, CR, bound_tol):

@@ -38,6 +38,7 @@ struct hh_net {
   double *d_mean = nullptr, *d_scale = nullptr;
   double fmu[kFrac], fsc[kFrac];  // standardization of the phase-fraction features
   double fzmax = 5.0;              // the gate's limit on |feature| (0: no test)
+  double imu = 0.0, isc = 0.0;     // interface density of the training windows (isc 0: no test)
   float *d_fmu = nullptr, *d_fsc = nullptr;
   long long step = 0;
   int cap = 0;  // batch capacity of the activation buffers
@@ -295,7 +296,7 @@ void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, 
   k_gate<<<(nitems + 63) / 64, 64, 0, st>>>(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, ga, gb, flag);
 }
 
-FracGate hh_net_fraction_gate(const hh_net* net, const int* counts) {
+FracGate hh_net_fraction_gate(const hh_net* net, const int* counts, const unsigned* iface) {
   FracGate q;
   if (!net) return q;
   q.counts = counts;
@@ -305,7 +306,21 @@ FracGate hh_net_fraction_gate(const hh_net* net, const int* counts) {
     q.sc[c] = net->fsc[c];
   }
   q.zmax = net->fzmax;
+  if (net->isc > 0.0 && iface) {
+    q.iface = iface;
+    q.inv_pairs = 1.0 / (3.0 * double(net->n) * net->n * (net->n - 1));
+    q.imu = net->imu;
+    q.isc = net->isc;
+  }
   return q;
+}
+
+bool hh_net_has_interface_stats(const hh_net* net) { return net && net->isc > 0.0 && net->n > 1; }
+
+void hh_launch_interfaces(const unsigned char* labels, int nitems, int box, int o, int n, unsigned* counts,
+                          hipStream_t st) {
+  k_zero_int<<<(nitems + 255) / 256, 256, 0, st>>>(reinterpret_cast<int*>(counts), nitems);
+  launch_count_interfaces(labels, (long long)box * box * box, box, o, n, 0, nitems, counts, st);
 }
 
 int hh_net_input_size(const hh_net* net) { return net ? net->n : 0; }
@@ -468,6 +483,24 @@ int hh_net_set_fraction_gate(hh_ctx* ctx, hh_net* net, double z_max) {
     net->fzmax = z_max;
     return HH_OK;
   });
+}
+
+int hh_net_set_interface_stats(hh_ctx* ctx, hh_net* net, double mean, double scale) {
+  return guarded(ctx, [&]() -> int {
+    if (!net) fail(ctx, HH_EINVAL, "null network");
+    if (!std::isfinite(mean) || !std::isfinite(scale) || mean < 0.0 || mean > 1.0 || scale < 0.0)
+      fail(ctx, HH_EINVAL, "interface statistics: mean in [0, 1] and a finite scale >= 0");
+    net->imu = mean;
+    net->isc = scale;
+    return HH_OK;
+  });
+}
+
+int hh_net_get_interface_stats(const hh_net* net, double* mean, double* scale) {
+  if (!net || !mean || !scale) return HH_EINVAL;
+  *mean = net->imu;
+  *scale = net->isc;
+  return HH_OK;
 }
 
 int hh_net_get_fraction_scaling(const hh_net* net, double mean[8], double scale[8]) {

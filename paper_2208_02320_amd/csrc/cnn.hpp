@@ -19,16 +19,27 @@ void hh_launch_counts(const unsigned char* labels, int nitems, int box, int o, i
 // components, device).
 void hh_launch_bounds(const int* counts, int nitems, int n, int nphase, const double* Cp21, const double* Sp21,
                       double* cv21, double* cr21, hipStream_t st);
-// Input-space test of the gate for one network: label counts of its input
-// windows ([nitems][8], device; null switches the test off), 1 / window
-// voxels, the fraction features' mean and scale, and the limit z_max.
+// Input-space tests of the gate for one network: label counts of its input
+// windows ([nitems][8], device; null switches the tests off), 1 / window
+// voxels, the fraction features' mean and scale, the limit z_max, and the
+// windows' interface counts (device, may be null) with 1 / pairs per window
+// and the training mean and inverse standard deviation of the density.
 struct FracGate {
   const int* counts = nullptr;
   double inv_nv = 0.0;
   double mu[8] = {}, sc[8] = {};
   double zmax = 0.0;
+  const unsigned* iface = nullptr;
+  double inv_pairs = 0.0, imu = 0.0, isc = 0.0;
 };
-FracGate hh_net_fraction_gate(const hh_net* net, const int* counts);
+FracGate hh_net_fraction_gate(const hh_net* net, const int* counts, const unsigned* iface);
+// Whether the network has interface-density statistics (the gate then needs
+// the windows' interface counts).
+bool hh_net_has_interface_stats(const hh_net* net);
+// counts[i] = face-adjacent voxel pairs with different labels inside the n^3
+// window at offset (o, o, o) of box i (box^3 labels, device); zeroes first.
+void hh_launch_interfaces(const unsigned char* labels, int nitems, int box, int o, int n, unsigned* counts,
+                          hipStream_t st);
 void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,
                     double spread_tol, double bound_tol, const FracGate& ga, const FracGate& gb, int* flag,
                     hipStream_t st);

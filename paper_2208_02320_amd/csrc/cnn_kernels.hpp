@@ -173,6 +173,72 @@ inline void launch_count_labels(const unsigned char* labels, long long stride, i
   }
 }
 
+// Interface counts of each window: cnt[b] += number of face-adjacent voxel
+// pairs inside the n^3 window (along x, y and z) whose labels differ.  Same
+// grid and W-byte chunks as k_count_labels; a chunk is compared byte by
+// byte with itself shifted by one voxel in x (and the first voxel of the
+// next chunk), with the chunk one row up in y and one plane up in z.  Wave
+// sums, then one atomic per block.
+template <int W>
+__global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, float inv_n, int cw, float inv_cw,
+                                                          int rows, int item0, unsigned* __restrict__ cnt) {
+  using CT = typename Chunk<W>::type;
+  const int b = item0 + blockIdx.y;
+  const int r0 = blockIdx.x * rows, nr = min(rows, n * n - r0);
+  const unsigned char* base = window_base(w, b);
+  const int tasks = nr * cw;
+  const long long plane = (long long)w.box * w.box;
+  unsigned c = 0u;
+  for (int t = threadIdx.x; t < tasks; t += 256) {
+    const int rl = fdiv(t, cw, inv_cw), k = t - rl * cw;
+    const int r = r0 + rl, z = fdiv(r, n, inv_n), y = r - z * n;
+    const unsigned char* p = base + (z * w.box + y) * w.box + k * W;
+    const CT v = *reinterpret_cast<const CT*>(p);
+#pragma unroll
+    for (int j = 0; j + 1 < W; ++j) c += chunk_byte(v, j) != chunk_byte(v, j + 1);
+    if (k + 1 < cw) c += chunk_byte(v, W - 1) != unsigned(p[W]);
+    if (y + 1 < n) {
+      const CT u = *reinterpret_cast<const CT*>(p + w.box);
+#pragma unroll
+      for (int j = 0; j < W; ++j) c += chunk_byte(v, j) != chunk_byte(u, j);
+    }
+    if (z + 1 < n) {
+      const CT u = *reinterpret_cast<const CT*>(p + plane);
+#pragma unroll
+      for (int j = 0; j < W; ++j) c += chunk_byte(v, j) != chunk_byte(u, j);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  __shared__ unsigned s;
+  if (threadIdx.x == 0) s = 0u;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(&s, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && s) atomicAdd(&cnt[b], s);
+}
+
+// cnt[item0 .. item0 + nitems) += interface counts of the n^3 windows at
+// (o, o, o) of the box^3 label boxes; the caller zeroes cnt.
+inline void launch_count_interfaces(const unsigned char* labels, long long stride, int box, int o, int n, int item0,
+                                    int nitems, unsigned* cnt, hipStream_t st) {
+  const LabelWindow lw{labels, stride, box, o};
+  const unsigned char* first = labels + ((long long)o * box + o) * box + o;
+  const int W = chunk_width({stride, (long long)box, (long long)n}, first, first);
+  const int cw = n / W, rows = count_rows_per_block(n);
+  const unsigned gx = unsigned((n * n + rows - 1) / rows);
+  const float inv_n = 1.0f / float(n), inv_cw = 1.0f / float(cw);
+  for (int i0 = 0; i0 < nitems; i0 += 65535) {
+    const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
+    const dim3 g(gx, unsigned(ni));
+    if (W == 8)
+      k_count_interfaces<8><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
+    else if (W == 4)
+      k_count_interfaces<4><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
+    else
+      k_count_interfaces<1><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
+  }
+}
+
 __global__ void k_zero_int(int* __restrict__ p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1003,6 +1069,10 @@ __global__ void k_gate(const double* __restrict__ c21a, const double* __restrict
       const double d = fabs(double(q.counts[(long long)it * 8 + c]) * q.inv_nv - q.mu[c]);
       out = out || (q.sc[c] > 0.0 ? d * q.sc[c] > q.zmax : d > 0.5 * q.inv_nv);
     }
+    // interface density of the window (its texture), where the network has
+    // training statistics of it
+    if (q.iface && q.isc > 0.0)
+      out = out || fabs(double(q.iface[it]) * q.inv_pairs - q.imu) * q.isc > q.zmax;
     return out;
   };
   if (outside(ga) || outside(gb)) bad = 1;

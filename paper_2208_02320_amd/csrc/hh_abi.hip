@@ -959,8 +959,21 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   HIPCHK(hipMemcpyAsync(d_sp, sp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
   prof.run(HH_K_OTHER, [&] {
     hh_launch_bounds(d_counts, nitems, n_sub, nphase, d_cp, d_sp, cv21, cr21, st);
-    const FracGate ga = hh_net_fraction_gate(net_a, in_a == n_sub ? d_counts : d_counts_box);
-    const FracGate gb = hh_net_fraction_gate(net_b, in_b == n_sub ? d_counts : d_counts_box);
+    // interface counts of the windows a network with texture statistics reads
+    unsigned* d_if_core = nullptr;
+    unsigned* d_if_box = nullptr;
+    for (hh_net* net : {net_a, net_b}) {
+      if (!hh_net_has_interface_stats(net)) continue;
+      const bool core = hh_net_input_size(net) == n_sub;
+      unsigned*& d = core ? d_if_core : d_if_box;
+      if (d) continue;
+      d = static_cast<unsigned*>(ws(ctx, core ? "sur_iface" : "sur_iface_box", sizeof(unsigned) * size_t(nitems)));
+      hh_launch_interfaces(d_pack, nitems, b, core ? pad : 0, core ? n_sub : b, d, st);
+    }
+    const FracGate ga = hh_net_fraction_gate(net_a, in_a == n_sub ? d_counts : d_counts_box,
+                                             in_a == n_sub ? d_if_core : d_if_box);
+    const FracGate gb = hh_net_fraction_gate(net_b, in_b == n_sub ? d_counts : d_counts_box,
+                                             in_b == n_sub ? d_if_core : d_if_box);
     hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, ga, gb, d_flag, st);
   });
   HIPCHK(hipGetLastError());

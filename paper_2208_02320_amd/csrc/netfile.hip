@@ -263,6 +263,23 @@ extern "C" int hh_net_load(hh_ctx* ctx, const char* path, hh_net** out) {
     hh_net_destroy(net);
     return rc;
   }
+  // optional: interface-density statistics of the training windows
+  auto im = members.find("imu.npy"), is = members.find("isc.npy");
+  if (im != members.end() && is != members.end()) {
+    if (!parse_npy(im->second, arr["imu"], err) || !parse_npy(is->second, arr["isc"], err)) {
+      ctx->err = "hh_net_load: arrays imu/isc unreadable " + err;
+      hh_net_destroy(net);
+      return HH_EINVAL;
+    }
+    if (!want("imu", "<f8", 1) || !want("isc", "<f8", 1)) {
+      hh_net_destroy(net);
+      return HH_EINVAL;
+    }
+    if ((rc = hh_net_set_interface_stats(ctx, net, f64("imu")[0], f64("isc")[0])) != HH_OK) {
+      hh_net_destroy(net);
+      return rc;
+    }
+  }
   *out = net;
   return HH_OK;
 }

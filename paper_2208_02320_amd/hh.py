@@ -32,6 +32,7 @@ SYMBOLS = ("hh_default_opts", "hh_create", "hh_set_stream", "hh_destroy", "hh_la
            "hh_gather_subimages",
            "hh_net_create", "hh_net_destroy", "hh_net_num_params", "hh_net_load", "hh_net_info", "hh_net_get_params",
            "hh_net_set_params", "hh_net_set_scaling", "hh_net_get_scaling", "hh_net_set_fraction_scaling", "hh_net_set_fraction_gate",
+           "hh_net_set_interface_stats", "hh_net_get_interface_stats",
            "hh_net_get_fraction_scaling", "hh_net_forward", "hh_set_surrogate", "hh_plan_cache",
            "hh_net_gradient", "hh_net_train_step", "hh_net_predict", "hh_hierarchical_surrogate",
            "hh_richardson", "hh_moduli", "hh_mean_moduli")
@@ -131,6 +132,8 @@ def load_library(path=LIB_PATH):
     lib.hh_net_get_scaling.argtypes = [P, DP, DP]
     lib.hh_net_set_fraction_scaling.argtypes = [P, P, DP, DP]
     lib.hh_net_set_fraction_gate.argtypes = [P, P, D]
+    lib.hh_net_set_interface_stats.argtypes = [P, P, D, D]
+    lib.hh_net_get_interface_stats.argtypes = [P, DP, DP]
     lib.hh_net_get_fraction_scaling.argtypes = [P, DP, DP]
     lib.hh_net_forward.argtypes = [P, P, P, I, I, I, I, FP]
     lib.hh_net_gradient.argtypes = [P, P, P, I, I, I, I, FP, FP, FP]
@@ -523,6 +526,18 @@ class Net:
     def set_fraction_gate(self, z_max):
         """Limit of the gate's phase-fraction test (feature scales; 0: off)."""
         self.ctx._check(self._lib.hh_net_set_fraction_gate(self.ctx._h, self._h, float(z_max)))
+
+    def set_interface_stats(self, mean, scale):
+        """Training mean and inverse standard deviation of the windows'
+        interface density (the gate's texture test; scale 0: off)."""
+        self.ctx._check(self._lib.hh_net_set_interface_stats(self.ctx._h, self._h, float(mean), float(scale)))
+
+    def get_interface_stats(self):
+        m, s = ct.c_double(), ct.c_double()
+        rc = self._lib.hh_net_get_interface_stats(self._h, ct.byref(m), ct.byref(s))
+        if rc != HH_OK:
+            raise HHError(rc, "hh_net_get_interface_stats failed")
+        return m.value, s.value
 
     def get_fraction_scaling(self):
         m, s = np.zeros(8), np.zeros(8)

@@ -191,6 +191,29 @@ def fraction_stats(data, edge=None, nch=8):
     return mu, np.where(sd > 1e-6, 1.0 / np.maximum(sd, 1e-6), 0.0)
 
 
+def interface_densities(boxes, offset, edge, chunk=256):
+    """Interface density of the edge^3 window at (offset, offset, offset) of
+    each box: the fraction of its face-adjacent voxel pairs (inside the
+    window, along x, y and z) whose labels differ (device tensors in, FP64
+    numpy out)."""
+    import torch
+    out = []
+    pairs = 3.0 * edge * edge * (edge - 1)
+    for a in range(0, boxes.shape[0], chunk):
+        w = boxes[a:a + chunk, offset:offset + edge, offset:offset + edge, offset:offset + edge]
+        d = ((w[..., 1:] != w[..., :-1]).sum(dim=(1, 2, 3)) + (w[:, :, 1:, :] != w[:, :, :-1, :]).sum(dim=(1, 2, 3)) +
+             (w[:, 1:] != w[:, :-1]).sum(dim=(1, 2, 3)))
+        out.append(d.to(torch.float64).cpu().numpy() / pairs)
+    return np.concatenate(out)
+
+
+def interface_stats(data, edge):
+    """Mean and inverse standard deviation of the training windows'
+    interface density (the gate's texture test)."""
+    d = interface_densities(data.boxes, data.window(edge), edge)
+    return float(d.mean()), float(1.0 / max(d.std(), 1e-6))
+
+
 def symmetric_scaling(c21, syms=None):
     """Mean and standard deviation per component over the data set and all
     its symmetric images (floor 1e-3 of the largest)."""
@@ -217,6 +240,7 @@ def train(ctx, data, nphase, epochs=20, batch=32, lr=1e-3, lr_final=2e-5, seed=0
     net = hh.Net(ctx, nphase, edge, seed=seed)
     net.set_scaling(mean, scale)
     net.set_fraction_scaling(*fraction_stats(data, edge))
+    net.set_interface_stats(*interface_stats(data, edge))
     dev = "cuda:%d" % ctx.device
     m = data.c21.shape[0]
     steps_per_epoch = max(1, m // batch)
@@ -265,8 +289,44 @@ def predict(net, data, chunk=512):
 def save(net, path, meta=None):
     mean, scale = net.get_scaling()
     fmu, fsc = net.get_fraction_scaling()
-    np.savez_compressed(path, params=net.get_params(), mean=mean, scale=scale, fmu=fmu, fsc=fsc, n=net.n,
-                        nphase=net.nphase, meta=json.dumps(meta or {}))
+    imu, isc = net.get_interface_stats()
+    np.savez_compressed(path, params=net.get_params(), mean=mean, scale=scale, fmu=fmu, fsc=fsc,
+                        imu=np.float64(imu), isc=np.float64(isc), n=net.n, nphase=net.nphase,
+                        meta=json.dumps(meta or {}))
+
+
+def add_gate_stats(ctx, paths, out_dir, log=print):
+    """Interface statistics for networks saved before the texture test
+    existed: the training windows are regenerated from the images named in
+    each file's record (device generator, same seeds and partition) and the
+    file is written again to out_dir with imu and isc added; every other
+    array is kept as it was."""
+    import torch
+    cache = {}
+    for path in paths:
+        with np.load(path, allow_pickle=False) as z:
+            arrays = {k: z[k] for k in z.files}
+        meta = json.loads(str(arrays["meta"]))
+        edge = int(arrays["n"])
+        key = (tuple(meta["images"]), meta["size"], meta["n"], meta["pad"], edge)
+        if key not in cache:
+            d = []
+            for seed in meta["images"]:
+                img = synth.four_phase_device(meta["size"], sigma=2.0, seed=seed, device="cuda:%d" % ctx.device)
+                boxes = ctx.gather_subimages(img, meta["n"], meta["pad"])
+                off = meta["pad"] if edge == meta["n"] else 0
+                d.append(interface_densities(boxes, off, edge))
+                del img, boxes
+                torch.cuda.empty_cache()
+            d = np.concatenate(d)
+            cache[key] = (float(d.mean()), float(1.0 / max(d.std(), 1e-6)), d.size)
+        imu, isc, cnt = cache[key]
+        arrays["imu"], arrays["isc"] = np.float64(imu), np.float64(isc)
+        os.makedirs(out_dir, exist_ok=True)
+        out = os.path.join(out_dir, os.path.basename(path))
+        np.savez_compressed(out, **arrays)
+        if log:
+            log("%s: interface density %.5f +- %.5f over %d training windows -> %s" % (path, imu, 1.0 / isc, cnt, out))
 
 
 def load(ctx, path):
@@ -298,12 +358,17 @@ def main(argv=None):
     ap.add_argument("--seeds", default="1,2", help="one network per seed")
     ap.add_argument("--window", choices=("core", "box"), default="core")
     ap.add_argument("--labels", default=None, help="npz cache of the FFT labels (read if present, else written)")
+    ap.add_argument("--gate-stats", nargs="*", default=None,
+                    help="add interface statistics to these saved networks (written to --out)")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
     ctx = hh.Context(0)
+    if a.gate_stats:
+        add_gate_stats(ctx, a.gate_stats, a.out, log=log)
+        return
     seeds = list(range(10000, 10000 + a.images))
     vseeds = list(range(20000, 20000 + a.val_images))
     cached = None

@@ -275,6 +275,42 @@ def test_fraction_gate_matches_oracle(ctx):
     net.close()
 
 
+def test_interface_gate_matches_oracle(ctx):
+    """Texture test: items whose core interface density lies more than
+    z_max training standard deviations from the training mean go to the FFT
+    solver, the same items as the oracle's test picks (identity fraction
+    scaling: the fraction test never triggers here); a network reading the
+    whole box counts the interfaces of the box."""
+    n = 16
+    for size, pad, whole_box in ((64, 4, False), (48, 8, True)):
+        lab = synth.four_phase(size, seed=4)
+        CV, CR = sg.core_bounds(lab, 0, size, FOUR)
+        c = hier.to21(0.5 * (CV + CR))
+        origins = hier.partition(lab, n)
+        edge, off = (n + 2 * pad, 0) if whole_box else (n, pad)
+        net = constant_net(ctx, 4, edge, c)
+        wins = [hier.padded_box(lab, o, n, pad)[off:off + edge, off:off + edge, off:off + edge] for o in origins]
+        d = np.array([sg.interface_density(w) for w in wins])
+        m, scale, z = float(np.median(d)), 1.0 / max(float(d.std()), 1e-6), 1.0
+        want = np.array([sg.interface_outside(w, m, scale, z) for w in wins])
+        tight = np.abs(np.abs(d - m) * scale - z) < 1e-9
+        net.set_interface_stats(m, scale)
+        assert net.get_interface_stats() == (m, scale)
+        net.set_fraction_gate(z)
+        C, Cs, fb, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=1.0,
+                                                  tol=1e-6)
+        print("window %d: interface gate sends %d of %d (oracle %d)" % (edge, fb.sum(), len(fb), want.sum()))
+        assert 0 < want.sum() < len(want)
+        assert np.array_equal(fb[~tight], want[~tight])
+        net.set_interface_stats(m, 0.0)  # no statistics: no texture test
+        _, _, fb0, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=1.0,
+                                                  tol=1e-6)
+        assert not fb0.any()
+        with pytest.raises(RuntimeError):
+            net.set_interface_stats(1.5, 1.0)
+        net.close()
+
+
 def test_spread_between_networks_sends_all_to_fft(ctx):
     lab = synth.four_phase(32, seed=6)
     n, pad = 16, 2
@@ -408,6 +444,8 @@ def test_network_file_loaded_by_the_library(ctx):
         fm, fs = na.get_fraction_scaling()
         assert np.array_equal(fm, z["fmu"]) and np.array_equal(fs, z["fsc"])
         assert (na.n, na.nphase) == (int(z["n"]), int(z["nphase"]))
+        if "imu" in z.files:
+            assert na.get_interface_stats() == (float(z["imu"]), float(z["isc"]))
     img = synth.four_phase_device(128, sigma=2.0, seed=31, device="cuda:0")
     C1, Cs1, fb1, r1 = ctx.hierarchical_surrogate(img, FOUR, 64, 8, na, nb, spread_tol=0.02, bound_tol=0.0)
     with pytest.raises(hh.HHError):

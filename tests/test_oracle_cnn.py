@@ -135,3 +135,22 @@ def test_gate_fraction_range():
     mu2 = mu.copy()
     mu2[2] = 1.0 / 64
     assert not sg.fractions_outside(w, mu2, sc, 0.6)
+
+
+def test_interface_density_closed_forms():
+    """Interface density on windows whose differing pairs can be counted by
+    hand: none (constant), all (checkerboard), one plane of pairs."""
+    from oracle import surrogate as sg
+    assert sg.interface_density(np.zeros((4, 4, 4), np.uint8)) == 0.0
+    z, y, x = np.indices((3, 3, 3))
+    assert sg.interface_density(((x + y + z) % 2).astype(np.uint8)) == 1.0
+    # 3^3 split at x = 1: the 9 rows each have one differing x pair, of 54 pairs
+    assert sg.interface_density((x >= 1).astype(np.uint8)) == 9 / 54
+    # 4^3 split at z = 2: 16 differing z pairs of 3 * 16 * 3 = 144
+    z4 = np.indices((4, 4, 4))[0]
+    assert sg.interface_density((z4 >= 2).astype(np.uint8)) == 16 / 144
+    w = (x >= 1).astype(np.uint8)
+    assert sg.interface_outside(w, 0.0, 10.0, 1.6)       # |1/6 - 0| * 10 = 1.67
+    assert not sg.interface_outside(w, 0.0, 10.0, 1.7)
+    assert not sg.interface_outside(w, 0.0, 0.0, 1.0)    # no statistics: no test
+    assert not sg.interface_outside(w, 0.0, 10.0, 0.0)   # test off

@@ -95,3 +95,18 @@ def test_float_reciprocal_division_is_exact():
         r = a - q * d
         q = q + (r >= d) - (r < 0)
         assert np.array_equal(q, a // d), d
+
+
+def test_interface_densities_match_oracle():
+    """The training pipeline's interface densities (torch, vectorized) of
+    the core and of the whole box against the oracle's pair-by-pair count."""
+    import torch
+    from oracle import surrogate as sg
+    rng = np.random.default_rng(3)
+    boxes = rng.integers(0, 4, size=(5, 10, 10, 10)).astype(np.uint8)
+    boxes[1] = 2  # constant box
+    t = torch.from_numpy(boxes)
+    for off, edge in ((2, 6), (0, 10)):
+        got = sur.interface_densities(t, off, edge, chunk=2)
+        want = [sg.interface_density(b[off:off + edge, off:off + edge, off:off + edge]) for b in boxes]
+        assert np.array_equal(got, np.array(want))
