@@ -97,14 +97,17 @@ constexpr int kPartX = 13;  // (p, C:p), then region sums of p and of sigma
 // Every FP64 reduction of the solve follows a fixed tree defined on the
 // grid, not on the tile a workgroup happens to hold, so that all tile
 // variants give the same bits:
-//  - a line of the x pass (one spectrum row and component pair) or of the z
-//    pass (one column) is summed in kLineGroups groups, group g taking the
-//    line positions g, g + kLineGroups, ... in increasing order, and the
-//    groups are added in a fixed butterfly;
+//  - a line of the x pass (one spectrum row and component pair) is summed
+//    in kLineGroups groups, group g taking the line positions g,
+//    g + kLineGroups, ... in increasing order, and the groups are added in a
+//    fixed butterfly; a column of the z pass likewise in kColGroups groups
+//    (one wave), added by a butterfly within each row of 16 lanes and then
+//    the four row sums in a fixed order;
 //  - the per-row (x) and per-column (z) sums are stored, summed in chunks of
 //    kFinChunk consecutive ones by one block each (fixed thread strides and
 //    tree), and the chunk sums of a system by one block in a fixed order.
 constexpr int kLineGroups = 16;
+constexpr int kColGroups = 64;
 constexpr int kFinChunk = 4096;
 
 }  // namespace hh

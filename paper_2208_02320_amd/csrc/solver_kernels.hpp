@@ -184,6 +184,23 @@ __device__ __forceinline__ double dpp_pair(double v) {
 // lane's partial.  Addition commutes, so every lane of the group ends with
 // the same bits, and the tree is the same whatever wave or task the group
 // sits in; every lane of the wave must take part.
+// Sum over the 64 lanes of a wave in a fixed tree: the butterfly within
+// each row of 16 lanes, then the four row sums as (r0 + r1) + (r2 + r3);
+// every lane gets the result.
+__device__ __forceinline__ double group_sum(double v);
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+  v = group_sum(v);
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  double r[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(u)), 16 * w));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(u >> 32)), 16 * w));
+    r[w] = __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+  }
+  return (r[0] + r[1]) + (r[2] + r[3]);
+}
+
 __device__ __forceinline__ double group_sum(double v) {
   static_assert(kLineGroups == 16, "butterfly over one row of 16 lanes");
   v += dpp_pair<0xB1>(v);
@@ -409,8 +426,10 @@ __global__ void __launch_bounds__((AxisCfg<N, T, V>::THREADS)) k_zpass(GroupArgs
         for (int i = 0; i < 3; ++i) ar[off + i] = r[i];
       }
     }
-    // column sums over z: staged by (column, position), each column in
-    // kLineGroups groups of positions and a butterfly
+    // column sums over z: staged by (column, position); one wave per
+    // column, lane g summing positions g, g + 64, ... in order, then the
+    // butterfly over each row of 16 lanes and the four row sums in a fixed
+    // order (every wave of every tile variant forms the same tree)
     __syncthreads();
     double* vd = reinterpret_cast<double*>(buf);  // [M][N]
 #pragma unroll
@@ -419,17 +438,18 @@ __global__ void __launch_bounds__((AxisCfg<N, T, V>::THREADS)) k_zpass(GroupArgs
       if (task < ntask) vd[(task % M) * N + task / M] = val[k];
     }
     __syncthreads();
-    constexpr int NC = M * kLineGroups, KC = (NC + TH - 1) / TH;
+    static_assert(TH % 64 == 0, "whole waves");
+    constexpr int NC = M * kColGroups, KC = (NC + TH - 1) / TH;
     double* pcol = g.part_z + (long long)s * g.ncol_z + (long long)y * g.hx + kx0;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
       const int q = threadIdx.x + k * TH;
-      const int kxl = q / kLineGroups, gq = q % kLineGroups;
+      const int kxl = q / kColGroups, gq = q % kColGroups;
       const bool task = (NC % TH == 0 || q < NC) && kxl < mk;
       double a = 0.0;
       if (task)
-        for (int pos = gq; pos < N; pos += kLineGroups) a += vd[kxl * N + pos];
-      a = group_sum(a);
+        for (int pos = gq; pos < N; pos += kColGroups) a += vd[kxl * N + pos];
+      a = wave_sum_fixed(a);
       if (task && gq == 0) pcol[kxl] = a;
     }
   }
