@@ -63,21 +63,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel, n):
+def profiled_traffic(kernel, n, plan):
     """HBM bytes per dispatch of a pass class from the committed counter
     profile (FETCH_SIZE/WRITE_SIZE scaled by the copy-kernel calibration),
-    or None if the profile is missing, for another size, or stale."""
+    or None if the profile is missing, for another size, for another tile
+    plan than the timed one, or stale."""
     path = os.path.join(ROOT, "profiles", "solver_passes_256cube_counters.md")
     if n != 256 or not os.path.exists(path):
         return None
-    sha, val = None, None
+    sha, val, prof_plan = None, None, None
     for line in open(path):
         w = line.split()
         if len(w) == 2 and w[0] == "source_sha256_16":
             sha = w[1]
+        if len(w) == 4 and w[0] == "tile_plan":
+            prof_plan = [int(x) for x in w[1:]]
         if len(w) == 3 and w[0] == "traffic_bytes_per_dispatch" and w[1] == kernel:
             val = float(w[2])
-    return val if sha == kernel_source_hash() else None
+    return val if sha == kernel_source_hash() and prof_plan == list(plan) else None
 
 
 def _mandel_rel_error(C, Cref):
@@ -762,6 +765,7 @@ def main():
                     default="solve256")
     ap.add_argument("--sur-size", type=int, default=1024)
     ap.add_argument("--weights-dir", default=None)
+    ap.add_argument("--plan", default=None, help="fixed tile variants z,y,x of the default workload (else tuned)")
     ap.add_argument("--spread-tol", type=float, default=0.02)
     ap.add_argument("--bound-tol", type=float, default=0.0)
     ap.add_argument("--frac-z", type=float, default=5.0,
@@ -818,6 +822,8 @@ def main():
         args.no_cpu = True
     ctx = hh.Context(0)
     opts = dict(tol=1e-6, precision=0)
+    if args.plan:  # a fixed tile plan (profiling runs), else the tuned one
+        opts["plan"] = [int(x) for x in args.plan.split(",")]
     print("bench: %d^3 four-phase, warmup %d" % (n, args.warmup), file=sys.stderr, flush=True)
     setup = []
     for _ in range(args.warmup):  # the first call autotunes and captures graphs (one-time)
@@ -897,7 +903,7 @@ def main():
                    "graph_replay": True, "one_time_setup_ms": round(setup[0], 2)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(dom, n),
+                     "traffic": profiled_traffic(dom, n, timed[-1]["plan"]),
                      "algorithmic_bytes_per_launch": round(bytes_dom / max(launches[dom], 1)),
                      "algorithmic_bytes_per_system_iter": ab[dom],
                      "mean_launch_ms": round(ms[dom] / max(launches[dom], 1), 4)},
