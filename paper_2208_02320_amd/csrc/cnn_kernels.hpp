@@ -173,6 +173,14 @@ inline void launch_count_labels(const unsigned char* labels, long long stride, i
   }
 }
 
+// Number of nonzero bytes of a 64-bit word.
+__device__ __forceinline__ unsigned nonzero_bytes(unsigned long long d) {
+  d |= d >> 4;
+  d |= d >> 2;
+  d |= d >> 1;
+  return unsigned(__popcll(d & 0x0101010101010101ull));
+}
+
 // Interface counts of each window: cnt[b] += number of face-adjacent voxel
 // pairs inside the n^3 window (along x, y and z) whose labels differ.  Same
 // grid and W-byte chunks as k_count_labels; a chunk is compared byte by
@@ -194,18 +202,33 @@ __global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, 
     const int r = r0 + rl, z = fdiv(r, n, inv_n), y = r - z * n;
     const unsigned char* p = base + (z * w.box + y) * w.box + k * W;
     const CT v = *reinterpret_cast<const CT*>(p);
+    if constexpr (W == 8) {
+      // whole words: bytes that differ are the nonzero bytes of an XOR
+      const unsigned long long a = (unsigned long long)v.x | ((unsigned long long)v.y << 32);
+      const unsigned long long nxt = k + 1 < cw ? (unsigned long long)p[W] : (a >> 56);  // no pair past the row end
+      c += nonzero_bytes(a ^ ((a >> 8) | (nxt << 56)));
+      if (y + 1 < n) {
+        const uint2 u = *reinterpret_cast<const uint2*>(p + w.box);
+        c += nonzero_bytes(a ^ ((unsigned long long)u.x | ((unsigned long long)u.y << 32)));
+      }
+      if (z + 1 < n) {
+        const uint2 u = *reinterpret_cast<const uint2*>(p + plane);
+        c += nonzero_bytes(a ^ ((unsigned long long)u.x | ((unsigned long long)u.y << 32)));
+      }
+    } else {
 #pragma unroll
-    for (int j = 0; j + 1 < W; ++j) c += chunk_byte(v, j) != chunk_byte(v, j + 1);
-    if (k + 1 < cw) c += chunk_byte(v, W - 1) != unsigned(p[W]);
-    if (y + 1 < n) {
-      const CT u = *reinterpret_cast<const CT*>(p + w.box);
+      for (int j = 0; j + 1 < W; ++j) c += chunk_byte(v, j) != chunk_byte(v, j + 1);
+      if (k + 1 < cw) c += chunk_byte(v, W - 1) != unsigned(p[W]);
+      if (y + 1 < n) {
+        const CT u = *reinterpret_cast<const CT*>(p + w.box);
 #pragma unroll
-      for (int j = 0; j < W; ++j) c += chunk_byte(v, j) != chunk_byte(u, j);
-    }
-    if (z + 1 < n) {
-      const CT u = *reinterpret_cast<const CT*>(p + plane);
+        for (int j = 0; j < W; ++j) c += chunk_byte(v, j) != chunk_byte(u, j);
+      }
+      if (z + 1 < n) {
+        const CT u = *reinterpret_cast<const CT*>(p + plane);
 #pragma unroll
-      for (int j = 0; j < W; ++j) c += chunk_byte(v, j) != chunk_byte(u, j);
+        for (int j = 0; j < W; ++j) c += chunk_byte(v, j) != chunk_byte(u, j);
+      }
     }
   }
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
