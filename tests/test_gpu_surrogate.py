@@ -282,7 +282,9 @@ def test_interface_gate_matches_oracle(ctx):
     scaling: the fraction test never triggers here); a network reading the
     whole box counts the interfaces of the box."""
     n = 16
-    for size, pad, whole_box in ((64, 4, False), (48, 8, True)):
+    # core windows at offset 4 (4-byte chunks), whole 32^3 boxes (8-byte
+    # chunks), core windows at offset 3 (single bytes)
+    for size, pad, whole_box in ((64, 4, False), (48, 8, True), (48, 3, False)):
         lab = synth.four_phase(size, seed=4)
         CV, CR = sg.core_bounds(lab, 0, size, FOUR)
         c = hier.to21(0.5 * (CV + CR))
