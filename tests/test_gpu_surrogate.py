@@ -283,8 +283,8 @@ def test_interface_gate_matches_oracle(ctx):
     whole box counts the interfaces of the box."""
     n = 16
     # core windows at offset 4 (4-byte chunks), whole 32^3 boxes (8-byte
-    # chunks), core windows at offset 3 (single bytes)
-    for size, pad, whole_box in ((64, 4, False), (48, 8, True), (48, 3, False)):
+    # chunks), core windows at offset 1 (single bytes; 18^3 boxes)
+    for size, pad, whole_box in ((64, 4, False), (48, 8, True), (48, 1, False)):
         lab = synth.four_phase(size, seed=4)
         CV, CR = sg.core_bounds(lab, 0, size, FOUR)
         c = hier.to21(0.5 * (CV + CR))
