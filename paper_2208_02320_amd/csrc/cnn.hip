@@ -34,6 +34,7 @@ struct hh_net {
   __bf16* W[kLayers] = {};
   __bf16* Wt[kLayers] = {};
   __bf16* W4 = nullptr;  // first layer by tap pairs (networks of at most four phases)
+  __bf16* WR = nullptr;  // first layer by rows of taps (the same networks, even-aligned label rows)
   double mean[kOut], scale[kOut];
   double *d_mean = nullptr, *d_scale = nullptr;
   double fmu[kFrac], fsc[kFrac];  // standardization of the phase-fraction features
@@ -128,6 +129,7 @@ void cast_all(hh_ctx* ctx, hh_net* net) {
   for (int l = 0; l < kLayers; ++l)
     k_cast_weights<<<256, 256, 0, ctx->stream>>>(net->p + net->woff[l], kCin[l], kCout[l], net->W[l], net->Wt[l]);
   k_cast_pairs4<<<16, 256, 0, ctx->stream>>>(net->p + net->woff[0], kCout[0], net->W4);
+  k_cast_rows4<<<20, 256, 0, ctx->stream>>>(net->p + net->woff[0], kCout[0], net->WR);
   HIPCHK(hipGetLastError());
 }
 
@@ -173,8 +175,29 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
     launch_count_labels(labels, (long long)box * box * box, box, o, n, 0, batch, net->cnt, ctx->stream);
     net->cnt_in = net->cnt;
   }
-  // labels of at most four phases: the four-channel path (half the k-steps)
-  if (net->nphase <= 4)
+  // labels of at most four phases: the four-channel paths (fewer k-steps);
+  // the row path loads two labels at a time and needs every window row to
+  // start on an even address
+  auto aligned = [&](int w) {
+    return box % w == 0 && o % w == 0 && reinterpret_cast<uintptr_t>(labels) % unsigned(w) == 0;
+  };
+  const int Do = n / 2, nvo = Do * Do * Do;
+  const dim3 g1(unsigned((nvo + 255) / 256), unsigned(batch));
+  const float* b0 = net->p + net->boff[0];
+  if (net->nphase <= 4 && aligned(2)) {
+    // output edges 16 and 32: the workgroup's labels and the weights staged in LDS
+    const bool a8 = aligned(8);
+    if (Do == 32 && a8)
+      k_conv_fwd_rows4s<32, 8, 32><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0]);
+    else if (Do == 32)
+      k_conv_fwd_rows4s<32, 2, 32><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0]);
+    else if (Do == 16 && a8)
+      k_conv_fwd_rows4s<16, 8, 32><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0]);
+    else if (Do == 16)
+      k_conv_fwd_rows4s<16, 2, 32><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0]);
+    else
+      k_conv_fwd_rows4<32, 4><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0], make_grid3(Do));
+  } else if (net->nphase <= 4)
     conv_fwd<4, 32, true, 4>(ctx, nullptr, net->lw, net->W4, net->p + net->boff[0], net->a[0], edge(net, 0), batch);
   else
     conv_fwd<8, 32, true, 4>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
@@ -359,6 +382,7 @@ int hh_net_create(hh_ctx* ctx, int nphase, int n, unsigned long long seed, hh_ne
         net->Wt[l] = dalloc<__bf16>(ctx, 27LL * kCout[l] * kCin[l]);
       }
       net->W4 = dalloc<__bf16>(ctx, 14LL * kCout[0] * 8);
+      net->WR = dalloc<__bf16>(ctx, 20LL * kCout[0] * 8);
       net->d_mean = dalloc<double>(ctx, kOut);
       net->d_scale = dalloc<double>(ctx, kOut);
       net->d_fmu = dalloc<float>(ctx, kFrac);
@@ -414,7 +438,10 @@ void hh_net_destroy(hh_net* net) {
   for (int l = 0; l < kLayers; ++l) {
     (void)hipFree(net->W[l]);
     (void)hipFree(net->Wt[l]);
-    if (l == 0) (void)hipFree(net->W4);
+    if (l == 0) {
+      (void)hipFree(net->W4);
+      (void)hipFree(net->WR);
+    }
   }
   (void)hipFree(net->d_mean);
   (void)hipFree(net->d_scale);

@@ -284,6 +284,50 @@ __device__ __forceinline__ bf16x8 from_left_lane(bf16x8 v) {
   return __builtin_bit_cast(bf16x8, o);
 }
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+// bias, BF16 and ReLU of four output channels.  The ReLU acts on the BF16
+// bit patterns: a value with its sign bit set is a negative 16-bit integer,
+// so a packed integer max with 0 clears it (rounding keeps the sign, so this
+// equals rounding after the ReLU)
+__device__ __forceinline__ bf16x4 bias_relu4(const f32x4& a, const float4& bb) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef short i16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 lo = __builtin_convertvector(f32x2{a[0] + bb.x, a[1] + bb.y}, bf16x2);
+  const bf16x2 hi = __builtin_convertvector(f32x2{a[2] + bb.z, a[3] + bb.w}, bf16x2);
+  const i16x2 l = __builtin_elementwise_max(__builtin_bit_cast(i16x2, lo), i16x2{0, 0});
+  const i16x2 h = __builtin_elementwise_max(__builtin_bit_cast(i16x2, hi), i16x2{0, 0});
+  const bf16x2 lr = __builtin_bit_cast(bf16x2, l), hr = __builtin_bit_cast(bf16x2, h);
+  return bf16x4{lr[0], lr[1], hr[0], hr[1]};
+}
+
+// A wave's RB x NT accumulator tiles (D = W x X^T, so lane l holds channels
+// t 16 + 4 (l / 16) + i of voxel v0 + 16 r + l % 16) with bias and ReLU,
+// written to Yb ([nvo][COUT], one item) through the wave's LDS tile so ([VW][COUT])
+// as whole 16-byte chunks: the wave's VW = 16 RB voxels are consecutive.
+template <int RB, int NT, int COUT>
+__device__ __forceinline__ void store_staged(const f32x4 (&acc)[RB][NT], const float* __restrict__ bias, __bf16* so,
+                                             __bf16* __restrict__ Yb, int nvo, int v0, int lane) {
+  constexpr int VW = 16 * RB;
+  const int q = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int co = t * 16 + 4 * q;
+    const float4 bb = *reinterpret_cast<const float4*>(bias + co);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      *reinterpret_cast<bf16x4*>(so + (r * 16 + (lane & 15)) * COUT + co) = bias_relu4(acc[r][t], bb);
+  }
+  __syncthreads();
+  constexpr int CH = VW * COUT * 2 / 16;  // chunks per wave
+  const int nv = min(VW, nvo - v0);       // valid voxels of this wave (may be <= 0)
+  uint4* dst = reinterpret_cast<uint4*>(Yb + (long long)v0 * COUT);
+  const uint4* src = reinterpret_cast<const uint4*>(so);
+#pragma unroll
+  for (int c = lane; c < CH; c += 64)
+    if (c * 16 < nv * COUT * 2) dst[c] = src[c];
+}
+
 // XS (x shift; CIN = 32, output rows of at most 16 voxels that tile the 16
 // lanes of a row block): the taps come in (tz, ty) groups of three.  A lane
 // loads its voxel's inputs at x = 2 ox (tx = 1) and 2 ox + 1 (tx = 2); the
@@ -492,37 +536,10 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
   // D = W x X^T: lane l holds, for row block r and tile t, output channels
   // t 16 + 4 (l / 16) + i (i = 0..3) of voxel v0 + 16 r + l % 16: bias, ReLU,
   // and the four channels as one 8-byte word
-  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-  const int q = lane >> 4;
-  auto out4 = [&](int r, int t, const float4& bb) {
-    bf16x4 o;
-    o[0] = (__bf16)fmaxf(acc[r][t][0] + bb.x, 0.0f);
-    o[1] = (__bf16)fmaxf(acc[r][t][1] + bb.y, 0.0f);
-    o[2] = (__bf16)fmaxf(acc[r][t][2] + bb.z, 0.0f);
-    o[3] = (__bf16)fmaxf(acc[r][t][3] + bb.w, 0.0f);
-    return o;
-  };
   if constexpr (STAGE) {
-    // the wave's tile [voxel][channel] in LDS, then out as whole 16-byte
-    // chunks (the wave's voxels are consecutive)
-    __bf16* so = sOut[wave];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int co = t * 16 + 4 * q;
-      const float4 bb = *reinterpret_cast<const float4*>(bias + co);
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-        *reinterpret_cast<bf16x4*>(so + (r * 16 + (lane & 15)) * COUT + co) = out4(r, t, bb);
-    }
-    __syncthreads();
-    constexpr int CH = VW * COUT * 2 / 16;  // chunks per wave
-    const int nv = min(VW, nvo - v0);       // valid voxels of this wave (may be <= 0)
-    uint4* dst = reinterpret_cast<uint4*>(Y + ((long long)b * nvo + v0) * COUT);
-    const uint4* src = reinterpret_cast<const uint4*>(so);
-#pragma unroll
-    for (int c = lane; c < CH; c += 64)
-      if (c * 16 < nv * COUT * 2) dst[c] = src[c];
+    store_staged<RB, NT, COUT>(acc, bias, sOut[wave], Y + (long long)b * nvo * COUT, nvo, v0, lane);
   } else {
+    const int q = lane >> 4;
     __bf16* Yb = Y + (long long)b * nvo * COUT;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -531,10 +548,236 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, 
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int v = v0 + r * 16 + (lane & 15);
-        if (v < nvo) *reinterpret_cast<bf16x4*>(Yb + (long long)v * COUT + co) = out4(r, t, bb);
+        if (v < nvo) *reinterpret_cast<bf16x4*>(Yb + (long long)v * COUT + co) = bias_relu4(acc[r][t], bb);
       }
     }
   }
+}
+
+// First layer of networks of at most four phases, for label windows whose
+// rows start on even addresses: the 27 taps go by rows (tz, ty) of three.
+// K slot s = 4 ks + q of a voxel (q = lane / 16) is half s & 1 of row
+// j = s / 2 (tz = j / 3, ty = j % 3):
+//   half 0: taps tx = 1, 2, the labels at x = 2 ox and 2 ox + 1 (one aligned
+//           2-byte load);
+//   half 1: tap tx = 0, the label at 2 ox - 1 (high byte of the 2-byte word at
+//           2 ox - 2; zero padding at ox = 0), and an empty tap.
+// Nine rows take 5 k-steps (rows 9, slots 18 and 19, are empty).  Per k-step
+// and row block a lane issues one load, and the two labels' four-channel
+// one-hot codes are one 16-byte entry of an LDS table (labels 4 and above:
+// the zero code).  W is laid out [slot][COUT][8] (k_cast_rows4).
+template <int COUT, int RB>
+__global__ void __launch_bounds__(256) k_conv_fwd_rows4(LabelWindow lw, const __bf16* __restrict__ W,
+                                                        const float* __restrict__ bias, __bf16* __restrict__ Y,
+                                                        Grid3 go) {
+  static_assert(COUT % 16 == 0, "channel count");
+  constexpr int KS = 5, NT = COUT / 16, VW = 16 * RB;
+  constexpr unsigned kPad = 0x00040004u;  // both labels of a slot in the padding
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  // entry 8 a + c: one-hot of a in channels 0-3 and of c in channels 4-7
+  __shared__ bf16x8 sPair[40];
+  __shared__ __align__(16) __bf16 sOut[4][VW * COUT];
+  const int nvo = go.D2 * go.D;  // output voxels per item
+  const int b = blockIdx.y;      // item
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+  const int v0 = blockIdx.x * (64 * RB) + wave * VW;
+  if (threadIdx.x < 40) {
+    const bf16x4v lo = onehot4(threadIdx.x >> 3), hi = onehot4(threadIdx.x & 7);
+    sPair[threadIdx.x] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  }
+  __syncthreads();
+  const unsigned char* Lb = window_base(lw, b);
+  const unsigned rs = unsigned(lw.box), rs2 = rs * rs;
+  const bool h1 = (q & 1) != 0;  // this lane's slots are halves 1
+  // per row block: offset of (2 oz - 1, 2 oy - 1, x0), x0 = 2 ox (half 0) or
+  // 2 ox - 2 (half 1), modulo 2^32; edge bits: 1 oz = 0, 2 oy = 0, 4 the
+  // tx = 0 tap at ox = 0 (half 1), 8 always (rows 9).  Voxels past the end
+  // take voxel 0's loads (their outputs are not stored).
+  unsigned base[RB], edge[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int va = v0 + r * 16 + (lane & 15);
+    int oz, oy, ox;
+    split3(go, va < nvo ? va : 0, oz, oy, ox);
+    base[r] = (unsigned(2 * oz - 1) * rs + unsigned(2 * oy - 1)) * rs + unsigned(2 * ox) - (h1 ? 2u : 0u);
+    edge[r] = (oz == 0 ? 1u : 0u) | (oy == 0 ? 2u : 0u) | (h1 && ox == 0 ? 4u : 0u) | 8u;
+  }
+  // row of k-step ks: j = 2 ks + q / 2; its offset and the edge bits that
+  // put it in the padding
+  auto row_off = [&](int j) { return unsigned(j / 3) * rs2 + unsigned(j % 3) * rs; };
+  auto row_mask = [](int j) { return j >= 9 ? 8u : (j / 3 == 0 ? 1u : 0u) | (j % 3 == 0 ? 2u : 0u) | 4u; };
+  const bool qhi = q >= 2;
+  unsigned roff[KS], rmask[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    roff[ks] = qhi ? row_off(2 * ks + 1) : row_off(2 * ks);
+    rmask[ks] = qhi ? row_mask(2 * ks + 1) : row_mask(2 * ks);
+  }
+  // byte selectors of v_perm over {4, word}: half 0 (label x0, label x0 + 1),
+  // half 1 (label x0 + 1, 4), as two 16-bit fields
+  const unsigned psel = h1 ? 0x0C040C01u : 0x0C010C00u;
+  auto load_a = [&](int ks, int r, bool& ok) -> unsigned {
+    ok = (edge[r] & rmask[ks]) == 0u;
+    const unsigned off = ok ? base[r] + roff[ks] : 0u;
+    return *reinterpret_cast<const unsigned short*>(Lb + off);
+  };
+  auto onehot_pair = [&](unsigned w, bool ok) -> bf16x8 {
+    u16x2 p = __builtin_bit_cast(u16x2, ok ? __builtin_amdgcn_perm(4u, w, psel) : kPad);
+    p = __builtin_elementwise_min(p, u16x2{4, 4});
+    const unsigned e = __builtin_amdgcn_udot2(p, u16x2{128, 16}, 0u, false);  // 16 (8 a + c)
+    return *reinterpret_cast<const bf16x8*>(reinterpret_cast<const unsigned char*>(sPair) + e);
+  };
+  auto load_b = [&](int ks, int t) { return ld8(W + ((4 * ks + q) * COUT + t * 16 + (lane & 15)) * 8); };
+  f32x4 acc[RB][NT];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // software pipeline: the loads of k-step ks + 1 are in flight during the MFMAs of ks
+  unsigned ra[RB];
+  bool rok[RB];
+  bf16x8 rb_[NT];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) ra[r] = load_a(0, r, rok[r]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) rb_[t] = load_b(0, t);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    bf16x8 a[RB], bw[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bw[t] = rb_[t];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) a[r] = onehot_pair(ra[r], rok[r]);
+    if (ks + 1 < KS) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) ra[r] = load_a(ks + 1, r, rok[r]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) rb_[t] = load_b(ks + 1, t);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(bw[t], a[r], acc[r][t]);
+  }
+  store_staged<RB, NT, COUT>(acc, bias, sOut[wave], Y + (long long)b * nvo * COUT, nvo, v0, lane);
+}
+
+// The same first layer with the workgroup's label footprint and the weights
+// staged in LDS, for output edges DO that divide 256 (a workgroup's 256
+// voxels are R = 256 / DO whole output rows of one slice) and label windows
+// whose rows start on W-aligned addresses (W = 2 or 8).  K slots as in
+// k_conv_fwd_rows4.  The footprint holds planes z = 2 oz - 1 .. 2 oz + 1 and
+// rows y = 2 oy0 - 1 .. 2 oy0 + 2 R - 1 of the labels at x = -8 .. 2 DO - 1,
+// with everything outside the window (the zero padding) stored as label 4,
+// the zero code, so no tap needs an edge test; a fourth plane of 4s serves
+// the empty row 9.
+template <int DO, int W, int COUT>
+__global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const __bf16* __restrict__ Wr,
+                                                         const float* __restrict__ bias, __bf16* __restrict__ Y) {
+  static_assert(256 % DO == 0 && DO % 16 == 0 && (W == 2 || W == 8) && COUT % 16 == 0, "shapes");
+  constexpr int RB = 4, KS = 5, NT = COUT / 16, VW = 16 * RB;
+  constexpr int R = 256 / DO;     // output rows per workgroup
+  constexpr int NY = 2 * R + 1;   // footprint rows per plane
+  constexpr int RW = 2 * DO + 8;  // bytes per footprint row; label x at byte 8 + x
+  constexpr int U = 2 * DO / W, NU = 3 * NY * U, KU = (NU + 255) / 256;  // label units of W bytes
+  constexpr int NWU = 20 * COUT, KW = (NWU + 255) / 256;                // weight units of 16 bytes
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  using Unit = typename std::conditional<W == 8, unsigned long long, unsigned short>::type;
+  constexpr Unit kFour = W == 8 ? Unit(0x0404040404040404ull) : Unit(0x0404u);
+  // the staged weights and labels, and after the last k-step the waves'
+  // output tiles in the same bytes (more resident workgroups per CU)
+  constexpr int IN_BYTES = NWU * 16 + 4 * NY * RW, OUT_BYTES = 4 * VW * COUT * 2;
+  __shared__ __align__(16) unsigned char smem[IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES];
+  __shared__ bf16x8 sPair[40];  // entry 8 a + c: one-hot of a in channels 0-3, of c in channels 4-7
+  bf16x8* sW = reinterpret_cast<bf16x8*>(smem);
+  unsigned char* sLab = smem + NWU * 16;
+  constexpr int nvo = DO * DO * DO;
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
+  const int oz = blockIdx.x / (DO / R), oy0 = (blockIdx.x % (DO / R)) * R;
+  const unsigned char* Lb = window_base(lw, b);
+  const long long rs = lw.box;
+  // every global load first, then the LDS writes
+  Unit lv[KU];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int u = threadIdx.x + k * 256;
+    const int row = u / U, c = u % U, zz = row / NY, yy = row % NY;
+    const int z = 2 * oz - 1 + zz, y = 2 * oy0 - 1 + yy;
+    lv[k] = kFour;
+    if ((NU % 256 == 0 || u < NU) && z >= 0 && y >= 0)
+      lv[k] = *reinterpret_cast<const Unit*>(Lb + (z * rs + y) * rs + c * W);
+  }
+  bf16x8 wv[KW];
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int i = threadIdx.x + k * 256;
+    if (NWU % 256 == 0 || i < NWU) wv[k] = ld8(Wr + i * 8);
+  }
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    const int u = threadIdx.x + k * 256;
+    const int row = u / U, c = u % U;
+    if (NU % 256 == 0 || u < NU) *reinterpret_cast<Unit*>(sLab + row * RW + 8 + c * W) = lv[k];
+  }
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int i = threadIdx.x + k * 256;
+    if (NWU % 256 == 0 || i < NWU) sW[i] = wv[k];
+  }
+  // x = -8 .. -1 of the three planes, and the whole fourth plane: 4s
+  for (int i = threadIdx.x; i < 3 * NY + NY * RW / 8; i += 256) {
+    const int off = i < 3 * NY ? i * RW : 3 * NY * RW + (i - 3 * NY) * 8;
+    *reinterpret_cast<unsigned long long*>(sLab + off) = 0x0404040404040404ull;
+  }
+  if (threadIdx.x < 40) {
+    const bf16x4v lo = onehot4(threadIdx.x >> 3), hi = onehot4(threadIdx.x & 7);
+    sPair[threadIdx.x] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  }
+  __syncthreads();
+  const bool h1 = (q & 1) != 0, qhi = q >= 2;
+  // row block r: output row rho (of the workgroup's R) and ox; footprint
+  // offset of its tap row (tz, ty) = (0, 0) at x0 = 2 ox (half 0) or 2 ox - 2
+  unsigned lb[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int u = wave * VW + r * 16 + (lane & 15);
+    const int rho = u / DO, ox = u % DO;
+    lb[r] = unsigned(2 * rho * RW + 8 + 2 * ox - (h1 ? 2 : 0));
+  }
+  // tap row j = 2 ks + q / 2 (tz = j / 3, ty = j % 3; j = 9 is the plane of 4s)
+  auto row_off = [](int j) { return unsigned(((j / 3) * NY + j % 3) * RW); };
+  unsigned roff[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) roff[ks] = qhi ? row_off(2 * ks + 1) : row_off(2 * ks);
+  const unsigned psel = h1 ? 0x0C040C01u : 0x0C010C00u;
+  auto onehot_pair = [&](int ks, int r) -> bf16x8 {
+    const unsigned w = *reinterpret_cast<const unsigned short*>(sLab + lb[r] + roff[ks]);
+    u16x2 p = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(4u, w, psel));
+    p = __builtin_elementwise_min(p, u16x2{4, 4});
+    const unsigned e = __builtin_amdgcn_udot2(p, u16x2{128, 16}, 0u, false);  // 16 (8 a + c)
+    return *reinterpret_cast<const bf16x8*>(reinterpret_cast<const unsigned char*>(sPair) + e);
+  };
+  f32x4 acc[RB][NT];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    bf16x8 a[RB], bw[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bw[t] = sW[(4 * ks + q) * COUT + t * 16 + (lane & 15)];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) a[r] = onehot_pair(ks, r);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[r][t] = mfma(bw[t], a[r], acc[r][t]);
+  }
+  __syncthreads();  // every wave is done with the staged inputs
+  store_staged<RB, NT, COUT>(acc, bias, reinterpret_cast<__bf16*>(smem) + wave * VW * COUT,
+                             Y + (long long)b * nvo * COUT, nvo, blockIdx.x * 256 + wave * VW, lane);
 }
 
 // Forward convolution with the K steps of one 16-voxel row block split over
@@ -1016,6 +1259,19 @@ __global__ void k_cast_pairs4(const float* __restrict__ w, int cout, __bf16* __r
     const int c = i % 8, co = (i / 8) % cout, j = i / (8 * cout);
     const int tap = 2 * j + c / 4;
     W4[i] = (__bf16)(tap < 27 ? w[((long long)tap * cout + co) * 8 + c % 4] : 0.0f);
+  }
+}
+
+// First-layer weights for the row path (k_conv_fwd_rows4): slot s < 20 is
+// half s & 1 of row j = s / 2 (taps 3 j .. 3 j + 2); half 0 holds tap 3 j + 1
+// (c < 4) and tap 3 j + 2 (c >= 4), half 1 tap 3 j (c < 4) and zeros; row 9
+// is zero.  WR[s][co][c], channel c % 4.
+__global__ void k_cast_rows4(const float* __restrict__ w, int cout, __bf16* __restrict__ WR) {
+  const int n = 20 * cout * 8;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int c = i % 8, co = (i / 8) % cout, s = i / (8 * cout), j = s / 2;
+    const int tap = (s & 1) ? (c < 4 ? 3 * j : -1) : 3 * j + 1 + c / 4;
+    WR[i] = (__bf16)(j < 9 && tap >= 0 ? w[((long long)tap * cout + co) * 8 + c % 4] : 0.0f);
   }
 }
 

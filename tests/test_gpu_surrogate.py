@@ -56,9 +56,11 @@ def net_with(ctx, nphase, n, params, fstats=FSTATS):
 
 # pad 2: byte-wise label counts; pad 4 and 8: 4- and 8-byte chunks.  Inner
 # layers on outputs of 16, 8, 4, 2 voxels per row: the x-shift path of every
-# row width (n = 64 has the network's own sizes)
+# row width (n = 64 has the network's own sizes).  Up to four phases the first
+# layer takes two labels per load where window rows start on even addresses
+# (even pad), else one (odd pad, the last case)
 @pytest.mark.parametrize("n,batch,nphase,pad", [(16, 3, 3, 2), (32, 2, 4, 2), (16, 5, 8, 2), (16, 3, 4, 4),
-                                                (16, 2, 5, 8), (64, 1, 4, 8)])
+                                                (16, 2, 5, 8), (64, 1, 4, 8), (32, 2, 4, 3)])
 def test_forward_matches_oracle(ctx, n, batch, nphase, pad):
     lab = boxes(batch, n + 2 * pad, nphase, seed=n + batch)
     p = ref.init_params(nphase, seed=7).astype(np.float32)
@@ -82,6 +84,25 @@ def test_forward_ignores_labels_outside_the_channels(ctx):
     lab[high] = rng.integers(8, 256, size=int(high.sum()))
     p = ref.init_params(8, seed=9).astype(np.float32)
     net = net_with(ctx, 8, n, p)
+    y = net.forward(lab, offset=pad)
+    core = lab[:, pad:pad + n, pad:pad + n, pad:pad + n]
+    yr, _ = ref.forward(p.astype(np.float64), core, bf=True, fstats=FSTATS)
+    assert np.abs(y - yr).max() / max(1.0, np.abs(yr).max()) < 2e-3
+    net.close()
+
+
+@pytest.mark.parametrize("pad", [2, 1])
+def test_four_phase_forward_ignores_labels_past_its_channels(ctx, pad):
+    """A network of four phases has no one-hot channel for labels 4..255, on
+    both first-layer paths (even and odd window offsets); the oracle's
+    channels 4..7 carry zero weights."""
+    n, batch = 16, 3
+    lab = boxes(batch, n + 2 * pad, 4, seed=23 + pad)
+    rng = np.random.default_rng(24)
+    high = rng.random(lab.shape) < 0.3
+    lab[high] = rng.integers(4, 256, size=int(high.sum()))
+    p = ref.init_params(4, seed=13).astype(np.float32)
+    net = net_with(ctx, 4, n, p)
     y = net.forward(lab, offset=pad)
     core = lab[:, pad:pad + n, pad:pad + n, pad:pad + n]
     yr, _ = ref.forward(p.astype(np.float64), core, bf=True, fstats=FSTATS)
