@@ -289,7 +289,9 @@ void check_input(hh_ctx* ctx, hh_net* net, int batch, int box, int o) {
 
 void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
                            double* c21, const int* counts) {
-  const int step = 256;
+  // items per forward pass: 512 fill the grids of the small deep layers
+  // (256: 5 % slower end to end; 1024: no faster)
+  const int step = 512;
   ensure_acts(ctx, net, std::min(step, batch));
   for (int b0 = 0; b0 < batch; b0 += step) {
     const int nb = std::min(step, batch - b0);

@@ -341,8 +341,11 @@ __device__ __forceinline__ void store_staged(const f32x4 (&acc)[RB][NT], const f
 // LAB with CIN = 4 (networks of at most four phases): a lane's eight K values
 // are the four channels of two consecutive taps, so K = 27 x 4 takes 4 k-steps
 // instead of 7; W is then laid out [tap pair][COUT][8] (k_cast_pairs4).
+// The 32-channel-input layers are asked to fit four waves per SIMD: the
+// compiler then keeps the accumulators in VGPRs (the second layer: 119
+// registers against 136 with AGPRs, three waves per SIMD), with no spills.
 template <int CIN, int COUT, bool LAB, int RB, bool XS = false, bool YR = false>
-__global__ void __launch_bounds__(256) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((CIN == 32 && !LAB) ? 4 : 1))) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
                                                   const __bf16* __restrict__ W, const float* __restrict__ bias,
                                                   __bf16* __restrict__ Y, int D, Grid3 go) {
   static_assert((LAB ? (CIN == 8 || CIN == 4) : CIN % 8 == 0) && COUT % 16 == 0, "channel counts");

@@ -80,16 +80,35 @@ __global__ void __launch_bounds__(256) k_gather_field(const T* __restrict__ src,
 }
 
 // Largest label of each item: blockIdx.y = item, blocks along x split it.
+// The item's 16-byte-aligned body goes in 16-byte loads, its even and odd
+// bytes kept as packed 16-bit maxima; the few bytes before and after it
+// one at a time.
 __global__ void k_label_max(const unsigned char* __restrict__ labels, const long long* __restrict__ off,
                             const long long* __restrict__ count, int* __restrict__ out) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
   __shared__ int smax[256];
   const int item = blockIdx.y;
   const unsigned char* p = labels + off[item];
   const long long n = count[item];
-  int m = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    m = max(m, int(p[i]));
+  const long long head = min(n, (long long)((16u - unsigned(reinterpret_cast<uintptr_t>(p) & 15u)) & 15u));
+  const long long nv = (n - head) / 16;  // aligned 16-byte words
+  const uint4* pv = reinterpret_cast<const uint4*>(p + head);
+  const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x, nt = (long long)gridDim.x * blockDim.x;
+  u16x2 me = {0, 0}, mo = {0, 0};
+  auto take = [&](unsigned w) {
+    me = __builtin_elementwise_max(me, __builtin_bit_cast(u16x2, w & 0x00FF00FFu));
+    mo = __builtin_elementwise_max(mo, __builtin_bit_cast(u16x2, (w >> 8) & 0x00FF00FFu));
+  };
+  for (long long i = tid; i < nv; i += nt) {
+    const uint4 v = pv[i];
+    take(v.x);
+    take(v.y);
+    take(v.z);
+    take(v.w);
+  }
+  int m = max(max(int(me[0]), int(me[1])), max(int(mo[0]), int(mo[1])));
+  for (long long i = tid; i < head; i += nt) m = max(m, int(p[i]));
+  for (long long i = head + nv * 16 + tid; i < n; i += nt) m = max(m, int(p[i]));
   smax[threadIdx.x] = m;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -165,8 +184,8 @@ void launch_gather_field(int precision, const void* src, int mx, int my, int mz,
 void launch_label_max(const unsigned char* labels, const long long* off, const long long* count, int nitems,
                       long long max_count, int* out, hipStream_t st) {
   k_fill_int<<<(nitems + 255) / 256, 256, 0, st>>>(out, nitems, 0);
-  long long bx = (max_count + 256 * 16 - 1) / (256 * 16);
-  bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
+  long long bx = (max_count + 256 * 64 - 1) / (256 * 64);  // at least 64 bytes per thread
+  bx = bx < 1 ? 1 : (bx > 4096 ? 4096 : bx);
   for (int i0 = 0; i0 < nitems; i0 += 65535) {
     const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
     k_label_max<<<dim3(unsigned(bx), unsigned(ni)), 256, 0, st>>>(labels, off + i0, count + i0, out + i0);

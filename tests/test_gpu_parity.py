@@ -302,6 +302,29 @@ def test_device_tensor_inputs(ctx):
     assert np.array_equal(r1.C, r2.C)
 
 
+@pytest.mark.parametrize("start", [0, 1, 8])
+def test_device_label_check(ctx, start):
+    """Labels on the device are checked against nphase there: an image whose
+    first byte sits at any alignment, with one bad label among the bytes
+    before its first 16-byte boundary, in the body, or in its last bytes."""
+    import torch
+    from paper_2208_02320_amd import hh
+    lab = synth.two_phase(16, 0.3, 1.5, 1)
+    base = torch.zeros(start + lab.size, dtype=torch.uint8, device="cuda")
+    d = base[start:].view(16, 16, 16)
+    d.copy_(torch.from_numpy(lab))
+    want = ctx.homogenize(lab, QP, tol=1e-6).C
+    assert np.array_equal(ctx.homogenize(d, QP, tol=1e-6).C, want)
+    for pos in (0, 3, 100, 2049, lab.size - 1):
+        flat = d.view(-1)
+        keep = int(flat[pos])
+        flat[pos] = 2 + pos % 200
+        with pytest.raises(hh.HHError) as e:
+            ctx.homogenize(d, QP, tol=1e-6)
+        assert e.value.code == -1 and "label %d" % (2 + pos % 200) in str(e.value), pos
+        flat[pos] = keep
+
+
 def test_errors(ctx):
     from paper_2208_02320_amd import hh
     lab = np.full((8, 8, 8), 2, np.uint8)
