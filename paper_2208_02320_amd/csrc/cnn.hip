@@ -141,9 +141,11 @@ void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16*
   if constexpr (CI == 32 && !LAB) {
     // output rows that tile the 16 lanes of a row block: the x-shift path
     if constexpr (RB == 4) {
-      // rows of 16: a wave's row blocks are consecutive rows of one slice
+      // rows of 16: a wave's row blocks are consecutive rows of one slice;
+      // workgroups of 8 waves share the layer's weights through LDS
       if (Do == 16) {
-        k_conv_fwd<CI, CO, LAB, RB, true, true><<<grid, 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
+        const dim3 g2(unsigned((nvo + 128 * RB - 1) / (128 * RB)), unsigned(batch));  // 8 waves of 16 RB voxels
+        k_conv_fwd<CI, CO, LAB, RB, true, true, true><<<g2, 512, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
         return;
       }
     }
