@@ -305,27 +305,36 @@ __device__ __forceinline__ bf16x4 bias_relu4(const f32x4& a, const float4& bb) {
 // t 16 + 4 (l / 16) + i of voxel v0 + 16 r + l % 16) with bias and ReLU,
 // written to Yb ([nvo][COUT], one item) through the wave's LDS tile so ([VW][COUT])
 // as whole 16-byte chunks: the wave's VW = 16 RB voxels are consecutive.
+// In the tile, 16-byte chunk j of voxel v sits at chunk j ^ ((v / 4) % CV)
+// of its row (CV chunks per voxel): the 16 lanes of a row block, whose
+// voxels' rows lie 64 bytes apart, then write 16 different banks.
 template <int RB, int NT, int COUT>
 __device__ __forceinline__ void store_staged(const f32x4 (&acc)[RB][NT], const float* __restrict__ bias, __bf16* so,
                                              __bf16* __restrict__ Yb, int nvo, int v0, int lane) {
-  constexpr int VW = 16 * RB;
-  const int q = lane >> 4;
+  constexpr int VW = 16 * RB, CV = COUT / 8;  // chunks per voxel
+  static_assert((CV & (CV - 1)) == 0, "chunks per voxel: a power of two");
+  const int q = lane >> 4, l = lane & 15;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int co = t * 16 + 4 * q;
+    const int co = t * 16 + 4 * q;  // four channels: half (co / 4) % 2 of chunk co / 8
     const float4 bb = *reinterpret_cast<const float4*>(bias + co);
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
-      *reinterpret_cast<bf16x4*>(so + (r * 16 + (lane & 15)) * COUT + co) = bias_relu4(acc[r][t], bb);
+    for (int r = 0; r < RB; ++r) {
+      const int v = r * 16 + l;
+      const int sw = ((co / 8) ^ ((v >> 2) & (CV - 1))) * 8 + (co & 7);
+      *reinterpret_cast<bf16x4*>(so + v * COUT + sw) = bias_relu4(acc[r][t], bb);
+    }
   }
   __syncthreads();
-  constexpr int CH = VW * COUT * 2 / 16;  // chunks per wave
-  const int nv = min(VW, nvo - v0);       // valid voxels of this wave (may be <= 0)
+  constexpr int CH = VW * CV;         // chunks per wave
+  const int nv = min(VW, nvo - v0);  // valid voxels of this wave (may be <= 0)
   uint4* dst = reinterpret_cast<uint4*>(Yb + (long long)v0 * COUT);
   const uint4* src = reinterpret_cast<const uint4*>(so);
 #pragma unroll
-  for (int c = lane; c < CH; c += 64)
-    if (c * 16 < nv * COUT * 2) dst[c] = src[c];
+  for (int c = lane; c < CH; c += 64) {
+    const int v = c / CV, j = c % CV;
+    if (c * 16 < nv * COUT * 2) dst[c] = src[v * CV + (j ^ ((v >> 2) & (CV - 1)))];
+  }
 }
 
 // XS (x shift; CIN = 32, output rows of at most 16 voxels that tile the 16
@@ -584,6 +593,23 @@ __global__ void __launch_bounds__(WL ? 512 : 256) __attribute__((amdgpu_waves_pe
   }
 }
 
+// One-hot codes of two labels a, c in 0..4 (4: the zero code) as one 16-byte
+// LDS entry 5 a + c, a in channels 0-3 and c in channels 4-7 (25 entries).
+constexpr int kPairs = 25;
+__device__ __forceinline__ void fill_pairs(bf16x8* t) {
+  if (threadIdx.x < kPairs) {
+    const bf16x4v lo = onehot4(threadIdx.x / 5), hi = onehot4(threadIdx.x % 5);
+    t[threadIdx.x] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  }
+}
+// the entry of labels a | c << 16 (each clamped to 4 first)
+__device__ __forceinline__ bf16x8 pair_code(const bf16x8* t, unsigned ac) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  const u16x2 p = __builtin_elementwise_min(__builtin_bit_cast(u16x2, ac), u16x2{4, 4});
+  const unsigned e = __builtin_amdgcn_udot2(p, u16x2{80, 16}, 0u, false);  // 16 (5 a + c)
+  return *reinterpret_cast<const bf16x8*>(reinterpret_cast<const unsigned char*>(t) + e);
+}
+
 // First layer of networks of at most four phases, for label windows whose
 // rows start on even addresses: the 27 taps go by rows (tz, ty) of three.
 // K slot s = 4 ks + q of a voxel (q = lane / 16) is half s & 1 of row
@@ -603,18 +629,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4(LabelWindow lw, const __
   static_assert(COUT % 16 == 0, "channel count");
   constexpr int KS = 5, NT = COUT / 16, VW = 16 * RB;
   constexpr unsigned kPad = 0x00040004u;  // both labels of a slot in the padding
-  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-  // entry 8 a + c: one-hot of a in channels 0-3 and of c in channels 4-7
-  __shared__ bf16x8 sPair[40];
+  __shared__ bf16x8 sPair[kPairs];
   __shared__ __align__(16) __bf16 sOut[4][VW * COUT];
   const int nvo = go.D2 * go.D;  // output voxels per item
   const int b = blockIdx.y;      // item
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
   const int v0 = blockIdx.x * (64 * RB) + wave * VW;
-  if (threadIdx.x < 40) {
-    const bf16x4v lo = onehot4(threadIdx.x >> 3), hi = onehot4(threadIdx.x & 7);
-    sPair[threadIdx.x] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-  }
+  fill_pairs(sPair);
   __syncthreads();
   const unsigned char* Lb = window_base(lw, b);
   const unsigned rs = unsigned(lw.box), rs2 = rs * rs;
@@ -652,10 +673,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4(LabelWindow lw, const __
     return *reinterpret_cast<const unsigned short*>(Lb + off);
   };
   auto onehot_pair = [&](unsigned w, bool ok) -> bf16x8 {
-    u16x2 p = __builtin_bit_cast(u16x2, ok ? __builtin_amdgcn_perm(4u, w, psel) : kPad);
-    p = __builtin_elementwise_min(p, u16x2{4, 4});
-    const unsigned e = __builtin_amdgcn_udot2(p, u16x2{128, 16}, 0u, false);  // 16 (8 a + c)
-    return *reinterpret_cast<const bf16x8*>(reinterpret_cast<const unsigned char*>(sPair) + e);
+    return pair_code(sPair, ok ? __builtin_amdgcn_perm(4u, w, psel) : kPad);
   };
   auto load_b = [&](int ks, int t) { return ld8(W + ((4 * ks + q) * COUT + t * 16 + (lane & 15)) * 8); };
   f32x4 acc[RB][NT];
@@ -711,14 +729,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const _
   constexpr int RW = 2 * DO + 8;  // bytes per footprint row; label x at byte 8 + x
   constexpr int U = 2 * DO / W, NU = 3 * NY * U, KU = (NU + 255) / 256;  // label units of W bytes
   constexpr int NWU = 20 * COUT, KW = (NWU + 255) / 256;                // weight units of 16 bytes
-  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
   using Unit = typename std::conditional<W == 8, unsigned long long, unsigned short>::type;
   constexpr Unit kFour = W == 8 ? Unit(0x0404040404040404ull) : Unit(0x0404u);
   // the staged weights and labels, and after the last k-step the waves'
   // output tiles in the same bytes (more resident workgroups per CU)
   constexpr int IN_BYTES = NWU * 16 + 4 * NY * RW, OUT_BYTES = 4 * VW * COUT * 2;
   __shared__ __align__(16) unsigned char smem[IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES];
-  __shared__ bf16x8 sPair[40];  // entry 8 a + c: one-hot of a in channels 0-3, of c in channels 4-7
+  __shared__ bf16x8 sPair[kPairs];
   bf16x8* sW = reinterpret_cast<bf16x8*>(smem);
   unsigned char* sLab = smem + NWU * 16;
   constexpr int nvo = DO * DO * DO;
@@ -760,10 +777,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const _
     const int off = i < 3 * NY ? i * RW : 3 * NY * RW + (i - 3 * NY) * 8;
     *reinterpret_cast<unsigned long long*>(sLab + off) = 0x0404040404040404ull;
   }
-  if (threadIdx.x < 40) {
-    const bf16x4v lo = onehot4(threadIdx.x >> 3), hi = onehot4(threadIdx.x & 7);
-    sPair[threadIdx.x] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-  }
+  fill_pairs(sPair);
   __syncthreads();
   const bool h1 = (q & 1) != 0, qhi = q >= 2;
   // row block r: output row rho (of the workgroup's R) and ox; footprint
@@ -783,10 +797,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const _
   const unsigned psel = h1 ? 0x0C040C01u : 0x0C010C00u;
   auto onehot_pair = [&](int ks, int r) -> bf16x8 {
     const unsigned w = *reinterpret_cast<const unsigned short*>(sLab + lb[r] + roff[ks]);
-    u16x2 p = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(4u, w, psel));
-    p = __builtin_elementwise_min(p, u16x2{4, 4});
-    const unsigned e = __builtin_amdgcn_udot2(p, u16x2{128, 16}, 0u, false);  // 16 (8 a + c)
-    return *reinterpret_cast<const bf16x8*>(reinterpret_cast<const unsigned char*>(sPair) + e);
+    return pair_code(sPair, __builtin_amdgcn_perm(4u, w, psel));
   };
   f32x4 acc[RB][NT];
 #pragma unroll
