@@ -101,7 +101,8 @@ int wgrad_chunk(long long total, int max_chunks) {
 
 void ensure_acts(hh_ctx* ctx, hh_net* net, int batch) {
   if (batch <= net->cap) return;
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  // the old buffers may still be read by work queued on any stream
+  HIPCHK(hipDeviceSynchronize());
   free_acts(net);
   net->cnt = dalloc<int>(ctx, size_t(batch) * kFrac);
   size_t pmax = 0, bmax = 0;
@@ -135,7 +136,7 @@ void cast_all(hh_ctx* ctx, hh_net* net) {
 
 template <int CI, int CO, bool LAB, int RB>
 void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16* W, const float* b, __bf16* Y, int D,
-              int batch) {
+              int batch, hipStream_t st) {
   const int Do = D / 2, nvo = Do * Do * Do;
   const dim3 grid(unsigned((nvo + 64 * RB - 1) / (64 * RB)), unsigned(batch));
   if constexpr (CI == 32 && !LAB) {
@@ -145,36 +146,37 @@ void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16*
       // workgroups of 8 waves share the layer's weights through LDS
       if (Do == 16) {
         const dim3 g2(unsigned((nvo + 128 * RB - 1) / (128 * RB)), unsigned(batch));  // 8 waves of 16 RB voxels
-        k_conv_fwd<CI, CO, LAB, RB, true, true, true><<<g2, 512, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
+        k_conv_fwd<CI, CO, LAB, RB, true, true, true><<<g2, 512, 0, st>>>(X, lw, W, b, Y, D, make_grid3(Do));
         return;
       }
     }
     if (Do <= 16 && 16 % Do == 0) {
-      k_conv_fwd<CI, CO, LAB, RB, true><<<grid, 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
+      k_conv_fwd<CI, CO, LAB, RB, true><<<grid, 256, 0, st>>>(X, lw, W, b, Y, D, make_grid3(Do));
       return;
     }
   }
-  k_conv_fwd<CI, CO, LAB, RB><<<grid, 256, 0, ctx->stream>>>(X, lw, W, b, Y, D, make_grid3(Do));
+  k_conv_fwd<CI, CO, LAB, RB><<<grid, 256, 0, st>>>(X, lw, W, b, Y, D, make_grid3(Do));
 }
 
 template <int CI, int CO>
-void conv_fwd_splitk(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float* b, __bf16* Y, int D, int batch) {
+void conv_fwd_splitk(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float* b, __bf16* Y, int D, int batch,
+                     hipStream_t st) {
   const int Do = D / 2, nvo = Do * Do * Do;
-  k_conv_fwd_splitk<CI, CO><<<dim3(unsigned((nvo + 15) / 16), unsigned(batch)), 256, 0, ctx->stream>>>(
+  k_conv_fwd_splitk<CI, CO><<<dim3(unsigned((nvo + 15) / 16), unsigned(batch)), 256, 0, st>>>(
       X, W, b, Y, D, make_grid3(Do));
 }
 
 // counts: label counts of the batch's input windows when the caller has them
-// (the fraction features), else counted here into net->cnt
-void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
-             const int* counts = nullptr) {
+// (the fraction features), else counted here into net->cnt; every launch on st
+void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o, const int* counts,
+             hipStream_t st) {
   const int n = net->n;
   net->lw = LabelWindow{labels, (long long)box * box * box, box, o};
   if (counts) {
     net->cnt_in = counts;
   } else {
-    k_zero_int<<<(batch * kFrac + 255) / 256, 256, 0, ctx->stream>>>(net->cnt, batch * kFrac);
-    launch_count_labels(labels, (long long)box * box * box, box, o, n, 0, batch, net->cnt, ctx->stream);
+    k_zero_int<<<(batch * kFrac + 255) / 256, 256, 0, st>>>(net->cnt, batch * kFrac);
+    launch_count_labels(labels, (long long)box * box * box, box, o, n, 0, batch, net->cnt, st);
     net->cnt_in = net->cnt;
   }
   // labels of at most four phases: the four-channel paths (fewer k-steps);
@@ -190,29 +192,30 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
     // output edges 16 and 32: the workgroup's labels and the weights staged in LDS
     const bool a8 = aligned(8);
     if (Do == 32 && a8)
-      k_conv_fwd_rows4s<32, 8, 32><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0]);
+      k_conv_fwd_rows4s<32, 8, 32><<<g1, 256, 0, st>>>(net->lw, net->WR, b0, net->a[0]);
     else if (Do == 32)
-      k_conv_fwd_rows4s<32, 2, 32><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0]);
+      k_conv_fwd_rows4s<32, 2, 32><<<g1, 256, 0, st>>>(net->lw, net->WR, b0, net->a[0]);
     else if (Do == 16 && a8)
-      k_conv_fwd_rows4s<16, 8, 32><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0]);
+      k_conv_fwd_rows4s<16, 8, 32><<<g1, 256, 0, st>>>(net->lw, net->WR, b0, net->a[0]);
     else if (Do == 16)
-      k_conv_fwd_rows4s<16, 2, 32><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0]);
+      k_conv_fwd_rows4s<16, 2, 32><<<g1, 256, 0, st>>>(net->lw, net->WR, b0, net->a[0]);
     else
-      k_conv_fwd_rows4<32, 4><<<g1, 256, 0, ctx->stream>>>(net->lw, net->WR, b0, net->a[0], make_grid3(Do));
+      k_conv_fwd_rows4<32, 4><<<g1, 256, 0, st>>>(net->lw, net->WR, b0, net->a[0], make_grid3(Do));
   } else if (net->nphase <= 4)
-    conv_fwd<4, 32, true, 4>(ctx, nullptr, net->lw, net->W4, net->p + net->boff[0], net->a[0], edge(net, 0), batch);
+    conv_fwd<4, 32, true, 4>(ctx, nullptr, net->lw, net->W4, net->p + net->boff[0], net->a[0], edge(net, 0), batch, st);
   else
-    conv_fwd<8, 32, true, 4>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch);
-  conv_fwd<32, 32, false, 4>(ctx, net->a[0], net->lw, net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch);
-  conv_fwd<32, 64, false, 2>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch);
-  conv_fwd_splitk<64, 64>(ctx, net->a[2], net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch);
+    conv_fwd<8, 32, true, 4>(ctx, nullptr, net->lw, net->W[0], net->p + net->boff[0], net->a[0], edge(net, 0), batch, st);
+  conv_fwd<32, 32, false, 4>(ctx, net->a[0], net->lw, net->W[1], net->p + net->boff[1], net->a[1], edge(net, 1), batch, st);
+  conv_fwd<32, 64, false, 2>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch, st);
+  conv_fwd_splitk<64, 64>(ctx, net->a[2], net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch, st);
   HIPCHK(hipGetLastError());
 }
 
-void head(hh_ctx* ctx, hh_net* net, int batch, const float* target, float* dA, float* dW, float* loss, float inv) {
+void head(hh_ctx* ctx, hh_net* net, int batch, const float* target, float* dA, float* dW, float* loss, float inv,
+          hipStream_t st) {
   const int V = edge(net, 3) / 2;
   const double nv = double(net->n) * net->n * net->n;
-  k_head<<<batch, 64, 0, ctx->stream>>>(net->a[3], V * V * V, net->cnt_in, 1.0 / nv, net->d_fmu, net->d_fsc,
+  k_head<<<batch, 64, 0, st>>>(net->a[3], V * V * V, net->cnt_in, 1.0 / nv, net->d_fmu, net->d_fsc,
                                         net->p + net->fcw_off, net->p + net->fcb_off, net->out, target, dA, dW, loss,
                                         inv);
 }
@@ -249,7 +252,7 @@ void conv_bwd(hh_ctx* ctx, hh_net* net, int l, const __bf16* X, int batch, float
 // loss and gradient into net->g; returns the mean squared error
 float backward(hh_ctx* ctx, hh_net* net, int batch) {
   const float inv = 1.0f / float(batch * kOut);
-  head(ctx, net, batch, net->tgt, net->ga[3], net->hw, net->loss, inv);
+  head(ctx, net, batch, net->tgt, net->ga[3], net->hw, net->loss, inv, ctx->stream);
   k_reduce_parts<<<8, 256, 0, ctx->stream>>>(net->hw, batch, kOut * kFeat + kOut, net->g + net->fcw_off);
   conv_bwd<64, 64, false>(ctx, net, 3, net->a[2], batch, net->ga[2]);
   conv_bwd<32, 64, false>(ctx, net, 2, net->a[1], batch, net->ga[1]);
@@ -290,7 +293,7 @@ void check_input(hh_ctx* ctx, hh_net* net, int batch, int box, int o) {
 }  // namespace
 
 void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
-                           double* c21, const int* counts) {
+                           double* c21, const int* counts, hipStream_t st) {
   // items per forward pass: 512 fill the grids of the small deep layers
   // (256: 5 % slower end to end; 1024: no faster)
   const int step = 512;
@@ -298,10 +301,10 @@ void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels
   for (int b0 = 0; b0 < batch; b0 += step) {
     const int nb = std::min(step, batch - b0);
     forward(ctx, net, labels + (long long)b0 * box * box * box, nb, box, o,
-            counts ? counts + (long long)b0 * kFrac : nullptr);
-    head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f);
-    k_denorm<<<(nb * kOut + 255) / 256, 256, 0, ctx->stream>>>(net->out, net->d_mean, net->d_scale, nb,
-                                                               c21 + (long long)b0 * kOut);
+            counts ? counts + (long long)b0 * kFrac : nullptr, st);
+    head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f, st);
+    k_denorm<<<(nb * kOut + 255) / 256, 256, 0, st>>>(net->out, net->d_mean, net->d_scale, nb,
+                                                      c21 + (long long)b0 * kOut);
     HIPCHK(hipGetLastError());
   }
 }
@@ -566,8 +569,8 @@ int hh_net_forward(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_o
     if (!labels || !out) fail(ctx, HH_EINVAL, "null argument");
     const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
     ensure_acts(ctx, net, batch);
-    forward(ctx, net, d, batch, box, offset);
-    head(ctx, net, batch, nullptr, nullptr, nullptr, nullptr, 0.0f);
+    forward(ctx, net, d, batch, box, offset, nullptr, ctx->stream);
+    head(ctx, net, batch, nullptr, nullptr, nullptr, nullptr, 0.0f, ctx->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(out, net->out, sizeof(float) * batch * kOut, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -583,7 +586,7 @@ int hh_net_gradient(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_
     const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
     ensure_acts(ctx, net, batch);
     HIPCHK(hipMemcpyAsync(net->tgt, target, sizeof(float) * batch * kOut, hipMemcpyHostToDevice, ctx->stream));
-    forward(ctx, net, d, batch, box, offset);
+    forward(ctx, net, d, batch, box, offset, nullptr, ctx->stream);
     const float l = backward(ctx, net, batch);
     if (loss) *loss = l;
     if (grad) {
@@ -603,7 +606,7 @@ int hh_net_train_step(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int label
     ensure_acts(ctx, net, batch);
     HIPCHK(hipMemcpyAsync(net->tgt, target, sizeof(float) * batch * kOut,
                           target_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
-    forward(ctx, net, d, batch, box, offset);
+    forward(ctx, net, d, batch, box, offset, nullptr, ctx->stream);
     const float l = backward(ctx, net, batch);
     net->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;
@@ -623,7 +626,7 @@ int hh_net_predict(hh_ctx* ctx, hh_net* net, const uint8_t* labels, int labels_o
     if (!labels || !C21) fail(ctx, HH_EINVAL, "null argument");
     const unsigned char* d = labels_to_device(ctx, labels, labels_on_device, (long long)batch * box * box * box);
     auto* c = static_cast<double*>(ws(ctx, "net_c21", sizeof(double) * batch * kOut));
-    hh_net_predict_device(ctx, net, d, batch, box, offset, c, nullptr);
+    hh_net_predict_device(ctx, net, d, batch, box, offset, c, nullptr, ctx->stream);
     HIPCHK(hipMemcpyAsync(C21, c, sizeof(double) * batch * kOut, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return HH_OK;

@@ -8,9 +8,10 @@
 // Predicted stiffness (21 components, denormalized, FP64, device) of `batch`
 // items; item i is the n^3 box at offset (o, o, o) of the box^3 labels at
 // labels + i * box^3 (device).  counts: label counts of those windows
-// ([batch][8], device), or null to count them here.
+// ([batch][8], device), or null to count them here.  Every launch goes on st
+// (the network's buffers are its own: two networks may run on two streams).
 void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
-                           double* c21, const int* counts);
+                           double* c21, const int* counts, hipStream_t st);
 // counts[i][c] = voxels with label c (< 8) in the n^3 window at offset
 // (o, o, o) of box i (box^3 labels, device).
 void hh_launch_counts(const unsigned char* labels, int nitems, int box, int o, int n, int* counts, hipStream_t st);

@@ -922,11 +922,33 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   prof.run(HH_K_OTHER, [&] {
     hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
     if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
+    // a second network runs on a lane stream of its own, concurrently with the
+    // first (each has its own buffers; one network given twice stays on st)
+    const bool two = net_b && net_b != net_a;
+    hipStream_t sb = st;
+    if (two) {
+      ensure_lanes(ctx, 1);
+      sb = ctx->aux[0].stream;
+      HIPCHK(hipEventRecord(ctx->fork, st));
+      HIPCHK(hipStreamWaitEvent(sb, ctx->fork, 0));
+    }
+    // st waits for the lane's work however this scope ends
+    struct Join {
+      hh_ctx* c;
+      hipStream_t st, sb;
+      bool on;
+      ~Join() {
+        if (on) {
+          (void)hipEventRecord(c->aux[0].e1, sb);
+          (void)hipStreamWaitEvent(st, c->aux[0].e1, 0);
+        }
+      }
+    } join{ctx, st, sb, two};
     hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a,
-                          in_a == n_sub ? d_counts : d_counts_box);
+                          in_a == n_sub ? d_counts : d_counts_box, st);
     if (net_b)
       hh_net_predict_device(ctx, net_b, d_pack, nitems, b, in_b == n_sub ? pad : 0, c21b,
-                            in_b == n_sub ? d_counts : d_counts_box);
+                            in_b == n_sub ? d_counts : d_counts_box, sb);
   });
   // Voigt and Reuss stiffness of each core's phase fractions
   std::vector<double> cp(21 * nphase), sp(21 * nphase);
