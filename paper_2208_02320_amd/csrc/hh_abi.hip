@@ -919,6 +919,8 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   auto* d_counts = static_cast<int*>(ws(ctx, "sur_counts", sizeof(int) * 8 * size_t(nitems)));
   const bool box_in = in_a != n_sub || (net_b && in_b != n_sub);
   int* d_counts_box = box_in ? static_cast<int*>(ws(ctx, "sur_counts_box", sizeof(int) * 8 * size_t(nitems))) : nullptr;
+  unsigned* d_if_core = nullptr;  // interface counts (core and box windows), where a network has their statistics
+  unsigned* d_if_box = nullptr;
   prof.run(HH_K_OTHER, [&] {
     hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
     if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
@@ -944,6 +946,16 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
         }
       }
     } join{ctx, st, sb, two};
+    // interface counts of the windows a network with texture statistics reads
+    // (only the gate needs them): on the lane, ahead of the second network
+    for (hh_net* net : {net_a, net_b}) {
+      if (!hh_net_has_interface_stats(net)) continue;
+      const bool core = hh_net_input_size(net) == n_sub;
+      unsigned*& d = core ? d_if_core : d_if_box;
+      if (d) continue;
+      d = static_cast<unsigned*>(ws(ctx, core ? "sur_iface" : "sur_iface_box", sizeof(unsigned) * size_t(nitems)));
+      hh_launch_interfaces(d_pack, nitems, b, core ? pad : 0, core ? n_sub : b, d, sb);
+    }
     hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a,
                           in_a == n_sub ? d_counts : d_counts_box, st);
     if (net_b)
@@ -981,17 +993,6 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   HIPCHK(hipMemcpyAsync(d_sp, sp.data(), sizeof(double) * 21 * nphase, hipMemcpyHostToDevice, st));
   prof.run(HH_K_OTHER, [&] {
     hh_launch_bounds(d_counts, nitems, n_sub, nphase, d_cp, d_sp, cv21, cr21, st);
-    // interface counts of the windows a network with texture statistics reads
-    unsigned* d_if_core = nullptr;
-    unsigned* d_if_box = nullptr;
-    for (hh_net* net : {net_a, net_b}) {
-      if (!hh_net_has_interface_stats(net)) continue;
-      const bool core = hh_net_input_size(net) == n_sub;
-      unsigned*& d = core ? d_if_core : d_if_box;
-      if (d) continue;
-      d = static_cast<unsigned*>(ws(ctx, core ? "sur_iface" : "sur_iface_box", sizeof(unsigned) * size_t(nitems)));
-      hh_launch_interfaces(d_pack, nitems, b, core ? pad : 0, core ? n_sub : b, d, st);
-    }
     const FracGate ga = hh_net_fraction_gate(net_a, in_a == n_sub ? d_counts : d_counts_box,
                                              in_a == n_sub ? d_if_core : d_if_box);
     const FracGate gb = hh_net_fraction_gate(net_b, in_b == n_sub ? d_counts : d_counts_box,
