@@ -58,9 +58,12 @@ def net_with(ctx, nphase, n, params, fstats=FSTATS):
 # layers on outputs of 16, 8, 4, 2 voxels per row: the x-shift path of every
 # row width (n = 64 has the network's own sizes).  Up to four phases the first
 # layer takes two labels per load where window rows start on even addresses
-# (even pad), else one (odd pad, the last case)
+# (even pad), else one (odd pad: (32, 2, 4, 3)); at n = 32 and 64 it stages
+# the workgroup's labels in LDS, in 8-byte units where box and offset are
+# multiples of 8 ((64, 1, 4, 8), (32, 2, 4, 8)), else 2-byte ones
 @pytest.mark.parametrize("n,batch,nphase,pad", [(16, 3, 3, 2), (32, 2, 4, 2), (16, 5, 8, 2), (16, 3, 4, 4),
-                                                (16, 2, 5, 8), (64, 1, 4, 8), (32, 2, 4, 3)])
+                                                (16, 2, 5, 8), (64, 1, 4, 8), (32, 2, 4, 3), (32, 2, 4, 8),
+                                                (64, 1, 4, 2)])
 def test_forward_matches_oracle(ctx, n, batch, nphase, pad):
     lab = boxes(batch, n + 2 * pad, nphase, seed=n + batch)
     p = ref.init_params(nphase, seed=7).astype(np.float32)
@@ -447,6 +450,28 @@ def test_trained_network_gains_over_the_method_without_it(ctx):
     assert err <= sub_err.max()
     for net in nets:
         net.close()
+
+
+def test_two_networks_on_two_streams_match_one_at_a_time(ctx):
+    """The two-level entry point runs the second network on a lane stream,
+    concurrently with the first: an accepted subimage's stiffness is exactly
+    the mean of the two networks' predictions made one at a time.  One
+    network given twice stays on one stream and gives its own prediction."""
+    import os
+    from paper_2208_02320_amd import hh, surrogate as sur
+    paths = sur.default_weights(64, 8)
+    if not all(os.path.exists(p) for p in paths):
+        pytest.skip("shipped weights missing")
+    na, nb = hh.Net.load(ctx, paths[0]), hh.Net.load(ctx, paths[1])
+    lab = synth.four_phase(128, seed=4)
+    boxes_ = ctx.gather_subimages(lab, 64, 8)
+    pa, pb = na.predict(boxes_, offset=8), nb.predict(boxes_, offset=8)
+    for a, b, want in ((na, nb, 0.5 * (pa + pb)), (na, na, pa)):
+        _, Cs, fb, _ = ctx.hierarchical_surrogate(lab, FOUR, 64, 8, a, b, spread_tol=0.05, bound_tol=0.0, tol=1e-6)
+        assert (~fb).sum() >= 6
+        assert np.array_equal(Cs[~fb], want[~fb])
+    na.close()
+    nb.close()
 
 
 def test_network_file_loaded_by_the_library(ctx):
