@@ -146,11 +146,20 @@ void conv_fwd(hh_ctx* ctx, const __bf16* X, const LabelWindow& lw, const __bf16*
       // workgroups of 8 waves share the layer's weights through LDS
       if (Do == 16) {
         const dim3 g2(unsigned((nvo + 128 * RB - 1) / (128 * RB)), unsigned(batch));  // 8 waves of 16 RB voxels
-        k_conv_fwd<CI, CO, LAB, RB, true, true, true><<<g2, 512, 0, st>>>(X, lw, W, b, Y, D, make_grid3(Do));
+        k_conv_fwd<CI, CO, LAB, RB, true, true, 8><<<g2, 512, 0, st>>>(X, lw, W, b, Y, D, make_grid3(Do));
         return;
       }
     }
     if (Do <= 16 && 16 % Do == 0) {
+      if constexpr (CO == 64) {
+        // 64 output channels (110 KB of weights): workgroups of 16 waves
+        // share them through LDS, where an item's output fills such a group
+        if (nvo >= 16 * 16 * RB) {
+          const dim3 g3(unsigned((nvo + 256 * RB - 1) / (256 * RB)), unsigned(batch));
+          k_conv_fwd<CI, CO, LAB, RB, true, false, 16><<<g3, 1024, 0, st>>>(X, lw, W, b, Y, D, make_grid3(Do));
+          return;
+        }
+      }
       k_conv_fwd<CI, CO, LAB, RB, true><<<grid, 256, 0, st>>>(X, lw, W, b, Y, D, make_grid3(Do));
       return;
     }

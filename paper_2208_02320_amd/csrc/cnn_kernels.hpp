@@ -347,17 +347,19 @@ __device__ __forceinline__ void store_staged(const f32x4 (&acc)[RB][NT], const f
 // are four consecutive output rows of one slice, so the ty = 0 inputs of row
 // block r are the ty = 2 inputs of row block r - 1, already in registers: 18
 // loads per tz instead of 24.
-// WL (with XS): workgroups of 8 waves; the layer's weights (27 x COUT x 32
-// BF16, 55 KB at COUT = 32) are staged once per workgroup in LDS as MFMA
-// fragments instead of every wave streaming them from L2.
+// WPB (with XS): waves per workgroup; above 4, the layer's weights
+// (27 x COUT x 32 BF16: 55 KB at COUT = 32, 110 KB at 64) are staged once
+// per workgroup in LDS as MFMA fragments instead of every wave streaming them
+// from L2 (8 waves for the second layer, two workgroups per CU; 16 for the
+// third, one).
 // LAB with CIN = 4 (networks of at most four phases): a lane's eight K values
 // are the four channels of two consecutive taps, so K = 27 x 4 takes 4 k-steps
 // instead of 7; W is then laid out [tap pair][COUT][8] (k_cast_pairs4).
 // The 32-channel-input layers are asked to fit four waves per SIMD: the
 // compiler then keeps the accumulators in VGPRs (the second layer: 119
 // registers against 136 with AGPRs, three waves per SIMD), with no spills.
-template <int CIN, int COUT, bool LAB, int RB, bool XS = false, bool YR = false, bool WL = false>
-__global__ void __launch_bounds__(WL ? 512 : 256) __attribute__((amdgpu_waves_per_eu((CIN == 32 && !LAB) ? 4 : 1))) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
+template <int CIN, int COUT, bool LAB, int RB, bool XS = false, bool YR = false, int WPB = 4>
+__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu((CIN == 32 && !LAB) ? 4 : 1))) k_conv_fwd(const __bf16* __restrict__ X, LabelWindow lw,
                                                   const __bf16* __restrict__ W, const float* __restrict__ bias,
                                                   __bf16* __restrict__ Y, int D, Grid3 go) {
   static_assert((LAB ? (CIN == 8 || CIN == 4) : CIN % 8 == 0) && COUT % 16 == 0, "channel counts");
@@ -376,7 +378,8 @@ __global__ void __launch_bounds__(WL ? 512 : 256) __attribute__((amdgpu_waves_pe
   const int nvo = go.D2 * go.D;  // output voxels per item
   const int b = blockIdx.y;      // item
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int WPB = WL ? 8 : 4;  // waves per workgroup
+  constexpr bool WL = WPB > 4;
+  constexpr int TH = 64 * WPB;  // threads per workgroup
   const int v0 = blockIdx.x * (WPB * VW) + wave * VW;
   // WL: the weights in LDS as MFMA fragments [tap][t][q][l] (16 bytes each),
   // so that a wave's fragment read is contiguous
@@ -384,18 +387,18 @@ __global__ void __launch_bounds__(WL ? 512 : 256) __attribute__((amdgpu_waves_pe
   __shared__ bf16x8 sWf[NWF];
   if constexpr (WL) {
     static_assert(XS && CIN == 32, "weights in LDS: the x-shift path");
-    constexpr int KF = (NWF + 511) / 512;
+    constexpr int KF = (NWF + TH - 1) / TH;
     bf16x8 wv[KF];
 #pragma unroll
     for (int k = 0; k < KF; ++k) {
-      const int e = threadIdx.x + k * 512;
+      const int e = threadIdx.x + k * TH;
       const int l = e % 16, qq = (e / 16) % 4, tt = (e / 64) % (COUT / 16), tap = e / (64 * (COUT / 16));
-      if (NWF % 512 == 0 || e < NWF) wv[k] = ld8(W + ((tap * COUT + tt * 16 + l) * CIN + 8 * qq));
+      if (NWF % TH == 0 || e < NWF) wv[k] = ld8(W + ((tap * COUT + tt * 16 + l) * CIN + 8 * qq));
     }
 #pragma unroll
     for (int k = 0; k < KF; ++k) {
-      const int e = threadIdx.x + k * 512;
-      if (NWF % 512 == 0 || e < NWF) sWf[e] = wv[k];
+      const int e = threadIdx.x + k * TH;
+      if (NWF % TH == 0 || e < NWF) sWf[e] = wv[k];
     }
     __syncthreads();
   }
