@@ -171,8 +171,15 @@ template <int CI, int CO>
 void conv_fwd_splitk(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float* b, __bf16* Y, int D, int batch,
                      hipStream_t st) {
   const int Do = D / 2, nvo = Do * Do * Do;
-  k_conv_fwd_splitk<CI, CO><<<dim3(unsigned((nvo + 15) / 16), unsigned(batch)), 256, 0, st>>>(
-      X, W, b, Y, D, make_grid3(Do));
+  // four row blocks per workgroup (an item's 4^3 outputs): a quarter of the
+  // weight traffic of one
+  constexpr int RB = 4;
+  if (nvo >= 16 * RB)
+    k_conv_fwd_splitk<CI, CO, RB><<<dim3(unsigned((nvo + 16 * RB - 1) / (16 * RB)), unsigned(batch)), 256, 0, st>>>(
+        X, W, b, Y, D, make_grid3(Do));
+  else
+    k_conv_fwd_splitk<CI, CO><<<dim3(unsigned((nvo + 15) / 16), unsigned(batch)), 256, 0, st>>>(
+        X, W, b, Y, D, make_grid3(Do));
 }
 
 // counts: label counts of the batch's input windows when the caller has them

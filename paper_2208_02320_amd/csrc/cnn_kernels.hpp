@@ -824,58 +824,70 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const _
                              Y + (long long)b * nvo * COUT, nvo, blockIdx.x * 256 + wave * VW, lane);
 }
 
-// Forward convolution with the K steps of one 16-voxel row block split over
+// Forward convolution with the K steps of RB 16-voxel row blocks split over
 // the 4 waves of a workgroup (for the deep layers with few voxels and long
-// K), partial sums reduced through LDS.
-template <int CIN, int COUT>
+// K): wave w takes k-steps w, w + 4, ... of every row block, so each weight
+// fragment it loads serves RB MFMAs.  The four partials of a row block are
+// summed through LDS in wave order, the same sums for every RB.
+template <int CIN, int COUT, int RB = 1>
 __global__ void __launch_bounds__(256) k_conv_fwd_splitk(const __bf16* __restrict__ X, const __bf16* __restrict__ W,
                                                          const float* __restrict__ bias, __bf16* __restrict__ Y, int D,
                                                          Grid3 go) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "channel counts");
   constexpr int KT = 27 * CIN, KS = (KT + 31) / 32, NT = COUT / 16;
-  __shared__ float red[3][NT][64][4];
+  __shared__ f32x4 red[4][RB][NT][64];
   const int nvo = go.D2 * go.D;
   const int b = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int v0 = blockIdx.x * 16;
-  const int va = v0 + (lane & 15);
-  const bool valid = va < nvo;
-  int oz, oy, ox;
-  split3(go, valid ? va : 0, oz, oy, ox);
-  const __bf16* Xb = X + (long long)b * D * D * D * CIN;
-  f32x4 acc[NT];
+  const int v0 = blockIdx.x * 16 * RB;
+  bool valid[RB];
+  int oz[RB], oy[RB], ox[RB];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < RB; ++r) {
+    const int va = v0 + r * 16 + (lane & 15);
+    valid[r] = va < nvo;
+    split3(go, valid[r] ? va : 0, oz[r], oy[r], ox[r]);
+  }
+  const __bf16* Xb = X + (long long)b * D * D * D * CIN;
+  f32x4 acc[RB][NT];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int ks = wave; ks < KS; ks += 4) {
     const int k = ks * 32 + (lane >> 4) * 8;
     const int tap = k / CIN, c0 = k % CIN;
-    bf16x8 a = zero8();
-    const int iz = 2 * oz + tap / 9 - 1, iy = 2 * oy + (tap / 3) % 3 - 1, ix = 2 * ox + tap % 3 - 1;
-    if (valid && tap < 27 && iz >= 0 && iy >= 0 && ix >= 0) a = ld8(Xb + ((iz * D + iy) * D + ix) * CIN + c0);
+    bf16x8 a[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      a[r] = zero8();
+      const int iz = 2 * oz[r] + tap / 9 - 1, iy = 2 * oy[r] + (tap / 3) % 3 - 1, ix = 2 * ox[r] + tap % 3 - 1;
+      if (valid[r] && tap < 27 && iz >= 0 && iy >= 0 && ix >= 0) a[r] = ld8(Xb + ((iz * D + iy) * D + ix) * CIN + c0);
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       bf16x8 bw = zero8();
       if (tap < 27) bw = ld8(W + (tap * COUT + t * 16 + (lane & 15)) * CIN + c0);
-      acc[t] = mfma(a, bw, acc[t]);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) acc[r][t] = mfma(a[r], bw, acc[r][t]);
     }
   }
-  if (wave > 0) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+  for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) red[wave - 1][t][lane][i] = acc[t][i];
-  }
+    for (int t = 0; t < NT; ++t) red[wave][r][t][lane] = acc[r][t];
   __syncthreads();
-  if (wave == 0) {
-    __bf16* Yb = Y + (long long)b * nvo * COUT;
+  __bf16* Yb = Y + (long long)b * nvo * COUT;
+  for (int r = wave; r < RB; r += 4) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int co = t * 16 + (lane & 15);
       const float bb = bias[co];
+      const f32x4 s0 = red[0][r][t][lane], s1 = red[1][r][t][lane], s2 = red[2][r][t][lane], s3 = red[3][r][t][lane];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float sum = acc[t][i] + red[0][t][lane][i] + red[1][t][lane][i] + red[2][t][lane][i];
-        const int v = v0 + (lane >> 4) * 4 + i;
+        const float sum = s0[i] + s1[i] + s2[i] + s3[i];
+        const int v = v0 + r * 16 + (lane >> 4) * 4 + i;
         if (v < nvo) Yb[v * COUT + co] = (__bf16)fmaxf(sum + bb, 0.0f);
       }
     }
