@@ -27,6 +27,7 @@ struct hh_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   std::map<std::string, std::pair<void*, size_t>> bufs;
+  std::map<std::string, std::pair<void*, size_t>> host_bufs;  // pinned host staging (hipHostMalloc)
   std::vector<hipEvent_t> evpool;
   hipEvent_t t0 = nullptr, t1 = nullptr;  // call timing
   hipEvent_t e0 = nullptr, e1 = nullptr;  // autotuner timing
@@ -123,6 +124,28 @@ inline void* ws(hh_ctx* ctx, const std::string& name, size_t bytes, hipStream_t 
   return p;
 }
 inline void* ws(hh_ctx* ctx, const std::string& name, size_t bytes) { return ws(ctx, name, bytes, ctx->stream); }
+
+// Pinned host buffer `name` for staging copies, grown on demand (after the
+// context's stream has drained); freed with the context.
+template <class T>
+inline T* pinned(hh_ctx* ctx, const std::string& name, size_t count) {
+  std::lock_guard<std::recursive_mutex> g(ctx->mu);
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+  auto it = ctx->host_bufs.find(name);
+  if (it != ctx->host_bufs.end() && it->second.second >= bytes) return static_cast<T*>(it->second.first);
+  if (it != ctx->host_bufs.end()) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipHostFree(it->second.first));
+    ctx->host_bufs.erase(it);
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(ctx, HH_ENOMEM, "pinned host allocation of " + std::to_string(bytes) + " bytes for " + name + " failed");
+  }
+  ctx->host_bufs[name] = {p, bytes};
+  return static_cast<T*>(p);
+}
 
 
 template <class F>

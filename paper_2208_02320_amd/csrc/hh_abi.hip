@@ -1000,22 +1000,23 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
     hh_launch_gate(c21a, c21b, cv21, cr21, nitems, spread_tol, bound_tol, ga, gb, d_flag, st);
   });
   HIPCHK(hipGetLastError());
-  std::vector<int> flag(nitems);
-  std::vector<double> ha(21 * size_t(nitems)), hb;
-  HIPCHK(hipMemcpyAsync(flag.data(), d_flag, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(ha.data(), c21a, sizeof(double) * 21 * nitems, hipMemcpyDeviceToHost, st));
-  if (net_b) {
-    hb.resize(ha.size());
-    HIPCHK(hipMemcpyAsync(hb.data(), c21b, sizeof(double) * 21 * nitems, hipMemcpyDeviceToHost, st));
-  }
+  // flags and predictions through pinned staging buffers (a pageable copy of
+  // these 0.7 MB arrays costs several times the transfer)
+  const size_t nf = 21 * size_t(nitems);
+  int* flag = pinned<int>(ctx, "sur_flag_h", size_t(nitems));
+  double* ha = pinned<double>(ctx, "sur_c21a_h", nf);
+  double* hb = net_b ? pinned<double>(ctx, "sur_c21b_h", nf) : nullptr;
+  double* field = pinned<double>(ctx, "sur_field_h", nf);
+  HIPCHK(hipMemcpyAsync(flag, d_flag, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ha, c21a, sizeof(double) * nf, hipMemcpyDeviceToHost, st));
+  if (net_b) HIPCHK(hipMemcpyAsync(hb, c21b, sizeof(double) * nf, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   prof.flush();
   // FFT solves of the gated items
   std::vector<int> fb;
   for (int i = 0; i < nitems; ++i)
     if (flag[i]) fb.push_back(i);
-  std::vector<double> field(21 * size_t(nitems));
-  for (size_t i = 0; i < field.size(); ++i) field[i] = net_b ? 0.5 * (ha[i] + hb[i]) : ha[i];
+  for (size_t i = 0; i < nf; ++i) field[i] = net_b ? 0.5 * (ha[i] + hb[i]) : ha[i];
   double vi = 0.0;
   int rc = HH_OK;
   double L[6][6];
@@ -1041,8 +1042,8 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
         for (int j = i; j < 6; ++j) field[size_t(fb[k]) * 21 + q++] = S[i * 6 + j];
     }
   }
-  if (C_sub) std::memcpy(C_sub, field.data(), sizeof(double) * field.size());
-  if (fallback) std::memcpy(fallback, flag.data(), sizeof(int) * nitems);
+  if (C_sub) std::memcpy(C_sub, field, sizeof(double) * nf);
+  if (fallback) std::memcpy(fallback, flag, sizeof(int) * nitems);
   if (single) {
     end_report(ctx, report);
     int q = 0;
@@ -1056,10 +1057,10 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
     return rc;
   }
   // level 2
-  auto* d_field = static_cast<double*>(ws(ctx, "sur_field", sizeof(double) * field.size()));
-  HIPCHK(hipMemcpyAsync(d_field, field.data(), sizeof(double) * field.size(), hipMemcpyHostToDevice, st));
-  void* cf = ws(ctx, "cfield", field.size() * (o.precision == 0 ? 4 : 8));
-  launch_convert_field(o.precision, d_field, cf, (long long)field.size(), st);
+  auto* d_field = static_cast<double*>(ws(ctx, "sur_field", sizeof(double) * nf));
+  HIPCHK(hipMemcpyAsync(d_field, field, sizeof(double) * nf, hipMemcpyHostToDevice, st));
+  void* cf = ws(ctx, "cfield", nf * (o.precision == 0 ? 4 : 8));
+  launch_convert_field(o.precision, d_field, cf, (long long)nf, st);
   HIPCHK(hipGetLastError());
   Item l2;
   l2.nx = mx;
@@ -1169,6 +1170,8 @@ void hh_release_workspace(hh_ctx* ctx) {
   clear_graphs(ctx);  // they hold the addresses of the buffers freed here
   for (auto& b : ctx->bufs) (void)hipFree(b.second.first);
   ctx->bufs.clear();
+  for (auto& b : ctx->host_bufs) (void)hipHostFree(b.second.first);
+  ctx->host_bufs.clear();
 }
 
 void hh_destroy(hh_ctx* ctx) {
