@@ -182,25 +182,37 @@ void conv_fwd_splitk(hh_ctx* ctx, const __bf16* X, const __bf16* W, const float*
         X, W, b, Y, D, make_grid3(Do));
 }
 
+// Whether every window row of lw starts on a w-aligned address.
+bool rows_aligned(const LabelWindow& lw, int n, int w) {
+  const long long step = lw.mx > 0 ? n : lw.stride;  // from one item's window to the next, along x
+  return lw.row % w == 0 && lw.plane % w == 0 && step % w == 0 &&
+         reinterpret_cast<uintptr_t>(window_base(lw, 0)) % unsigned(w) == 0;
+}
+
+// Whether the first layer reads windows of lw from LDS-staged footprints
+// (k_conv_fwd_rows4s): at most four phases, output edges 16 and 32, rows on
+// even addresses.  Image windows need it.
+bool staged_first_layer(const hh_net* net, const LabelWindow& lw) {
+  return net->nphase <= 4 && (net->n == 32 || net->n == 64) && rows_aligned(lw, net->n, 2);
+}
+
 // counts: label counts of the batch's input windows when the caller has them
 // (the fraction features), else counted here into net->cnt; every launch on st
-void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o, const int* counts,
-             hipStream_t st) {
+void forward_window(hh_ctx* ctx, hh_net* net, const LabelWindow& lw, int batch, const int* counts, hipStream_t st) {
   const int n = net->n;
-  net->lw = LabelWindow{labels, (long long)box * box * box, box, o};
+  net->lw = lw;
   if (counts) {
     net->cnt_in = counts;
   } else {
     k_zero_int<<<(batch * kFrac + 255) / 256, 256, 0, st>>>(net->cnt, batch * kFrac);
-    launch_count_labels(labels, (long long)box * box * box, box, o, n, 0, batch, net->cnt, st);
+    launch_count_labels(lw, n, 0, batch, net->cnt, st);
     net->cnt_in = net->cnt;
   }
+  if (lw.mx > 0 && !staged_first_layer(net, lw)) fail(ctx, HH_EINVAL, "internal: image windows need the staged first layer");
   // labels of at most four phases: the four-channel paths (fewer k-steps);
   // the row path loads two labels at a time and needs every window row to
   // start on an even address
-  auto aligned = [&](int w) {
-    return box % w == 0 && o % w == 0 && reinterpret_cast<uintptr_t>(labels) % unsigned(w) == 0;
-  };
+  auto aligned = [&](int w) { return rows_aligned(lw, n, w); };
   const int Do = n / 2, nvo = Do * Do * Do;
   const dim3 g1(unsigned((nvo + 255) / 256), unsigned(batch));
   const float* b0 = net->p + net->boff[0];
@@ -225,6 +237,12 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
   conv_fwd<32, 64, false, 2>(ctx, net->a[1], net->lw, net->W[2], net->p + net->boff[2], net->a[2], edge(net, 2), batch, st);
   conv_fwd_splitk<64, 64>(ctx, net->a[2], net->W[3], net->p + net->boff[3], net->a[3], edge(net, 3), batch, st);
   HIPCHK(hipGetLastError());
+}
+
+// the windows at (o, o, o) of `batch` label boxes of edge box, back to back
+void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o, const int* counts,
+             hipStream_t st) {
+  forward_window(ctx, net, box_window(labels, (long long)box * box * box, box, o), batch, counts, st);
 }
 
 void head(hh_ctx* ctx, hh_net* net, int batch, const float* target, float* dA, float* dW, float* loss, float inv,
@@ -325,9 +343,34 @@ void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels
   }
 }
 
+bool hh_net_image_input(const hh_net* net, const unsigned char* img, int nx, int ny) {
+  return net && staged_first_layer(net, image_window(img, nx, ny, net->n, 0));
+}
+
+void hh_net_predict_image(hh_ctx* ctx, hh_net* net, const unsigned char* img, int nx, int ny, int nitems,
+                          double* c21, const int* counts, hipStream_t st) {
+  const int step = 512;  // as in hh_net_predict_device
+  ensure_acts(ctx, net, std::min(step, nitems));
+  for (int b0 = 0; b0 < nitems; b0 += step) {
+    const int nb = std::min(step, nitems - b0);
+    forward_window(ctx, net, image_window(img, nx, ny, net->n, b0), nb,
+                   counts ? counts + (long long)b0 * kFrac : nullptr, st);
+    head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f, st);
+    k_denorm<<<(nb * kOut + 255) / 256, 256, 0, st>>>(net->out, net->d_mean, net->d_scale, nb,
+                                                      c21 + (long long)b0 * kOut);
+    HIPCHK(hipGetLastError());
+  }
+}
+
 void hh_launch_counts(const unsigned char* labels, int nitems, int box, int o, int n, int* counts, hipStream_t st) {
   k_zero_int<<<(nitems * 8 + 255) / 256, 256, 0, st>>>(counts, nitems * 8);
-  launch_count_labels(labels, (long long)box * box * box, box, o, n, 0, nitems, counts, st);
+  launch_count_labels(box_window(labels, (long long)box * box * box, box, o), n, 0, nitems, counts, st);
+}
+
+void hh_launch_counts_image(const unsigned char* img, int nx, int ny, int n, int nitems, int* counts,
+                            hipStream_t st) {
+  k_zero_int<<<(nitems * 8 + 255) / 256, 256, 0, st>>>(counts, nitems * 8);
+  launch_count_labels(image_window(img, nx, ny, n, 0), n, 0, nitems, counts, st);
 }
 
 void hh_launch_bounds(const int* counts, int nitems, int n, int nphase, const double* Cp21, const double* Sp21,
@@ -366,7 +409,13 @@ bool hh_net_has_interface_stats(const hh_net* net) { return net && net->isc > 0.
 void hh_launch_interfaces(const unsigned char* labels, int nitems, int box, int o, int n, unsigned* counts,
                           hipStream_t st) {
   k_zero_int<<<(nitems + 255) / 256, 256, 0, st>>>(reinterpret_cast<int*>(counts), nitems);
-  launch_count_interfaces(labels, (long long)box * box * box, box, o, n, 0, nitems, counts, st);
+  launch_count_interfaces(box_window(labels, (long long)box * box * box, box, o), n, 0, nitems, counts, st);
+}
+
+void hh_launch_interfaces_image(const unsigned char* img, int nx, int ny, int n, int nitems, unsigned* counts,
+                                hipStream_t st) {
+  k_zero_int<<<(nitems + 255) / 256, 256, 0, st>>>(reinterpret_cast<int*>(counts), nitems);
+  launch_count_interfaces(image_window(img, nx, ny, n, 0), n, 0, nitems, counts, st);
 }
 
 int hh_net_input_size(const hh_net* net) { return net ? net->n : 0; }

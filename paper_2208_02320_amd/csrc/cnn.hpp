@@ -12,9 +12,19 @@
 // (the network's buffers are its own: two networks may run on two streams).
 void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, int box, int o,
                            double* c21, const int* counts, hipStream_t st);
+// Whether the network can read its input windows straight from an image of
+// nx x ny x nz labels (device), item i being the n^3 block i in C order
+// (x fastest): at most four phases, n = 32 or 64, rows on even addresses.
+bool hh_net_image_input(const hh_net* net, const unsigned char* img, int nx, int ny);
+// As hh_net_predict_device for the nitems blocks of such an image.
+void hh_net_predict_image(hh_ctx* ctx, hh_net* net, const unsigned char* img, int nx, int ny, int nitems,
+                          double* c21, const int* counts, hipStream_t st);
 // counts[i][c] = voxels with label c (< 8) in the n^3 window at offset
 // (o, o, o) of box i (box^3 labels, device).
 void hh_launch_counts(const unsigned char* labels, int nitems, int box, int o, int n, int* counts, hipStream_t st);
+// The same for the n^3 blocks of an nx x ny x nz image (item i: block i in C order).
+void hh_launch_counts_image(const unsigned char* img, int nx, int ny, int n, int nitems, int* counts,
+                            hipStream_t st);
 // Phase fractions counts / n^3 -> Voigt and Reuss stiffness (21 components
 // each, device).  Cp21/Sp21: per phase stiffness and compliance (21
 // components, device).
@@ -41,6 +51,8 @@ bool hh_net_has_interface_stats(const hh_net* net);
 // window at offset (o, o, o) of box i (box^3 labels, device); zeroes first.
 void hh_launch_interfaces(const unsigned char* labels, int nitems, int box, int o, int n, unsigned* counts,
                           hipStream_t st);
+void hh_launch_interfaces_image(const unsigned char* img, int nx, int ny, int n, int nitems, unsigned* counts,
+                                hipStream_t st);
 void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,
                     double spread_tol, double bound_tol, const FracGate& ga, const FracGate& gb, int* flag,
                     hipStream_t st);

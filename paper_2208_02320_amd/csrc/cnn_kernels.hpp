@@ -50,18 +50,29 @@ __device__ __forceinline__ bf16x8 zero8() {
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
 // ---------------------------------------------------------------------------
-// The network input: the n^3 window at (o, o, o) of each of `batch` label
-// boxes of edge `box` (uint8, `stride` bytes apart).  The first layer reads
-// the labels and forms their one-hot code (8 channels) in registers.
+// The network input, one n^3 window of uint8 labels per item, in one of two
+// layouts:
+//   box mode: the window at (o, o, o) of each of the label boxes of edge
+//     `box`, `stride` bytes apart (rows box bytes apart, planes box^2);
+//   image mode (mx > 0): item item0 + b is the n^3 block (bz, by, bx) of one
+//     image with rows `row` and planes `plane` bytes apart, where
+//     item0 + b = (bz my + by) mx + bx.
+// The first layer reads the labels and forms their one-hot code in registers.
+// Only the label and interface counts and the LDS-staged first layer
+// (k_conv_fwd_rows4s) take image windows; every reader uses row and plane.
 // ---------------------------------------------------------------------------
 struct LabelWindow {
   const unsigned char* labels;
-  long long stride;
-  int box, o;
+  long long stride;      // box mode: bytes from one box to the next
+  int box, o;            // box mode: box edge and the window's offset in it
+  long long row, plane;  // bytes between window rows and between window planes
+  int mx, my, n, item0;  // image mode: blocks per row and column, block edge, first item
 };
-
-__device__ __forceinline__ int label_at(const LabelWindow& w, long long b, int z, int y, int x) {
-  return w.labels[b * w.stride + ((long long)(z + w.o) * w.box + (y + w.o)) * w.box + (x + w.o)];
+__host__ inline LabelWindow box_window(const unsigned char* labels, long long stride, int box, int o) {
+  return LabelWindow{labels, stride, box, o, box, (long long)box * box, 0, 0, 0, 0};
+}
+__host__ inline LabelWindow image_window(const unsigned char* img, int nx, int ny, int n, int item0) {
+  return LabelWindow{img, 0, 0, 0, nx, (long long)nx * ny, nx / n, ny / n, n, item0};
 }
 
 
@@ -78,9 +89,13 @@ __device__ __forceinline__ void split3(const Grid3& g, int v, int& z, int& y, in
   x = r - y * g.D;
 }
 
-// labels of item b as a base pointer at window origin (o, o, o)
-__device__ __forceinline__ const unsigned char* window_base(const LabelWindow& w, int b) {
-  return w.labels + (long long)b * w.stride + ((long long)w.o * w.box + w.o) * w.box + w.o;
+// labels of item b as a base pointer at its window's origin
+__host__ __device__ __forceinline__ const unsigned char* window_base(const LabelWindow& w, int b) {
+  if (w.mx > 0) {
+    const int i = w.item0 + b, bx = i % w.mx, by = (i / w.mx) % w.my, bz = i / (w.mx * w.my);
+    return w.labels + (long long)bz * w.n * w.plane + (long long)by * w.n * w.row + (long long)bx * w.n;
+  }
+  return w.labels + (long long)b * w.stride + w.o * w.plane + w.o * w.row + w.o;
 }
 
 typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
@@ -124,7 +139,7 @@ __global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, floa
   for (int t = threadIdx.x; t < tasks; t += 256) {
     const int rl = fdiv(t, cw, inv_cw), k = t - rl * cw;
     const int r = r0 + rl, z = fdiv(r, n, inv_n), y = r - z * n;
-    const CT v = *reinterpret_cast<const CT*>(base + (z * w.box + y) * w.box + k * W);
+    const CT v = *reinterpret_cast<const CT*>(base + z * w.plane + y * w.row + k * W);
     unsigned nib = 0u;
 #pragma unroll
     for (int j = 0; j < W; ++j) nib += unsigned(1ull << (4u * min(chunk_byte(v, j), 8u)));
@@ -151,13 +166,11 @@ __global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, floa
   if (threadIdx.x < 8 && s[threadIdx.x]) atomicAdd(&cnt[b * 8 + threadIdx.x], s[threadIdx.x]);
 }
 
-// cnt[item0 .. item0 + nitems) += label counts of the n^3 windows at (o, o, o)
-// of the box^3 label boxes; the caller zeroes cnt.
-inline void launch_count_labels(const unsigned char* labels, long long stride, int box, int o, int n, int item0,
-                                int nitems, int* cnt, hipStream_t st) {
-  const LabelWindow lw{labels, stride, box, o};
-  const unsigned char* first = labels + ((long long)o * box + o) * box + o;
-  const int W = chunk_width({stride, (long long)box, (long long)n}, first, first);
+// cnt[item0 .. item0 + nitems) += label counts of the n^3 windows of lw
+// (items item0 ...); the caller zeroes cnt.
+inline void launch_count_labels(const LabelWindow& lw, int n, int item0, int nitems, int* cnt, hipStream_t st) {
+  const unsigned char* first = window_base(lw, 0);
+  const int W = chunk_width({lw.mx > 0 ? (long long)n : lw.stride, lw.row, lw.plane, (long long)n}, first, first);
   const int cw = n / W, rows = count_rows_per_block(n);
   const unsigned gx = unsigned((n * n + rows - 1) / rows);
   const float inv_n = 1.0f / float(n), inv_cw = 1.0f / float(cw);
@@ -195,12 +208,12 @@ __global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, 
   const int r0 = blockIdx.x * rows, nr = min(rows, n * n - r0);
   const unsigned char* base = window_base(w, b);
   const int tasks = nr * cw;
-  const long long plane = (long long)w.box * w.box;
+  const long long plane = w.plane;
   unsigned c = 0u;
   for (int t = threadIdx.x; t < tasks; t += 256) {
     const int rl = fdiv(t, cw, inv_cw), k = t - rl * cw;
     const int r = r0 + rl, z = fdiv(r, n, inv_n), y = r - z * n;
-    const unsigned char* p = base + (z * w.box + y) * w.box + k * W;
+    const unsigned char* p = base + z * w.plane + y * w.row + k * W;
     const CT v = *reinterpret_cast<const CT*>(p);
     if constexpr (W == 8) {
       // whole words: bytes that differ are the nonzero bytes of an XOR
@@ -208,7 +221,7 @@ __global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, 
       const unsigned long long nxt = k + 1 < cw ? (unsigned long long)p[W] : (a >> 56);  // no pair past the row end
       c += nonzero_bytes(a ^ ((a >> 8) | (nxt << 56)));
       if (y + 1 < n) {
-        const uint2 u = *reinterpret_cast<const uint2*>(p + w.box);
+        const uint2 u = *reinterpret_cast<const uint2*>(p + w.row);
         c += nonzero_bytes(a ^ ((unsigned long long)u.x | ((unsigned long long)u.y << 32)));
       }
       if (z + 1 < n) {
@@ -220,7 +233,7 @@ __global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, 
       for (int j = 0; j + 1 < W; ++j) c += chunk_byte(v, j) != chunk_byte(v, j + 1);
       if (k + 1 < cw) c += chunk_byte(v, W - 1) != unsigned(p[W]);
       if (y + 1 < n) {
-        const CT u = *reinterpret_cast<const CT*>(p + w.box);
+        const CT u = *reinterpret_cast<const CT*>(p + w.row);
 #pragma unroll
         for (int j = 0; j < W; ++j) c += chunk_byte(v, j) != chunk_byte(u, j);
       }
@@ -240,13 +253,12 @@ __global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, 
   if (threadIdx.x == 0 && s) atomicAdd(&cnt[b], s);
 }
 
-// cnt[item0 .. item0 + nitems) += interface counts of the n^3 windows at
-// (o, o, o) of the box^3 label boxes; the caller zeroes cnt.
-inline void launch_count_interfaces(const unsigned char* labels, long long stride, int box, int o, int n, int item0,
-                                    int nitems, unsigned* cnt, hipStream_t st) {
-  const LabelWindow lw{labels, stride, box, o};
-  const unsigned char* first = labels + ((long long)o * box + o) * box + o;
-  const int W = chunk_width({stride, (long long)box, (long long)n}, first, first);
+// cnt[item0 .. item0 + nitems) += interface counts of the n^3 windows of lw
+// (items item0 ...); the caller zeroes cnt.
+inline void launch_count_interfaces(const LabelWindow& lw, int n, int item0, int nitems, unsigned* cnt,
+                                    hipStream_t st) {
+  const unsigned char* first = window_base(lw, 0);
+  const int W = chunk_width({lw.mx > 0 ? (long long)n : lw.stride, lw.row, lw.plane, (long long)n}, first, first);
   const int cw = n / W, rows = count_rows_per_block(n);
   const unsigned gx = unsigned((n * n + rows - 1) / rows);
   const float inv_n = 1.0f / float(n), inv_cw = 1.0f / float(cw);
@@ -746,7 +758,6 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const _
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, q = lane >> 4;
   const int oz = blockIdx.x / (DO / R), oy0 = (blockIdx.x % (DO / R)) * R;
   const unsigned char* Lb = window_base(lw, b);
-  const long long rs = lw.box;
   // every global load first, then the LDS writes
   Unit lv[KU];
 #pragma unroll
@@ -756,7 +767,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const _
     const int z = 2 * oz - 1 + zz, y = 2 * oy0 - 1 + yy;
     lv[k] = kFour;
     if ((NU % 256 == 0 || u < NU) && z >= 0 && y >= 0)
-      lv[k] = *reinterpret_cast<const Unit*>(Lb + (z * rs + y) * rs + c * W);
+      lv[k] = *reinterpret_cast<const Unit*>(Lb + z * lw.plane + y * lw.row + c * W);
   }
   bf16x8 wv[KW];
 #pragma unroll

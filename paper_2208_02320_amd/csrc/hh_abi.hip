@@ -909,9 +909,18 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   const hipStream_t st = ctx->stream;
   const unsigned char* d_img = device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "image");
   const long long box = (long long)b * b * b;
-  auto* d_pack = static_cast<unsigned char*>(ws(ctx, "pack", size_t(box * nitems)));
   Profile prof{ctx, o.profile != 0, {}, 0, report};
-  prof.run(HH_K_SETUP, [&] { launch_gather_pad(d_img, nx, ny, nz, n_sub, pad, d_pack, st); });
+  // Networks that read the cores take them straight from the image (its
+  // blocks are the cores); the padded boxes are then gathered only when the
+  // gate sends items to the FFT solver.
+  const bool image_in = in_a == n_sub && (!net_b || in_b == n_sub) && hh_net_image_input(net_a, d_img, nx, ny) &&
+                        (!net_b || hh_net_image_input(net_b, d_img, nx, ny));
+  unsigned char* d_pack = nullptr;
+  auto gather = [&] {
+    d_pack = static_cast<unsigned char*>(ws(ctx, "pack", size_t(box * nitems)));
+    prof.run(HH_K_SETUP, [&] { launch_gather_pad(d_img, nx, ny, nz, n_sub, pad, d_pack, st); });
+  };
+  if (!image_in) gather();
   // label counts of the cores (bounds, core-input networks) and, for a
   // network that reads the whole box, of the boxes; then the predictions
   auto* c21a = static_cast<double*>(ws(ctx, "sur_c21a", sizeof(double) * 21 * nitems));
@@ -922,7 +931,10 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   unsigned* d_if_core = nullptr;  // interface counts (core and box windows), where a network has their statistics
   unsigned* d_if_box = nullptr;
   prof.run(HH_K_OTHER, [&] {
-    hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
+    if (image_in)
+      hh_launch_counts_image(d_img, nx, ny, n_sub, nitems, d_counts, st);
+    else
+      hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
     if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
     // a second network runs on a lane stream of its own, concurrently with the
     // first (each has its own buffers; one network given twice stays on st)
@@ -954,13 +966,21 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
       unsigned*& d = core ? d_if_core : d_if_box;
       if (d) continue;
       d = static_cast<unsigned*>(ws(ctx, core ? "sur_iface" : "sur_iface_box", sizeof(unsigned) * size_t(nitems)));
-      hh_launch_interfaces(d_pack, nitems, b, core ? pad : 0, core ? n_sub : b, d, sb);
+      if (image_in)
+        hh_launch_interfaces_image(d_img, nx, ny, n_sub, nitems, d, sb);
+      else
+        hh_launch_interfaces(d_pack, nitems, b, core ? pad : 0, core ? n_sub : b, d, sb);
     }
-    hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a,
-                          in_a == n_sub ? d_counts : d_counts_box, st);
-    if (net_b)
-      hh_net_predict_device(ctx, net_b, d_pack, nitems, b, in_b == n_sub ? pad : 0, c21b,
-                            in_b == n_sub ? d_counts : d_counts_box, sb);
+    if (image_in) {
+      hh_net_predict_image(ctx, net_a, d_img, nx, ny, nitems, c21a, d_counts, st);
+      if (net_b) hh_net_predict_image(ctx, net_b, d_img, nx, ny, nitems, c21b, d_counts, sb);
+    } else {
+      hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a,
+                            in_a == n_sub ? d_counts : d_counts_box, st);
+      if (net_b)
+        hh_net_predict_device(ctx, net_b, d_pack, nitems, b, in_b == n_sub ? pad : 0, c21b,
+                              in_b == n_sub ? d_counts : d_counts_box, sb);
+    }
   });
   // Voigt and Reuss stiffness of each core's phase fractions
   std::vector<double> cp(21 * nphase), sp(21 * nphase);
@@ -1022,6 +1042,7 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   double L[6][6];
   unit_loads(L);
   if (!fb.empty()) {
+    if (!d_pack) gather();
     std::vector<Item> items(fb.size());
     for (size_t k = 0; k < fb.size(); ++k) {
       Item& it = items[k];

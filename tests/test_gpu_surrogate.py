@@ -233,6 +233,46 @@ def test_total_fallback_equals_plain_hierarchy(ctx):
         assert g.rel_error(hier.from21(Cs[i]), hier.from21(Csp[i])) < 1e-6, i
 
 
+def test_total_fallback_from_image_windows(ctx):
+    """Networks of 32^3 cores read them straight from the image; the padded
+    boxes are gathered only for the FFT fallback, here of every item."""
+    lab = synth.four_phase(64, seed=10)
+    n, pad = 32, 8
+    CV, _ = sg.core_bounds(lab, 0, 64, FOUR)
+    net = constant_net(ctx, 4, n, hier.to21(2.0 * CV))
+    C, Cs, fb, _ = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=0.0, tol=1e-6)
+    Cp, Csp, _ = ctx.hierarchical(lab, FOUR, n, pad, tol=1e-6)
+    assert fb.all()
+    assert g.rel_error(C, Cp) < 1e-6
+    for i in range(len(fb)):
+        assert g.rel_error(hier.from21(Cs[i]), hier.from21(Csp[i])) < 1e-6, i
+
+
+def test_networks_read_the_image_or_the_gathered_boxes_alike(ctx):
+    """The same image on the device twice: rows on even addresses (the
+    networks, label and interface counts read the cores from the image) and
+    one byte off (they read the gathered padded boxes).  Flags, subimage
+    stiffness and C* are identical."""
+    import os
+    import torch
+    from paper_2208_02320_amd import hh, surrogate as sur
+    paths = sur.default_weights(64, 8)
+    if not all(os.path.exists(p) for p in paths):
+        pytest.skip("shipped weights missing")
+    na, nb = hh.Net.load(ctx, paths[0]), hh.Net.load(ctx, paths[1])
+    lab = synth.four_phase(128, seed=6)
+    even = torch.from_numpy(lab).cuda()
+    base = torch.zeros(lab.size + 1, dtype=torch.uint8, device="cuda")
+    odd = base[1:].view(lab.shape)
+    odd.copy_(even)
+    for tol in (0.05, 0.003):  # the second sends every item to the FFT solver
+        C1, Cs1, fb1, _ = ctx.hierarchical_surrogate(even, FOUR, 64, 8, na, nb, spread_tol=tol, bound_tol=0.0, tol=1e-6)
+        C2, Cs2, fb2, _ = ctx.hierarchical_surrogate(odd, FOUR, 64, 8, na, nb, spread_tol=tol, bound_tol=0.0, tol=1e-6)
+        assert np.array_equal(fb1, fb2) and np.array_equal(Cs1, Cs2) and np.array_equal(C1, C2), tol
+    na.close()
+    nb.close()
+
+
 def test_gate_and_fallback_match_oracle(ctx):
     lab = synth.four_phase(64, seed=4)
     n, pad = 16, 4
