@@ -805,9 +805,11 @@ void fill_item_report(hh_report* rep, const GroupResult& r, int item) {
 }
 
 // Labels to the device (copy when on host) and check them against nphase.
+// check_device = false leaves labels already on the device unchecked: the
+// caller then checks them itself before anything indexes a phase table.
 const unsigned char* device_labels(hh_ctx* ctx, const uint8_t* labels, long long bytes, bool on_device,
                                    const std::vector<long long>& off, const std::vector<long long>& cnt,
-                                   const std::vector<int>& nphase, const char* bufname) {
+                                   const std::vector<int>& nphase, const char* bufname, bool check_device = true) {
   const unsigned char* d = nullptr;
   const int n = int(off.size());
   if (!on_device) {
@@ -820,6 +822,8 @@ const unsigned char* device_labels(hh_ctx* ctx, const uint8_t* labels, long long
     auto* buf = static_cast<unsigned char*>(ws(ctx, bufname, size_t(bytes)));
     HIPCHK(hipMemcpyAsync(buf, labels, size_t(bytes), hipMemcpyHostToDevice, ctx->stream));
     d = buf;
+  } else if (!check_device) {
+    d = labels;
   } else {
     d = labels;
     auto* d_off = static_cast<long long*>(ws(ctx, "lm_off", sizeof(long long) * n));
@@ -907,7 +911,10 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   const int nitems = mx * my * mz;
   begin_report(ctx, report);
   const hipStream_t st = ctx->stream;
-  const unsigned char* d_img = device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "image");
+  // device labels are checked from the cores' label counts below (the cores
+  // tile the image), not by a pass of their own
+  const unsigned char* d_img =
+      device_labels(ctx, labels, nvox, labels_on_device != 0, {0}, {nvox}, {nphase}, "image", false);
   const long long box = (long long)b * b * b;
   Profile prof{ctx, o.profile != 0, {}, 0, report};
   // Networks that read the cores take them straight from the image (its
@@ -1027,11 +1034,28 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   double* ha = pinned<double>(ctx, "sur_c21a_h", nf);
   double* hb = net_b ? pinned<double>(ctx, "sur_c21b_h", nf) : nullptr;
   double* field = pinned<double>(ctx, "sur_field_h", nf);
+  int* hc = labels_on_device ? pinned<int>(ctx, "sur_counts_h", 8 * size_t(nitems)) : nullptr;
   HIPCHK(hipMemcpyAsync(flag, d_flag, sizeof(int) * nitems, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(ha, c21a, sizeof(double) * nf, hipMemcpyDeviceToHost, st));
   if (net_b) HIPCHK(hipMemcpyAsync(hb, c21b, sizeof(double) * nf, hipMemcpyDeviceToHost, st));
+  if (hc) HIPCHK(hipMemcpyAsync(hc, d_counts, sizeof(int) * 8 * nitems, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   prof.flush();
+  // labels >= nphase (device input): every voxel lies in exactly one core; a
+  // label below 8 shows in its count, and a core whose counts sum to less than
+  // n_sub^3 holds a label of 8 or more
+  if (hc) {
+    const long long nc = (long long)n_sub * n_sub * n_sub;
+    for (int i = 0; i < nitems; ++i) {
+      long long sum = 0;
+      for (int c = 0; c < 8; ++c) {
+        sum += hc[8 * i + c];
+        if (c >= nphase && hc[8 * i + c] > 0)
+          fail(ctx, HH_EINVAL, "label " + std::to_string(c) + " >= nphase in subimage " + std::to_string(i));
+      }
+      if (sum != nc) fail(ctx, HH_EINVAL, "a label of 8 or more (>= nphase) in subimage " + std::to_string(i));
+    }
+  }
   // FFT solves of the gated items
   std::vector<int> fb;
   for (int i = 0; i < nitems; ++i)

@@ -248,6 +248,34 @@ def test_total_fallback_from_image_windows(ctx):
         assert g.rel_error(hier.from21(Cs[i]), hier.from21(Csp[i])) < 1e-6, i
 
 
+@pytest.mark.parametrize("start", [0, 1])
+def test_surrogate_device_label_check(ctx, start):
+    """Device labels of the two-level entry point are checked from the cores'
+    label counts (the cores tile the image): a label in 4..7 is named, one of
+    8 or more is reported as such, on image windows (start 0) and on gathered
+    boxes (start 1)."""
+    import torch
+    from paper_2208_02320_amd import hh
+    lab = synth.four_phase(64, seed=12)
+    n, pad = 32, 8
+    CV, CR = sg.core_bounds(lab, 0, 64, FOUR)
+    net = constant_net(ctx, 4, n, hier.to21(0.5 * (CV + CR)))
+    base = torch.zeros(start + lab.size, dtype=torch.uint8, device="cuda")
+    d = base[start:].view(lab.shape)
+    d.copy_(torch.from_numpy(lab))
+    want = ctx.hierarchical_surrogate(lab, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=1.0, tol=1e-6)[0]
+    got = ctx.hierarchical_surrogate(d, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=1.0, tol=1e-6)[0]
+    assert np.array_equal(got, want)
+    for (z, y, x), bad, text in (((40, 3, 50), 5, "label 5 >= nphase in subimage 5"),
+                                 ((1, 60, 2), 200, "8 or more")):
+        d[z, y, x] = bad
+        with pytest.raises(hh.HHError) as e:
+            ctx.hierarchical_surrogate(d, FOUR, n, pad, net, None, spread_tol=0.05, bound_tol=1.0, tol=1e-6)
+        assert e.value.code == -1 and text in str(e.value), str(e.value)
+        d[z, y, x] = int(lab[z, y, x])
+    net.close()
+
+
 def test_networks_read_the_image_or_the_gathered_boxes_alike(ctx):
     """The same image on the device twice: rows on even addresses (the
     networks, label and interface counts read the cores from the image) and
