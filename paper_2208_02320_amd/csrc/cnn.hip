@@ -348,13 +348,14 @@ bool hh_net_image_input(const hh_net* net, const unsigned char* img, int nx, int
 }
 
 void hh_net_predict_image(hh_ctx* ctx, hh_net* net, const unsigned char* img, int nx, int ny, int nitems,
-                          double* c21, const int* counts, hipStream_t st) {
+                          double* c21, const int* counts, hipStream_t st, hipEvent_t counts_ready) {
   const int step = 512;  // as in hh_net_predict_device
   ensure_acts(ctx, net, std::min(step, nitems));
   for (int b0 = 0; b0 < nitems; b0 += step) {
     const int nb = std::min(step, nitems - b0);
     forward_window(ctx, net, image_window(img, nx, ny, net->n, b0), nb,
                    counts ? counts + (long long)b0 * kFrac : nullptr, st);
+    if (b0 == 0 && counts_ready) HIPCHK(hipStreamWaitEvent(st, counts_ready, 0));
     head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f, st);
     k_denorm<<<(nb * kOut + 255) / 256, 256, 0, st>>>(net->out, net->d_mean, net->d_scale, nb,
                                                       c21 + (long long)b0 * kOut);

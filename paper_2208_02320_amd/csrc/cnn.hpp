@@ -16,9 +16,11 @@ void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels
 // nx x ny x nz labels (device), item i being the n^3 block i in C order
 // (x fastest): at most four phases, n = 32 or 64, rows on even addresses.
 bool hh_net_image_input(const hh_net* net, const unsigned char* img, int nx, int ny);
-// As hh_net_predict_device for the nitems blocks of such an image.
+// As hh_net_predict_device for the nitems blocks of such an image; with
+// counts given, st waits for counts_ready (when not null) before the first
+// head reads them.
 void hh_net_predict_image(hh_ctx* ctx, hh_net* net, const unsigned char* img, int nx, int ny, int nitems,
-                          double* c21, const int* counts, hipStream_t st);
+                          double* c21, const int* counts, hipStream_t st, hipEvent_t counts_ready);
 // counts[i][c] = voxels with label c (< 8) in the n^3 window at offset
 // (o, o, o) of box i (box^3 labels, device).
 void hh_launch_counts(const unsigned char* labels, int nitems, int box, int o, int n, int* counts, hipStream_t st);

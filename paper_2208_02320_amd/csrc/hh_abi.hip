@@ -929,7 +929,7 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   };
   if (!image_in) gather();
   // label counts of the cores (bounds, core-input networks) and, for a
-  // network that reads the whole box, of the boxes; then the predictions
+  // network that reads the whole box, of the boxes; the predictions
   auto* c21a = static_cast<double*>(ws(ctx, "sur_c21a", sizeof(double) * 21 * nitems));
   double* c21b = net_b ? static_cast<double*>(ws(ctx, "sur_c21b", sizeof(double) * 21 * nitems)) : nullptr;
   auto* d_counts = static_cast<int*>(ws(ctx, "sur_counts", sizeof(int) * 8 * size_t(nitems)));
@@ -938,11 +938,6 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
   unsigned* d_if_core = nullptr;  // interface counts (core and box windows), where a network has their statistics
   unsigned* d_if_box = nullptr;
   prof.run(HH_K_OTHER, [&] {
-    if (image_in)
-      hh_launch_counts_image(d_img, nx, ny, n_sub, nitems, d_counts, st);
-    else
-      hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
-    if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
     // a second network runs on a lane stream of its own, concurrently with the
     // first (each has its own buffers; one network given twice stays on st)
     const bool two = net_b && net_b != net_a;
@@ -965,6 +960,20 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
         }
       }
     } join{ctx, st, sb, two};
+    // label counts of the cores (the heads' fraction features, the bounds):
+    // with two networks on image windows, on the lane, and the first network
+    // waits for them only before its first head
+    const bool counts_on_lane = two && image_in;
+    hipEvent_t counts_ready = nullptr;
+    if (image_in)
+      hh_launch_counts_image(d_img, nx, ny, n_sub, nitems, d_counts, counts_on_lane ? sb : st);
+    else
+      hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
+    if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
+    if (counts_on_lane) {
+      counts_ready = ctx->aux[0].e0;
+      HIPCHK(hipEventRecord(counts_ready, sb));
+    }
     // interface counts of the windows a network with texture statistics reads
     // (only the gate needs them): on the lane, ahead of the second network
     for (hh_net* net : {net_a, net_b}) {
@@ -979,8 +988,8 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
         hh_launch_interfaces(d_pack, nitems, b, core ? pad : 0, core ? n_sub : b, d, sb);
     }
     if (image_in) {
-      hh_net_predict_image(ctx, net_a, d_img, nx, ny, nitems, c21a, d_counts, st);
-      if (net_b) hh_net_predict_image(ctx, net_b, d_img, nx, ny, nitems, c21b, d_counts, sb);
+      hh_net_predict_image(ctx, net_a, d_img, nx, ny, nitems, c21a, d_counts, st, counts_ready);
+      if (net_b) hh_net_predict_image(ctx, net_b, d_img, nx, ny, nitems, c21b, d_counts, sb, nullptr);
     } else {
       hh_net_predict_device(ctx, net_a, d_pack, nitems, b, in_a == n_sub ? pad : 0, c21a,
                             in_a == n_sub ? d_counts : d_counts_box, st);
