@@ -130,7 +130,7 @@ void cast_all(hh_ctx* ctx, hh_net* net) {
   for (int l = 0; l < kLayers; ++l)
     k_cast_weights<<<256, 256, 0, ctx->stream>>>(net->p + net->woff[l], kCin[l], kCout[l], net->W[l], net->Wt[l]);
   k_cast_pairs4<<<16, 256, 0, ctx->stream>>>(net->p + net->woff[0], kCout[0], net->W4);
-  k_cast_rows4<<<20, 256, 0, ctx->stream>>>(net->p + net->woff[0], kCout[0], net->WR);
+  k_cast_rows4<<<20, 256, 0, ctx->stream>>>(net->p + net->woff[0], net->p + net->boff[0], kCout[0], net->WR);
   HIPCHK(hipGetLastError());
 }
 

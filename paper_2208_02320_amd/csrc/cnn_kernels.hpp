@@ -297,20 +297,24 @@ __device__ __forceinline__ bf16x8 from_left_lane(bf16x8 v) {
 }
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-// bias, BF16 and ReLU of four output channels.  The ReLU acts on the BF16
-// bit patterns: a value with its sign bit set is a negative 16-bit integer,
-// so a packed integer max with 0 clears it (rounding keeps the sign, so this
+// BF16 and ReLU of four output channels.  The ReLU acts on the BF16 bit
+// patterns: a value with its sign bit set is a negative 16-bit integer, so a
+// packed integer max with 0 clears it (rounding keeps the sign, so this
 // equals rounding after the ReLU)
-__device__ __forceinline__ bf16x4 bias_relu4(const f32x4& a, const float4& bb) {
+__device__ __forceinline__ bf16x4 relu4(const f32x4& a) {
   typedef float f32x2 __attribute__((ext_vector_type(2)));
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
   typedef short i16x2 __attribute__((ext_vector_type(2)));
-  const bf16x2 lo = __builtin_convertvector(f32x2{a[0] + bb.x, a[1] + bb.y}, bf16x2);
-  const bf16x2 hi = __builtin_convertvector(f32x2{a[2] + bb.z, a[3] + bb.w}, bf16x2);
+  const bf16x2 lo = __builtin_convertvector(f32x2{a[0], a[1]}, bf16x2);
+  const bf16x2 hi = __builtin_convertvector(f32x2{a[2], a[3]}, bf16x2);
   const i16x2 l = __builtin_elementwise_max(__builtin_bit_cast(i16x2, lo), i16x2{0, 0});
   const i16x2 h = __builtin_elementwise_max(__builtin_bit_cast(i16x2, hi), i16x2{0, 0});
   const bf16x2 lr = __builtin_bit_cast(bf16x2, l), hr = __builtin_bit_cast(bf16x2, h);
   return bf16x4{lr[0], lr[1], hr[0], hr[1]};
+}
+// bias, BF16 and ReLU
+__device__ __forceinline__ bf16x4 bias_relu4(const f32x4& a, const float4& bb) {
+  return relu4(f32x4{a[0] + bb.x, a[1] + bb.y, a[2] + bb.z, a[3] + bb.w});
 }
 
 // A wave's RB x NT accumulator tiles (D = W x X^T, so lane l holds channels
@@ -320,7 +324,8 @@ __device__ __forceinline__ bf16x4 bias_relu4(const f32x4& a, const float4& bb) {
 // In the tile, 16-byte chunk j of voxel v sits at chunk j ^ ((v / 4) % CV)
 // of its row (CV chunks per voxel): the 16 lanes of a row block, whose
 // voxels' rows lie 64 bytes apart, then write 16 different banks.
-template <int RB, int NT, int COUT>
+// ADD_BIAS false: the accumulators already hold the bias (bias unused).
+template <int RB, int NT, int COUT, bool ADD_BIAS = true>
 __device__ __forceinline__ void store_staged(const f32x4 (&acc)[RB][NT], const float* __restrict__ bias, __bf16* so,
                                              __bf16* __restrict__ Yb, int nvo, int v0, int lane) {
   constexpr int VW = 16 * RB, CV = COUT / 8;  // chunks per voxel
@@ -329,12 +334,13 @@ __device__ __forceinline__ void store_staged(const f32x4 (&acc)[RB][NT], const f
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int co = t * 16 + 4 * q;  // four channels: half (co / 4) % 2 of chunk co / 8
-    const float4 bb = *reinterpret_cast<const float4*>(bias + co);
+    float4 bb = float4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (ADD_BIAS) bb = *reinterpret_cast<const float4*>(bias + co);
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int v = r * 16 + l;
       const int sw = ((co / 8) ^ ((v >> 2) & (CV - 1))) * 8 + (co & 7);
-      *reinterpret_cast<bf16x4*>(so + v * COUT + sw) = bias_relu4(acc[r][t], bb);
+      *reinterpret_cast<bf16x4*>(so + v * COUT + sw) = ADD_BIAS ? bias_relu4(acc[r][t], bb) : relu4(acc[r][t]);
     }
   }
   __syncthreads();
@@ -609,19 +615,23 @@ __global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu((
 }
 
 // One-hot codes of two labels a, c in 0..4 (4: the zero code) as one 16-byte
-// LDS entry 5 a + c, a in channels 0-3 and c in channels 4-7 (25 entries).
-constexpr int kPairs = 25;
+// LDS entry 5 a + c, a in channels 0-3 and c in channels 4-7 (25 entries),
+// and entry 25, ones in channels 0 and 1: the input of the bias slot.
+constexpr int kPairs = 26;
 __device__ __forceinline__ void fill_pairs(bf16x8* t) {
   if (threadIdx.x < kPairs) {
     const bf16x4v lo = onehot4(threadIdx.x / 5), hi = onehot4(threadIdx.x % 5);
-    t[threadIdx.x] = bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    const __bf16 one = (__bf16)1.0f, z = (__bf16)0.0f;
+    t[threadIdx.x] = threadIdx.x < 25 ? bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]}
+                                      : bf16x8{one, one, z, z, z, z, z, z};
   }
 }
-// the entry of labels a | c << 16 (each clamped to 4 first)
-__device__ __forceinline__ bf16x8 pair_code(const bf16x8* t, unsigned ac) {
+// the entry of labels a | c << 16 (each clamped to 4 first), plus `skip`
+// bytes (16: from the zero pair (4, 4) to the bias entry)
+__device__ __forceinline__ bf16x8 pair_code(const bf16x8* t, unsigned ac, unsigned skip = 0u) {
   typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
   const u16x2 p = __builtin_elementwise_min(__builtin_bit_cast(u16x2, ac), u16x2{4, 4});
-  const unsigned e = __builtin_amdgcn_udot2(p, u16x2{80, 16}, 0u, false);  // 16 (5 a + c)
+  const unsigned e = __builtin_amdgcn_udot2(p, u16x2{80, 16}, skip, false);  // 16 (5 a + c) + skip
   return *reinterpret_cast<const bf16x8*>(reinterpret_cast<const unsigned char*>(t) + e);
 }
 
@@ -735,7 +745,7 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4(LabelWindow lw, const __
 // the zero code, so no tap needs an edge test; a fourth plane of 4s serves
 // the empty row 9.
 template <int DO, int W, int COUT>
-__global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const __bf16* __restrict__ Wr,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_conv_fwd_rows4s(LabelWindow lw, const __bf16* __restrict__ Wr,
                                                          const float* __restrict__ bias, __bf16* __restrict__ Y) {
   static_assert(256 % DO == 0 && DO % 16 == 0 && (W == 2 || W == 8) && COUT % 16 == 0, "shapes");
   constexpr int RB = 4, KS = 5, NT = COUT / 16, VW = 16 * RB;
@@ -809,9 +819,13 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const _
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) roff[ks] = qhi ? row_off(2 * ks + 1) : row_off(2 * ks);
   const unsigned psel = h1 ? 0x0C040C01u : 0x0C010C00u;
+  // slot 19 (k-step 4, q = 3) reads the zero pair of the plane of 4s and
+  // takes the bias entry instead: WR's slot 19 holds the bias (high and low
+  // BF16 parts), so the MFMAs add it
+  const unsigned bias_skip = q == 3 ? 16u : 0u;
   auto onehot_pair = [&](int ks, int r) -> bf16x8 {
     const unsigned w = *reinterpret_cast<const unsigned short*>(sLab + lb[r] + roff[ks]);
-    return pair_code(sPair, __builtin_amdgcn_perm(4u, w, psel));
+    return pair_code(sPair, __builtin_amdgcn_perm(4u, w, psel), ks == KS - 1 ? bias_skip : 0u);
   };
   f32x4 acc[RB][NT];
 #pragma unroll
@@ -831,8 +845,8 @@ __global__ void __launch_bounds__(256) k_conv_fwd_rows4s(LabelWindow lw, const _
       for (int t = 0; t < NT; ++t) acc[r][t] = mfma(bw[t], a[r], acc[r][t]);
   }
   __syncthreads();  // every wave is done with the staged inputs
-  store_staged<RB, NT, COUT>(acc, bias, reinterpret_cast<__bf16*>(smem) + wave * VW * COUT,
-                             Y + (long long)b * nvo * COUT, nvo, blockIdx.x * 256 + wave * VW, lane);
+  store_staged<RB, NT, COUT, false>(acc, bias, reinterpret_cast<__bf16*>(smem) + wave * VW * COUT,
+                                    Y + (long long)b * nvo * COUT, nvo, blockIdx.x * 256 + wave * VW, lane);
 }
 
 // Forward convolution with the K steps of RB 16-voxel row blocks split over
@@ -1329,14 +1343,23 @@ __global__ void k_cast_pairs4(const float* __restrict__ w, int cout, __bf16* __r
   }
 }
 
-// First-layer weights for the row path (k_conv_fwd_rows4): slot s < 20 is
-// half s & 1 of row j = s / 2 (taps 3 j .. 3 j + 2); half 0 holds tap 3 j + 1
-// (c < 4) and tap 3 j + 2 (c >= 4), half 1 tap 3 j (c < 4) and zeros; row 9
-// is zero.  WR[s][co][c], channel c % 4.
-__global__ void k_cast_rows4(const float* __restrict__ w, int cout, __bf16* __restrict__ WR) {
+// First-layer weights for the row paths (k_conv_fwd_rows4, _rows4s): slot
+// s < 18 is half s & 1 of row j = s / 2 (taps 3 j .. 3 j + 2); half 0 holds
+// tap 3 j + 1 (c < 4) and tap 3 j + 2 (c >= 4), half 1 tap 3 j (c < 4) and
+// zeros.  Slot 18 is zero; slot 19 holds the bias as a high and a low BF16
+// part (c = 0, 1; their sum is the bias to 2^-16 relative), which
+// k_conv_fwd_rows4s multiplies by ones and k_conv_fwd_rows4 by zeros.
+// WR[s][co][c], channel c % 4.
+__global__ void k_cast_rows4(const float* __restrict__ w, const float* __restrict__ bias, int cout,
+                             __bf16* __restrict__ WR) {
   const int n = 20 * cout * 8;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int c = i % 8, co = (i / 8) % cout, s = i / (8 * cout), j = s / 2;
+    if (s == 19) {
+      const __bf16 hi = (__bf16)bias[co];
+      WR[i] = c == 0 ? hi : (c == 1 ? (__bf16)(bias[co] - (float)hi) : (__bf16)0.0f);
+      continue;
+    }
     const int tap = (s & 1) ? (c < 4 ? 3 * j : -1) : 3 * j + 1 + c / 4;
     WR[i] = (__bf16)(j < 9 && tap >= 0 ? w[((long long)tap * cout + co) * 8 + c % 4] : 0.0f);
   }
