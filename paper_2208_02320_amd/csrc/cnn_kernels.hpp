@@ -1284,11 +1284,27 @@ __global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V
   constexpr int C = 64, F = 72, O = 21;
   __shared__ float feat[F];
   __shared__ float dout[O];
+  __shared__ float part[C][9];  // [thread][channel of its group of 8] (padded row)
   const int b = blockIdx.x, c = threadIdx.x;
   const __bf16* Ab = A + (long long)b * V * C;
-  float s = 0.0f;
-  for (int v = 0; v < V; ++v) s += (float)Ab[(long long)v * C + c];
-  feat[c] = s / float(V);
+  // mean pool: 16-byte chunk k holds channels 8 (k % 8) .. + 7 of voxel k / 8;
+  // thread c takes chunks c, c + 64, ... (always channel group c % 8), then
+  // the 8 threads of a group are summed in a fixed order
+  float p8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+  for (int k = c; k < V * 8; k += C) {
+    const bf16x8 x = ld8(Ab + (long long)k * 8);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) p8[j] += (float)x[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) part[c][j] = p8[j];
+  __syncthreads();
+  {
+    float s = 0.0f;
+    for (int t = c / 8; t < C; t += 8) s += part[t][c % 8];
+    feat[c] = s / float(V);
+  }
   if (c < F - C) feat[C + c] = (float(double(cnt[b * (F - C) + c]) * inv_nv) - fmu[c]) * fsc[c];
   __syncthreads();
   if (c < O) {
