@@ -414,9 +414,10 @@ void hh_launch_interfaces(const unsigned char* labels, int nitems, int box, int 
 }
 
 void hh_launch_interfaces_image(const unsigned char* img, int nx, int ny, int n, int nitems, unsigned* counts,
-                                hipStream_t st) {
+                                hipStream_t st, int* label_counts) {
   k_zero_int<<<(nitems + 255) / 256, 256, 0, st>>>(reinterpret_cast<int*>(counts), nitems);
-  launch_count_interfaces(image_window(img, nx, ny, n, 0), n, 0, nitems, counts, st);
+  if (label_counts) k_zero_int<<<(nitems * 8 + 255) / 256, 256, 0, st>>>(label_counts, nitems * 8);
+  launch_count_interfaces(image_window(img, nx, ny, n, 0), n, 0, nitems, counts, st, label_counts);
 }
 
 int hh_net_input_size(const hh_net* net) { return net ? net->n : 0; }

@@ -53,8 +53,10 @@ bool hh_net_has_interface_stats(const hh_net* net);
 // window at offset (o, o, o) of box i (box^3 labels, device); zeroes first.
 void hh_launch_interfaces(const unsigned char* labels, int nitems, int box, int o, int n, unsigned* counts,
                           hipStream_t st);
+// The same for the n^3 blocks of an image; with label_counts ([nitems][8],
+// device, or null) the same pass also gives hh_launch_counts_image's counts.
 void hh_launch_interfaces_image(const unsigned char* img, int nx, int ny, int n, int nitems, unsigned* counts,
-                                hipStream_t st);
+                                hipStream_t st, int* label_counts);
 void hh_launch_gate(const double* c21a, const double* c21b, const double* cv21, const double* cr21, int nitems,
                     double spread_tol, double bound_tol, const FracGate& ga, const FracGate& gb, int* flag,
                     hipStream_t st);

@@ -127,25 +127,22 @@ inline int count_rows_per_block(int n) {
   return r < 1 ? 1 : (r > n * n ? n * n : r);
 }
 
-template <int W>
-__global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, float inv_n, int cw, float inv_cw,
-                                                      int rows, int item0, int* __restrict__ cnt) {
-  using CT = typename Chunk<W>::type;
-  const int b = item0 + blockIdx.y, lane = threadIdx.x & 63;
-  const int r0 = blockIdx.x * rows, nr = min(rows, n * n - r0);
-  const unsigned char* base = window_base(w, b);
-  const int tasks = nr * cw;
-  unsigned ev = 0u, od = 0u;  // byte counters of labels 0 2 4 6 and 1 3 5 7
-  for (int t = threadIdx.x; t < tasks; t += 256) {
-    const int rl = fdiv(t, cw, inv_cw), k = t - rl * cw;
-    const int r = r0 + rl, z = fdiv(r, n, inv_n), y = r - z * n;
-    const CT v = *reinterpret_cast<const CT*>(base + z * w.plane + y * w.row + k * W);
-    unsigned nib = 0u;
+// Per chunk, each label adds 1 to its 4-bit field (labels 8 and above shift
+// out); the fields go to byte counters of the even and odd labels.
+template <int W, class CT>
+__device__ __forceinline__ void count_chunk(const CT& v, unsigned& ev, unsigned& od) {
+  unsigned nib = 0u;
 #pragma unroll
-    for (int j = 0; j < W; ++j) nib += unsigned(1ull << (4u * min(chunk_byte(v, j), 8u)));
-    ev += nib & 0x0F0F0F0Fu;
-    od += (nib >> 4) & 0x0F0F0F0Fu;
-  }
+  for (int j = 0; j < W; ++j) nib += unsigned(1ull << (4u * min(chunk_byte(v, j), 8u)));
+  ev += nib & 0x0F0F0F0Fu;
+  od += (nib >> 4) & 0x0F0F0F0Fu;
+}
+
+// The block's byte counters summed into cnt8[0..8): wave sums in 16-bit
+// fields, then one atomic per block and label.  Every thread of the block
+// takes part.
+__device__ __forceinline__ void flush_counts(unsigned ev, unsigned od, int* __restrict__ cnt8) {
+  const int lane = threadIdx.x & 63;
   // 16-bit fields: (0, 1), (2, 3), (4, 5), (6, 7)
   unsigned pr[4];
 #pragma unroll
@@ -163,7 +160,24 @@ __global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, floa
     }
   }
   __syncthreads();
-  if (threadIdx.x < 8 && s[threadIdx.x]) atomicAdd(&cnt[b * 8 + threadIdx.x], s[threadIdx.x]);
+  if (threadIdx.x < 8 && s[threadIdx.x]) atomicAdd(&cnt8[threadIdx.x], s[threadIdx.x]);
+}
+
+template <int W>
+__global__ void __launch_bounds__(256) k_count_labels(LabelWindow w, int n, float inv_n, int cw, float inv_cw,
+                                                      int rows, int item0, int* __restrict__ cnt) {
+  using CT = typename Chunk<W>::type;
+  const int b = item0 + blockIdx.y;
+  const int r0 = blockIdx.x * rows, nr = min(rows, n * n - r0);
+  const unsigned char* base = window_base(w, b);
+  const int tasks = nr * cw;
+  unsigned ev = 0u, od = 0u;  // byte counters of labels 0 2 4 6 and 1 3 5 7
+  for (int t = threadIdx.x; t < tasks; t += 256) {
+    const int rl = fdiv(t, cw, inv_cw), k = t - rl * cw;
+    const int r = r0 + rl, z = fdiv(r, n, inv_n), y = r - z * n;
+    count_chunk<W>(*reinterpret_cast<const CT*>(base + z * w.plane + y * w.row + k * W), ev, od);
+  }
+  flush_counts(ev, od, cnt + b * 8);
 }
 
 // cnt[item0 .. item0 + nitems) += label counts of the n^3 windows of lw
@@ -200,9 +214,12 @@ __device__ __forceinline__ unsigned nonzero_bytes(unsigned long long d) {
 // byte with itself shifted by one voxel in x (and the first voxel of the
 // next chunk), with the chunk one row up in y and one plane up in z.  Wave
 // sums, then one atomic per block.
-template <int W>
+// LABELS: the same pass also adds the windows' label counts to lcnt[b][8]
+// (as k_count_labels, whose grid and chunks it shares).
+template <int W, bool LABELS = false>
 __global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, float inv_n, int cw, float inv_cw,
-                                                          int rows, int item0, unsigned* __restrict__ cnt) {
+                                                          int rows, int item0, unsigned* __restrict__ cnt,
+                                                          int* __restrict__ lcnt) {
   using CT = typename Chunk<W>::type;
   const int b = item0 + blockIdx.y;
   const int r0 = blockIdx.x * rows, nr = min(rows, n * n - r0);
@@ -210,11 +227,13 @@ __global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, 
   const int tasks = nr * cw;
   const long long plane = w.plane;
   unsigned c = 0u;
+  unsigned ev = 0u, od = 0u;  // label byte counters (LABELS)
   for (int t = threadIdx.x; t < tasks; t += 256) {
     const int rl = fdiv(t, cw, inv_cw), k = t - rl * cw;
     const int r = r0 + rl, z = fdiv(r, n, inv_n), y = r - z * n;
     const unsigned char* p = base + z * w.plane + y * w.row + k * W;
     const CT v = *reinterpret_cast<const CT*>(p);
+    if constexpr (LABELS) count_chunk<W>(v, ev, od);
     if constexpr (W == 8) {
       // whole words: bytes that differ are the nonzero bytes of an XOR
       const unsigned long long a = (unsigned long long)v.x | ((unsigned long long)v.y << 32);
@@ -251,12 +270,14 @@ __global__ void __launch_bounds__(256) k_count_interfaces(LabelWindow w, int n, 
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(&s, c);
   __syncthreads();
   if (threadIdx.x == 0 && s) atomicAdd(&cnt[b], s);
+  if constexpr (LABELS) flush_counts(ev, od, lcnt + b * 8);
 }
 
 // cnt[item0 .. item0 + nitems) += interface counts of the n^3 windows of lw
-// (items item0 ...); the caller zeroes cnt.
+// (items item0 ...), and with lcnt the label counts as well ([item][8]); the
+// caller zeroes both.
 inline void launch_count_interfaces(const LabelWindow& lw, int n, int item0, int nitems, unsigned* cnt,
-                                    hipStream_t st) {
+                                    hipStream_t st, int* lcnt = nullptr) {
   const unsigned char* first = window_base(lw, 0);
   const int W = chunk_width({lw.mx > 0 ? (long long)n : lw.stride, lw.row, lw.plane, (long long)n}, first, first);
   const int cw = n / W, rows = count_rows_per_block(n);
@@ -265,12 +286,20 @@ inline void launch_count_interfaces(const LabelWindow& lw, int n, int item0, int
   for (int i0 = 0; i0 < nitems; i0 += 65535) {
     const int ni = nitems - i0 < 65535 ? nitems - i0 : 65535;
     const dim3 g(gx, unsigned(ni));
-    if (W == 8)
-      k_count_interfaces<8><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
-    else if (W == 4)
-      k_count_interfaces<4><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
-    else
-      k_count_interfaces<1><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt);
+    if (lcnt) {
+      if (W == 8)
+        k_count_interfaces<8, true><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt, lcnt);
+      else if (W == 4)
+        k_count_interfaces<4, true><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt, lcnt);
+      else
+        k_count_interfaces<1, true><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt, lcnt);
+    } else if (W == 8) {
+      k_count_interfaces<8><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt, nullptr);
+    } else if (W == 4) {
+      k_count_interfaces<4><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt, nullptr);
+    } else {
+      k_count_interfaces<1><<<g, 256, 0, st>>>(lw, n, inv_n, cw, inv_cw, rows, item0 + i0, cnt, nullptr);
+    }
   }
 }
 

@@ -965,10 +965,17 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
     // waits for them only before its first head
     const bool counts_on_lane = two && image_in;
     hipEvent_t counts_ready = nullptr;
-    if (image_in)
+    // with image windows and an interface test (then of the cores), one pass
+    // gives the interface and the label counts
+    const bool fused = image_in && (hh_net_has_interface_stats(net_a) || hh_net_has_interface_stats(net_b));
+    if (fused) {
+      d_if_core = static_cast<unsigned*>(ws(ctx, "sur_iface", sizeof(unsigned) * size_t(nitems)));
+      hh_launch_interfaces_image(d_img, nx, ny, n_sub, nitems, d_if_core, counts_on_lane ? sb : st, d_counts);
+    } else if (image_in) {
       hh_launch_counts_image(d_img, nx, ny, n_sub, nitems, d_counts, counts_on_lane ? sb : st);
-    else
+    } else {
       hh_launch_counts(d_pack, nitems, b, pad, n_sub, d_counts, st);
+    }
     if (box_in) hh_launch_counts(d_pack, nitems, b, 0, b, d_counts_box, st);
     if (counts_on_lane) {
       counts_ready = ctx->aux[0].e0;
@@ -983,7 +990,7 @@ int hierarchical_surrogate_impl(hh_ctx* ctx, const uint8_t* labels, int nx, int 
       if (d) continue;
       d = static_cast<unsigned*>(ws(ctx, core ? "sur_iface" : "sur_iface_box", sizeof(unsigned) * size_t(nitems)));
       if (image_in)
-        hh_launch_interfaces_image(d_img, nx, ny, n_sub, nitems, d, sb);
+        hh_launch_interfaces_image(d_img, nx, ny, n_sub, nitems, d, sb, nullptr);
       else
         hh_launch_interfaces(d_pack, nitems, b, core ? pad : 0, core ? n_sub : b, d, sb);
     }
