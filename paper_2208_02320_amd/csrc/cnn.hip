@@ -245,13 +245,14 @@ void forward(hh_ctx* ctx, hh_net* net, const unsigned char* labels, int batch, i
   forward_window(ctx, net, box_window(labels, (long long)box * box * box, box, o), batch, counts, st);
 }
 
+// c21 (or null): the denormalized predictions, written by the head as well
 void head(hh_ctx* ctx, hh_net* net, int batch, const float* target, float* dA, float* dW, float* loss, float inv,
-          hipStream_t st) {
+          hipStream_t st, double* c21 = nullptr) {
   const int V = edge(net, 3) / 2;
   const double nv = double(net->n) * net->n * net->n;
   k_head<<<batch, 64, 0, st>>>(net->a[3], V * V * V, net->cnt_in, 1.0 / nv, net->d_fmu, net->d_fsc,
                                         net->p + net->fcw_off, net->p + net->fcb_off, net->out, target, dA, dW, loss,
-                                        inv);
+                                        inv, net->d_mean, net->d_scale, c21);
 }
 
 template <int CI, int CO, bool LAB>
@@ -336,9 +337,7 @@ void hh_net_predict_device(hh_ctx* ctx, hh_net* net, const unsigned char* labels
     const int nb = std::min(step, batch - b0);
     forward(ctx, net, labels + (long long)b0 * box * box * box, nb, box, o,
             counts ? counts + (long long)b0 * kFrac : nullptr, st);
-    head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f, st);
-    k_denorm<<<(nb * kOut + 255) / 256, 256, 0, st>>>(net->out, net->d_mean, net->d_scale, nb,
-                                                      c21 + (long long)b0 * kOut);
+    head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f, st, c21 + (long long)b0 * kOut);
     HIPCHK(hipGetLastError());
   }
 }
@@ -356,9 +355,7 @@ void hh_net_predict_image(hh_ctx* ctx, hh_net* net, const unsigned char* img, in
     forward_window(ctx, net, image_window(img, nx, ny, net->n, b0), nb,
                    counts ? counts + (long long)b0 * kFrac : nullptr, st);
     if (b0 == 0 && counts_ready) HIPCHK(hipStreamWaitEvent(st, counts_ready, 0));
-    head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f, st);
-    k_denorm<<<(nb * kOut + 255) / 256, 256, 0, st>>>(net->out, net->d_mean, net->d_scale, nb,
-                                                      c21 + (long long)b0 * kOut);
+    head(ctx, net, nb, nullptr, nullptr, nullptr, nullptr, 0.0f, st, c21 + (long long)b0 * kOut);
     HIPCHK(hipGetLastError());
   }
 }

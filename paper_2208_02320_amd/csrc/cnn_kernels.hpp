@@ -1309,7 +1309,9 @@ __global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V
                                              const float* __restrict__ bfc,
                                              float* __restrict__ out, const float* __restrict__ target,
                                              float* __restrict__ dA, float* __restrict__ dW_item,
-                                             float* __restrict__ loss_item, float inv_count) {
+                                             float* __restrict__ loss_item, float inv_count,
+                                             const double* __restrict__ dmean, const double* __restrict__ dscale,
+                                             double* __restrict__ c21) {
   constexpr int C = 64, F = 72, O = 21;
   __shared__ float feat[F];
   __shared__ float dout[O];
@@ -1340,6 +1342,8 @@ __global__ void __launch_bounds__(64) k_head(const __bf16* __restrict__ A, int V
     float y = bfc[c];
     for (int k = 0; k < F; ++k) y += Wfc[c * F + k] * feat[k];
     out[b * O + c] = y;
+    // the denormalized stiffness y scale + mean (FP64) when asked for
+    if (c21) c21[b * O + c] = double(y) * dscale[c] + dmean[c];
     if (target) dout[c] = 2.0f * (y - target[b * O + c]) * inv_count;
   }
   __syncthreads();
@@ -1537,13 +1541,6 @@ __global__ void k_bounds_from_counts(const int* __restrict__ cnt, int nitems, do
   k = 0;
   for (int i = 0; i < 6; ++i)
     for (int j = i; j < 6; ++j) cr21[(long long)it * 21 + k++] = Ci[i][j];
-}
-
-// y = x * scale + mean per component (denormalize FP32 network outputs)
-__global__ void k_denorm(const float* __restrict__ x, const double* __restrict__ mean,
-                         const double* __restrict__ scale, int n, double* __restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n * 21) y[i] = double(x[i]) * scale[i % 21] + mean[i % 21];
 }
 
 }  // namespace cnn
